@@ -1,0 +1,262 @@
+"""Seeded synthetic inputs for the dsDNA Langevin hot path.
+
+This module serves both the oracle tests and the HIP path.  It only builds
+input geometry and load tables (positions of beads and patches, chain
+lengths, forces, torques, K2 scale factors); it holds none of the model's
+energy, force or integration arithmetic.
+
+Geometry of the ideal B-helix, from Fosado et al. (arXiv:1608.03722), Sec. 2
+and the caption of Fig. 1:
+  - patches of a base pair coincide on the helix axis (hydrogen-bond
+    equilibrium distance 0), consecutive patches 0.34 nm apart (rise);
+  - a bead sits 0.5 nm from its patch, perpendicular to the axis;
+  - 10 bp per turn, i.e. 36 degrees of twist per base pair;
+  - the two beads of a base pair are on opposite sides of the axis.
+Nucleotide (strand s, base pair n) of a chain starting at offset `off` has
+index off + 2 n + s.
+
+Every generator draws from its own numpy Generator(PCG64(seed)).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+RISE = 0.34          # nm per base pair (Fig. 1(b), E-F distance)
+RADIUS = 0.5         # nm, bead-patch distance (Sec. 2)
+TWIST = math.radians(36.0)   # 10 bp per turn
+PN_PER_UNIT = 4.1419         # force unit (Table 3): 4.1419 pN
+PNNM_PER_UNIT = 4.1419       # torque unit: k_B T = 4.1419 pN nm
+
+
+def _frame(t):
+    """Two unit vectors completing the unit tangent t to a right-handed frame."""
+    t = np.asarray(t, dtype=np.float64)
+    t = t / np.linalg.norm(t)
+    a = np.array([1.0, 0.0, 0.0]) if abs(t[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    e1 = a - t * np.dot(a, t)
+    e1 /= np.linalg.norm(e1)
+    e2 = np.cross(t, e1)
+    return t, e1, e2
+
+
+def helix_on_axis(axis_pts, tangents, e1, phase0=0.0, twist=TWIST, radius=RADIUS):
+    """Beads and patches of a duplex whose patches sit on the given axis points.
+
+    axis_pts, tangents, e1: [n_bp, 3]; e1 is a unit normal to the tangent that is
+    parallel-transported along the axis.  Returns bead, patch of shape
+    [2 n_bp, 3] in base-pair-major order."""
+    n_bp = axis_pts.shape[0]
+    e2 = np.cross(tangents, e1)
+    n = np.arange(n_bp, dtype=np.float64)
+    bead = np.empty((n_bp, 2, 3))
+    patch = np.empty((n_bp, 2, 3))
+    for s in (0, 1):
+        ang = phase0 + twist * n + math.pi * s
+        bead[:, s, :] = axis_pts + radius * (np.cos(ang)[:, None] * e1 + np.sin(ang)[:, None] * e2)
+        patch[:, s, :] = axis_pts
+    return bead.reshape(-1, 3), patch.reshape(-1, 3)
+
+
+def ideal_helix(n_bp, origin=(0.0, 0.0, 0.0), direction=(0.0, 0.0, 1.0), phase0=0.0,
+                rise=RISE, twist=TWIST, radius=RADIUS):
+    """Straight ideal helix: patch (s, n) at origin + rise n t, bead at radius
+    `radius` and azimuth phase0 + twist n + 180 deg s.  With the default z axis
+    this is P = (0, 0, 0.34 n), B = (0.5 cos(36n + 180s), 0.5 sin(...), 0.34 n)."""
+    t, e1, e2 = _frame(direction)
+    if np.allclose(t, [0.0, 0.0, 1.0]):
+        e1, e2 = np.array([1.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0])
+    n = np.arange(n_bp, dtype=np.float64)
+    axis = np.asarray(origin, dtype=np.float64)[None, :] + rise * n[:, None] * t[None, :]
+    return helix_on_axis(axis, np.tile(t, (n_bp, 1)), np.tile(e1, (n_bp, 1)), phase0, twist, radius)
+
+
+def mirror_helix(n_bp, **kw):
+    """Left-handed counterpart of ideal_helix (twist -36 deg per bp)."""
+    return ideal_helix(n_bp, twist=-TWIST, **kw)
+
+
+def perturb(x, amplitude, seed):
+    """x + N(0, amplitude^2) per coordinate."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.asarray(x, dtype=np.float64) + amplitude * rng.standard_normal(np.shape(x))
+
+
+def concat_replicas(parts):
+    """Stack (bead, patch) pairs of several chains in replica order."""
+    bead = np.concatenate([p[0] for p in parts], axis=0)
+    patch = np.concatenate([p[1] for p in parts], axis=0)
+    return bead, patch
+
+
+# ---------------------------------------------------------------- workloads
+
+def box_for_volume_fraction(n_beads, phi, sigma=1.0):
+    """Cubic box edge with bead volume fraction phi = N (pi/6) sigma^3 / V."""
+    return (n_beads * math.pi / 6.0 * sigma ** 3 / phi) ** (1.0 / 3.0)
+
+
+def config_100bp():
+    """100 bp ideal helix along z from the origin, open boundaries (200 sigma box)."""
+    bead, patch = ideal_helix(100)
+    return dict(n_bp=np.array([100]), bead=bead, patch=patch,
+                box=np.array([[-100.0, -100.0, -100.0, 100.0, 100.0, 100.0]]),
+                periodic=np.zeros((1, 3), np.uint8))
+
+
+def config_10kbp():
+    """10 kbp straight ideal helix in a periodic cube at 1% bead volume fraction,
+    laid along the lattice direction (34, 11, 2) so its periodic passes stay apart."""
+    n_bp = 10_000
+    L = box_for_volume_fraction(2 * n_bp, 0.01)
+    d = np.array([34.0, 11.0, 2.0])
+    bead, patch = ideal_helix(n_bp, origin=(0.5 * L, 0.5 * L, 0.5 * L), direction=d)
+    return dict(n_bp=np.array([n_bp]), bead=bead, patch=patch,
+                box=np.array([[0.0, 0.0, 0.0, L, L, L]]), periodic=np.ones((1, 3), np.uint8))
+
+
+def _rotate(v, axis, ang):
+    """Rodrigues rotation of the rows of v about the unit vector `axis` by the
+    angle(s) `ang` (scalar or one per row)."""
+    v = np.atleast_2d(np.asarray(v, dtype=np.float64))
+    ang = np.broadcast_to(np.asarray(ang, dtype=np.float64), (v.shape[0],))[:, None]
+    a = np.asarray(axis, dtype=np.float64)[None, :]
+    c, s = np.cos(ang), np.sin(ang)
+    return v * c + np.cross(a, v) * s + a * (v @ a.T) * (1.0 - c)
+
+
+def random_walk_helix(n_bp, L, seed=0, seg_bp=30, excl=3.0, max_tries=64):
+    """A long duplex pre-coiled as a persistent random walk in a periodic cube.
+
+    The axis is a chain of seg_bp-bp segments; the direction turns by
+    arccos(1 - 0.362 xi), xi ~ U(0, 1), about a uniformly random azimuth from
+    one segment to the next (mean cosine exp(-1/5): an axis persistence of five
+    segments, about 150 bp).  Within a segment the tangent turns uniformly from
+    one direction to the next, so the axis has no kinks.  A segment is redrawn
+    when its axis comes within `excl` of an axis point laid down more than two
+    segments earlier (minimum image).  The twist frame is parallel-transported.
+    Returns unwrapped bead, patch [2 n_bp, 3]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n_seg = -(-n_bp // seg_bp)
+    cell = 4.0
+    ng = max(1, int(L // cell))
+    cw = L / ng
+    grid = {}
+
+    def gkey(p):
+        q = np.floor(np.mod(p, L) / cw).astype(np.int64) % ng
+        return (int(q[0]), int(q[1]), int(q[2]))
+
+    def too_close(pts, seg_id):
+        for p in pts:
+            g = gkey(p)
+            for dx in (-1, 0, 1):
+                for dy in (-1, 0, 1):
+                    for dz in (-1, 0, 1):
+                        lst = grid.get(((g[0] + dx) % ng, (g[1] + dy) % ng, (g[2] + dz) % ng))
+                        if not lst:
+                            continue
+                        for (q, sid) in lst:
+                            if sid >= seg_id - 2:
+                                continue
+                            d = p - q
+                            d -= L * np.round(d / L)
+                            if d @ d < excl * excl:
+                                return True
+        return False
+
+    def random_perp(d):
+        _, e1, e2 = _frame(d)
+        a = rng.uniform(0.0, 2.0 * math.pi)
+        return math.cos(a) * e1 + math.sin(a) * e2
+
+    axis = np.empty((n_seg * seg_bp, 3))
+    tang = np.empty((n_seg * seg_bp, 3))
+    e1s = np.empty((n_seg * seg_bp, 3))
+    start = rng.uniform(0.0, L, 3)
+    d = rng.standard_normal(3)
+    d /= np.linalg.norm(d)
+    _, e1, _ = _frame(d)
+    pos = start.copy()
+    j = np.arange(seg_bp, dtype=np.float64)
+    for k in range(n_seg):
+        best = None
+        for attempt in range(max_tries):
+            th = math.acos(1.0 - 0.362 * rng.uniform())
+            ax = random_perp(d)
+            step_ang = th / seg_bp
+            t = _rotate(np.tile(d, (seg_bp, 1)), ax, j * step_ang)
+            pts = pos + RISE * np.concatenate([np.zeros((1, 3)), np.cumsum(t[:-1], axis=0)])
+            chk = pts[::3]
+            if not too_close(chk, k):
+                best = (th, ax, t, pts)
+                break
+            if best is None:
+                best = (th, ax, t, pts)
+        th, ax, t, pts = best
+        e1_seg = _rotate(np.tile(e1, (seg_bp, 1)), ax, j * (th / seg_bp))
+        sl = slice(k * seg_bp, (k + 1) * seg_bp)
+        axis[sl] = pts
+        tang[sl] = t
+        e1s[sl] = e1_seg
+        for p in pts[::3]:
+            grid.setdefault(gkey(p), []).append((p.copy(), k))
+        d_new = _rotate(d[None, :], ax, th)[0]
+        e1 = _rotate(e1[None, :], ax, th)[0]
+        e1 -= d_new * np.dot(e1, d_new)
+        e1 /= np.linalg.norm(e1)
+        pos = pts[-1] + RISE * t[-1]
+        d = d_new / np.linalg.norm(d_new)
+    axis, tang, e1s = axis[:n_bp], tang[:n_bp], e1s[:n_bp]
+    e1s -= tang * np.sum(e1s * tang, axis=1, keepdims=True)
+    e1s /= np.linalg.norm(e1s, axis=1, keepdims=True)
+    return helix_on_axis(axis, tang, e1s)
+
+
+def config_1mbp(seed=0, n_bp=1_000_000, phi=0.02):
+    """1 Mbp random-walk helix in a periodic cube at 2% bead volume fraction."""
+    L = box_for_volume_fraction(2 * n_bp, phi)
+    bead, patch = random_walk_helix(n_bp, L, seed=seed)
+    return dict(n_bp=np.array([n_bp]), bead=bead, patch=patch,
+                box=np.array([[0.0, 0.0, 0.0, L, L, L]]), periodic=np.ones((1, 3), np.uint8))
+
+
+def config_tethered_replicas(n_rep=256, n_torque=64, lo=500, hi=5000, f_lo_pn=0.05, f_hi_pn=20.0,
+                             g_max_pnnm=10.0, seeds=(1, 2, 3)):
+    """Replicas anchored at a wall z = 0 (first bp at z = 1), pulled along +z on
+    the last bp with forces log-uniform in [f_lo, f_hi] pN; the first n_torque
+    also get an end torque uniform in [-g_max, g_max] pN nm about z.  Chain
+    lengths uniform in {lo..hi} bp.  Loads returned in reduced units."""
+    r1 = np.random.Generator(np.random.PCG64(seeds[0]))
+    r2 = np.random.Generator(np.random.PCG64(seeds[1]))
+    r3 = np.random.Generator(np.random.PCG64(seeds[2]))
+    n_bp = r1.integers(lo, hi + 1, size=n_rep).astype(np.int32)
+    f_pn = np.exp(r2.uniform(math.log(f_lo_pn), math.log(f_hi_pn), size=n_rep))
+    g_pnnm = np.zeros(n_rep)
+    g_pnnm[:n_torque] = r3.uniform(-g_max_pnnm, g_max_pnnm, size=n_torque)
+    pull = np.zeros((n_rep, 3))
+    pull[:, 2] = f_pn / PN_PER_UNIT
+    torque = np.zeros((n_rep, 3))
+    torque[:, 2] = g_pnnm / PNNM_PER_UNIT
+    parts = [ideal_helix(int(n), origin=(0.0, 0.0, 1.0)) for n in n_bp]
+    bead, patch = concat_replicas(parts)
+    big = 1e5
+    return dict(n_bp=n_bp, bead=bead, patch=patch,
+                box=np.tile([-big, -big, -big, big, big, big], (n_rep, 1)).astype(np.float64),
+                periodic=np.zeros((n_rep, 3), np.uint8), pull=pull, torque=torque,
+                tether=np.ones(n_rep, np.uint8), wall_z=np.zeros(n_rep))
+
+
+def config_denaturation(n_rep=64, n_bp=2000, seed=4):
+    """Replicas of n_bp ideal helix with the hydrogen-bond strength scaled by
+    0.5 + 0.5 k/(n_rep-1), k = 0..n_rep-1, in a seeded permutation."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    scale = 0.5 + 0.5 * np.arange(n_rep) / max(1, n_rep - 1)
+    scale = scale[rng.permutation(n_rep)]
+    lens = np.full(n_rep, n_bp, dtype=np.int32)
+    bead, patch = concat_replicas([ideal_helix(n_bp) for _ in range(n_rep)])
+    big = 1e5
+    return dict(n_bp=lens, bead=bead, patch=patch,
+                box=np.tile([-big, -big, -big, big, big, big], (n_rep, 1)).astype(np.float64),
+                periodic=np.zeros((n_rep, 3), np.uint8), k2_scale=scale)

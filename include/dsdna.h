@@ -1,0 +1,232 @@
+/*
+ * dsdna.h -- C ABI of the MI355X (gfx950) Langevin hot path of the
+ * single-nucleotide double-stranded DNA model of Fosado, Michieletto, Allan,
+ * Brackley, Henrich and Marenduzzo (arXiv:1608.03722).
+ *
+ * One time step follows Appendix A of the paper: the Langevin equation of
+ * motion with the potentials of Sec. 2 and Appendix A (Table 2 parameters),
+ * integrated by NVT velocity-Verlet with dt = 0.005 tau_Br.  Each nucleotide
+ * is the rigid bead+patch body of Sec. 2.  Per step the library bins beads
+ * into a counting-sort cell list, evaluates the excluded volume (WCA with the
+ * steric/ghost rule of Sec. 2) and the fixed-topology terms (FENE backbone,
+ * Morse stacking, hydrogen bond, helical-twist dihedral, planarity,
+ * Kratky-Porod bending, Appendix A), adds the external loads of Sec. 4 and
+ * the Langevin friction and counter-based noise, and integrates.
+ *
+ * Conventions
+ *   - Reduced units of Table 3: length sigma = 1 nm, energy k_B T, force
+ *     k_B T / nm = 4.1419 pN, time tau_Br.
+ *   - Replica r holds n_bp[r] base pairs.  Nucleotide (strand s, base pair n)
+ *     of replica r has global index off[r] + 2 n + s, off[r] = 2 sum_{q<r}
+ *     n_bp[q] ("base-pair-major" order).  Replicas never interact.
+ *   - Every array argument is a HOST pointer, caller-owned, read or written
+ *     during the call only.  Vectors are packed [count][3] (x, y, z) doubles.
+ *   - The context owns all device memory; it is freed by dsdna_destroy.
+ *   - Work is enqueued on the context's HIP stream.  Calls on one context are
+ *     not thread-safe.  Functions that return data synchronise the stream.
+ *   - Every function returns a dsdna_status; DSDNA_OK is 0.  On failure
+ *     dsdna_last_error() describes the cause (with step and nucleotide for
+ *     DSDNA_EBOND, DSDNA_ENAN, DSDNA_EWALL).
+ *   - Call order: create -> set_topology -> (set_box, set_external,
+ *     set_k2_scale) -> set_sites or set_state -> (thermalize or
+ *     set_velocities) -> step ...  Out-of-order calls return DSDNA_ESTATE.
+ */
+#ifndef DSDNA_H
+#define DSDNA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DSDNA_OK = 0,
+    DSDNA_EINVAL = 1,   /* bad argument                                      */
+    DSDNA_ENOMEM = 2,   /* device or host allocation failed                  */
+    DSDNA_EDEVICE = 3,  /* HIP runtime error                                 */
+    DSDNA_EBOND = 4,    /* backbone bond reached R0: the FENE energy is
+                           infinite (Appendix A, U_bb for r >= R0)           */
+    DSDNA_ENAN = 5,     /* non-finite position or orientation                */
+    DSDNA_ESTATE = 6,   /* call out of order                                 */
+    DSDNA_EWALL = 7,    /* a bead of a tethered replica reached its wall     */
+    DSDNA_EDOMAIN = 8   /* a bead left the representable coordinate range   */
+} dsdna_status;
+
+/* Slots of the per-term force and energy arrays. */
+enum {
+    DSDNA_TERM_EXCL = 0,   /* bead excluded volume, WCA (Sec. 2, App. A)     */
+    DSDNA_TERM_BOND = 1,   /* backbone FENE + its WCA core (App. A, U_bb)    */
+    DSDNA_TERM_STACK = 2,  /* Morse between consecutive patches (U_morse)    */
+    DSDNA_TERM_HBOND = 3,  /* truncated harmonic between paired patches      */
+    DSDNA_TERM_TWIST = 4,  /* dihedral (bead n, patch n, patch n+1, bead n+1) */
+    DSDNA_TERM_PLANAR = 5, /* harmonic angle at patch n+1 (patch n, bead n+1) */
+    DSDNA_TERM_BEND = 6,   /* Kratky-Porod on three consecutive patches      */
+    DSDNA_TERM_EXT = 7,    /* anchoring wall, pulling force, end torque      */
+    DSDNA_NTERMS = 8
+};
+/* dsdna_get_energies writes DSDNA_NENERGY values per replica: the
+ * DSDNA_NTERMS potential terms, then translational and rotational kinetic
+ * energy of the full-step velocities. */
+#define DSDNA_NENERGY (DSDNA_NTERMS + 2)
+
+/* Kernels timed by dsdna_profile_kernels. */
+enum {
+    DSDNA_KERNEL_STEP = 0,    /* fused forces + Langevin + integrate + bin   */
+    DSDNA_KERNEL_SCAN = 1,    /* exclusive scan of the cell histogram (2 kernels) */
+    DSDNA_KERNEL_SCATTER = 2, /* counting-sort scatter into cell order       */
+    DSDNA_NKERNELS = 3
+};
+
+typedef struct dsdna_ctx dsdna_ctx; /* opaque */
+
+typedef struct {
+    /* Table 2 (Appendix A), simulation units; angles in radians */
+    double K1, R0, eps_bb, sig_bb;  /* FENE spring, max length, its WCA core */
+    double K2, r0_hb, rc_hb;        /* H-bond strength, rest length, break   */
+    double eps, sig_s, sig_x;       /* steric WCA: same-strand sigma (steric
+                                       beads), cross-strand sigma (all beads) */
+    double K3, d_dih;               /* dihedral strength and phase d         */
+    double K4, lam, r0_m;           /* Morse depth, width, rest length       */
+    double K5, a0;                  /* planarity stiffness, rest angle       */
+    double K6;                      /* Kratky-Porod stiffness                */
+    /* Sec. 2: rigid nucleotide: bead-patch distance and site masses */
+    double ell, m_bead, m_patch;
+    /* Appendix A: friction per site, temperature, time step */
+    double gamma, kT, dt;
+    uint64_t seed;                  /* key of the Philox noise               */
+    int32_t noise_kind;             /* 0: Gaussian (Box-Muller), 1: uniform
+                                       with the same variance               */
+    int32_t force_fp64;             /* 0: forces in FP32 (positions and the
+                                       integrator always FP64); 1: FP64     */
+    int32_t ssdna_rule;             /* 1: drop dihedral and bending terms
+                                       inside bubbles > 2 bp (Sec. 5)        */
+    int32_t hb_depth_convention;    /* 0: H-bond prefactor K2/(2(r0-rc)^2)
+                                       as printed; 1: K2/(r0-rc)^2           */
+    double cell_size;               /* cell edge; 0 selects the default      */
+    int32_t hash_log2;              /* log2 of cell-hash buckets; 0 = auto   */
+    int32_t graph_steps;            /* steps per captured HIP graph; 0 = off */
+} dsdna_params;
+
+/* Table 2 values plus the defaults for what the paper leaves open: unit
+ * masses, gamma = 1 (tau_Br = sigma^2/D with D = kT/gamma, Table 3),
+ * dt = 0.005 (Appendix A), Gaussian noise, FP32 forces, rule off. */
+dsdna_status dsdna_default_params(dsdna_params *out);
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * enqueue on (e.g. a torch stream handle); NULL makes the context create and
+ * own a default-priority stream. */
+dsdna_status dsdna_create(dsdna_ctx **out, const dsdna_params *params, int device,
+                          void *hip_stream);
+dsdna_status dsdna_destroy(dsdna_ctx *ctx);
+/* Description of the last failure on this context ("" if none). */
+const char *dsdna_last_error(const dsdna_ctx *ctx);
+
+/* Replica lengths n_bp[n_rep] (each >= 1).  Allocates device memory for
+ * sum 2 n_bp nucleotides.  Resets boxes to open, loads to zero, K2 scales
+ * to 1. */
+dsdna_status dsdna_set_topology(dsdna_ctx *ctx, int32_t n_rep, const int32_t *n_bp);
+
+/* Per-replica box lo_hi[n_rep][6] (lo x, y, z, hi x, y, z) and periodic
+ * flags periodic[n_rep][3] (0/1).  Periodic dimensions wrap pair distances
+ * (minimum image); positions are kept unwrapped.  For open dimensions lo
+ * is the origin of single-precision neighbour coordinates (beads must stay
+ * within 8192 of it).  A periodic edge must hold at least 3 cells. */
+dsdna_status dsdna_set_box(dsdna_ctx *ctx, const double *lo_hi, const uint8_t *periodic);
+
+/* External loads of replica `rep` (Sec. 4): pulling force F[3] on the last
+ * base pair (half on each patch), torque G[3] applied as a couple on the two
+ * beads of the last base pair, and anchoring (tether != 0: the first base
+ * pair is fixed and every bead feels a WCA wall, sigma = sig_s, at z = wall_z). */
+dsdna_status dsdna_set_external(dsdna_ctx *ctx, int32_t rep, const double F[3],
+                                const double G[3], int32_t tether, double wall_z);
+
+/* Multiply K2 of each replica by scale[n_rep] (denaturation, Sec. 5). */
+dsdna_status dsdna_set_k2_scale(dsdna_ctx *ctx, const double *scale);
+
+/* Temperature kT used by the noise from the next step on. */
+dsdna_status dsdna_set_temperature(dsdna_ctx *ctx, double kT);
+
+/* Positions of all beads and patches (bead[N][3], patch[N][3]).  Each body
+ * gets R = centre of mass and u = unit vector bead -> patch; the sites are
+ * then placed ell apart on u.  Velocities are set to zero and the step
+ * counter to 0. */
+dsdna_status dsdna_set_sites(dsdna_ctx *ctx, const double *bead, const double *patch);
+
+/* Body velocities V[N][3] and angular momenta L[N][3] at the current step
+ * (the component of L along the body axis is removed). */
+dsdna_status dsdna_set_velocities(dsdna_ctx *ctx, const double *V, const double *L);
+
+/* Maxwell-Boltzmann velocities at kT from noise stream 1 keyed by `seed`:
+ * V ~ N(0, kT/M) per component, L ~ N(0, I kT) per component minus its
+ * part along u.  Anchored bodies get zero. */
+dsdna_status dsdna_thermalize(dsdna_ctx *ctx, double kT, uint64_t seed);
+
+/* Advance n_steps >= 0 time steps.  Enqueued on the stream; returns after
+ * reading the device status word once.  On DSDNA_EBOND / DSDNA_ENAN /
+ * DSDNA_EWALL / DSDNA_EDOMAIN the remaining steps are skipped and the state
+ * is left at the step where the error was found. */
+dsdna_status dsdna_step(dsdna_ctx *ctx, int64_t n_steps);
+
+/* Current full-step state: body centres R, velocities V, axes u, angular
+ * momenta L ([N][3] each, any may be NULL) and the step counter. */
+dsdna_status dsdna_get_state(dsdna_ctx *ctx, double *R, double *V, double *u, double *L,
+                             int64_t *step);
+/* Replace the full-step state (arrays as in dsdna_get_state).  The next step
+ * evaluates forces at this state first (friction from V). */
+dsdna_status dsdna_set_state(dsdna_ctx *ctx, const double *R, const double *V, const double *u,
+                             const double *L, int64_t step);
+
+/* Exact resume point: the full-step state plus the total site forces
+ * (f_bead, f_patch [N][3], including the Langevin forces) that the next half
+ * kick uses.  Restoring it with dsdna_set_resume continues the trajectory
+ * bit for bit.  Needs at least one step since the last set_state/set_sites. */
+dsdna_status dsdna_get_resume(dsdna_ctx *ctx, double *R, double *V, double *u, double *L,
+                              double *f_bead, double *f_patch, int64_t *step);
+dsdna_status dsdna_set_resume(dsdna_ctx *ctx, const double *R, const double *V,
+                              const double *u, const double *L, const double *f_bead,
+                              const double *f_patch, int64_t step);
+
+/* Site positions of the current state (bead[N][3], patch[N][3]). */
+dsdna_status dsdna_get_sites(dsdna_ctx *ctx, double *bead, double *patch);
+
+/* Conservative and external site forces of one term (DSDNA_TERM_*), or of
+ * all terms summed (term = -1), at the current positions, computed by the
+ * same device code as the step in the context's precision. */
+dsdna_status dsdna_get_forces(dsdna_ctx *ctx, int32_t term, double *f_bead, double *f_patch);
+
+/* Energies E[n_rep][DSDNA_NENERGY] at the current state. */
+dsdna_status dsdna_get_energies(dsdna_ctx *ctx, double *E);
+
+/* Open flags (H-bond beyond r_c) of every base pair, open[sum n_bp]. */
+dsdna_status dsdna_get_bp_open(dsdna_ctx *ctx, uint8_t *open);
+
+/* Bubble statistics of Sec. 5 per replica: frac[n_rep] = fraction of open
+ * base pairs; hist[n_rep][nhist] = number of maximal open runs of length k
+ * (k < nhist; longer runs counted in nhist-1). */
+dsdna_status dsdna_get_bubbles(dsdna_ctx *ctx, int32_t nhist, double *frac, int64_t *hist);
+
+/* Run n_steps steps with a HIP event pair around every kernel launch and
+ * return the mean duration in milliseconds of each DSDNA_KERNEL_* class
+ * (ms[DSDNA_NKERNELS]).  The steps advance the state like dsdna_step. */
+dsdna_status dsdna_profile_kernels(dsdna_ctx *ctx, int64_t n_steps, double *ms);
+
+/* Sizes chosen for the cell list: cell edge, number of hash buckets and
+ * cells per periodic dimension of replica 0 (cells[3], 0 for open). */
+dsdna_status dsdna_get_grid(dsdna_ctx *ctx, double *cell_size, int64_t *n_buckets,
+                            int32_t *cells);
+
+/* Try cell edges cell_sizes[n] (each >= the largest WCA cutoff) and bucket
+ * counts 2^hash_log2s[m] for `trial_steps` steps each on the current state,
+ * keep the fastest, and report it in best_cell / best_hash_log2.  Trial
+ * steps advance the state. */
+dsdna_status dsdna_autotune(dsdna_ctx *ctx, int32_t n, const double *cell_sizes, int32_t m,
+                            const int32_t *hash_log2s, int64_t trial_steps, double *best_cell,
+                            int32_t *best_hash_log2);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DSDNA_H */

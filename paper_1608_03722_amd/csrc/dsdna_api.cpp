@@ -1,0 +1,999 @@
+// dsdna_api.cpp -- host runtime of libdsdna: the C ABI of include/dsdna.h.
+//
+// The context owns every device buffer.  The state machine of a context:
+//   NONE       topology set, no positions yet
+//   FULL       full-step state uploaded (set_sites / set_state /
+//              thermalize / set_velocities): the next step first evaluates
+//              the forces of this state (MODE_FIRST)
+//   RESUME     full-step state plus its site forces (set_resume): the next
+//              step starts from the stored forces (MODE_FROM_FORCES)
+//   LEAPFROG   after dsdna_step: positions one step ahead and half-step
+//              velocities live in the device buffers; the full-step state is
+//              the previous position buffer plus the full-step velocities
+//              the last step wrote
+//   HALTED     a step raised an error: only getters and setters work
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dsdna.h"
+#include "dsdna_dev.h"
+
+using namespace dsdna;
+
+namespace {
+
+enum Phase { PH_NONE = 0, PH_FULL, PH_RESUME, PH_LEAPFROG, PH_HALTED };
+
+constexpr double TWO_16 = 1.12246204830937298143;  // 2^(1/6)
+
+}  // namespace
+
+struct dsdna_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    dsdna_params prm{};
+    std::string err;
+
+    int32_t n_rep = 0;
+    std::vector<int32_t> n_bp;
+    std::vector<int64_t> off;
+    int64_t N = 0, n_bp_total = 0;
+    std::vector<RepInfo> rep_h;
+    std::vector<Tile> tiles_h;
+
+    StepArgs a{};  // buffers, physics, grid
+    Phase phase = PH_NONE;
+    int full_par = 0;
+    int64_t full_step = 0;
+    int binned_buf = -1;  // buffer the cell list describes, -1 if none
+    int cur_par = 0;      // host mirror of ctl.par
+    int64_t cur_step = 0; // host mirror of ctl.step
+
+    hipGraphExec_t gexec = nullptr;
+    int gsteps = 0;
+};
+
+// ------------------------------------------------------------------ helpers
+
+static dsdna_status fail(dsdna_ctx *c, dsdna_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return st;
+}
+
+#define HIPCHK(c, expr)                                                                              \
+    do {                                                                                             \
+        hipError_t e_ = (expr);                                                                      \
+        if (e_ != hipSuccess)                                                                        \
+            return fail((c), DSDNA_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+    } while (0)
+
+template <typename T>
+static hipError_t dalloc(T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc((void **)p, count * sizeof(T));
+}
+
+static void dfree(void *p)
+{
+    if (p) (void)hipFree(p);
+}
+
+static void free_state(dsdna_ctx *c)
+{
+    Bufs &b = c->a.b;
+    for (int k = 0; k < 2; ++k) {
+        dfree(b.R[k]); dfree(b.u[k]); dfree(b.V[k]); dfree(b.L[k]);
+    }
+    dfree(b.Vf); dfree(b.Lf); dfree(b.Fb); dfree(b.Fp);
+    dfree(b.rec); dfree(b.key); dfree(b.slot); dfree(b.srec); dfree(b.sid);
+    dfree(b.rep); dfree(b.tiles); dfree(b.eacc); dfree(b.open);
+    dfree(b.diag_fb); dfree(b.diag_fp);
+    Ctl *ctl = b.ctl;
+    int32_t *count = b.count, *start = b.start, *bsum = b.bsum;
+    std::memset(&b, 0, sizeof b);
+    b.ctl = ctl;
+    b.count = count; b.start = start; b.bsum = bsum;
+}
+
+static void free_grid(dsdna_ctx *c)
+{
+    dfree(c->a.b.count); dfree(c->a.b.start); dfree(c->a.b.bsum);
+    c->a.b.count = c->a.b.start = c->a.b.bsum = nullptr;
+}
+
+static void drop_graph(dsdna_ctx *c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    c->gsteps = 0;
+}
+
+static void fill_phys(dsdna_ctx *c)
+{
+    const dsdna_params &p = c->prm;
+    Phys &h = c->a.ph;
+    h.K1 = p.K1; h.R0 = p.R0; h.eps_bb = p.eps_bb; h.sig_bb = p.sig_bb;
+    h.K2 = p.K2; h.r0_hb = p.r0_hb; h.rc_hb = p.rc_hb;
+    h.eps = p.eps; h.sig_s = p.sig_s; h.sig_x = p.sig_x;
+    h.K3 = p.K3; h.d_dih = p.d_dih; h.K4 = p.K4; h.lam = p.lam; h.r0_m = p.r0_m;
+    h.K5 = p.K5; h.a0 = p.a0; h.K6 = p.K6;
+    h.ell = p.ell; h.m_bead = p.m_bead; h.m_patch = p.m_patch;
+    h.gamma = p.gamma; h.kT = p.kT; h.dt = p.dt;
+    h.M = p.m_bead + p.m_patch;
+    h.I = p.m_bead * p.m_patch / h.M * p.ell * p.ell;
+    h.db = p.ell * p.m_patch / h.M;
+    h.dp = p.ell * p.m_bead / h.M;
+    h.noise_amp = std::sqrt(2.0 * p.gamma * p.kT / p.dt);
+    const double w = (p.r0_hb - p.rc_hb) * (p.r0_hb - p.rc_hb);
+    h.hb_pref = p.hb_depth_convention == 0 ? p.K2 / (2.0 * w) : p.K2 / w;
+    h.rc_bb = TWO_16 * p.sig_bb;
+    h.rc_s = TWO_16 * p.sig_s;
+    h.rc_x = TWO_16 * p.sig_x;
+    h.cos_d = std::cos(p.d_dih);
+    h.sin_d = std::sin(p.d_dih);
+    h.kick = 0.5 * p.dt;
+    h.seed = p.seed;
+    h.noise_kind = p.noise_kind;
+    h.ssdna_rule = p.ssdna_rule;
+}
+
+static double rc_max(const dsdna_ctx *c) { return TWO_16 * std::max(c->prm.sig_s, c->prm.sig_x); }
+
+static double cell_edge(const dsdna_ctx *c)
+{
+    return c->prm.cell_size > 0.0 ? c->prm.cell_size : 1.3;
+}
+
+// The 27 cells around any cell must hash to 27 distinct buckets, also across
+// periodic wraps: check every coordinate difference two such cells can have.
+static bool hash_separates(uint32_t A, uint32_t B, uint32_t mask, const std::vector<RepInfo> &reps)
+{
+    for (const RepInfo &r : reps) {
+        std::vector<int64_t> D[3];
+        for (int k = 0; k < 3; ++k) {
+            const bool per = r.flags & (REP_PER_X << k);
+            for (int d = -2; d <= 2; ++d) {
+                if (!per) { D[k].push_back(d); continue; }
+                const int64_t n = r.ncell[k];
+                for (int w = -1; w <= 1; ++w) {
+                    const int64_t v = d + w * n;
+                    if (v > -n && v < n) D[k].push_back(v);
+                }
+            }
+            std::sort(D[k].begin(), D[k].end());
+            D[k].erase(std::unique(D[k].begin(), D[k].end()), D[k].end());
+        }
+        for (int64_t dx : D[0])
+            for (int64_t dy : D[1])
+                for (int64_t dz : D[2]) {
+                    if (dx == 0 && dy == 0 && dz == 0) continue;
+                    const uint32_t k = ((uint32_t)dx + A * (uint32_t)dy + B * (uint32_t)dz) & mask;
+                    if (k == 0) return false;
+                }
+    }
+    return true;
+}
+
+// Choose the cell edge, per-replica cell counts, bucket count and hash.
+static dsdna_status configure_grid(dsdna_ctx *c)
+{
+    const double h = cell_edge(c);
+    if (!(h >= rc_max(c) * (1.0 + 1e-6)))
+        return fail(c, DSDNA_EINVAL, "cell_size %g is below the largest WCA cutoff %g", h, rc_max(c));
+    bool all_per_same = c->n_rep > 0;
+    for (int r = 0; r < c->n_rep; ++r) {
+        RepInfo &ri = c->rep_h[r];
+        for (int k = 0; k < 3; ++k) {
+            if (ri.flags & (REP_PER_X << k)) {
+                const int64_t n = (int64_t)std::floor(ri.len[k] / h);
+                if (n < 3)
+                    return fail(c, DSDNA_EINVAL, "replica %d: periodic edge %g holds fewer than 3 cells of %g", r,
+                                ri.len[k], h);
+                if (n > (1 << 20)) return fail(c, DSDNA_EINVAL, "replica %d: periodic edge too long", r);
+                ri.ncell[k] = (int32_t)n;
+                ri.inv_h[k] = (double)n / ri.len[k];
+            } else {
+                ri.ncell[k] = 0;
+                ri.inv_h[k] = 1.0 / h;
+                all_per_same = false;
+            }
+        }
+        if (r > 0)
+            for (int k = 0; k < 3; ++k) all_per_same = all_per_same && ri.ncell[k] == c->rep_h[0].ncell[k];
+    }
+    int lg = c->prm.hash_log2;
+    if (lg <= 0) {
+        int64_t want = std::max<int64_t>(SCAN_CHUNK, 2 * c->N);
+        lg = 12;
+        while ((int64_t(1) << lg) < want && lg < 24) ++lg;
+    }
+    if (lg < 12 || lg > 28) return fail(c, DSDNA_EINVAL, "hash_log2 %d out of [12, 28]", lg);
+    const uint32_t nb = 1u << lg, mask = nb - 1u;
+    uint32_t A = 1031u, B = 1031u * 1031u;
+    if (all_per_same) {
+        A = (uint32_t)c->rep_h[0].ncell[0];
+        B = A * (uint32_t)c->rep_h[0].ncell[1];
+    }
+    // fall back to other odd multipliers if the first choice folds two
+    // neighbouring cells into one bucket
+    uint64_t x = 0x9E3779B97F4A7C15ull;
+    int tries = 0;
+    while (!hash_separates(A, B, mask, c->rep_h)) {
+        if (++tries > 1000) return fail(c, DSDNA_EINVAL, "no cell hash separates neighbours with 2^%d buckets", lg);
+        x ^= x << 13; x ^= x >> 7; x ^= x << 17;
+        A = ((uint32_t)x | 1u) & 0xFFFFu;
+        if (A < 17) A += 17;
+        B = (uint32_t)(x >> 32) | 1u;
+    }
+    Grid &g = c->a.g;
+    g.A = A;
+    g.B = B;
+    g.C = all_per_same ? B * (uint32_t)c->rep_h[0].ncell[2] : B * 1031u + 7u;
+    g.mask = mask;
+    g.h = h;
+    g.margin = 2e-3f;
+    if (g.nbucket != (int32_t)nb || !c->a.b.count) {
+        free_grid(c);
+        HIPCHK(c, dalloc(&c->a.b.count, nb));
+        HIPCHK(c, dalloc(&c->a.b.start, nb + 1));
+        HIPCHK(c, dalloc(&c->a.b.bsum, nb / SCAN_CHUNK));
+        HIPCHK(c, hipMemsetAsync(c->a.b.count, 0, sizeof(int32_t) * nb, c->stream));
+        g.nbucket = (int32_t)nb;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->a.b.rep, c->rep_h.data(), sizeof(RepInfo) * c->n_rep, hipMemcpyHostToDevice,
+                             c->stream));
+    c->binned_buf = -1;
+    drop_graph(c);
+    return DSDNA_OK;
+}
+
+static dsdna_status upload_reps(dsdna_ctx *c)
+{
+    HIPCHK(c, hipMemcpyAsync(c->a.b.rep, c->rep_h.data(), sizeof(RepInfo) * c->n_rep, hipMemcpyHostToDevice,
+                             c->stream));
+    return DSDNA_OK;
+}
+
+static dsdna_status write_ctl(dsdna_ctx *c, int64_t step, int par)
+{
+    Ctl h{};
+    h.step = step;
+    h.par = par;
+    HIPCHK(c, hipMemcpyAsync(c->a.b.ctl, &h, sizeof h, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->cur_step = step;
+    c->cur_par = par;
+    return DSDNA_OK;
+}
+
+static dsdna_status read_ctl(dsdna_ctx *c, Ctl *h)
+{
+    HIPCHK(c, hipMemcpyAsync(h, c->a.b.ctl, sizeof *h, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return DSDNA_OK;
+}
+
+// Copy on the context's stream and wait for it (the stream does not
+// synchronise with the legacy default stream).
+static dsdna_status copy(dsdna_ctx *c, void *dst, const void *src, size_t bytes, hipMemcpyKind kind)
+{
+    HIPCHK(c, hipMemcpyAsync(dst, src, bytes, kind, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return DSDNA_OK;
+}
+
+// SoA device [3][N] <-> host [N][3]
+static dsdna_status up3(dsdna_ctx *c, double *dst, const double *src)
+{
+    std::vector<double> t(3 * (size_t)c->N);
+    for (int64_t i = 0; i < c->N; ++i)
+        for (int k = 0; k < 3; ++k) t[k * c->N + i] = src[3 * i + k];
+    return copy(c, dst, t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice);
+}
+
+static dsdna_status down3(dsdna_ctx *c, double *dst, const double *src)
+{
+    std::vector<double> t(3 * (size_t)c->N);
+    dsdna_status st = copy(c, t.data(), src, sizeof(double) * t.size(), hipMemcpyDeviceToHost);
+    if (st) return st;
+    for (int64_t i = 0; i < c->N; ++i)
+        for (int k = 0; k < 3; ++k) dst[3 * i + k] = t[k * c->N + i];
+    return DSDNA_OK;
+}
+
+static dsdna_status check_ready(dsdna_ctx *c, bool need_state)
+{
+    if (!c) return DSDNA_EINVAL;
+    if (c->n_rep == 0) return fail(c, DSDNA_ESTATE, "set_topology has not been called");
+    if (need_state && c->phase == PH_NONE) return fail(c, DSDNA_ESTATE, "no positions: call set_sites or set_state");
+    return DSDNA_OK;
+}
+
+// Rebuild the cell list of buffer `which`: bin, scan, scatter.
+static dsdna_status rebin(dsdna_ctx *c, int which)
+{
+    HIPCHK(c, launch_bin(c->a, which, c->stream));
+    HIPCHK(c, launch_scan(c->a, c->stream));
+    HIPCHK(c, launch_scatter(c->a, 0, c->stream));
+    c->binned_buf = which;
+    return DSDNA_OK;
+}
+
+static dsdna_status upload_full_state(dsdna_ctx *c, const double *R, const double *V, const double *u,
+                                      const double *L, int64_t step)
+{
+    Bufs &b = c->a.b;
+    dsdna_status st;
+    if ((st = up3(c, b.R[0], R)) || (st = up3(c, b.u[0], u))) return st;
+    if (V) {
+        if ((st = up3(c, b.V[0], V))) return st;
+    } else {
+        HIPCHK(c, hipMemsetAsync(b.V[0], 0, sizeof(double) * 3 * c->N, c->stream));
+    }
+    if (L) {
+        if ((st = up3(c, b.L[0], L))) return st;
+    } else {
+        HIPCHK(c, hipMemsetAsync(b.L[0], 0, sizeof(double) * 3 * c->N, c->stream));
+    }
+    HIPCHK(c, hipMemcpyAsync(b.Vf, b.V[0], sizeof(double) * 3 * c->N, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(b.Lf, b.L[0], sizeof(double) * 3 * c->N, hipMemcpyDeviceToDevice, c->stream));
+    // a halted step may have left histogram entries behind
+    HIPCHK(c, hipMemsetAsync(b.count, 0, sizeof(int32_t) * c->a.g.nbucket, c->stream));
+    if ((st = write_ctl(c, step, 0))) return st;
+    c->full_par = 0;
+    c->full_step = step;
+    c->binned_buf = -1;
+    c->phase = PH_FULL;
+    return DSDNA_OK;
+}
+
+// Bring a LEAPFROG context back to its full-step state in buffer full_par so
+// that velocities can be replaced.
+static dsdna_status to_full(dsdna_ctx *c)
+{
+    if (c->phase != PH_LEAPFROG && c->phase != PH_RESUME && c->phase != PH_HALTED) return DSDNA_OK;
+    Bufs &b = c->a.b;
+    const int p = c->full_par;
+    if (c->phase != PH_HALTED) {  // halted: the buffer keeps its own velocities
+        HIPCHK(c, hipMemcpyAsync(b.V[p], b.Vf, sizeof(double) * 3 * c->N, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(b.L[p], b.Lf, sizeof(double) * 3 * c->N, hipMemcpyDeviceToDevice, c->stream));
+    }
+    HIPCHK(c, hipMemsetAsync(b.count, 0, sizeof(int32_t) * c->a.g.nbucket, c->stream));
+    dsdna_status st = write_ctl(c, c->full_step, p);
+    if (st) return st;
+    c->binned_buf = -1;
+    c->phase = PH_FULL;
+    return DSDNA_OK;
+}
+
+static dsdna_status status_from_ctl(dsdna_ctx *c, const Ctl &h)
+{
+    if (h.code == 0) return DSDNA_OK;
+    c->phase = PH_HALTED;
+    c->full_par = h.par;
+    c->full_step = h.step;
+    const char *what = h.code == DSDNA_EBOND    ? "backbone bond reached R0 (FENE energy infinite)"
+                       : h.code == DSDNA_ENAN   ? "non-finite position or orientation"
+                       : h.code == DSDNA_EWALL  ? "bead reached the anchoring wall"
+                       : h.code == DSDNA_EDOMAIN ? "bead left the representable coordinate range"
+                                                 : "device error";
+    return fail(c, (dsdna_status)h.code, "%s at step %lld, nucleotide %lld", what, (long long)h.err_step,
+                (long long)h.err_id);
+}
+
+// One step: fused step kernel, scan, scatter (advances ctl.step/par).
+static hipError_t enqueue_step(dsdna_ctx *c, int mode, int write_full, hipStream_t s)
+{
+    StepArgs a = c->a;
+    a.mode = mode;
+    a.write_full = write_full;
+    hipError_t e = launch_step(a, c->prm.force_fp64, s);
+    if (e == hipSuccess) e = launch_scan(a, s);
+    if (e == hipSuccess) e = launch_scatter(a, 1, s);
+    return e;
+}
+
+static dsdna_status build_graph(dsdna_ctx *c, int steps)
+{
+    drop_graph(c);
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < steps && e == hipSuccess; ++k) e = enqueue_step(c, MODE_NORMAL, 0, c->stream);
+    hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(c, DSDNA_EDEVICE, "graph capture failed: %s",
+                    hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c->gexec = nullptr;
+        return fail(c, DSDNA_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+    }
+    c->gsteps = steps;
+    return DSDNA_OK;
+}
+
+// Run n_steps; with `events` (2 per launch class per step) record timings.
+static dsdna_status run_steps(dsdna_ctx *c, int64_t n_steps, std::vector<double> *prof)
+{
+    dsdna_status st = check_ready(c, true);
+    if (st) return st;
+    if (n_steps < 0) return fail(c, DSDNA_EINVAL, "n_steps < 0");
+    if (c->phase == PH_HALTED) return fail(c, DSDNA_ESTATE, "halted by an earlier error; set a state first");
+    if (n_steps == 0) return DSDNA_OK;
+    if (c->binned_buf != c->cur_par) {
+        if ((st = rebin(c, c->cur_par))) return st;
+    }
+    int64_t launches = n_steps;
+    int first_mode = MODE_NORMAL;
+    if (c->phase == PH_FULL) { first_mode = MODE_FIRST; launches += 1; }
+    if (c->phase == PH_RESUME) { first_mode = MODE_FROM_FORCES; launches += 1; }
+
+    auto mark = [&](hipEvent_t *e) -> hipError_t {
+        hipError_t r = hipEventCreate(e);
+        if (r == hipSuccess) r = hipEventRecord(*e, c->stream);
+        return r;
+    };
+    int64_t k = 0;
+    if (prof) {
+        // eager launches with an event pair around each kernel class
+        std::vector<hipEvent_t> evs;
+        for (; k < launches; ++k) {
+            StepArgs a = c->a;
+            a.mode = k == 0 ? first_mode : MODE_NORMAL;
+            a.write_full = k == launches - 1;
+            hipEvent_t e0, e1, e2, e3;
+            HIPCHK(c, mark(&e0));
+            HIPCHK(c, launch_step(a, c->prm.force_fp64, c->stream));
+            HIPCHK(c, mark(&e1));
+            HIPCHK(c, launch_scan(a, c->stream));
+            HIPCHK(c, mark(&e2));
+            HIPCHK(c, launch_scatter(a, 1, c->stream));
+            HIPCHK(c, mark(&e3));
+            evs.insert(evs.end(), {e0, e1, e2, e3});
+        }
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        prof->assign(DSDNA_NKERNELS, 0.0);
+        for (size_t q = 0; q + 3 < evs.size(); q += 4) {
+            float t0, t1, t2;
+            HIPCHK(c, hipEventElapsedTime(&t0, evs[q], evs[q + 1]));
+            HIPCHK(c, hipEventElapsedTime(&t1, evs[q + 1], evs[q + 2]));
+            HIPCHK(c, hipEventElapsedTime(&t2, evs[q + 2], evs[q + 3]));
+            (*prof)[DSDNA_KERNEL_STEP] += t0;
+            (*prof)[DSDNA_KERNEL_SCAN] += t1;
+            (*prof)[DSDNA_KERNEL_SCATTER] += t2;
+        }
+        for (auto &x : *prof) x /= (double)launches;
+        for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+    } else {
+        if (first_mode != MODE_NORMAL) {
+            HIPCHK(c, enqueue_step(c, first_mode, launches == 1, c->stream));
+            ++k;
+        }
+        const int G = c->prm.graph_steps;
+        if (G > 0 && launches - 1 - k >= G) {
+            if (!c->gexec || c->gsteps != G) {
+                if ((st = build_graph(c, G))) return st;
+            }
+            while (launches - 1 - k >= G) {
+                HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+                k += G;
+            }
+        }
+        for (; k < launches; ++k) HIPCHK(c, enqueue_step(c, MODE_NORMAL, k == launches - 1, c->stream));
+    }
+    Ctl h;
+    if ((st = read_ctl(c, &h))) return st;
+    c->cur_step = h.step;
+    c->cur_par = h.par;
+    if (h.code != 0) return status_from_ctl(c, h);
+    c->binned_buf = h.par;
+    c->full_par = h.par ^ 1;
+    c->full_step = h.step - 1;
+    c->phase = PH_LEAPFROG;
+    return DSDNA_OK;
+}
+
+// Buffer holding the full-step positions.
+static int full_buffer(const dsdna_ctx *c) { return c->phase == PH_LEAPFROG ? c->full_par : c->cur_par; }
+
+// Run the diagnostic kernel on the full-step positions.
+static dsdna_status run_diag(dsdna_ctx *c, uint32_t mask)
+{
+    dsdna_status st;
+    const int which = full_buffer(c);
+    if (c->binned_buf != which) {
+        if ((st = rebin(c, which))) return st;
+    }
+    HIPCHK(c, launch_diag(c->a, which, c->prm.force_fp64, mask, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    Ctl h;
+    if ((st = read_ctl(c, &h))) return st;
+    if (h.code != 0) {
+        // a diagnostic evaluation found an invalid state: report it, but do
+        // not leave the error latched for the stepping kernels
+        dsdna_status code = (dsdna_status)h.code;
+        Ctl clr = h;
+        clr.code = 0;
+        if ((st = copy(c, c->a.b.ctl, &clr, sizeof clr, hipMemcpyHostToDevice))) return st;
+        // the failed evaluation may have left histogram entries behind
+        HIPCHK(c, hipMemsetAsync(c->a.b.count, 0, sizeof(int32_t) * c->a.g.nbucket, c->stream));
+        c->binned_buf = -1;
+        return fail(c, code, "invalid state: error %d at nucleotide %lld", (int)code, (long long)h.err_id);
+    }
+    return DSDNA_OK;
+}
+
+// ----------------------------------------------------------------- C ABI
+
+extern "C" {
+
+dsdna_status dsdna_default_params(dsdna_params *p)
+{
+    if (!p) return DSDNA_EINVAL;
+    std::memset(p, 0, sizeof *p);
+    p->K1 = 30.0; p->R0 = 0.6825; p->eps_bb = 1.0; p->sig_bb = 0.4430;
+    p->K2 = 6.0; p->r0_hb = 0.0; p->rc_hb = 0.3;
+    p->eps = 1.0; p->sig_s = 1.0; p->sig_x = 0.5;
+    p->K3 = 50.0; p->d_dih = -144.0 * M_PI / 180.0;
+    p->K4 = 30.0; p->lam = 8.0; p->r0_m = 0.34;
+    p->K5 = 200.0; p->a0 = 90.0 * M_PI / 180.0;
+    p->K6 = 52.0;
+    p->ell = 0.5; p->m_bead = 1.0; p->m_patch = 1.0;
+    p->gamma = 1.0; p->kT = 1.0; p->dt = 0.005;
+    p->seed = 0;
+    p->noise_kind = 0; p->force_fp64 = 0; p->ssdna_rule = 0; p->hb_depth_convention = 0;
+    p->cell_size = 0.0; p->hash_log2 = 0; p->graph_steps = 0;
+    return DSDNA_OK;
+}
+
+dsdna_status dsdna_create(dsdna_ctx **out, const dsdna_params *params, int device, void *hip_stream)
+{
+    if (!out || !params) return DSDNA_EINVAL;
+    *out = nullptr;
+    if (params->dt <= 0 || params->ell <= 0 || params->m_bead <= 0 || params->m_patch <= 0 || params->gamma < 0 ||
+        params->kT < 0 || params->R0 <= 0 || params->rc_hb <= params->r0_hb)
+        return DSDNA_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return DSDNA_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return DSDNA_EDEVICE;
+    dsdna_ctx *c = new dsdna_ctx();
+    c->device = device;
+    c->prm = *params;
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return DSDNA_EDEVICE;
+        }
+        c->own_stream = true;
+    }
+    if (dalloc(&c->a.b.ctl, 1) != hipSuccess) {
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        delete c;
+        return DSDNA_ENOMEM;
+    }
+    fill_phys(c);
+    *out = c;
+    return DSDNA_OK;
+}
+
+dsdna_status dsdna_destroy(dsdna_ctx *c)
+{
+    if (!c) return DSDNA_EINVAL;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    drop_graph(c);
+    free_state(c);
+    free_grid(c);
+    dfree(c->a.b.ctl);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return DSDNA_OK;
+}
+
+const char *dsdna_last_error(const dsdna_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+dsdna_status dsdna_set_topology(dsdna_ctx *c, int32_t n_rep, const int32_t *n_bp)
+{
+    if (!c) return DSDNA_EINVAL;
+    if (n_rep <= 0 || !n_bp) return fail(c, DSDNA_EINVAL, "need n_rep >= 1 and n_bp");
+    int64_t N = 0;
+    for (int r = 0; r < n_rep; ++r) {
+        if (n_bp[r] < 1) return fail(c, DSDNA_EINVAL, "replica %d has %d base pairs", r, n_bp[r]);
+        N += 2 * (int64_t)n_bp[r];
+    }
+    if (N >= (int64_t(1) << 31) || n_rep >= (1 << 29)) return fail(c, DSDNA_EINVAL, "too many nucleotides");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    drop_graph(c);
+    free_state(c);
+    c->n_rep = n_rep;
+    c->n_bp.assign(n_bp, n_bp + n_rep);
+    c->off.resize(n_rep);
+    c->N = N;
+    c->n_bp_total = N / 2;
+    c->rep_h.assign(n_rep, RepInfo{});
+    c->tiles_h.clear();
+    int64_t o = 0;
+    for (int r = 0; r < n_rep; ++r) {
+        c->off[r] = o;
+        RepInfo &ri = c->rep_h[r];
+        ri.off = o;
+        ri.n_bp = n_bp[r];
+        ri.flags = 0;
+        ri.k2_scale = 1.0;
+        for (int k = 0; k < 3; ++k) {
+            ri.lo[k] = 0.0;
+            ri.len[k] = 1.0;
+            ri.inv_len[k] = 1.0;
+        }
+        for (int n0 = 0; n0 < n_bp[r]; n0 += TILE_BP) c->tiles_h.push_back(Tile{r, n0});
+        o += 2 * (int64_t)n_bp[r];
+    }
+    StepArgs &a = c->a;
+    a.n_nt = N;
+    a.n_tiles = (int32_t)c->tiles_h.size();
+    a.n_tiles_pad = (a.n_tiles + 7) / 8 * 8;
+    Bufs &b = a.b;
+    const size_t n3 = 3 * (size_t)N;
+    for (int k = 0; k < 2; ++k) {
+        HIPCHK(c, dalloc(&b.R[k], n3)); HIPCHK(c, dalloc(&b.u[k], n3));
+        HIPCHK(c, dalloc(&b.V[k], n3)); HIPCHK(c, dalloc(&b.L[k], n3));
+    }
+    HIPCHK(c, dalloc(&b.Vf, n3)); HIPCHK(c, dalloc(&b.Lf, n3));
+    HIPCHK(c, dalloc(&b.Fb, n3)); HIPCHK(c, dalloc(&b.Fp, n3));
+    HIPCHK(c, dalloc(&b.key, (size_t)N)); HIPCHK(c, dalloc(&b.slot, (size_t)N));
+    HIPCHK(c, dalloc(&b.rec, (size_t)N));
+    HIPCHK(c, dalloc(&b.srec, (size_t)N)); HIPCHK(c, dalloc(&b.sid, (size_t)N));
+    HIPCHK(c, dalloc(&b.rep, (size_t)n_rep));
+    HIPCHK(c, dalloc(&b.tiles, c->tiles_h.size()));
+    HIPCHK(c, dalloc(&b.eacc, (size_t)a.n_tiles * DSDNA_NTERMS));
+    HIPCHK(c, dalloc(&b.open, (size_t)c->n_bp_total));
+    HIPCHK(c, dalloc(&b.diag_fb, n3)); HIPCHK(c, dalloc(&b.diag_fp, n3));
+    c->phase = PH_NONE;
+    dsdna_status st0 = copy(c, b.tiles, c->tiles_h.data(), sizeof(Tile) * c->tiles_h.size(), hipMemcpyHostToDevice);
+    if (st0) return st0;
+    dsdna_status st = configure_grid(c);
+    if (st) return st;
+    return write_ctl(c, 0, 0);
+}
+
+dsdna_status dsdna_set_box(dsdna_ctx *c, const double *lo_hi, const uint8_t *periodic)
+{
+    dsdna_status st = check_ready(c, false);
+    if (st) return st;
+    if (!lo_hi || !periodic) return fail(c, DSDNA_EINVAL, "null box");
+    for (int r = 0; r < c->n_rep; ++r) {
+        RepInfo &ri = c->rep_h[r];
+        ri.flags &= ~(uint32_t)(REP_PER_X | REP_PER_Y | REP_PER_Z);
+        for (int k = 0; k < 3; ++k) {
+            const double lo = lo_hi[6 * r + k], hi = lo_hi[6 * r + 3 + k];
+            if (!(hi > lo)) return fail(c, DSDNA_EINVAL, "replica %d: empty box along %d", r, k);
+            ri.lo[k] = lo;
+            ri.len[k] = hi - lo;
+            ri.inv_len[k] = 1.0 / (hi - lo);
+            if (periodic[3 * r + k]) ri.flags |= (REP_PER_X << k);
+        }
+    }
+    return configure_grid(c);
+}
+
+dsdna_status dsdna_set_external(dsdna_ctx *c, int32_t rep, const double F[3], const double G[3], int32_t tether,
+                                double wall_z)
+{
+    dsdna_status st = check_ready(c, false);
+    if (st) return st;
+    if (rep < 0 || rep >= c->n_rep) return fail(c, DSDNA_EINVAL, "replica %d out of range", rep);
+    RepInfo &ri = c->rep_h[rep];
+    ri.flags &= ~(uint32_t)(REP_TETHER | REP_PULL | REP_TORQUE);
+    for (int k = 0; k < 3; ++k) {
+        ri.pull[k] = F ? F[k] : 0.0;
+        ri.torque[k] = G ? G[k] : 0.0;
+    }
+    if (ri.pull[0] != 0.0 || ri.pull[1] != 0.0 || ri.pull[2] != 0.0) ri.flags |= REP_PULL;
+    if (ri.torque[0] != 0.0 || ri.torque[1] != 0.0 || ri.torque[2] != 0.0) ri.flags |= REP_TORQUE;
+    if (tether) ri.flags |= REP_TETHER;
+    ri.wall_z = wall_z;
+    return upload_reps(c);
+}
+
+dsdna_status dsdna_set_k2_scale(dsdna_ctx *c, const double *scale)
+{
+    dsdna_status st = check_ready(c, false);
+    if (st) return st;
+    if (!scale) return fail(c, DSDNA_EINVAL, "null scale");
+    for (int r = 0; r < c->n_rep; ++r) c->rep_h[r].k2_scale = scale[r];
+    return upload_reps(c);
+}
+
+dsdna_status dsdna_set_temperature(dsdna_ctx *c, double kT)
+{
+    if (!c) return DSDNA_EINVAL;
+    if (!(kT >= 0)) return fail(c, DSDNA_EINVAL, "kT < 0");
+    c->prm.kT = kT;
+    fill_phys(c);
+    drop_graph(c);
+    return DSDNA_OK;
+}
+
+dsdna_status dsdna_set_sites(dsdna_ctx *c, const double *bead, const double *patch)
+{
+    dsdna_status st = check_ready(c, false);
+    if (st) return st;
+    if (!bead || !patch) return fail(c, DSDNA_EINVAL, "null sites");
+    const double M = c->prm.m_bead + c->prm.m_patch;
+    std::vector<double> R(3 * c->N), u(3 * c->N);
+    for (int64_t i = 0; i < c->N; ++i) {
+        double d[3], l2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            d[k] = patch[3 * i + k] - bead[3 * i + k];
+            l2 += d[k] * d[k];
+        }
+        const double l = std::sqrt(l2);
+        if (!(l > 0.0) || !std::isfinite(l)) return fail(c, DSDNA_EINVAL, "nucleotide %lld: bead and patch coincide", (long long)i);
+        for (int k = 0; k < 3; ++k) {
+            u[3 * i + k] = d[k] * (1.0 / l);
+            R[3 * i + k] = (bead[3 * i + k] * c->prm.m_bead + patch[3 * i + k] * c->prm.m_patch) * (1.0 / M);
+        }
+    }
+    return upload_full_state(c, R.data(), nullptr, u.data(), nullptr, 0);
+}
+
+dsdna_status dsdna_set_velocities(dsdna_ctx *c, const double *V, const double *L)
+{
+    dsdna_status st = check_ready(c, true);
+    if (st) return st;
+    if (!V || !L) return fail(c, DSDNA_EINVAL, "null velocities");
+    if ((st = to_full(c))) return st;
+    std::vector<double> u(3 * c->N), Lp(3 * c->N);
+    if ((st = down3(c, u.data(), c->a.b.u[c->full_par]))) return st;
+    for (int64_t i = 0; i < c->N; ++i) {
+        const double dl = L[3 * i] * u[3 * i] + L[3 * i + 1] * u[3 * i + 1] + L[3 * i + 2] * u[3 * i + 2];
+        for (int k = 0; k < 3; ++k) Lp[3 * i + k] = L[3 * i + k] - u[3 * i + k] * dl;
+    }
+    Bufs &b = c->a.b;
+    if ((st = up3(c, b.V[c->full_par], V)) || (st = up3(c, b.L[c->full_par], Lp.data()))) return st;
+    HIPCHK(c, hipMemcpyAsync(b.Vf, b.V[c->full_par], sizeof(double) * 3 * c->N, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(b.Lf, b.L[c->full_par], sizeof(double) * 3 * c->N, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->phase = PH_FULL;
+    return DSDNA_OK;
+}
+
+dsdna_status dsdna_thermalize(dsdna_ctx *c, double kT, uint64_t seed)
+{
+    dsdna_status st = check_ready(c, true);
+    if (st) return st;
+    if (!(kT >= 0)) return fail(c, DSDNA_EINVAL, "kT < 0");
+    if ((st = to_full(c))) return st;
+    HIPCHK(c, launch_thermalize(c->a, kT, seed, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->phase = PH_FULL;
+    return DSDNA_OK;
+}
+
+dsdna_status dsdna_step(dsdna_ctx *c, int64_t n_steps)
+{
+    if (!c) return DSDNA_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, DSDNA_EDEVICE, "hipSetDevice failed");
+    return run_steps(c, n_steps, nullptr);
+}
+
+dsdna_status dsdna_get_state(dsdna_ctx *c, double *R, double *V, double *u, double *L, int64_t *step)
+{
+    dsdna_status st = check_ready(c, true);
+    if (st) return st;
+    const int p = full_buffer(c);
+    Bufs &b = c->a.b;
+    const bool halted = c->phase == PH_HALTED;
+    if (R && (st = down3(c, R, b.R[p]))) return st;
+    if (u && (st = down3(c, u, b.u[p]))) return st;
+    if (V && (st = down3(c, V, halted ? b.V[p] : b.Vf))) return st;
+    if (L && (st = down3(c, L, halted ? b.L[p] : b.Lf))) return st;
+    if (step) *step = c->full_step;
+    return DSDNA_OK;
+}
+
+dsdna_status dsdna_set_state(dsdna_ctx *c, const double *R, const double *V, const double *u, const double *L,
+                             int64_t step)
+{
+    dsdna_status st = check_ready(c, false);
+    if (st) return st;
+    if (!R || !u) return fail(c, DSDNA_EINVAL, "null R or u");
+    if (step < 0) return fail(c, DSDNA_EINVAL, "step < 0");
+    return upload_full_state(c, R, V, u, L, step);
+}
+
+dsdna_status dsdna_get_resume(dsdna_ctx *c, double *R, double *V, double *u, double *L, double *fb, double *fp,
+                              int64_t *step)
+{
+    dsdna_status st = check_ready(c, true);
+    if (st) return st;
+    if (c->phase != PH_LEAPFROG && c->phase != PH_RESUME)
+        return fail(c, DSDNA_ESTATE, "no site forces yet: take at least one step first");
+    if ((st = dsdna_get_state(c, R, V, u, L, step))) return st;
+    if (fb && (st = down3(c, fb, c->a.b.Fb))) return st;
+    if (fp && (st = down3(c, fp, c->a.b.Fp))) return st;
+    return DSDNA_OK;
+}
+
+dsdna_status dsdna_set_resume(dsdna_ctx *c, const double *R, const double *V, const double *u, const double *L,
+                              const double *fb, const double *fp, int64_t step)
+{
+    dsdna_status st = check_ready(c, false);
+    if (st) return st;
+    if (!R || !V || !u || !L || !fb || !fp) return fail(c, DSDNA_EINVAL, "null argument");
+    if ((st = upload_full_state(c, R, V, u, L, step))) return st;
+    if ((st = up3(c, c->a.b.Fb, fb)) || (st = up3(c, c->a.b.Fp, fp))) return st;
+    c->phase = PH_RESUME;
+    return DSDNA_OK;
+}
+
+dsdna_status dsdna_get_sites(dsdna_ctx *c, double *bead, double *patch)
+{
+    dsdna_status st = check_ready(c, true);
+    if (st) return st;
+    std::vector<double> R(3 * c->N), u(3 * c->N);
+    if ((st = dsdna_get_state(c, R.data(), nullptr, u.data(), nullptr, nullptr))) return st;
+    const double db = c->a.ph.db, dp = c->a.ph.dp;
+    for (int64_t i = 0; i < 3 * c->N; ++i) {
+        if (bead) bead[i] = R[i] - u[i] * db;
+        if (patch) patch[i] = R[i] + u[i] * dp;
+    }
+    return DSDNA_OK;
+}
+
+dsdna_status dsdna_get_forces(dsdna_ctx *c, int32_t term, double *fb, double *fp)
+{
+    dsdna_status st = check_ready(c, true);
+    if (st) return st;
+    if (term < -1 || term >= DSDNA_NTERMS) return fail(c, DSDNA_EINVAL, "term %d out of range", term);
+    const uint32_t mask = term < 0 ? (1u << DSDNA_NTERMS) - 1u : (1u << term);
+    if ((st = run_diag(c, mask))) return st;
+    if (fb && (st = copy(c, fb, c->a.b.diag_fb, sizeof(double) * 3 * c->N, hipMemcpyDeviceToHost))) return st;
+    if (fp && (st = copy(c, fp, c->a.b.diag_fp, sizeof(double) * 3 * c->N, hipMemcpyDeviceToHost))) return st;
+    return DSDNA_OK;
+}
+
+dsdna_status dsdna_get_energies(dsdna_ctx *c, double *E)
+{
+    dsdna_status st = check_ready(c, true);
+    if (st) return st;
+    if (!E) return fail(c, DSDNA_EINVAL, "null E");
+    if ((st = run_diag(c, (1u << DSDNA_NTERMS) - 1u))) return st;
+    std::vector<double> part((size_t)c->a.n_tiles * DSDNA_NTERMS);
+    if ((st = copy(c, part.data(), c->a.b.eacc, sizeof(double) * part.size(), hipMemcpyDeviceToHost))) return st;
+    std::fill(E, E + (size_t)c->n_rep * DSDNA_NENERGY, 0.0);
+    for (int t = 0; t < c->a.n_tiles; ++t)
+        for (int k = 0; k < DSDNA_NTERMS; ++k) E[(size_t)c->tiles_h[t].rep * DSDNA_NENERGY + k] += part[(size_t)t * DSDNA_NTERMS + k];
+    std::vector<double> V(3 * c->N), L(3 * c->N);
+    if ((st = dsdna_get_state(c, nullptr, V.data(), nullptr, L.data(), nullptr))) return st;
+    for (int r = 0; r < c->n_rep; ++r) {
+        double kt = 0.0, kr = 0.0;
+        for (int64_t i = c->off[r]; i < c->off[r] + 2 * (int64_t)c->n_bp[r]; ++i) {
+            kt += 0.5 * c->a.ph.M * (V[3 * i] * V[3 * i] + V[3 * i + 1] * V[3 * i + 1] + V[3 * i + 2] * V[3 * i + 2]);
+            kr += 0.5 * (L[3 * i] * L[3 * i] + L[3 * i + 1] * L[3 * i + 1] + L[3 * i + 2] * L[3 * i + 2]) / c->a.ph.I;
+        }
+        E[(size_t)r * DSDNA_NENERGY + DSDNA_NTERMS] = kt;
+        E[(size_t)r * DSDNA_NENERGY + DSDNA_NTERMS + 1] = kr;
+    }
+    return DSDNA_OK;
+}
+
+dsdna_status dsdna_get_bp_open(dsdna_ctx *c, uint8_t *open)
+{
+    dsdna_status st = check_ready(c, true);
+    if (st) return st;
+    if (!open) return fail(c, DSDNA_EINVAL, "null open");
+    if ((st = run_diag(c, 1u << DSDNA_TERM_HBOND))) return st;
+    if ((st = copy(c, open, c->a.b.open, (size_t)c->n_bp_total, hipMemcpyDeviceToHost))) return st;
+    return DSDNA_OK;
+}
+
+dsdna_status dsdna_get_bubbles(dsdna_ctx *c, int32_t nhist, double *frac, int64_t *hist)
+{
+    dsdna_status st = check_ready(c, true);
+    if (st) return st;
+    if (nhist < 2 || !frac || !hist) return fail(c, DSDNA_EINVAL, "need nhist >= 2, frac and hist");
+    std::vector<uint8_t> op((size_t)c->n_bp_total);
+    if ((st = dsdna_get_bp_open(c, op.data()))) return st;
+    int64_t base = 0;
+    for (int r = 0; r < c->n_rep; ++r) {
+        int64_t *h = hist + (size_t)r * nhist;
+        std::fill(h, h + nhist, 0);
+        int64_t nopen = 0, n = 0;
+        const int64_t nb = c->n_bp[r];
+        while (n < nb) {
+            if (!op[base + n]) { ++n; continue; }
+            int64_t e = n;
+            while (e < nb && op[base + e]) ++e;
+            nopen += e - n;
+            h[std::min<int64_t>(e - n, nhist - 1)] += 1;
+            n = e;
+        }
+        frac[r] = (double)nopen / (double)nb;
+        base += nb;
+    }
+    return DSDNA_OK;
+}
+
+dsdna_status dsdna_profile_kernels(dsdna_ctx *c, int64_t n_steps, double *ms)
+{
+    if (!c || !ms) return DSDNA_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, DSDNA_EDEVICE, "hipSetDevice failed");
+    std::vector<double> prof;
+    dsdna_status st = run_steps(c, n_steps, &prof);
+    if (st) return st;
+    for (int k = 0; k < DSDNA_NKERNELS; ++k) ms[k] = prof.empty() ? 0.0 : prof[k];
+    return DSDNA_OK;
+}
+
+dsdna_status dsdna_get_grid(dsdna_ctx *c, double *cell_size, int64_t *n_buckets, int32_t *cells)
+{
+    dsdna_status st = check_ready(c, false);
+    if (st) return st;
+    if (cell_size) *cell_size = c->a.g.h;
+    if (n_buckets) *n_buckets = c->a.g.nbucket;
+    if (cells)
+        for (int k = 0; k < 3; ++k) cells[k] = c->rep_h[0].ncell[k];
+    return DSDNA_OK;
+}
+
+dsdna_status dsdna_autotune(dsdna_ctx *c, int32_t n, const double *cell_sizes, int32_t m, const int32_t *hash_log2s,
+                            int64_t trial_steps, double *best_cell, int32_t *best_hash_log2)
+{
+    dsdna_status st = check_ready(c, true);
+    if (st) return st;
+    if (n < 1 || m < 1 || !cell_sizes || !hash_log2s || trial_steps < 1)
+        return fail(c, DSDNA_EINVAL, "autotune needs candidates and trial_steps >= 1");
+    double best_t = 1e300, bc = cell_edge(c);
+    int32_t bl = c->prm.hash_log2;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < m; ++j) {
+            c->prm.cell_size = cell_sizes[i];
+            c->prm.hash_log2 = hash_log2s[j];
+            if ((st = configure_grid(c))) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return st; }
+            if ((st = run_steps(c, 1, nullptr))) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return st; }
+            HIPCHK(c, hipEventRecord(e0, c->stream));
+            if ((st = run_steps(c, trial_steps, nullptr))) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return st; }
+            HIPCHK(c, hipEventRecord(e1, c->stream));
+            HIPCHK(c, hipEventSynchronize(e1));
+            float t = 0.0f;
+            HIPCHK(c, hipEventElapsedTime(&t, e0, e1));
+            if (t < best_t) { best_t = t; bc = cell_sizes[i]; bl = hash_log2s[j]; }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->prm.cell_size = bc;
+    c->prm.hash_log2 = bl;
+    if ((st = configure_grid(c))) return st;
+    if (best_cell) *best_cell = bc;
+    if (best_hash_log2) *best_hash_log2 = bl;
+    return DSDNA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,128 @@
+// dsdna_dev.h -- internal layout shared by the HIP kernels and the host
+// runtime of libdsdna.  Not part of the public ABI (include/dsdna.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dsdna {
+
+// Base pairs per tile: one workgroup of 2*TILE_BP threads owns the
+// nucleotides of TILE_BP consecutive base pairs of one replica.
+constexpr int TILE_BP = 128;
+constexpr int TILE_NT = 2 * TILE_BP;
+constexpr int HALO_BP = 2;  // bending reaches two base pairs away
+constexpr int SCAN_CHUNK = 4096;  // histogram entries per scan workgroup
+
+// Physics constants as the kernels use them (double; the force precision is
+// chosen per kernel instantiation).  Derived values are filled by the host.
+struct Phys {
+    double K1, R0, eps_bb, sig_bb;
+    double K2, r0_hb, rc_hb;
+    double eps, sig_s, sig_x;
+    double K3, d_dih, K4, lam, r0_m, K5, a0, K6;
+    double ell, m_bead, m_patch, gamma, kT, dt;
+    // derived
+    double M, I, db, dp;      // body mass, moment of inertia, |bead-R|, |patch-R|
+    double noise_amp;         // sqrt(2 gamma kT / dt)
+    double hb_pref;           // H-bond prefactor before the per-replica scale
+    double rc_bb, rc_s, rc_x; // WCA cutoffs 2^(1/6) sigma
+    double cos_d, sin_d;      // cos and sin of the dihedral phase
+    double kick;              // dt / 2
+    uint64_t seed;
+    int32_t noise_kind, ssdna_rule;
+};
+
+enum : uint32_t {
+    REP_TETHER = 1u,
+    REP_PER_X = 2u,
+    REP_PER_Y = 4u,
+    REP_PER_Z = 8u,
+    REP_PULL = 16u,
+    REP_TORQUE = 32u,
+};
+
+struct RepInfo {
+    int64_t off;        // first nucleotide
+    int32_t n_bp;
+    uint32_t flags;     // REP_*
+    double lo[3];       // box low corner: origin of the single-precision records
+    double len[3];      // box edge (periodic dims)
+    double inv_len[3];
+    double pull[3], torque[3];
+    double wall_z, k2_scale;
+    int32_t ncell[3];   // cells per periodic dim (0 for open dims)
+    int32_t pad;
+    double inv_h[3];    // cells per unit length per dim
+};
+
+struct Tile {
+    int32_t rep;
+    int32_t n0;  // first base pair of the tile within its replica
+};
+
+// Control block in device memory.  `step` is the step index of the positions
+// in buffer `par`; kernels read both at launch so that captured graphs replay
+// without argument changes.
+struct Ctl {
+    int64_t step;
+    int32_t par;
+    int32_t code;      // first error (dsdna_status), 0 if none
+    int64_t err_step;
+    int64_t err_id;
+};
+
+// Hash of cell (cx, cy, cz) of replica r into [0, nbucket): linear in the
+// cell coordinates so that the three cells cx-1, cx, cx+1 of a row are three
+// consecutive buckets.  The host chooses A, B, C such that the 27 cells
+// around any cell fall in 27 distinct buckets.
+struct Grid {
+    uint32_t A, B, C, mask;  // mask = nbucket - 1
+    double h;                // cell edge for open dims
+    float margin;            // slack of the single-precision pre-check
+    int32_t nbucket;
+};
+
+// Device buffers of one context.
+struct Bufs {
+    double *R[2], *u[2], *V[2], *L[2];  // SoA [3][N] (x block, y block, z block)
+    double *Vf, *Lf;                    // full-step velocities of the last step
+    double *Fb, *Fp;                    // full-step site forces (SoA [3][N])
+    float4 *rec;                        // bead (x, y, z) + tag bits, per nt
+    int32_t *key, *slot;                // bucket and slot of each nt's bead
+    float4 *srec;                       // records in bucket order (counting sort)
+    int32_t *sid;                       // nucleotide of each sorted record
+    int32_t *count, *start, *bsum;      // per bucket (start has nbucket+1)
+    RepInfo *rep;
+    Tile *tiles;
+    Ctl *ctl;
+    double *eacc;                       // per tile energy partials
+    uint8_t *open;                      // per bp open flags (diagnostics)
+    double *diag_fb, *diag_fp;          // per-term diagnostic forces (AoS [N][3])
+};
+
+enum StepMode : int { MODE_NORMAL = 0, MODE_FIRST = 1, MODE_FROM_FORCES = 2 };
+
+struct StepArgs {
+    Phys ph;
+    Grid g;
+    Bufs b;
+    int64_t n_nt;
+    int32_t n_tiles;
+    int32_t n_tiles_pad;   // launched workgroups (multiple of 8)
+    int32_t write_full;    // store full-step V, L and site forces
+    int32_t mode;          // StepMode
+};
+
+// Launchers (defined in dsdna_kernels.hip).
+hipError_t launch_bin(const StepArgs &a, int which, hipStream_t s);
+hipError_t launch_scan(const StepArgs &a, hipStream_t s);
+hipError_t launch_scatter(const StepArgs &a, int inc_step, hipStream_t s);
+hipError_t launch_step(const StepArgs &a, int fp64, hipStream_t s);
+hipError_t launch_thermalize(const StepArgs &a, double kT, uint64_t seed, hipStream_t s);
+// term_mask: bit t selects term t; writes per-term forces (AoS doubles) to
+// b.diag_fb / b.diag_fp, energies per tile to b.eacc[tile][DSDNA_NTERMS] and
+// open flags per bp to b.open.
+hipError_t launch_diag(const StepArgs &a, int which, int fp64, uint32_t term_mask, hipStream_t s);
+
+}  // namespace dsdna

@@ -1,0 +1,345 @@
+"""ctypes binding of libdsdna (include/dsdna.h): the same entry points, with
+numpy arrays marshalled to host pointers.  Every computation runs in the HIP
+library; this module only converts arguments and raises on error status.
+
+Loading fails loudly when libdsdna.so has not been built: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdsdna.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EBOND, ENAN, ESTATE, EWALL, EDOMAIN = range(9)
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EBOND", 5: "ENAN", 6: "ESTATE",
+                7: "EWALL", 8: "EDOMAIN"}
+TERMS = ("excl", "bond", "stack", "hbond", "twist", "planar", "bend", "ext")
+NTERMS = len(TERMS)
+NENERGY = NTERMS + 2
+KERNELS = ("step", "scan", "scatter")
+
+# every symbol include/dsdna.h declares
+EXPORTS = (
+    "dsdna_default_params", "dsdna_create", "dsdna_destroy", "dsdna_last_error", "dsdna_set_topology",
+    "dsdna_set_box", "dsdna_set_external", "dsdna_set_k2_scale", "dsdna_set_temperature", "dsdna_set_sites",
+    "dsdna_set_velocities", "dsdna_thermalize", "dsdna_step", "dsdna_get_state", "dsdna_set_state",
+    "dsdna_get_resume", "dsdna_set_resume", "dsdna_get_sites", "dsdna_get_forces", "dsdna_get_energies",
+    "dsdna_get_bp_open", "dsdna_get_bubbles", "dsdna_profile_kernels", "dsdna_get_grid", "dsdna_autotune",
+)
+
+
+class DsdnaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [(n, C.c_double) for n in (
+        "K1", "R0", "eps_bb", "sig_bb", "K2", "r0_hb", "rc_hb", "eps", "sig_s", "sig_x",
+        "K3", "d_dih", "K4", "lam", "r0_m", "K5", "a0", "K6", "ell", "m_bead", "m_patch",
+        "gamma", "kT", "dt")] + [
+        ("seed", C.c_uint64), ("noise_kind", C.c_int32), ("force_fp64", C.c_int32),
+        ("ssdna_rule", C.c_int32), ("hb_depth_convention", C.c_int32), ("cell_size", C.c_double),
+        ("hash_log2", C.c_int32), ("graph_steps", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libdsdna.so (raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libdsdna.so is not built (run __graft_entry__.build()); "
+                              "there is no fallback path")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        sigs = {
+            "dsdna_default_params": [vp],
+            "dsdna_create": [vp, vp, C.c_int, vp],
+            "dsdna_destroy": [vp],
+            "dsdna_set_topology": [vp, i32, vp],
+            "dsdna_set_box": [vp, vp, vp],
+            "dsdna_set_external": [vp, i32, vp, vp, i32, d],
+            "dsdna_set_k2_scale": [vp, vp],
+            "dsdna_set_temperature": [vp, d],
+            "dsdna_set_sites": [vp, vp, vp],
+            "dsdna_set_velocities": [vp, vp, vp],
+            "dsdna_thermalize": [vp, d, C.c_uint64],
+            "dsdna_step": [vp, i64],
+            "dsdna_get_state": [vp, vp, vp, vp, vp, vp],
+            "dsdna_set_state": [vp, vp, vp, vp, vp, i64],
+            "dsdna_get_resume": [vp, vp, vp, vp, vp, vp, vp, vp],
+            "dsdna_set_resume": [vp, vp, vp, vp, vp, vp, vp, i64],
+            "dsdna_get_sites": [vp, vp, vp],
+            "dsdna_get_forces": [vp, i32, vp, vp],
+            "dsdna_get_energies": [vp, vp],
+            "dsdna_get_bp_open": [vp, vp],
+            "dsdna_get_bubbles": [vp, i32, vp, vp],
+            "dsdna_profile_kernels": [vp, i64, vp],
+            "dsdna_get_grid": [vp, vp, vp, vp],
+            "dsdna_autotune": [vp, i32, vp, i32, vp, i64, vp, vp],
+        }
+        for name, args in sigs.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.dsdna_last_error.argtypes = [vp]
+        L.dsdna_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+# ------------------------------------------------------------ entry points
+
+def dsdna_default_params(**over) -> Params:
+    p = Params()
+    lib().dsdna_default_params(C.byref(p))
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+def _check(ctx, st):
+    if st != OK:
+        msg = lib().dsdna_last_error(ctx).decode() if ctx else ""
+        raise DsdnaError(st, msg)
+
+
+def dsdna_create(params: Params, device: int = 0, stream=None):
+    h = C.c_void_p()
+    st = lib().dsdna_create(C.byref(h), C.byref(params), int(device), stream)
+    if st != OK:
+        raise DsdnaError(st, "dsdna_create failed")
+    return h
+
+
+def dsdna_destroy(ctx):
+    _check(None, lib().dsdna_destroy(ctx))
+
+
+def dsdna_last_error(ctx) -> str:
+    return lib().dsdna_last_error(ctx).decode()
+
+
+def dsdna_set_topology(ctx, n_bp):
+    n = np.ascontiguousarray(np.atleast_1d(n_bp), dtype=np.int32)
+    _check(ctx, lib().dsdna_set_topology(ctx, len(n), _p(n)))
+
+
+def dsdna_set_box(ctx, lo_hi, periodic):
+    b = _f64(lo_hi).reshape(-1, 6)
+    p = np.ascontiguousarray(periodic, dtype=np.uint8).reshape(-1, 3)
+    _check(ctx, lib().dsdna_set_box(ctx, _p(b), _p(p)))
+
+
+def dsdna_set_external(ctx, rep, F=(0, 0, 0), G=(0, 0, 0), tether=0, wall_z=0.0):
+    f = _f64(F, (3,))
+    g = _f64(G, (3,))
+    _check(ctx, lib().dsdna_set_external(ctx, int(rep), _p(f), _p(g), int(tether), float(wall_z)))
+
+
+def dsdna_set_k2_scale(ctx, scale):
+    s = _f64(np.atleast_1d(scale))
+    _check(ctx, lib().dsdna_set_k2_scale(ctx, _p(s)))
+
+
+def dsdna_set_temperature(ctx, kT):
+    _check(ctx, lib().dsdna_set_temperature(ctx, float(kT)))
+
+
+def dsdna_set_sites(ctx, bead, patch):
+    b, p = _f64(bead), _f64(patch)
+    _check(ctx, lib().dsdna_set_sites(ctx, _p(b), _p(p)))
+
+
+def dsdna_set_velocities(ctx, V, L):
+    v, l = _f64(V), _f64(L)
+    _check(ctx, lib().dsdna_set_velocities(ctx, _p(v), _p(l)))
+
+
+def dsdna_thermalize(ctx, kT, seed):
+    _check(ctx, lib().dsdna_thermalize(ctx, float(kT), int(seed)))
+
+
+def dsdna_step(ctx, n_steps):
+    _check(ctx, lib().dsdna_step(ctx, int(n_steps)))
+
+
+def dsdna_get_state(ctx, n_nt):
+    R, V, u, L = (np.zeros((n_nt, 3)) for _ in range(4))
+    step = C.c_int64()
+    _check(ctx, lib().dsdna_get_state(ctx, _p(R), _p(V), _p(u), _p(L), C.byref(step)))
+    return R, V, u, L, step.value
+
+
+def dsdna_set_state(ctx, R, V, u, L, step):
+    R, V, u, L = (_f64(x) for x in (R, V, u, L))
+    _check(ctx, lib().dsdna_set_state(ctx, _p(R), _p(V), _p(u), _p(L), int(step)))
+
+
+def dsdna_get_resume(ctx, n_nt):
+    R, V, u, L, fb, fp = (np.zeros((n_nt, 3)) for _ in range(6))
+    step = C.c_int64()
+    _check(ctx, lib().dsdna_get_resume(ctx, _p(R), _p(V), _p(u), _p(L), _p(fb), _p(fp), C.byref(step)))
+    return R, V, u, L, fb, fp, step.value
+
+
+def dsdna_set_resume(ctx, R, V, u, L, fb, fp, step):
+    R, V, u, L, fb, fp = (_f64(x) for x in (R, V, u, L, fb, fp))
+    _check(ctx, lib().dsdna_set_resume(ctx, _p(R), _p(V), _p(u), _p(L), _p(fb), _p(fp), int(step)))
+
+
+def dsdna_get_sites(ctx, n_nt):
+    b, p = np.zeros((n_nt, 3)), np.zeros((n_nt, 3))
+    _check(ctx, lib().dsdna_get_sites(ctx, _p(b), _p(p)))
+    return b, p
+
+
+def dsdna_get_forces(ctx, term, n_nt):
+    b, p = np.zeros((n_nt, 3)), np.zeros((n_nt, 3))
+    t = term if isinstance(term, int) else TERMS.index(term)
+    _check(ctx, lib().dsdna_get_forces(ctx, int(t), _p(b), _p(p)))
+    return b, p
+
+
+def dsdna_get_energies(ctx, n_rep):
+    E = np.zeros((n_rep, NENERGY))
+    _check(ctx, lib().dsdna_get_energies(ctx, _p(E)))
+    return E
+
+
+def dsdna_get_bp_open(ctx, n_bp_total):
+    o = np.zeros(n_bp_total, dtype=np.uint8)
+    _check(ctx, lib().dsdna_get_bp_open(ctx, _p(o)))
+    return o
+
+
+def dsdna_get_bubbles(ctx, n_rep, nhist=64):
+    frac = np.zeros(n_rep)
+    hist = np.zeros((n_rep, nhist), dtype=np.int64)
+    _check(ctx, lib().dsdna_get_bubbles(ctx, int(nhist), _p(frac), _p(hist)))
+    return frac, hist
+
+
+def dsdna_profile_kernels(ctx, n_steps):
+    ms = np.zeros(len(KERNELS))
+    _check(ctx, lib().dsdna_profile_kernels(ctx, int(n_steps), _p(ms)))
+    return dict(zip(KERNELS, ms))
+
+
+def dsdna_get_grid(ctx):
+    h = C.c_double()
+    nb = C.c_int64()
+    cells = np.zeros(3, dtype=np.int32)
+    _check(ctx, lib().dsdna_get_grid(ctx, C.byref(h), C.byref(nb), _p(cells)))
+    return h.value, nb.value, cells
+
+
+def dsdna_autotune(ctx, cell_sizes, hash_log2s, trial_steps):
+    cs = _f64(np.atleast_1d(cell_sizes))
+    hl = np.ascontiguousarray(np.atleast_1d(hash_log2s), dtype=np.int32)
+    bc = C.c_double()
+    bl = C.c_int32()
+    _check(ctx, lib().dsdna_autotune(ctx, len(cs), _p(cs), len(hl), _p(hl), int(trial_steps),
+                                     C.byref(bc), C.byref(bl)))
+    return bc.value, bl.value
+
+
+# ----------------------------------------------------- convenience wrapper
+
+class DsDNA:
+    """One context: topology, box, loads and positions from a dict such as
+    those of the `synth` configs (keys n_bp, bead, patch and optionally box,
+    periodic, pull, torque, tether, wall_z, k2_scale)."""
+
+    def __init__(self, cfg, params: Params | None = None, device=0, stream=None):
+        self.params = params if params is not None else dsdna_default_params()
+        self.ctx = dsdna_create(self.params, device, stream)
+        self.n_bp = np.ascontiguousarray(cfg["n_bp"], dtype=np.int32)
+        self.n_rep = len(self.n_bp)
+        self.n_nt = int(2 * self.n_bp.astype(np.int64).sum())
+        dsdna_set_topology(self.ctx, self.n_bp)
+        if "box" in cfg:
+            dsdna_set_box(self.ctx, cfg["box"], cfg.get("periodic", np.zeros((self.n_rep, 3))))
+        for r in range(self.n_rep):
+            F = cfg["pull"][r] if "pull" in cfg else (0, 0, 0)
+            G = cfg["torque"][r] if "torque" in cfg else (0, 0, 0)
+            te = int(cfg["tether"][r]) if "tether" in cfg else 0
+            wz = float(cfg["wall_z"][r]) if "wall_z" in cfg else 0.0
+            if te or np.any(F) or np.any(G):
+                dsdna_set_external(self.ctx, r, F, G, te, wz)
+        if "k2_scale" in cfg:
+            dsdna_set_k2_scale(self.ctx, cfg["k2_scale"])
+        dsdna_set_sites(self.ctx, cfg["bead"], cfg["patch"])
+
+    def close(self):
+        if self.ctx:
+            dsdna_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def thermalize(self, kT=1.0, seed=0):
+        dsdna_thermalize(self.ctx, kT, seed)
+
+    def step(self, n):
+        dsdna_step(self.ctx, n)
+
+    def state(self):
+        return dsdna_get_state(self.ctx, self.n_nt)
+
+    def set_state(self, R, V, u, L, step=0):
+        dsdna_set_state(self.ctx, R, V, u, L, step)
+
+    def sites(self):
+        return dsdna_get_sites(self.ctx, self.n_nt)
+
+    def forces(self, term=-1):
+        return dsdna_get_forces(self.ctx, term, self.n_nt)
+
+    def energies(self):
+        return dsdna_get_energies(self.ctx, self.n_rep)
+
+    def bp_open(self):
+        return dsdna_get_bp_open(self.ctx, int(self.n_bp.sum()))
+
+    def bubbles(self, nhist=64):
+        return dsdna_get_bubbles(self.ctx, self.n_rep, nhist)
+
+    def resume_point(self):
+        return dsdna_get_resume(self.ctx, self.n_nt)
+
+    def set_resume(self, *args):
+        dsdna_set_resume(self.ctx, *args)
+
+    def profile(self, n):
+        return dsdna_profile_kernels(self.ctx, n)
+
+    def grid(self):
+        return dsdna_get_grid(self.ctx)
+
+    def autotune(self, cell_sizes, hash_log2s, trial_steps):
+        return dsdna_autotune(self.ctx, cell_sizes, hash_log2s, trial_steps)

@@ -19,7 +19,10 @@ Every generator draws from its own numpy Generator(PCG64(seed)).
 """
 from __future__ import annotations
 
+import ctypes as C
 import math
+import os
+import subprocess
 
 import numpy as np
 
@@ -126,92 +129,68 @@ def _rotate(v, axis, ang):
     return v * c + np.cross(a, v) * s + a * (v @ a.T) * (1.0 - c)
 
 
-def random_walk_helix(n_bp, L, seed=0, seg_bp=30, excl=3.0, max_tries=64):
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_RW_SRC = os.path.join(_HERE, "rwalk.c")
+_RW_LIB = os.path.join(_HERE, "librwalk.so")
+_rw = None
+
+
+def build_rwalk(force=False):
+    """Compile the random-walk layout helper (plain C, gcc)."""
+    if force or not os.path.exists(_RW_LIB) or os.path.getmtime(_RW_LIB) < os.path.getmtime(_RW_SRC):
+        tmp = _RW_LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-o", tmp,
+                               _RW_SRC, "-lm"])
+        os.replace(tmp, _RW_LIB)
+    return _RW_LIB
+
+
+def _rwlib():
+    global _rw
+    if _rw is None:
+        build_rwalk()
+        lib = C.CDLL(_RW_LIB)
+        vp = C.c_void_p
+        lib.rw_generate.argtypes = [C.c_int64, C.c_int, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
+                                    C.c_uint64, vp, vp, vp, vp, vp, vp]
+        lib.rw_generate.restype = C.c_int
+        _rw = lib
+    return _rw
+
+
+def random_walk_helix(n_bp, L, seed=0, seg_bp=30, excl=2.2, max_tries=200, stats=None, window=6):
     """A long duplex pre-coiled as a persistent random walk in a periodic cube.
 
     The axis is a chain of seg_bp-bp segments; the direction turns by
-    arccos(1 - 0.362 xi), xi ~ U(0, 1), about a uniformly random azimuth from
-    one segment to the next (mean cosine exp(-1/5): an axis persistence of five
-    segments, about 150 bp).  Within a segment the tangent turns uniformly from
-    one direction to the next, so the axis has no kinks.  A segment is redrawn
-    when its axis comes within `excl` of an axis point laid down more than two
-    segments earlier (minimum image).  The twist frame is parallel-transported.
-    Returns unwrapped bead, patch [2 n_bp, 3]."""
+    arccos(1 - 0.362 xi), xi ~ U(0, 1), about a uniformly random axis
+    perpendicular to it from one segment to the next (mean cosine exp(-1/5):
+    an axis persistence of five segments, about 150 bp).  Within a segment the
+    tangent turns uniformly, so the axis has no kinks.  Self-avoidance: axes of
+    different passes (more than `window` segments apart) stay at least `excl`
+    apart (occupancy grid, see rwalk.c).  The twist frame is
+    parallel-transported, 36 deg per bp.  Returns unwrapped bead, patch
+    [2 n_bp, 3]."""
     rng = np.random.Generator(np.random.PCG64(seed))
     n_seg = -(-n_bp // seg_bp)
-    cell = 4.0
-    ng = max(1, int(L // cell))
-    cw = L / ng
-    grid = {}
-
-    def gkey(p):
-        q = np.floor(np.mod(p, L) / cw).astype(np.int64) % ng
-        return (int(q[0]), int(q[1]), int(q[2]))
-
-    def too_close(pts, seg_id):
-        for p in pts:
-            g = gkey(p)
-            for dx in (-1, 0, 1):
-                for dy in (-1, 0, 1):
-                    for dz in (-1, 0, 1):
-                        lst = grid.get(((g[0] + dx) % ng, (g[1] + dy) % ng, (g[2] + dz) % ng))
-                        if not lst:
-                            continue
-                        for (q, sid) in lst:
-                            if sid >= seg_id - 2:
-                                continue
-                            d = p - q
-                            d -= L * np.round(d / L)
-                            if d @ d < excl * excl:
-                                return True
-        return False
-
-    def random_perp(d):
-        _, e1, e2 = _frame(d)
-        a = rng.uniform(0.0, 2.0 * math.pi)
-        return math.cos(a) * e1 + math.sin(a) * e2
-
+    pos0 = rng.uniform(0.0, L, 3)
+    d0 = rng.standard_normal(3)
+    d0 /= np.linalg.norm(d0)
+    walk_seed = int(rng.integers(0, 2**63))
     axis = np.empty((n_seg * seg_bp, 3))
-    tang = np.empty((n_seg * seg_bp, 3))
-    e1s = np.empty((n_seg * seg_bp, 3))
-    start = rng.uniform(0.0, L, 3)
-    d = rng.standard_normal(3)
-    d /= np.linalg.norm(d)
-    _, e1, _ = _frame(d)
-    pos = start.copy()
-    j = np.arange(seg_bp, dtype=np.float64)
-    for k in range(n_seg):
-        best = None
-        for attempt in range(max_tries):
-            th = math.acos(1.0 - 0.362 * rng.uniform())
-            ax = random_perp(d)
-            step_ang = th / seg_bp
-            t = _rotate(np.tile(d, (seg_bp, 1)), ax, j * step_ang)
-            pts = pos + RISE * np.concatenate([np.zeros((1, 3)), np.cumsum(t[:-1], axis=0)])
-            chk = pts[::3]
-            if not too_close(chk, k):
-                best = (th, ax, t, pts)
-                break
-            if best is None:
-                best = (th, ax, t, pts)
-        th, ax, t, pts = best
-        e1_seg = _rotate(np.tile(e1, (seg_bp, 1)), ax, j * (th / seg_bp))
-        sl = slice(k * seg_bp, (k + 1) * seg_bp)
-        axis[sl] = pts
-        tang[sl] = t
-        e1s[sl] = e1_seg
-        for p in pts[::3]:
-            grid.setdefault(gkey(p), []).append((p.copy(), k))
-        d_new = _rotate(d[None, :], ax, th)[0]
-        e1 = _rotate(e1[None, :], ax, th)[0]
-        e1 -= d_new * np.dot(e1, d_new)
-        e1 /= np.linalg.norm(e1)
-        pos = pts[-1] + RISE * t[-1]
-        d = d_new / np.linalg.norm(d_new)
-    axis, tang, e1s = axis[:n_bp], tang[:n_bp], e1s[:n_bp]
-    e1s -= tang * np.sum(e1s * tang, axis=1, keepdims=True)
-    e1s /= np.linalg.norm(e1s, axis=1, keepdims=True)
-    return helix_on_axis(axis, tang, e1s)
+    tang = np.empty_like(axis)
+    e1 = np.empty_like(axis)
+    nb = C.c_int64(0)
+    st = _rwlib().rw_generate(n_seg, seg_bp, float(L), RISE, float(excl), int(window), int(max_tries), walk_seed,
+                              d0.ctypes.data, pos0.ctypes.data, axis.ctypes.data, tang.ctypes.data,
+                              e1.ctypes.data, C.byref(nb))
+    if st != 0:
+        raise RuntimeError("random walk cannot be placed at this density")
+    if stats is not None:
+        stats["backups"] = nb.value
+    axis, tang, e1 = axis[:n_bp], tang[:n_bp], e1[:n_bp]
+    e1 = e1 - tang * np.sum(e1 * tang, axis=1, keepdims=True)
+    e1 /= np.linalg.norm(e1, axis=1, keepdims=True)
+    return helix_on_axis(axis, tang, e1)
 
 
 def config_1mbp(seed=0, n_bp=1_000_000, phi=0.02):

@@ -1,0 +1,276 @@
+"""GPU path vs the FP64 oracle, element by element, through the C ABI.
+
+Tolerance (per term t, over all sites): ||F_gpu,t - F_ref,t||_2 / ||F_ref,t||_2
+<= 1e-5 with FP32 forces; for the total, max_i |dF_i| / max(1, sum_t |F_i,t|)
+<= 1e-5 (an absolute floor where every term vanishes).
+FP64-force mode must agree to ~1e-10 (the excluded volume is accumulated in
+2^-32 fixed point)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def D():
+    from paper_1608_03722_amd import dsdna
+    dsdna.lib()
+    return dsdna
+
+
+def _oracle_state(n_bp=100, steps=1500, seed=11, cfg=None, params=None):
+    """A thermal state produced by the oracle from the given start."""
+    P = params or O.default_params(seed=seed)
+    cfg = cfg or dict(n_bp=np.array([n_bp]), **dict(zip(("bead", "patch"), synth.ideal_helix(n_bp))))
+    S = _oracle_system(cfg)
+    R, u = O.bodies_from_sites(P, cfg["bead"], cfg["patch"])
+    st = O.State(R, u)
+    O.thermalize(P, S, st, 1.0, seed)
+    code, _, _ = O.step(P, S, st, steps, use_cells=int(S.n_nt > 600))
+    assert code == O.OK
+    return P, S, st
+
+
+def _oracle_system(cfg):
+    keys = ("box", "periodic", "pull", "torque", "tether", "wall_z", "k2_scale")
+    return O.System(cfg["n_bp"], **{k: cfg[k] for k in keys if k in cfg})
+
+
+def _gpu(D, cfg, **prm):
+    return D.DsDNA(cfg, D.dsdna_default_params(**prm))
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a - b)
+
+
+def _compare_terms(D, sim, P, S, R, u, tol, use_cells=False):
+    b, p = O.sites_from_bodies(P, R, u)
+    st, _, fb, fp, E, op = O.forces(P, S, b, p, use_cells=use_cells)
+    assert st == O.OK
+    worst = {}
+    for t, name in enumerate(D.TERMS):
+        gb, gp = sim.forces(t)
+        ref = np.concatenate([fb[t], fp[t]])
+        got = np.concatenate([gb, gp])
+        if np.linalg.norm(ref) < 1e-12:
+            assert np.abs(got).max() < 1e-7, (name, np.abs(got).max())
+            continue
+        worst[name] = _rel(got, ref)
+        assert worst[name] <= tol, (name, worst[name])
+    gb, gp = sim.forces(-1)
+    tot_ref = np.concatenate([fb.sum(0), fp.sum(0)])
+    scale = np.concatenate([np.linalg.norm(fb, axis=2).sum(0), np.linalg.norm(fp, axis=2).sum(0)])
+    err = np.linalg.norm(np.concatenate([gb, gp]) - tot_ref, axis=1)
+    # sites whose terms all vanish (e.g. a straight bending triple cancels
+    # exactly in FP64) are held to an absolute floor of tol (kT/nm)
+    assert (err / np.maximum(scale, 1.0)).max() <= tol
+    Eg = sim.energies()
+    for t in range(D.NTERMS):
+        assert abs(Eg[:, t] - E[:, t]).max() <= max(tol, 1e-12) * max(1.0, np.abs(E[:, t]).max()), D.TERMS[t]
+    return worst
+
+
+@pytest.mark.parametrize("fp64,tol", [(0, 1e-5), (1, 1e-10)])
+def test_forces_thermal_100bp(D, fp64, tol):
+    """Per-term forces and energies of a thermalised 100 bp duplex."""
+    P, S, st = _oracle_state()
+    cfg = dict(n_bp=np.array([100]), **dict(zip(("bead", "patch"), O.sites_from_bodies(P, st.R, st.u))))
+    sim = _gpu(D, cfg, force_fp64=fp64)
+    sim.set_state(st.R, st.V, st.u, st.L, 0)
+    _compare_terms(D, sim, P, S, st.R, st.u, tol)
+
+
+@pytest.mark.parametrize("fp64,tol", [(0, 1e-5), (1, 1e-10)])
+def test_forces_compressed_contacts(D, fp64, tol):
+    """A compressed, narrowed duplex: many excluded-volume contacts on and
+    across strands, spanning several tiles with a ragged tail (300 bp)."""
+    n = 300
+    bead, patch = synth.ideal_helix(n, rise=0.29, radius=0.3)
+    bead, patch = synth.perturb(bead, 0.02, 3), synth.perturb(patch, 0.02, 4)
+    P = O.default_params()
+    R, u = O.bodies_from_sites(P, bead, patch)
+    cfg = dict(n_bp=np.array([n]), bead=bead, patch=patch)
+    sim = _gpu(D, cfg, force_fp64=fp64)
+    S = O.System([n])
+    b, p = O.sites_from_bodies(P, R, u)
+    assert len(O.wca_pairs(P, S, b)) > 100
+    _compare_terms(D, sim, P, S, R, u, tol)
+
+
+def test_forces_periodic_box(D):
+    """A compressed duplex in a periodic box: it straddles the x and y faces
+    (wrapped cells, minimum image) and its two ends meet across the z face
+    (contacts through the periodic seam).  Forces agree with the oracle at
+    several cell sizes and bucket counts, and are identical bit for bit across
+    them (order-independent accumulation)."""
+    n = 301
+    d = np.array([0.004, 0.003, 1.0])
+    d /= np.linalg.norm(d)
+    bead, patch = synth.ideal_helix(n, origin=(9.9, 9.95, 0.0), direction=d, rise=0.29, radius=0.3)
+    bead, patch = synth.perturb(bead, 0.02, 3), synth.perturb(patch, 0.02, 4)
+    box = np.array([[0.0, 0.0, 0.0, 10.0, 10.0, 0.29 * n * d[2]]])
+    cfg = dict(n_bp=np.array([n]), bead=bead, patch=patch, box=box, periodic=np.ones((1, 3), np.uint8))
+    P = O.default_params()
+    S = _oracle_system(cfg)
+    R, u = O.bodies_from_sites(P, bead, patch)
+    b, p = O.sites_from_bodies(P, R, u)
+    pairs = O.wca_pairs(P, S, b, use_cells=True)
+    seam = [(i, j) for i, j in pairs if abs(b[i, 2] - b[j, 2]) > box[0, 5] / 2]
+    assert len(pairs) > 100 and len(seam) >= 1
+    ref = None
+    for cell in (1.1235, 1.3, 1.83):
+        for lg in (12, 16):
+            sim = _gpu(D, cfg, cell_size=cell, hash_log2=lg)
+            _compare_terms(D, sim, P, S, R, u, 1e-5, use_cells=True)
+            f = np.concatenate(sim.forces(0))
+            if ref is None:
+                ref = f
+            assert np.array_equal(f, ref), (cell, lg)
+            sim.close()
+
+
+def test_replicas_with_loads(D):
+    """Uneven replicas stacked in the same region of space (they must not
+    interact), tethered to a wall, pulled and twisted, with K2 scales."""
+    lens = [37, 130, 5, 260]
+    parts = [synth.ideal_helix(m, origin=(0.0, 0.0, 1.0)) for m in lens]
+    bead, patch = synth.concat_replicas(parts)
+    bead, patch = synth.perturb(bead, 0.02, 8), synth.perturb(patch, 0.02, 9)
+    k = len(lens)
+    cfg = dict(n_bp=np.array(lens), bead=bead, patch=patch,
+               pull=np.array([[0, 0, 1.2], [0.3, 0, 2.0], [0, 0, 0], [0, 0.1, 4.8]]),
+               torque=np.array([[0, 0, 2.0], [0, 0, 0], [0, 0, -1.0], [0.5, 0, 1.5]]),
+               tether=np.array([1, 1, 0, 1]), wall_z=np.array([0.0, 0.0, 0.0, -0.2]),
+               k2_scale=np.array([1.0, 0.5, 0.8, 0.66]))
+    P = O.default_params()
+    S = _oracle_system(cfg)
+    R, u = O.bodies_from_sites(P, bead, patch)
+    for fp64, tol in ((0, 1e-5), (1, 1e-10)):
+        sim = _gpu(D, cfg, force_fp64=fp64)
+        _compare_terms(D, sim, P, S, R, u, tol)
+        sim.close()
+
+
+def test_ssdna_rule(D):
+    """Dihedral and bending terms inside bubbles > 2 bp are dropped; open flags
+    and bubble statistics match the oracle."""
+    n = 150
+    bead, patch = synth.mirror_helix(n)
+    open_bp = set()
+    for start, ln in ((3, 1), (10, 2), (20, 5), (60, 3), (126, 6), (146, 4)):
+        open_bp.update(range(start, start + ln))
+    for q in open_bp:  # after the rigid-body projection the patch moves ~0.35 off its partner
+        patch[2 * q + 1] += np.array([0.7, 0.0, 0.0])
+    cfg = dict(n_bp=np.array([n]), bead=bead, patch=patch)
+    P = O.default_params(ssdna_rule=1)
+    S = O.System([n])
+    R, u = O.bodies_from_sites(P, bead, patch)
+    sim = _gpu(D, cfg, ssdna_rule=1)
+    _compare_terms(D, sim, P, S, R, u, 1e-5)
+    b, p = O.sites_from_bodies(P, R, u)
+    op_ref = O.forces(P, S, b, p)[5]
+    assert set(np.nonzero(op_ref)[0]) == open_bp
+    assert np.array_equal(sim.bp_open(), op_ref)
+    frac, hist = sim.bubbles(16)
+    f_ref, h_ref = O.bubbles(op_ref, 16)
+    assert frac[0] == pytest.approx(f_ref) and np.array_equal(hist[0], h_ref)
+
+
+def test_thermalize_matches_oracle(D):
+    bead, patch = synth.ideal_helix(40, origin=(0, 0, 1.0))
+    cfg = dict(n_bp=np.array([40]), bead=bead, patch=patch, tether=np.array([1]), wall_z=np.array([0.0]))
+    sim = _gpu(D, cfg)
+    sim.thermalize(1.3, 77)
+    R, V, u, L, k = sim.state()
+    P = O.default_params()
+    S = _oracle_system(cfg)
+    st = O.State(*O.bodies_from_sites(P, bead, patch))
+    O.thermalize(P, S, st, 1.3, 77)
+    assert k == 0
+    assert np.abs(V - st.V).max() < 1e-13 and np.abs(L - st.L).max() < 1e-13
+    assert np.all(V[:2] == 0)
+
+
+@pytest.mark.parametrize("noise_kind", [0, 1])
+def test_fp64_trajectory_matches_oracle(D, noise_kind):
+    """FP64-force mode reproduces the oracle's trajectory (same Philox stream)
+    over 200 steps, through set_state at a nonzero step."""
+    P, S, st = _oracle_state(n_bp=64, steps=300, seed=4,
+                             params=O.default_params(seed=4, noise_kind=noise_kind))
+    cfg = dict(n_bp=np.array([64]), **dict(zip(("bead", "patch"), O.sites_from_bodies(P, st.R, st.u))))
+    sim = _gpu(D, cfg, force_fp64=1, seed=4, noise_kind=noise_kind)
+    ref = O.State(st.R, st.u, st.V, st.L, st.step)  # drop the stored forces: both start from a full state
+    sim.set_state(ref.R, ref.V, ref.u, ref.L, ref.step)
+    for chunk in (1, 49, 150):
+        sim.step(chunk)
+        code, _, _ = O.step(P, S, ref, chunk)
+        assert code == O.OK
+        R, V, u, L, k = sim.state()
+        assert k == ref.step
+        assert np.abs(R - ref.R).max() < 1e-9, (k, np.abs(R - ref.R).max())
+        assert np.abs(u - ref.u).max() < 1e-9
+        assert np.abs(V - ref.V).max() < 1e-7
+        assert np.abs(L - ref.L).max() < 1e-7
+
+
+def test_fp32_first_steps_match_oracle(D):
+    """FP32 forces: positions after 5 steps agree to the force tolerance."""
+    P, S, st = _oracle_state(n_bp=100, steps=500, seed=9)
+    cfg = dict(n_bp=np.array([100]), **dict(zip(("bead", "patch"), O.sites_from_bodies(P, st.R, st.u))))
+    sim = _gpu(D, cfg, seed=9)
+    ref = O.State(st.R, st.u, st.V, st.L, st.step)
+    sim.set_state(ref.R, ref.V, ref.u, ref.L, ref.step)
+    sim.step(5)
+    O.step(P, S, ref, 5)
+    R, V, u, L, k = sim.state()
+    assert np.abs(R - ref.R).max() < 1e-8
+    assert np.abs(V - ref.V).max() < 5e-5 * max(1.0, np.abs(ref.V).max())
+
+
+def test_deterministic_graph_and_resume(D):
+    """Two runs are bit-identical; a captured graph gives the eager result bit
+    for bit; N steps + resume + N steps equal 2N steps."""
+    P, S, st = _oracle_state(n_bp=200, steps=200, seed=2)
+    cfg = dict(n_bp=np.array([200]), **dict(zip(("bead", "patch"), O.sites_from_bodies(P, st.R, st.u))))
+    outs = []
+    for gsteps in (0, 0, 7):
+        sim = _gpu(D, cfg, seed=2, graph_steps=gsteps)
+        sim.set_state(st.R, st.V, st.u, st.L, 0)
+        sim.step(60)
+        outs.append(sim.state())
+        sim.close()
+    for o in outs[1:]:
+        for x, y in zip(o[:4], outs[0][:4]):
+            assert np.array_equal(x, y)
+    sim = _gpu(D, cfg, seed=2)
+    sim.set_state(st.R, st.V, st.u, st.L, 0)
+    sim.step(30)
+    snap = sim.resume_point()
+    sim2 = _gpu(D, cfg, seed=2)
+    sim2.set_resume(*snap)
+    sim2.step(30)
+    for x, y in zip(sim2.state()[:4], outs[0][:4]):
+        assert np.array_equal(x, y)
+
+
+def test_error_paths(D):
+    """A backbone bond at r >= R0 stops the run with EBOND and its location."""
+    bead, patch = synth.ideal_helix(20)
+    bead[21] += np.array([0.0, 0.0, 0.3])
+    patch[21] += np.array([0.0, 0.0, 0.3])
+    sim = _gpu(D, dict(n_bp=np.array([20]), bead=bead, patch=patch))
+    with pytest.raises(D.DsdnaError) as ei:
+        sim.step(3)
+    assert ei.value.status == D.EBOND and "step 0" in str(ei.value)
+    # the context stays usable after a new state
+    b2, p2 = synth.ideal_helix(20)
+    D.dsdna_set_sites(sim.ctx, b2, p2)
+    sim.step(3)
+    with pytest.raises(D.DsdnaError) as ei:
+        D.dsdna_step(sim.ctx, -1)
+    assert ei.value.status == D.EINVAL

@@ -106,6 +106,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (a counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -123,6 +125,14 @@ def main():
     torch.cuda.init()
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
+    if args.calib_copy_mb > 0:
+        src = torch.ones(args.calib_copy_mb * (1 << 20) // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d MiB read + %d MiB written" % (args.calib_copy_mb, args.calib_copy_mb))
+        del src, dst
     prm = D.dsdna_default_params(seed=0, cell_size=args.cell, hash_log2=args.hash_log2,
                                  graph_steps=args.graph_steps,
                                  ssdna_rule=1 if args.config == "denat" else 0)

@@ -49,7 +49,10 @@ struct dsdna_ctx {
     std::vector<RepInfo> rep_h;
     std::vector<Tile> tiles_h;
 
-    StepArgs a{};  // buffers, physics, grid
+    StepArgs a{};  // buffers, physics, grid (host copy)
+    StepArgs *dA = nullptr;  // device copy read by the kernels
+    StepArgs up{};           // contents of dA as last uploaded
+    bool up_valid = false;
     Phase phase = PH_NONE;
     int full_par = 0;
     int64_t full_step = 0;
@@ -115,6 +118,22 @@ static void free_grid(dsdna_ctx *c)
 {
     dfree(c->a.b.count); dfree(c->a.b.start); dfree(c->a.b.bsum);
     c->a.b.count = c->a.b.start = c->a.b.bsum = nullptr;
+}
+
+// Upload the argument block if it changed since the last upload.  Never
+// called during graph capture: a captured graph reads the block through dA.
+static dsdna_status sync_args(dsdna_ctx *c)
+{
+    if (!c->dA) {
+        HIPCHK(c, dalloc(&c->dA, 1));
+        c->up_valid = false;
+    }
+    if (c->up_valid && std::memcmp(&c->up, &c->a, sizeof(StepArgs)) == 0) return DSDNA_OK;
+    std::memcpy(&c->up, &c->a, sizeof(StepArgs));
+    HIPCHK(c, hipMemcpyAsync(c->dA, &c->up, sizeof(StepArgs), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->up_valid = true;
+    return DSDNA_OK;
 }
 
 static void drop_graph(dsdna_ctx *c)
@@ -247,13 +266,32 @@ static dsdna_status configure_grid(dsdna_ctx *c)
     g.C = all_per_same ? B * (uint32_t)c->rep_h[0].ncell[2] : B * 1031u + 7u;
     g.mask = mask;
     g.h = h;
-    g.margin = 2e-3f;
+    // 16-bit neighbour coordinates: unit q per dim; the pre-check slack covers
+    // the quantisation of both beads (a difference is off by < q per dim)
+    double qmax = 0.0;
+    for (int r = 0; r < c->n_rep; ++r) {
+        RepInfo &ri = c->rep_h[r];
+        for (int k = 0; k < 3; ++k) {
+            ri.q[k] = (ri.flags & (REP_PER_X << k)) ? (float)(ri.len[k] / 65536.0) : (float)(1.0 / OPEN_Q_INV);
+            qmax = std::max(qmax, (double)ri.q[k]);
+        }
+    }
+    g.margin = (float)(2.0 * std::sqrt(3.0) * qmax + 1e-4);
+    // integer pre-check thresholds (squared cutoff plus slack, in q^2 units)
+    for (int r = 0; r < c->n_rep; ++r) {
+        RepInfo &ri = c->rep_h[r];
+        ri.qsame = ri.q[0] == ri.q[1] && ri.q[1] == ri.q[2];
+        const double q = ri.q[0];
+        const double ts = (c->a.ph.rc_s + g.margin) / q, tx = (c->a.ph.rc_x + g.margin) / q;
+        ri.t2_same = (int32_t)std::min(std::ceil(ts * ts), 2.0e9);
+        ri.t2_cross = (int32_t)std::min(std::ceil(tx * tx), 2.0e9);
+    }
     if (g.nbucket != (int32_t)nb || !c->a.b.count) {
         free_grid(c);
-        HIPCHK(c, dalloc(&c->a.b.count, nb));
-        HIPCHK(c, dalloc(&c->a.b.start, nb + 1));
-        HIPCHK(c, dalloc(&c->a.b.bsum, nb / SCAN_CHUNK));
-        HIPCHK(c, hipMemsetAsync(c->a.b.count, 0, sizeof(int32_t) * nb, c->stream));
+        HIPCHK(c, dalloc(&c->a.b.count, 2 * (size_t)nb));
+        HIPCHK(c, dalloc(&c->a.b.start, 2 * (size_t)nb + 1));
+        HIPCHK(c, dalloc(&c->a.b.bsum, 2 * (size_t)nb / SCAN_CHUNK));
+        HIPCHK(c, hipMemsetAsync(c->a.b.count, 0, sizeof(int32_t) * 2 * nb, c->stream));
         g.nbucket = (int32_t)nb;
     }
     HIPCHK(c, hipMemcpyAsync(c->a.b.rep, c->rep_h.data(), sizeof(RepInfo) * c->n_rep, hipMemcpyHostToDevice,
@@ -328,7 +366,9 @@ static dsdna_status check_ready(dsdna_ctx *c, bool need_state)
 // Rebuild the cell list of buffer `which`: bin, scan, scatter.
 static dsdna_status rebin(dsdna_ctx *c, int which)
 {
-    HIPCHK(c, launch_bin(c->a, which, c->stream));
+    dsdna_status st = sync_args(c);
+    if (st) return st;
+    HIPCHK(c, launch_bin(c->a, c->dA, which, c->stream));
     HIPCHK(c, launch_scan(c->a, c->stream));
     HIPCHK(c, launch_scatter(c->a, 0, c->stream));
     c->binned_buf = which;
@@ -354,7 +394,7 @@ static dsdna_status upload_full_state(dsdna_ctx *c, const double *R, const doubl
     HIPCHK(c, hipMemcpyAsync(b.Vf, b.V[0], sizeof(double) * 3 * c->N, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(b.Lf, b.L[0], sizeof(double) * 3 * c->N, hipMemcpyDeviceToDevice, c->stream));
     // a halted step may have left histogram entries behind
-    HIPCHK(c, hipMemsetAsync(b.count, 0, sizeof(int32_t) * c->a.g.nbucket, c->stream));
+    HIPCHK(c, hipMemsetAsync(b.count, 0, sizeof(int32_t) * 2 * (size_t)c->a.g.nbucket, c->stream));
     if ((st = write_ctl(c, step, 0))) return st;
     c->full_par = 0;
     c->full_step = step;
@@ -374,7 +414,7 @@ static dsdna_status to_full(dsdna_ctx *c)
         HIPCHK(c, hipMemcpyAsync(b.V[p], b.Vf, sizeof(double) * 3 * c->N, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(b.L[p], b.Lf, sizeof(double) * 3 * c->N, hipMemcpyDeviceToDevice, c->stream));
     }
-    HIPCHK(c, hipMemsetAsync(b.count, 0, sizeof(int32_t) * c->a.g.nbucket, c->stream));
+    HIPCHK(c, hipMemsetAsync(b.count, 0, sizeof(int32_t) * 2 * (size_t)c->a.g.nbucket, c->stream));
     dsdna_status st = write_ctl(c, c->full_step, p);
     if (st) return st;
     c->binned_buf = -1;
@@ -400,12 +440,9 @@ static dsdna_status status_from_ctl(dsdna_ctx *c, const Ctl &h)
 // One step: fused step kernel, scan, scatter (advances ctl.step/par).
 static hipError_t enqueue_step(dsdna_ctx *c, int mode, int write_full, hipStream_t s)
 {
-    StepArgs a = c->a;
-    a.mode = mode;
-    a.write_full = write_full;
-    hipError_t e = launch_step(a, c->prm.force_fp64, s);
-    if (e == hipSuccess) e = launch_scan(a, s);
-    if (e == hipSuccess) e = launch_scatter(a, 1, s);
+    hipError_t e = launch_step(c->a, c->dA, c->prm.force_fp64, mode, write_full, s);
+    if (e == hipSuccess) e = launch_scan(c->a, s);
+    if (e == hipSuccess) e = launch_scatter(c->a, 1, s);
     return e;
 }
 
@@ -440,6 +477,7 @@ static dsdna_status run_steps(dsdna_ctx *c, int64_t n_steps, std::vector<double>
     if (n_steps < 0) return fail(c, DSDNA_EINVAL, "n_steps < 0");
     if (c->phase == PH_HALTED) return fail(c, DSDNA_ESTATE, "halted by an earlier error; set a state first");
     if (n_steps == 0) return DSDNA_OK;
+    if ((st = sync_args(c))) return st;
     if (c->binned_buf != c->cur_par) {
         if ((st = rebin(c, c->cur_par))) return st;
     }
@@ -458,16 +496,14 @@ static dsdna_status run_steps(dsdna_ctx *c, int64_t n_steps, std::vector<double>
         // eager launches with an event pair around each kernel class
         std::vector<hipEvent_t> evs;
         for (; k < launches; ++k) {
-            StepArgs a = c->a;
-            a.mode = k == 0 ? first_mode : MODE_NORMAL;
-            a.write_full = k == launches - 1;
+            const int mode = k == 0 ? first_mode : MODE_NORMAL;
             hipEvent_t e0, e1, e2, e3;
             HIPCHK(c, mark(&e0));
-            HIPCHK(c, launch_step(a, c->prm.force_fp64, c->stream));
+            HIPCHK(c, launch_step(c->a, c->dA, c->prm.force_fp64, mode, k == launches - 1, c->stream));
             HIPCHK(c, mark(&e1));
-            HIPCHK(c, launch_scan(a, c->stream));
+            HIPCHK(c, launch_scan(c->a, c->stream));
             HIPCHK(c, mark(&e2));
-            HIPCHK(c, launch_scatter(a, 1, c->stream));
+            HIPCHK(c, launch_scatter(c->a, 1, c->stream));
             HIPCHK(c, mark(&e3));
             evs.insert(evs.end(), {e0, e1, e2, e3});
         }
@@ -521,10 +557,11 @@ static dsdna_status run_diag(dsdna_ctx *c, uint32_t mask)
 {
     dsdna_status st;
     const int which = full_buffer(c);
+    if ((st = sync_args(c))) return st;
     if (c->binned_buf != which) {
         if ((st = rebin(c, which))) return st;
     }
-    HIPCHK(c, launch_diag(c->a, which, c->prm.force_fp64, mask, c->stream));
+    HIPCHK(c, launch_diag(c->a, c->dA, which, c->prm.force_fp64, mask, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     Ctl h;
     if ((st = read_ctl(c, &h))) return st;
@@ -536,7 +573,7 @@ static dsdna_status run_diag(dsdna_ctx *c, uint32_t mask)
         clr.code = 0;
         if ((st = copy(c, c->a.b.ctl, &clr, sizeof clr, hipMemcpyHostToDevice))) return st;
         // the failed evaluation may have left histogram entries behind
-        HIPCHK(c, hipMemsetAsync(c->a.b.count, 0, sizeof(int32_t) * c->a.g.nbucket, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->a.b.count, 0, sizeof(int32_t) * 2 * (size_t)c->a.g.nbucket, c->stream));
         c->binned_buf = -1;
         return fail(c, code, "invalid state: error %d at nucleotide %lld", (int)code, (long long)h.err_id);
     }
@@ -607,6 +644,7 @@ dsdna_status dsdna_destroy(dsdna_ctx *c)
     free_state(c);
     free_grid(c);
     dfree(c->a.b.ctl);
+    dfree(c->dA);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return DSDNA_OK;
@@ -787,7 +825,8 @@ dsdna_status dsdna_thermalize(dsdna_ctx *c, double kT, uint64_t seed)
     if (st) return st;
     if (!(kT >= 0)) return fail(c, DSDNA_EINVAL, "kT < 0");
     if ((st = to_full(c))) return st;
-    HIPCHK(c, launch_thermalize(c->a, kT, seed, c->stream));
+    if ((st = sync_args(c))) return st;
+    HIPCHK(c, launch_thermalize(c->a, c->dA, kT, seed, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->phase = PH_FULL;
     return DSDNA_OK;

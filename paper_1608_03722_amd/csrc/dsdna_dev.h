@@ -54,7 +54,17 @@ struct RepInfo {
     int32_t ncell[3];   // cells per periodic dim (0 for open dims)
     int32_t pad;
     double inv_h[3];    // cells per unit length per dim
+    float q[3];         // length of one unit of the 16-bit neighbour coordinates
+    int32_t qsame;      // 1 when q is the same along x, y and z
+    int32_t t2_same;    // (same-strand cutoff + slack)^2 in units of q^2
+    int32_t t2_cross;   // (cross-strand cutoff + slack)^2 in units of q^2
 };
+
+// 16-bit neighbour coordinates: periodic dims map [lo, lo + L) onto the full
+// 16-bit range (q = L / 65536) so that wrapped 16-bit differences are minimum
+// images; open dims use q = 1/256 (differences of nearby beads are exact
+// modulo 256 nm, which is all the cell search needs).
+constexpr double OPEN_Q_INV = 256.0;
 
 struct Tile {
     int32_t rep;
@@ -75,12 +85,13 @@ struct Ctl {
 // Hash of cell (cx, cy, cz) of replica r into [0, nbucket): linear in the
 // cell coordinates so that the three cells cx-1, cx, cx+1 of a row are three
 // consecutive buckets.  The host chooses A, B, C such that the 27 cells
-// around any cell fall in 27 distinct buckets.
+// around any cell fall in 27 distinct buckets.  The counting sort keys are
+// bucket + strand * nbucket: one plane of buckets per strand.
 struct Grid {
     uint32_t A, B, C, mask;  // mask = nbucket - 1
     double h;                // cell edge for open dims
-    float margin;            // slack of the single-precision pre-check
-    int32_t nbucket;
+    float margin;            // slack of the 16-bit pre-check (length units)
+    int32_t nbucket;         // buckets per strand plane
 };
 
 // Device buffers of one context.
@@ -88,11 +99,11 @@ struct Bufs {
     double *R[2], *u[2], *V[2], *L[2];  // SoA [3][N] (x block, y block, z block)
     double *Vf, *Lf;                    // full-step velocities of the last step
     double *Fb, *Fp;                    // full-step site forces (SoA [3][N])
-    float4 *rec;                        // bead (x, y, z) + tag bits, per nt
-    int32_t *key, *slot;                // bucket and slot of each nt's bead
-    float4 *srec;                       // records in bucket order (counting sort)
+    uint2 *rec;                         // bead record (16-bit x, y, z, tag), per nt
+    int32_t *key, *slot;                // counting-sort key and slot of each bead
+    uint2 *srec;                        // records in key order (counting sort)
     int32_t *sid;                       // nucleotide of each sorted record
-    int32_t *count, *start, *bsum;      // per bucket (start has nbucket+1)
+    int32_t *count, *start, *bsum;      // per key: 2 * nbucket (start: +1)
     RepInfo *rep;
     Tile *tiles;
     Ctl *ctl;
@@ -103,6 +114,10 @@ struct Bufs {
 
 enum StepMode : int { MODE_NORMAL = 0, MODE_FIRST = 1, MODE_FROM_FORCES = 2 };
 
+// Everything the kernels read that does not change from launch to launch.
+// The host keeps a copy in device memory and passes its address, so the
+// large block is loaded through the scalar cache on demand instead of
+// occupying scalar registers.
 struct StepArgs {
     Phys ph;
     Grid g;
@@ -110,19 +125,19 @@ struct StepArgs {
     int64_t n_nt;
     int32_t n_tiles;
     int32_t n_tiles_pad;   // launched workgroups (multiple of 8)
-    int32_t write_full;    // store full-step V, L and site forces
-    int32_t mode;          // StepMode
 };
 
-// Launchers (defined in dsdna_kernels.hip).
-hipError_t launch_bin(const StepArgs &a, int which, hipStream_t s);
+// Launchers (defined in dsdna_kernels.hip).  `a` is the host copy (grid
+// sizes), `dA` the device copy the kernels read.
+hipError_t launch_bin(const StepArgs &a, const StepArgs *dA, int which, hipStream_t s);
 hipError_t launch_scan(const StepArgs &a, hipStream_t s);
 hipError_t launch_scatter(const StepArgs &a, int inc_step, hipStream_t s);
-hipError_t launch_step(const StepArgs &a, int fp64, hipStream_t s);
-hipError_t launch_thermalize(const StepArgs &a, double kT, uint64_t seed, hipStream_t s);
+hipError_t launch_step(const StepArgs &a, const StepArgs *dA, int fp64, int mode, int write_full, hipStream_t s);
+hipError_t launch_thermalize(const StepArgs &a, const StepArgs *dA, double kT, uint64_t seed, hipStream_t s);
 // term_mask: bit t selects term t; writes per-term forces (AoS doubles) to
 // b.diag_fb / b.diag_fp, energies per tile to b.eacc[tile][DSDNA_NTERMS] and
 // open flags per bp to b.open.
-hipError_t launch_diag(const StepArgs &a, int which, int fp64, uint32_t term_mask, hipStream_t s);
+hipError_t launch_diag(const StepArgs &a, const StepArgs *dA, int which, int fp64, uint32_t term_mask,
+                       hipStream_t s);
 
 }  // namespace dsdna

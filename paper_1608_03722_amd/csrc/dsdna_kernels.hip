@@ -6,14 +6,14 @@
 //   k_step     one workgroup per tile of TILE_BP base pairs of one replica:
 //              stage the tile's FP64 sites in LDS, evaluate every
 //              fixed-topology term once into LDS outboxes, gather them per
-//              site (no atomics), add the bead's excluded volume from the
+//              site (no atomics), add each bead's excluded volume from the
 //              cell list (fixed-point accumulation, order independent), the
 //              external loads and the Langevin forces, then integrate the
 //              rigid body (FP64) and bin its new bead position (histogram
 //              atomics: the counting-sort count phase).
-//   k_scan_*   exclusive scan of the bucket histogram (counting-sort offsets)
-//   k_scatter  counting-sort scatter of the bead records into bucket
-//              order; clears the histogram for the next step.
+//   k_scan_*   exclusive scan of the histogram (counting-sort offsets)
+//   k_scatter  counting-sort scatter of the bead records into key order;
+//              clears the histogram for the next step.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -63,12 +63,20 @@ __device__ __forceinline__ void st3(double *soa, int64_t n, int64_t i, D3 a)
     soa[2 * n + i] = a.z;
 }
 
+// Reciprocal and reciprocal square root: the hardware approximations
+// (1 ulp) for FP32 forces, correctly rounded division for FP64.
 template <typename T>
-__device__ __forceinline__ T rsqrt_t(T x);
+__device__ __forceinline__ T rcp(T x);
 template <>
-__device__ __forceinline__ float rsqrt_t<float>(float x) { return 1.0f / sqrtf(x); }
+__device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 template <>
-__device__ __forceinline__ double rsqrt_t<double>(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ double rcp<double>(double x) { return 1.0 / x; }
+template <typename T>
+__device__ __forceinline__ T rsq(T x);
+template <>
+__device__ __forceinline__ float rsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <>
+__device__ __forceinline__ double rsq<double>(double x) { return 1.0 / sqrt(x); }
 
 // Sites of a rigid nucleotide (Sec. 2): bead = R - db u, patch = R + dp u.
 // Written with explicit fused multiply-adds so every kernel that recomputes
@@ -102,18 +110,26 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k)
     return c;
 }
 
-// Six unit-variance numbers for nucleotide `id` at `step`: counter
+// The six 32-bit words of nucleotide `id` at `step`: counter
 // (id, stream << 16 | call, step lo, step hi), key (seed lo, seed hi);
-// u = (x + 1/2) 2^-32; Box-Muller on (w0,w1), (w2,w3) of call 0 and (w0,w1)
-// of call 1, or sqrt(12)(u - 1/2) for the uniform kind.  Order: bead xyz,
-// patch xyz.
-__device__ __forceinline__ void noise6(uint64_t seed, int kind, uint64_t step, uint32_t id,
-                                       uint32_t stream, double xi[6])
+// words 0..3 of call 0 and 0..1 of call 1.
+__device__ __forceinline__ void philox_words(uint64_t seed, uint64_t step, uint32_t id, uint32_t stream,
+                                             uint32_t w[6])
 {
     const uint2 key = make_uint2((uint32_t)seed, (uint32_t)(seed >> 32));
     const uint4 w0 = philox4x32_10(make_uint4(id, stream << 16, (uint32_t)step, (uint32_t)(step >> 32)), key);
     const uint4 w1 = philox4x32_10(make_uint4(id, (stream << 16) | 1u, (uint32_t)step, (uint32_t)(step >> 32)), key);
-    const uint32_t w[6] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y};
+    w[0] = w0.x; w[1] = w0.y; w[2] = w0.z; w[3] = w0.w; w[4] = w1.x; w[5] = w1.y;
+}
+
+// Six unit-variance numbers (bead xyz, patch xyz): u = (w + 1/2) 2^-32;
+// Box-Muller on (w0,w1), (w2,w3), (w4,w5), or sqrt(12)(u - 1/2) for the
+// uniform kind.  Evaluated in FP64.
+__device__ __forceinline__ void noise6(uint64_t seed, int kind, uint64_t step, uint32_t id, uint32_t stream,
+                                       double xi[6])
+{
+    uint32_t w[6];
+    philox_words(seed, step, id, stream, w);
     double u[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) u[k] = ((double)w[k] + 0.5) * 0x1p-32;
@@ -133,6 +149,37 @@ __device__ __forceinline__ void noise6(uint64_t seed, int kind, uint64_t step, u
     }
 }
 
+// The same numbers evaluated in FP32 (forces in FP32).  For u > 1/2, ln u
+// is taken as log1p(-(1 - u)) with 1 - u formed exactly from the integer,
+// so the radius keeps its relative accuracy near u = 1.
+__device__ __forceinline__ void noise6f(uint64_t seed, int kind, uint64_t step, uint32_t id, uint32_t stream,
+                                        float xi[6])
+{
+    uint32_t w[6];
+    philox_words(seed, step, id, stream, w);
+    if (kind == 1) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            // u - 1/2 = (w - 2^31 + 1/2) 2^-32, formed from the signed integer
+            const float c = ((float)(int32_t)(w[k] ^ 0x80000000u) + 0.5f) * 0x1p-32f;
+            xi[k] = 3.46410161513775459f * c;
+        }
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; k += 2) {
+        const uint32_t a = w[k];
+        const float lnu = a < 0x80000000u ? logf(((float)a + 0.5f) * 0x1p-32f)
+                                          : log1pf(-(((float)(0xFFFFFFFFu - a) + 0.5f) * 0x1p-32f));
+        const float rad = sqrtf(-2.0f * lnu);
+        const float ang = 6.28318530717958648f * (((float)w[k + 1] + 0.5f) * 0x1p-32f);
+        float s, c;
+        sincosf(ang, &s, &c);
+        xi[k] = rad * c;
+        xi[k + 1] = rad * s;
+    }
+}
+
 // ------------------------------------------------------------------ errors
 
 __device__ __forceinline__ void raise_error(Ctl *ctl, int code, int64_t step, int64_t id)
@@ -145,11 +192,12 @@ __device__ __forceinline__ void raise_error(Ctl *ctl, int code, int64_t step, in
 
 // --------------------------------------------------------------- cell list
 
-// Cell of a bead and its single-precision neighbour record.  Periodic dims:
-// wrapped into [0, L), cell = floor(frac * ncell); open dims: relative to the
-// replica origin, cell = floor(x / h).  Returns false if the position cannot
-// be represented (non-finite or too far from the origin).
-__device__ __forceinline__ bool cell_of(const RepInfo &ri, D3 p, int c[3], float r[3])
+// Cell of a bead and its 16-bit neighbour coordinates.  Periodic dims:
+// wrapped into [0, L), cell = floor(frac * ncell), coordinate = frac * 2^16;
+// open dims: relative to the replica origin, cell = floor(x / h), coordinate
+// = x * 256 modulo 2^16.  Returns false if the position is not finite or too
+// far from the origin to be binned.
+__device__ __forceinline__ bool cell_of(const RepInfo &ri, D3 p, int c[3], uint32_t qc[3])
 {
     const double x[3] = {p.x - ri.lo[0], p.y - ri.lo[1], p.z - ri.lo[2]};
     bool ok = true;
@@ -157,17 +205,17 @@ __device__ __forceinline__ bool cell_of(const RepInfo &ri, D3 p, int c[3], float
     for (int k = 0; k < 3; ++k) {
         if (ri.flags & (REP_PER_X << k)) {
             double t = x[k] * ri.inv_len[k];
-            t = t - floor(t);
+            ok = ok && isfinite(t);
+            t = ok ? t - floor(t) : 0.0;
             int ci = (int)(t * (double)ri.ncell[k]);
             ci = ci >= ri.ncell[k] ? ri.ncell[k] - 1 : (ci < 0 ? 0 : ci);
             c[k] = ci;
-            r[k] = (float)(t * ri.len[k]);
-            ok = ok && isfinite(x[k]);
+            qc[k] = (uint32_t)(t * 65536.0) & 0xFFFFu;
         } else {
-            const double t = x[k] * ri.inv_h[k];
-            ok = ok && (fabs(x[k]) < 8192.0);  // also rejects NaN
-            c[k] = ok ? (int)floor(t) : 0;
-            r[k] = (float)x[k];
+            ok = ok && (fabs(x[k]) < 1.0e6);  // also rejects NaN
+            const double xs = ok ? x[k] : 0.0;
+            c[k] = (int)floor(xs * ri.inv_h[k]);
+            qc[k] = (uint32_t)(long long)rint(xs * OPEN_Q_INV) & 0xFFFFu;
         }
     }
     return ok;
@@ -178,23 +226,25 @@ __device__ __forceinline__ uint32_t bucket_of(const Grid &g, int cx, int cy, int
     return ((uint32_t)cx + g.A * (uint32_t)cy + g.B * (uint32_t)cz + g.C * (uint32_t)rep) & g.mask;
 }
 
+// 16-bit tag: strand (bit 0), steric (bit 1), replica modulo 2^14 (bits 2..15).
 __device__ __forceinline__ uint32_t make_tag(int rep, int n, int s)
 {
-    return ((uint32_t)rep << 2) | ((n % 3 == 0) ? 2u : 0u) | (uint32_t)s;
+    return (((uint32_t)rep & 0x3FFFu) << 2) | ((n % 3 == 0) ? 2u : 0u) | (uint32_t)s;
 }
 
-// Bin one bead: record, bucket, and slot within the bucket (histogram).
+// Bin one bead: record, counting-sort key (bucket in its strand's plane) and
+// slot within the key (histogram).
 __device__ __forceinline__ void insert_bead(const StepArgs &a, const RepInfo &ri, int rep, int n, int s,
                                             int64_t i, D3 bead, int64_t step)
 {
     int c[3];
-    float r[3];
-    if (!cell_of(ri, bead, c, r)) {
+    uint32_t qc[3];
+    if (!cell_of(ri, bead, c, qc)) {
         raise_error(a.b.ctl, isfinite(bead.x + bead.y + bead.z) ? DSDNA_EDOMAIN : DSDNA_ENAN, step, i);
         c[0] = c[1] = c[2] = 0;
     }
-    const uint32_t key = bucket_of(a.g, c[0], c[1], c[2], rep);
-    a.b.rec[i] = make_float4(r[0], r[1], r[2], __uint_as_float(make_tag(rep, n, s)));
+    const uint32_t key = bucket_of(a.g, c[0], c[1], c[2], rep) + (uint32_t)s * (uint32_t)a.g.nbucket;
+    a.b.rec[i] = make_uint2(qc[0] | (qc[1] << 16), qc[2] | (make_tag(rep, n, s) << 16));
     a.b.key[i] = (int32_t)key;
     a.b.slot[i] = atomicAdd(&a.b.count[key], 1);
 }
@@ -209,6 +259,9 @@ struct TileLds {
     real oBend[2][TILE_BP + 2][3][3];      // per strand, per bending centre
     real oHb[TILE_BP][3];                  // force on strand-0 patch
     uint8_t sOpen[TILE_BP + 2 * HALO_BP];  // open flags of bp n0-2 .. n0+129
+    real sW[TILE_NT][3];                   // excluded-volume force per nucleotide
+    uint8_t perm[TILE_NT];                 // search order: steric beads first
+    int wcnt[2][TILE_NT / 64];             // per-wave steric / ghost counts
 };
 
 template <typename real>
@@ -229,13 +282,14 @@ __device__ __forceinline__ V3<real> get3(const real *src) { return v3(src[0], sr
 
 constexpr uint32_t ALL_TERMS = (1u << DSDNA_NTERMS) - 1u;
 
+typedef short short2v __attribute__((ext_vector_type(2)));
+
 // All conservative and external site forces of the calling thread's
 // nucleotide, restricted to the terms in `mask`.  Must be called by all
-// threads of the workgroup (it synchronises).  own_valid: the nucleotide
-// exists.  With energies != nullptr the per-term energies owned by this
-// thread are added there (diagnostics only).
+// threads of the workgroup (it synchronises).  With energies != nullptr the
+// per-term energies owned by this thread are added there (diagnostics only).
 template <typename real>
-__device__ SiteForces<real> tile_forces(const StepArgs &a, TileLds<real> &S, const RepInfo &ri, int rep, int n0,
+__device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileLds<real> &S, const RepInfo &ri, int rep, int n0,
                                         int cur, uint32_t mask, int64_t step, double *energies)
 {
     const int t = threadIdx.x;
@@ -274,7 +328,7 @@ __device__ SiteForces<real> tile_forces(const StepArgs &a, TileLds<real> &S, con
                 const real pref = (real)(ph.hb_pref * k2s);
                 const real c = (ph.r0_hb == 0.0) ? (real)2 * pref : (real)2 * pref * ((real)1 - (real)(ph.r0_hb / r));
                 f = cvt<real>(d64) * c;
-                if (energies && q >= HALO_BP && q < TILE_BP + HALO_BP && bp < nbp)
+                if (energies && q >= HALO_BP && q < TILE_BP + HALO_BP)
                     energies[DSDNA_TERM_HBOND] += ph.hb_pref * k2s *
                         ((r - ph.r0_hb) * (r - ph.r0_hb) - (ph.rc_hb - ph.r0_hb) * (ph.rc_hb - ph.r0_hb));
             }
@@ -297,26 +351,24 @@ __device__ SiteForces<real> tile_forces(const StepArgs &a, TileLds<real> &S, con
             // backbone: FENE + WCA(eps_bb, sig_bb) between consecutive beads
             if (mask & (1u << DSDNA_TERM_BOND)) {
                 const D3 d64 = Bb - Ba;
-                const double r2_64 = dot(d64, d64);
-                if (r2_64 >= ph.R0 * ph.R0) {
+                const double r2 = dot(d64, d64);
+                if (r2 >= ph.R0 * ph.R0) {
                     raise_error(a.b.ctl, DSDNA_EBOND, step, ri.off + 2 * (int64_t)m + s);
                 } else {
-                    const V3<real> d = cvt<real>(d64);
-                    const real r2 = dot(d, d);
-                    const real x = (real)1 - r2 / (real)(ph.R0 * ph.R0);
-                    real g = (real)ph.K1 / x;  // (dU/dr)/r of FENE
+                    // FENE attraction and the WCA core cancel to a few percent
+                    // near the bond minimum, so (dU/dr)/r is formed in FP64
+                    const double x = 1.0 - r2 / (ph.R0 * ph.R0);
+                    double g = ph.K1 / x;
                     double e = 0.0;
-                    if (energies && own) e = -0.5 * ph.K1 * ph.R0 * ph.R0 * log(1.0 - r2_64 / (ph.R0 * ph.R0));
-                    if (r2 < (real)(ph.rc_bb * ph.rc_bb)) {
-                        const real sr2 = (real)(ph.sig_bb * ph.sig_bb) / r2;
-                        const real sr6 = sr2 * sr2 * sr2;
-                        g -= (real)(24.0 * ph.eps_bb) * ((real)2 * sr6 * sr6 - sr6) / r2;
-                        if (energies && own) {
-                            const double s2 = ph.sig_bb * ph.sig_bb / r2_64, s6 = s2 * s2 * s2;
-                            e += 4.0 * ph.eps_bb * (s6 * s6 - s6 + 0.25);
-                        }
+                    if (energies && own) e = -0.5 * ph.K1 * ph.R0 * ph.R0 * log(x);
+                    if (r2 < ph.rc_bb * ph.rc_bb) {
+                        const double ir2 = 1.0 / r2;
+                        const double sr2 = ph.sig_bb * ph.sig_bb * ir2;
+                        const double sr6 = sr2 * sr2 * sr2;
+                        g -= 24.0 * ph.eps_bb * (2.0 * sr6 * sr6 - sr6) * ir2;
+                        if (energies && own) e += 4.0 * ph.eps_bb * (sr6 * sr6 - sr6 + 0.25);
                     }
-                    const V3<real> f = d * g;
+                    const V3<real> f = cvt<real>(d64 * g);
                     fBa = fBa + f;
                     fBb = fBb - f;
                     if (energies && own) energies[DSDNA_TERM_BOND] += e;
@@ -326,9 +378,10 @@ __device__ SiteForces<real> tile_forces(const StepArgs &a, TileLds<real> &S, con
             if (mask & (1u << DSDNA_TERM_STACK)) {
                 const D3 d64 = Pb - Pa;
                 const V3<real> d = cvt<real>(d64);
-                const real r = sqrt(dot(d, d));
+                const real ir = rsq(dot(d, d));
+                const real r = dot(d, d) * ir;
                 const real ex = exp(-(real)ph.lam * (r - (real)ph.r0_m));
-                const V3<real> f = d * ((real)(2.0 * ph.K4 * ph.lam) * ex * ((real)1 - ex) / r);
+                const V3<real> f = d * ((real)(2.0 * ph.K4 * ph.lam) * ex * ((real)1 - ex) * ir);
                 fPa = fPa + f;
                 fPb = fPb - f;
                 if (energies && own) {
@@ -343,15 +396,16 @@ __device__ SiteForces<real> tile_forces(const StepArgs &a, TileLds<real> &S, con
             if ((mask & (1u << DSDNA_TERM_TWIST)) && !masked) {
                 const V3<real> A = cross(b1, b2), B = cross(b2, b3);
                 const real AA = dot(A, A), BB = dot(B, B), GG = dot(b2, b2);
-                const real lG = sqrt(GG);
-                const real inv = rsqrt_t<real>(AA * BB);
+                const real iG = rsq(GG), lG = GG * iG;
+                const real inv = rsq(AA * BB);
                 const real cphi = dot(A, B) * inv, sphi = lG * dot(b1, B) * inv;
                 const real cd = (real)ph.cos_d, sd = (real)ph.sin_d;
                 // -dU/dphi = K3 sin(phi - d)
                 const real mdU = (real)ph.K3 * (sphi * cd - cphi * sd);
                 const real FG = dot(b1, b2), HG = -dot(b3, b2);
-                const V3<real> tA = A * (lG / AA), tB = B * (lG / BB);
-                const V3<real> sA = A * (FG / (AA * lG)), sB = B * (HG / (BB * lG));
+                const real iAA = rcp(AA), iBB = rcp(BB);
+                const V3<real> tA = A * (lG * iAA), tB = B * (lG * iBB);
+                const V3<real> sA = A * (FG * iAA * iG), sB = B * (HG * iBB * iG);
                 fBa = fBa + (-tA) * mdU;
                 fPa = fPa + (tA + sA - sB) * mdU;
                 fPb = fPb + (-tB - sA + sB) * mdU;
@@ -362,13 +416,13 @@ __device__ SiteForces<real> tile_forces(const StepArgs &a, TileLds<real> &S, con
             if (mask & (1u << DSDNA_TERM_PLANAR)) {
                 const V3<real> r1 = -b2, r2 = b3;
                 const real l11 = dot(r1, r1), l22 = dot(r2, r2);
-                const real il = rsqrt_t<real>(l11 * l22);
+                const real il = rsq(l11 * l22);
                 real c = dot(r1, r2) * il;
                 c = c > (real)1 ? (real)1 : (c < (real)-1 ? (real)-1 : c);
                 const real al = acos(c);
                 const real sn = sqrt((real)1 - c * c);
-                const real dUdc = -(real)ph.K5 * (al - (real)ph.a0) / sn;
-                const V3<real> dca = r2 * il - r1 * (c / l11), dcc = r1 * il - r2 * (c / l22);
+                const real dUdc = -(real)ph.K5 * (al - (real)ph.a0) * rcp(sn);
+                const V3<real> dca = r2 * il - r1 * (c * rcp(l11)), dcc = r1 * il - r2 * (c * rcp(l22));
                 const V3<real> fa = dca * (-dUdc), fc = dcc * (-dUdc);
                 fPa = fPa + fa;
                 fBb = fBb + fc;
@@ -391,11 +445,11 @@ __device__ SiteForces<real> tile_forces(const StepArgs &a, TileLds<real> &S, con
             const D3 Pa = lds3(S.sP, la), Pc = lds3(S.sP, la + 2), Pe = lds3(S.sP, la + 4);
             const V3<real> r1 = cvt<real>(Pa - Pc), r2 = cvt<real>(Pe - Pc);
             const real l11 = dot(r1, r1), l22 = dot(r2, r2);
-            const real il = rsqrt_t<real>(l11 * l22);
+            const real il = rsq(l11 * l22);
             const real c = dot(r1, r2) * il;
             const real K6 = (real)ph.K6;
-            f0 = (r2 * il - r1 * (c / l11)) * (-K6);
-            f2 = (r1 * il - r2 * (c / l22)) * (-K6);
+            f0 = (r2 * il - r1 * (c * rcp(l11))) * (-K6);
+            f2 = (r1 * il - r2 * (c * rcp(l22))) * (-K6);
             f1 = -(f0 + f2);
             if (energies && mi >= 1 && mi <= TILE_BP) energies[DSDNA_TERM_BEND] += ph.K6 * (1.0 + (double)c);
         }
@@ -407,72 +461,91 @@ __device__ SiteForces<real> tile_forces(const StepArgs &a, TileLds<real> &S, con
 
     // --- gather per site (fixed order, no atomics)
     const int s = t & 1, bl = t >> 1, n = n0 + bl;
+    const int nbp_tile = min(TILE_BP, nbp - n0);
     SiteForces<real> out;
     out.b = v3<real>(0, 0, 0);
     out.p = out.b;
-    if (n >= nbp) return out;
-    out.b = get3(S.oStep[s][bl][2]) + get3(S.oStep[s][bl + 1][0]);
-    out.p = get3(S.oStep[s][bl][3]) + get3(S.oStep[s][bl + 1][1]) + get3(S.oBend[s][bl][2]) +
-            get3(S.oBend[s][bl + 1][1]) + get3(S.oBend[s][bl + 2][0]);
-    const V3<real> hb = get3(S.oHb[bl]);
-    out.p = s == 0 ? out.p + hb : out.p - hb;
+    if (n < nbp) {
+        out.b = get3(S.oStep[s][bl][2]) + get3(S.oStep[s][bl + 1][0]);
+        out.p = get3(S.oStep[s][bl][3]) + get3(S.oStep[s][bl + 1][1]) + get3(S.oBend[s][bl][2]) +
+                get3(S.oBend[s][bl + 1][1]) + get3(S.oBend[s][bl + 2][0]);
+        const V3<real> hb = get3(S.oHb[bl]);
+        out.p = s == 0 ? out.p + hb : out.p - hb;
+    }
 
-    const int l = t + 2 * HALO_BP;
-    const D3 bi = lds3(S.sB, l);
-    const int64_t i = ri.off + 2 * (int64_t)n + s;
-
-    // --- excluded volume of this bead (WCA, steric/ghost rule of Sec. 2)
+    // --- excluded volume (WCA, steric/ghost rule of Sec. 2).  Every bead
+    //     scans the other strand's bucket plane (cross-strand pairs, any bead
+    //     type); steric beads also scan their own strand's plane (steric
+    //     pairs).  Searched in an order that puts the steric beads in the
+    //     first waves; forces go back to the natural order through LDS.
     if (mask & (1u << DSDNA_TERM_EXCL)) {
-        int c[3];
-        float me[3];
-        cell_of(ri, bi, c, me);
-        const uint32_t mytag = make_tag(rep, n, s);
-        const bool mysteric = (mytag & 2u) != 0;
-        const float rs = (float)ph.rc_s + a.g.margin, rx = (float)ph.rc_x + a.g.margin;
-        const float rs2 = rs * rs, rx2 = rx * rx;
-        const real rcs2 = (real)(ph.rc_s * ph.rc_s), rcx2 = (real)(ph.rc_x * ph.rc_x);
-        const real sig_s2 = (real)(ph.sig_s * ph.sig_s), sig_x2 = (real)(ph.sig_x * ph.sig_x);
-        const bool px = ri.flags & REP_PER_X, py = ri.flags & REP_PER_Y, pz = ri.flags & REP_PER_Z;
-        const float Lx = (float)ri.len[0], Ly = (float)ri.len[1], Lz = (float)ri.len[2];
-        const float iLx = (float)ri.inv_len[0], iLy = (float)ri.inv_len[1], iLz = (float)ri.inv_len[2];
-        long long ax = 0, ay = 0, az = 0;  // fixed point, 2^-32 units: order independent
-        double e_excl = 0.0;
-        const double *Rcj = a.b.R[cur], *ucj = a.b.u[cur];
-        const float4 *__restrict__ srec = a.b.srec;
+        {
+            const bool valid = bl < nbp_tile;
+            const bool st = valid && ((n % 3) == 0);
+            const uint64_t bs = __ballot(st), bg = __ballot(valid && !st);
+            const int lane = t & 63, w = t >> 6;
+            const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+            if (lane == 0) {
+                S.wcnt[0][w] = __popcll(bs);
+                S.wcnt[1][w] = __popcll(bg);
+            }
+            __syncthreads();
+            int os = 0, og = 0, nst = 0;
+            for (int k = 0; k < TILE_NT / 64; ++k) {
+                if (k < w) { os += S.wcnt[0][k]; og += S.wcnt[1][k]; }
+                nst += S.wcnt[0][k];
+            }
+            if (st) S.perm[os + __popcll(bs & below)] = (uint8_t)t;
+            else if (valid) S.perm[nst + og + __popcll(bg & below)] = (uint8_t)t;
+        }
+        __syncthreads();
+        if (t < 2 * nbp_tile) {
+            const int lw = S.perm[t];
+            const int sw = lw & 1, nw = n0 + (lw >> 1);
+            const int64_t iw = ri.off + 2 * (int64_t)nw + sw;
+            const D3 bw = lds3(S.sB, lw + 2 * HALO_BP);
+            int c[3];
+            uint32_t mq[3];
+            cell_of(ri, bw, c, mq);
+            const bool mysteric = (nw % 3) == 0;
+            const uint32_t myrep = (uint32_t)rep & 0x3FFFu;
+            const float rs = (float)ph.rc_s + a.g.margin, rx = (float)ph.rc_x + a.g.margin;
+            const float rs2 = rs * rs, rx2 = rx * rx;
+            const real rcs2 = (real)(ph.rc_s * ph.rc_s), rcx2 = (real)(ph.rc_x * ph.rc_x);
+            const real sig_s2 = (real)(ph.sig_s * ph.sig_s), sig_x2 = (real)(ph.sig_x * ph.sig_x);
+            const bool px = ri.flags & REP_PER_X, py = ri.flags & REP_PER_Y, pz = ri.flags & REP_PER_Z;
+            const float qx = ri.q[0], qy = ri.q[1], qz = ri.q[2];
+            const bool qint = ri.qsame != 0;
+            const int64_t jlo = ri.off, jhi = ri.off + 2 * (int64_t)nbp;
+            const short2v mxy = __builtin_bit_cast(short2v, mq[0] | (mq[1] << 16));
+            long long ax = 0, ay = 0, az = 0;  // fixed point, 2^-32 units: order independent
+            double e_excl = 0.0;
+            const double *Rcj = a.b.R[cur], *ucj = a.b.u[cur];
+            const uint2 *__restrict__ srec = a.b.srec;
 
-        auto visit = [&](int p0, int p1) {
-            for (int p = p0; p < p1; ++p) {
-                const float4 o = srec[p];
-                const uint32_t tj = __float_as_uint(o.w);
-                if ((tj >> 2) != (mytag >> 2)) continue;         // other replica
-                const bool same = ((tj ^ mytag) & 1u) == 0u;
-                if (same && !(mysteric && (tj & 2u))) continue;    // same strand: steric pairs only
-                float dx = o.x - me[0], dy = o.y - me[1], dz = o.z - me[2];
-                if (px) dx -= Lx * rintf(dx * iLx);
-                if (py) dy -= Ly * rintf(dy * iLy);
-                if (pz) dz -= Lz * rintf(dz * iLz);
-                const float r2c = dx * dx + dy * dy + dz * dz;
-                if (r2c >= (same ? rs2 : rx2)) continue;
+            // exact test and force for a candidate that passed the 16-bit
+            // pre-check (rare: true contacts and the slack shell)
+            auto refine = [&](int p, bool same) {
                 const int j = a.b.sid[p];
-                if (j == (int)i) continue;
-                // refine from the FP64 bodies
+                if (j == (int)iw || j < jlo || j >= jhi) return;   // itself, other replica
                 const D3 bj = bead_of(ld3(Rcj, N, j), ld3(ucj, N, j), ph.db);
-                D3 d64 = bj - bi;
+                D3 d64 = bj - bw;
                 if (px) d64.x -= ri.len[0] * rint(d64.x * ri.inv_len[0]);
                 if (py) d64.y -= ri.len[1] * rint(d64.y * ri.inv_len[1]);
                 if (pz) d64.z -= ri.len[2] * rint(d64.z * ri.inv_len[2]);
                 const V3<real> d = cvt<real>(d64);
                 const real r2 = dot(d, d);
-                if (r2 >= (same ? rcs2 : rcx2)) continue;
-                const real sr2 = (same ? sig_s2 : sig_x2) / r2;
+                if (r2 >= (same ? rcs2 : rcx2)) return;
+                const real ir2 = rcp(r2);
+                const real sr2 = (same ? sig_s2 : sig_x2) * ir2;
                 const real sr6 = sr2 * sr2 * sr2;
-                const real g = (real)(24.0 * ph.eps) * ((real)2 * sr6 * sr6 - sr6) / r2;
+                const real g = (real)(24.0 * ph.eps) * ((real)2 * sr6 * sr6 - sr6) * ir2;
                 const double fx = (double)(g * d.x), fy = (double)(g * d.y), fz = (double)(g * d.z);
                 if (!(fabs(fx) + fabs(fy) + fabs(fz) < 1.0e9)) {  // overlapping beads: out of range
-                    raise_error(a.b.ctl, DSDNA_ENAN, step, i);
-                    continue;
+                    raise_error(a.b.ctl, DSDNA_ENAN, step, iw);
+                    return;
                 }
-                // force on i = -g d (repulsive)
+                // force on the bead = -g d (repulsive)
                 ax -= __double2ll_rn(fx * 4294967296.0);
                 ay -= __double2ll_rn(fy * 4294967296.0);
                 az -= __double2ll_rn(fz * 4294967296.0);
@@ -481,45 +554,102 @@ __device__ SiteForces<real> tile_forces(const StepArgs &a, TileLds<real> &S, con
                     const double s6 = s2 * s2 * s2;
                     e_excl += 0.5 * 4.0 * ph.eps * (s6 * s6 - s6 + 0.25);
                 }
-            }
-        };
+            };
+            // 16-bit pre-check of one record: replica and type, then the
+            // squared distance in coordinate units (integer when the unit is
+            // the same along x, y and z)
+            auto precheck = [&](const uint2 o, bool same, int t2) -> bool {
+                const uint32_t tj = o.y >> 16;
+                if ((tj >> 2) != myrep) return false;
+                if (same && !(tj & 2u)) return false;
+                if (qint) {
+                    const short2v dxy = __builtin_bit_cast(short2v, o.x) - mxy;
+                    const int dz = (int)(short)(uint16_t)(o.y - mq[2]);
+                    return __builtin_amdgcn_sdot2(dxy, dxy, dz * dz, false) < t2;
+                }
+                const float dx = (float)(int16_t)(uint16_t)((o.x & 0xFFFFu) - mq[0]) * qx;
+                const float dy = (float)(int16_t)(uint16_t)((o.x >> 16) - mq[1]) * qy;
+                const float dz = (float)(int16_t)(uint16_t)((o.y & 0xFFFFu) - mq[2]) * qz;
+                return dx * dx + dy * dy + dz * dz < (same ? rs2 : rx2);
+            };
 
-        // nine rows of three cells (dz, dy; cx-1..cx+1): three consecutive
-        // buckets each unless the row wraps (periodic x or bucket index)
-        const int ncx = ri.ncell[0], ncy = ri.ncell[1], ncz = ri.ncell[2];
-        const bool xwrap = px && (c[0] == 0 || c[0] == ncx - 1);
-        int lo[9], hi[9];
-        uint32_t kr[9];
+            // nine rows of three cells (dz, dy; cx-1..cx+1): three consecutive
+            // buckets each unless the row wraps (periodic x or bucket index)
+            const int ncx = ri.ncell[0], ncy = ri.ncell[1], ncz = ri.ncell[2];
+            const bool xwrap = px && (c[0] == 0 || c[0] == ncx - 1);
+            uint32_t kr[9];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            int cy = c[1] + (q % 3) - 1, cz = c[2] + (q / 3) - 1;
-            if (py) cy = cy < 0 ? cy + ncy : (cy >= ncy ? cy - ncy : cy);
-            if (pz) cz = cz < 0 ? cz + ncz : (cz >= ncz ? cz - ncz : cz);
-            kr[q] = bucket_of(a.g, c[0] - 1, cy, cz, rep);
-        }
-#pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            const bool reg = !xwrap && kr[q] + 2u <= a.g.mask;
-            lo[q] = reg ? a.b.start[kr[q]] : 0;
-            hi[q] = reg ? a.b.start[kr[q] + 3] : 0;
-        }
-        for (int q = 0; q < 9; ++q) visit(lo[q], hi[q]);
-        for (int q = 0; q < 9; ++q) {
-            if (!xwrap && kr[q] + 2u <= a.g.mask) continue;
-            int cy = c[1] + (q % 3) - 1, cz = c[2] + (q / 3) - 1;
-            if (py) cy = cy < 0 ? cy + ncy : (cy >= ncy ? cy - ncy : cy);
-            if (pz) cz = cz < 0 ? cz + ncz : (cz >= ncz ? cz - ncz : cz);
-            for (int dx = -1; dx <= 1; ++dx) {
-                int cx = c[0] + dx;
-                if (px) cx = cx < 0 ? cx + ncx : (cx >= ncx ? cx - ncx : cx);
-                const uint32_t k = bucket_of(a.g, cx, cy, cz, rep);
-                visit(a.b.start[k], a.b.start[k + 1]);
+            for (int q = 0; q < 9; ++q) {
+                int cy = c[1] + (q % 3) - 1, cz = c[2] + (q / 3) - 1;
+                if (py) cy = cy < 0 ? cy + ncy : (cy >= ncy ? cy - ncy : cy);
+                if (pz) cz = cz < 0 ? cz + ncz : (cz >= ncz ? cz - ncz : cz);
+                kr[q] = bucket_of(a.g, c[0] - 1, cy, cz, rep);
             }
+            // pass 0: the other strand's plane (every bead); pass 1: the own
+            // strand's plane (steric beads only)
+            for (int pass = 0; pass < (mysteric ? 2 : 1); ++pass) {
+                const bool same = pass == 1;
+                const int t2 = same ? ri.t2_same : ri.t2_cross;
+                const uint32_t plane = (uint32_t)(same ? sw : 1 - sw) * (uint32_t)a.g.nbucket;
+                // stream position k of range q sits at k + sh[q] in the sorted
+                // records; pre[q] = first stream position of range q
+                int sh[9], pre[9];
+                int total = 0;
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    const bool reg = !xwrap && kr[q] + 2u <= a.g.mask;
+                    const int l0 = reg ? a.b.start[plane + kr[q]] : 0;
+                    const int h0 = reg ? a.b.start[plane + kr[q] + 3] : 0;
+                    pre[q] = total;
+                    sh[q] = l0 - total;
+                    total += h0 - l0;
+                }
+                // the nine ranges as one candidate stream, four independent
+                // loads per trip (the wave runs max over lanes of the total)
+                constexpr int U = 4;
+                for (int k0 = 0; k0 < total; k0 += U) {
+                    uint2 o[U];
+                    int pp[U];
+#pragma unroll
+                    for (int v = 0; v < U; ++v) {
+                        const int k = k0 + v < total ? k0 + v : total - 1;
+                        int d = sh[0];
+#pragma unroll
+                        for (int r = 1; r < 9; ++r) d = (k >= pre[r]) ? sh[r] : d;
+                        pp[v] = k + d;
+                        o[v] = srec[pp[v]];
+                    }
+#pragma unroll
+                    for (int v = 0; v < U; ++v)
+                        if (k0 + v < total && precheck(o[v], same, t2)) refine(pp[v], same);
+                }
+                // rows that wrap: cell by cell (rare)
+                for (int q = 0; q < 9; ++q) {
+                    int cy = c[1] + (q % 3) - 1, cz = c[2] + (q / 3) - 1;
+                    if (py) cy = cy < 0 ? cy + ncy : (cy >= ncy ? cy - ncy : cy);
+                    if (pz) cz = cz < 0 ? cz + ncz : (cz >= ncz ? cz - ncz : cz);
+                    if (!xwrap && bucket_of(a.g, c[0] - 1, cy, cz, rep) + 2u <= a.g.mask) continue;
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        int cx = c[0] + dx;
+                        if (px) cx = cx < 0 ? cx + ncx : (cx >= ncx ? cx - ncx : cx);
+                        const uint32_t kb = plane + bucket_of(a.g, cx, cy, cz, rep);
+                        for (int p = a.b.start[kb]; p < a.b.start[kb + 1]; ++p)
+                            if (precheck(srec[p], same, t2)) refine(p, same);
+                    }
+                }
+            }
+            put3(S.sW[lw], v3<real>((real)((double)ax * 0x1p-32), (real)((double)ay * 0x1p-32),
+                                    (real)((double)az * 0x1p-32)));
+            if (energies) energies[DSDNA_TERM_EXCL] += e_excl;
         }
-        out.b = out.b + v3<real>((real)((double)ax * 0x1p-32), (real)((double)ay * 0x1p-32),
-                                 (real)((double)az * 0x1p-32));
-        if (energies) energies[DSDNA_TERM_EXCL] += e_excl;
+        __syncthreads();
+        if (n < nbp) out.b = out.b + get3(S.sW[t]);
     }
+    if (n >= nbp) return out;
+
+    const int l = t + 2 * HALO_BP;
+    const D3 bi = lds3(S.sB, l);
+    const int64_t i = ri.off + 2 * (int64_t)n + s;
 
     // --- external loads (Sec. 4)
     if (mask & (1u << DSDNA_TERM_EXT)) {
@@ -529,9 +659,10 @@ __device__ SiteForces<real> tile_forces(const StepArgs &a, TileLds<real> &S, con
                 raise_error(a.b.ctl, DSDNA_EWALL, step, i);
             } else if (dz < ph.rc_s) {
                 const real z = (real)dz;
-                const real sr2 = (real)(ph.sig_s * ph.sig_s) / (z * z);
+                const real iz2 = rcp(z * z);
+                const real sr2 = (real)(ph.sig_s * ph.sig_s) * iz2;
                 const real sr6 = sr2 * sr2 * sr2;
-                out.b.z += (real)(24.0 * ph.eps) * ((real)2 * sr6 * sr6 - sr6) / z;
+                out.b.z += (real)(24.0 * ph.eps) * ((real)2 * sr6 * sr6 - sr6) * rcp(z);
                 if (energies) {
                     const double s2 = ph.sig_s * ph.sig_s / (dz * dz), s6 = s2 * s2 * s2;
                     energies[DSDNA_TERM_EXT] += 4.0 * ph.eps * (s6 * s6 - s6 + 0.25);
@@ -569,18 +700,36 @@ __device__ __forceinline__ int tile_index(int n_tiles, int n_tiles_pad)
     return (b & 7) * per + (b >> 3);
 }
 
+// Rotation of the axis of a free linear rotor by th about unit k:
+// u cos th + (k x u) sin th + k (k.u)(1 - cos th).  cos and sin come from
+// their Taylor series through th^10 for th < 1/32 (error below 1e-19),
+// otherwise from sincos.
+__device__ __forceinline__ D3 rotate(D3 u, D3 k, double th)
+{
+    double sn, cs;
+    if (th < 0.03125) {
+        const double t2 = th * th;
+        cs = 1.0 - t2 * (1.0 / 2 - t2 * (1.0 / 24 - t2 * (1.0 / 720 - t2 * (1.0 / 40320 - t2 * (1.0 / 3628800)))));
+        sn = th * (1.0 - t2 * (1.0 / 6 - t2 * (1.0 / 120 - t2 * (1.0 / 5040 - t2 * (1.0 / 362880)))));
+    } else {
+        sincos(th, &sn, &cs);
+    }
+    return u * cs + cross(k, u) * sn + k * (dot(k, u) * (1.0 - cs));
+}
+
 // ---------------------------------------------------------------- k_step
 
 template <typename real>
-__global__ void __launch_bounds__(TILE_NT) k_step(StepArgs a)
+__global__ void __launch_bounds__(TILE_NT, 4) k_step(const StepArgs *__restrict__ A, int mode, int write_full)
 {
     __shared__ TileLds<real> S;
+    const StepArgs &a = *A;
     const Ctl ctl = *a.b.ctl;
     if (ctl.code != 0) return;
     const int tix = tile_index(a.n_tiles, a.n_tiles_pad);
     if (tix >= a.n_tiles) return;
     const Tile tile = a.b.tiles[tix];
-    const RepInfo ri = a.b.rep[tile.rep];
+    const RepInfo &ri = a.b.rep[tile.rep];
     const int cur = ctl.par, nxt = cur ^ 1;
     const int64_t step = ctl.step;
     const int64_t N = a.n_nt;
@@ -589,7 +738,7 @@ __global__ void __launch_bounds__(TILE_NT) k_step(StepArgs a)
     SiteForces<real> f;
     f.b = v3<real>(0, 0, 0);
     f.p = f.b;
-    if (a.mode != MODE_FROM_FORCES) f = tile_forces<real>(a, S, ri, tile.rep, tile.n0, cur, ALL_TERMS, step, nullptr);
+    if (mode != MODE_FROM_FORCES) f = tile_forces<real>(a, S, ri, tile.rep, tile.n0, cur, ALL_TERMS, step, nullptr);
 
     const int s = threadIdx.x & 1, n = tile.n0 + (threadIdx.x >> 1);
     if (n >= ri.n_bp) return;
@@ -599,7 +748,7 @@ __global__ void __launch_bounds__(TILE_NT) k_step(StepArgs a)
     const bool frozen = (ri.flags & REP_TETHER) && n == 0;
 
     D3 fb, fp;  // total site forces of this step
-    if (a.mode == MODE_FROM_FORCES) {
+    if (mode == MODE_FROM_FORCES) {
         fb = ld3(a.b.Fb, N, i);
         fp = ld3(a.b.Fp, N, i);
     } else {
@@ -609,10 +758,18 @@ __global__ void __launch_bounds__(TILE_NT) k_step(StepArgs a)
             // velocity on the rigid body plus counter-based noise
             const D3 w = L * (1.0 / ph.I);
             const D3 vb = V + cross(w, u * (-ph.db)), vp = V + cross(w, u * ph.dp);
-            double xi[6];
-            noise6(ph.seed, ph.noise_kind, (uint64_t)step, (uint32_t)i, 0u, xi);
-            lb = cvt<real>(vb * (-ph.gamma) + v3(xi[0], xi[1], xi[2]) * ph.noise_amp);
-            lp = cvt<real>(vp * (-ph.gamma) + v3(xi[3], xi[4], xi[5]) * ph.noise_amp);
+            if (sizeof(real) == sizeof(double)) {
+                double xi[6];
+                noise6(ph.seed, ph.noise_kind, (uint64_t)step, (uint32_t)i, 0u, xi);
+                lb = cvt<real>(vb * (-ph.gamma) + v3(xi[0], xi[1], xi[2]) * ph.noise_amp);
+                lp = cvt<real>(vp * (-ph.gamma) + v3(xi[3], xi[4], xi[5]) * ph.noise_amp);
+            } else {
+                float xi[6];
+                noise6f(ph.seed, ph.noise_kind, (uint64_t)step, (uint32_t)i, 0u, xi);
+                const real amp = (real)ph.noise_amp;
+                lb = cvt<real>(vb * (-ph.gamma)) + v3<real>(xi[0], xi[1], xi[2]) * amp;
+                lp = cvt<real>(vp * (-ph.gamma)) + v3<real>(xi[3], xi[4], xi[5]) * amp;
+            }
         }
         fb = cvt<double>(f.b + lb);
         fp = cvt<double>(f.p + lp);
@@ -621,7 +778,7 @@ __global__ void __launch_bounds__(TILE_NT) k_step(StepArgs a)
     if (frozen) {
         V = v3(0.0, 0.0, 0.0);
         L = V;
-        if (a.write_full) {
+        if (write_full) {
             st3(a.b.Vf, N, i, V);
             st3(a.b.Lf, N, i, L);
             st3(a.b.Fb, N, i, fb);
@@ -631,11 +788,11 @@ __global__ void __launch_bounds__(TILE_NT) k_step(StepArgs a)
         const D3 F = fb + fp;
         const D3 tau = cross(u, fp * ph.dp - fb * ph.db);
         const double km = ph.kick / ph.M;
-        if (a.mode == MODE_NORMAL) {  // second half kick of the previous step
+        if (mode == MODE_NORMAL) {  // second half kick of the previous step
             V = V + F * km;
             L = L + tau * ph.kick;
         }
-        if (a.write_full) {
+        if (write_full) {
             st3(a.b.Vf, N, i, V);
             st3(a.b.Lf, N, i, L);
             st3(a.b.Fb, N, i, fb);
@@ -647,13 +804,7 @@ __global__ void __launch_bounds__(TILE_NT) k_step(StepArgs a)
         R = R + V * ph.dt;
         const D3 w = L * (1.0 / ph.I);
         const double wl = sqrt(dot(w, w));
-        if (wl > 0.0) {
-            const double th = wl * ph.dt;
-            const D3 k = w * (1.0 / wl);
-            double sn, cs;
-            sincos(th, &sn, &cs);
-            u = u * cs + cross(k, u) * sn + k * (dot(k, u) * (1.0 - cs));
-        }
+        if (wl > 0.0) u = rotate(u, w * (1.0 / wl), wl * ph.dt);
         u = u * (1.0 / sqrt(dot(u, u)));
         L = L - u * dot(L, u);
     }
@@ -668,12 +819,13 @@ __global__ void __launch_bounds__(TILE_NT) k_step(StepArgs a)
 // ------------------------------------------------------------ binning only
 
 // Bins the beads of buffer `which` (after the state was set from the host).
-__global__ void __launch_bounds__(256) k_bin(StepArgs a, int which)
+__global__ void __launch_bounds__(256) k_bin(const StepArgs *__restrict__ A, int which)
 {
+    const StepArgs &a = *A;
     const int tix = tile_index(a.n_tiles, a.n_tiles_pad);
     if (tix >= a.n_tiles) return;
     const Tile tile = a.b.tiles[tix];
-    const RepInfo ri = a.b.rep[tile.rep];
+    const RepInfo &ri = a.b.rep[tile.rep];
     const int s = threadIdx.x & 1, n = tile.n0 + (threadIdx.x >> 1);
     if (n >= ri.n_bp) return;
     const int64_t i = ri.off + 2 * (int64_t)n + s;
@@ -726,7 +878,7 @@ __global__ void __launch_bounds__(256) k_scan_reduce(const int *__restrict__ cou
 }
 
 __global__ void __launch_bounds__(256) k_scan_down(const int *__restrict__ count, const int *__restrict__ bsum,
-                                                   int *__restrict__ start, int nbucket, const Ctl *ctl)
+                                                   int *__restrict__ start, int nkeys, const Ctl *ctl)
 {
     if (ctl->code != 0) return;
     // offset of this chunk: sum of the preceding chunks' totals
@@ -757,16 +909,15 @@ __global__ void __launch_bounds__(256) k_scan_down(const int *__restrict__ count
         o.w = run; run += v[4 * k + 3];
         s4[k] = o;
     }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == blockDim.x - 1) start[nbucket] = run;
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == blockDim.x - 1) start[nkeys] = run;
 }
 
-// Counting-sort scatter: bead records (and their nucleotide ids) into bucket
+// Counting-sort scatter: bead records (and their nucleotide ids) into key
 // order; clears the histogram entries it used.  inc: also advance the step
-// and flip the position buffers (the records of the new positions are in
-// `rec` whichever buffer holds them).
+// and flip the position buffers.
 __global__ void __launch_bounds__(256) k_scatter(const int *__restrict__ key, const int *__restrict__ slot,
-                                                 const int *__restrict__ start, const float4 *__restrict__ rec,
-                                                 float4 *__restrict__ srec, int *__restrict__ sid,
+                                                 const int *__restrict__ start, const uint2 *__restrict__ rec,
+                                                 uint2 *__restrict__ srec, int *__restrict__ sid,
                                                  int *__restrict__ count, Ctl *ctl, int64_t n, int inc)
 {
     if (ctl->code != 0) return;
@@ -786,12 +937,13 @@ __global__ void __launch_bounds__(256) k_scatter(const int *__restrict__ key, co
 
 // --------------------------------------------------------------- thermalize
 
-__global__ void __launch_bounds__(256) k_thermalize(StepArgs a, double kT, uint64_t seed)
+__global__ void __launch_bounds__(256) k_thermalize(const StepArgs *__restrict__ A, double kT, uint64_t seed)
 {
+    const StepArgs &a = *A;
     const int tix = tile_index(a.n_tiles, a.n_tiles_pad);
     if (tix >= a.n_tiles) return;
     const Tile tile = a.b.tiles[tix];
-    const RepInfo ri = a.b.rep[tile.rep];
+    const RepInfo &ri = a.b.rep[tile.rep];
     const int s = threadIdx.x & 1, n = tile.n0 + (threadIdx.x >> 1);
     if (n >= ri.n_bp) return;
     const int64_t i = ri.off + 2 * (int64_t)n + s;
@@ -816,17 +968,18 @@ __global__ void __launch_bounds__(256) k_thermalize(StepArgs a, double kT, uint6
 // --------------------------------------------------------------- diagnostics
 
 template <typename real>
-__global__ void __launch_bounds__(TILE_NT) k_diag(StepArgs a, int which, uint32_t mask)
+__global__ void __launch_bounds__(TILE_NT) k_diag(const StepArgs *__restrict__ A, int which, uint32_t mask)
 {
     __shared__ TileLds<real> S;
     __shared__ double red[DSDNA_NTERMS][TILE_NT / 64];
+    const StepArgs &a = *A;
     // the cell list is only valid when the binning before this launch
     // completed without error
     if (a.b.ctl->code != 0) return;
     const int tix = tile_index(a.n_tiles, a.n_tiles_pad);
     if (tix >= a.n_tiles) return;
     const Tile tile = a.b.tiles[tix];
-    const RepInfo ri = a.b.rep[tile.rep];
+    const RepInfo &ri = a.b.rep[tile.rep];
     double e[DSDNA_NTERMS];
     for (int k = 0; k < DSDNA_NTERMS; ++k) e[k] = 0.0;
     const int64_t step = a.b.ctl->step;
@@ -860,17 +1013,18 @@ __global__ void __launch_bounds__(TILE_NT) k_diag(StepArgs a, int which, uint32_
 
 static dim3 tiles_grid(const StepArgs &a) { return dim3((unsigned)a.n_tiles_pad); }
 
-hipError_t launch_bin(const StepArgs &a, int which, hipStream_t s)
+hipError_t launch_bin(const StepArgs &a, const StepArgs *dA, int which, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_bin, tiles_grid(a), dim3(TILE_NT), 0, s, a, which);
+    hipLaunchKernelGGL(k_bin, tiles_grid(a), dim3(TILE_NT), 0, s, dA, which);
     return hipGetLastError();
 }
 
 hipError_t launch_scan(const StepArgs &a, hipStream_t s)
 {
-    const int nchunk = a.g.nbucket / SCAN_CHUNK;
+    const int nkeys = 2 * a.g.nbucket;  // one plane of buckets per strand
+    const int nchunk = nkeys / SCAN_CHUNK;
     hipLaunchKernelGGL(k_scan_reduce, dim3(nchunk), dim3(256), 0, s, a.b.count, a.b.bsum, a.b.ctl);
-    hipLaunchKernelGGL(k_scan_down, dim3(nchunk), dim3(256), 0, s, a.b.count, a.b.bsum, a.b.start, a.g.nbucket,
+    hipLaunchKernelGGL(k_scan_down, dim3(nchunk), dim3(256), 0, s, a.b.count, a.b.bsum, a.b.start, nkeys,
                        a.b.ctl);
     return hipGetLastError();
 }
@@ -883,27 +1037,28 @@ hipError_t launch_scatter(const StepArgs &a, int inc_step, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_step(const StepArgs &a, int fp64, hipStream_t s)
+hipError_t launch_step(const StepArgs &a, const StepArgs *dA, int fp64, int mode, int write_full, hipStream_t s)
 {
     if (fp64)
-        hipLaunchKernelGGL(k_step<double>, tiles_grid(a), dim3(TILE_NT), 0, s, a);
+        hipLaunchKernelGGL(k_step<double>, tiles_grid(a), dim3(TILE_NT), 0, s, dA, mode, write_full);
     else
-        hipLaunchKernelGGL(k_step<float>, tiles_grid(a), dim3(TILE_NT), 0, s, a);
+        hipLaunchKernelGGL(k_step<float>, tiles_grid(a), dim3(TILE_NT), 0, s, dA, mode, write_full);
     return hipGetLastError();
 }
 
-hipError_t launch_thermalize(const StepArgs &a, double kT, uint64_t seed, hipStream_t s)
+hipError_t launch_thermalize(const StepArgs &a, const StepArgs *dA, double kT, uint64_t seed, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_thermalize, tiles_grid(a), dim3(TILE_NT), 0, s, a, kT, seed);
+    hipLaunchKernelGGL(k_thermalize, tiles_grid(a), dim3(TILE_NT), 0, s, dA, kT, seed);
     return hipGetLastError();
 }
 
-hipError_t launch_diag(const StepArgs &a, int which, int fp64, uint32_t term_mask, hipStream_t s)
+hipError_t launch_diag(const StepArgs &a, const StepArgs *dA, int which, int fp64, uint32_t term_mask,
+                       hipStream_t s)
 {
     if (fp64)
-        hipLaunchKernelGGL(k_diag<double>, tiles_grid(a), dim3(TILE_NT), 0, s, a, which, term_mask);
+        hipLaunchKernelGGL(k_diag<double>, tiles_grid(a), dim3(TILE_NT), 0, s, dA, which, term_mask);
     else
-        hipLaunchKernelGGL(k_diag<float>, tiles_grid(a), dim3(TILE_NT), 0, s, a, which, term_mask);
+        hipLaunchKernelGGL(k_diag<float>, tiles_grid(a), dim3(TILE_NT), 0, s, dA, which, term_mask);
     return hipGetLastError();
 }
 

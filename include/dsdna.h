@@ -73,10 +73,11 @@ enum {
 
 /* Kernels timed by dsdna_profile_kernels. */
 enum {
-    DSDNA_KERNEL_STEP = 0,    /* fused forces + Langevin + integrate + bin   */
+    DSDNA_KERNEL_STEP = 0,    /* bonded forces + Langevin + integrate + bin  */
     DSDNA_KERNEL_SCAN = 1,    /* exclusive scan of the cell histogram (2 kernels) */
     DSDNA_KERNEL_SCATTER = 2, /* counting-sort scatter into cell order       */
-    DSDNA_NKERNELS = 3
+    DSDNA_KERNEL_EXCL = 3,    /* excluded volume from the sorted cell list   */
+    DSDNA_NKERNELS = 4
 };
 
 typedef struct dsdna_ctx dsdna_ctx; /* opaque */

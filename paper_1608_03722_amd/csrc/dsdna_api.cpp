@@ -104,7 +104,8 @@ static void free_state(dsdna_ctx *c)
         dfree(b.R[k]); dfree(b.u[k]); dfree(b.V[k]); dfree(b.L[k]);
     }
     dfree(b.Vf); dfree(b.Lf); dfree(b.Fb); dfree(b.Fp);
-    dfree(b.rec); dfree(b.key); dfree(b.slot); dfree(b.srec); dfree(b.sid);
+    dfree(b.rec); dfree(b.rcell); dfree(b.key); dfree(b.slot); dfree(b.srec); dfree(b.sinfo);
+    dfree(b.fex); dfree(b.eex);
     dfree(b.rep); dfree(b.tiles); dfree(b.eacc); dfree(b.open);
     dfree(b.diag_fb); dfree(b.diag_fp);
     Ctl *ctl = b.ctl;
@@ -266,32 +267,20 @@ static dsdna_status configure_grid(dsdna_ctx *c)
     g.C = all_per_same ? B * (uint32_t)c->rep_h[0].ncell[2] : B * 1031u + 7u;
     g.mask = mask;
     g.h = h;
-    // 16-bit neighbour coordinates: unit q per dim; the pre-check slack covers
-    // the quantisation of both beads (a difference is off by < q per dim)
-    double qmax = 0.0;
+    g.any_open = 0;
+    for (int r = 0; r < c->n_rep; ++r)
+        for (int k = 0; k < 3; ++k) g.any_open |= (c->rep_h[r].flags & (REP_PER_X << k)) ? 0 : 1;
     for (int r = 0; r < c->n_rep; ++r) {
         RepInfo &ri = c->rep_h[r];
-        for (int k = 0; k < 3; ++k) {
-            ri.q[k] = (ri.flags & (REP_PER_X << k)) ? (float)(ri.len[k] / 65536.0) : (float)(1.0 / OPEN_Q_INV);
-            qmax = std::max(qmax, (double)ri.q[k]);
-        }
-    }
-    g.margin = (float)(2.0 * std::sqrt(3.0) * qmax + 1e-4);
-    // integer pre-check thresholds (squared cutoff plus slack, in q^2 units)
-    for (int r = 0; r < c->n_rep; ++r) {
-        RepInfo &ri = c->rep_h[r];
-        ri.qsame = ri.q[0] == ri.q[1] && ri.q[1] == ri.q[2];
-        const double q = ri.q[0];
-        const double ts = (c->a.ph.rc_s + g.margin) / q, tx = (c->a.ph.rc_x + g.margin) / q;
-        ri.t2_same = (int32_t)std::min(std::ceil(ts * ts), 2.0e9);
-        ri.t2_cross = (int32_t)std::min(std::ceil(tx * tx), 2.0e9);
+        for (int k = 0; k < 3; ++k)
+            ri.qlen[k] = (ri.flags & (REP_PER_X << k)) ? (float)(ri.len[k] / 4294967296.0) : (float)(1.0 / OPEN_QINV);
     }
     if (g.nbucket != (int32_t)nb || !c->a.b.count) {
         free_grid(c);
-        HIPCHK(c, dalloc(&c->a.b.count, 2 * (size_t)nb));
-        HIPCHK(c, dalloc(&c->a.b.start, 2 * (size_t)nb + 1));
-        HIPCHK(c, dalloc(&c->a.b.bsum, 2 * (size_t)nb / SCAN_CHUNK));
-        HIPCHK(c, hipMemsetAsync(c->a.b.count, 0, sizeof(int32_t) * 2 * nb, c->stream));
+        HIPCHK(c, dalloc(&c->a.b.count, (size_t)nb));
+        HIPCHK(c, dalloc(&c->a.b.start, (size_t)nb + 1));
+        HIPCHK(c, dalloc(&c->a.b.bsum, (size_t)nb / SCAN_CHUNK));
+        HIPCHK(c, hipMemsetAsync(c->a.b.count, 0, sizeof(int32_t) * nb, c->stream));
         g.nbucket = (int32_t)nb;
     }
     HIPCHK(c, hipMemcpyAsync(c->a.b.rep, c->rep_h.data(), sizeof(RepInfo) * c->n_rep, hipMemcpyHostToDevice,
@@ -394,7 +383,7 @@ static dsdna_status upload_full_state(dsdna_ctx *c, const double *R, const doubl
     HIPCHK(c, hipMemcpyAsync(b.Vf, b.V[0], sizeof(double) * 3 * c->N, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(b.Lf, b.L[0], sizeof(double) * 3 * c->N, hipMemcpyDeviceToDevice, c->stream));
     // a halted step may have left histogram entries behind
-    HIPCHK(c, hipMemsetAsync(b.count, 0, sizeof(int32_t) * 2 * (size_t)c->a.g.nbucket, c->stream));
+    HIPCHK(c, hipMemsetAsync(b.count, 0, sizeof(int32_t) * (size_t)c->a.g.nbucket, c->stream));
     if ((st = write_ctl(c, step, 0))) return st;
     c->full_par = 0;
     c->full_step = step;
@@ -414,7 +403,7 @@ static dsdna_status to_full(dsdna_ctx *c)
         HIPCHK(c, hipMemcpyAsync(b.V[p], b.Vf, sizeof(double) * 3 * c->N, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(b.L[p], b.Lf, sizeof(double) * 3 * c->N, hipMemcpyDeviceToDevice, c->stream));
     }
-    HIPCHK(c, hipMemsetAsync(b.count, 0, sizeof(int32_t) * 2 * (size_t)c->a.g.nbucket, c->stream));
+    HIPCHK(c, hipMemsetAsync(b.count, 0, sizeof(int32_t) * (size_t)c->a.g.nbucket, c->stream));
     dsdna_status st = write_ctl(c, c->full_step, p);
     if (st) return st;
     c->binned_buf = -1;
@@ -440,7 +429,9 @@ static dsdna_status status_from_ctl(dsdna_ctx *c, const Ctl &h)
 // One step: fused step kernel, scan, scatter (advances ctl.step/par).
 static hipError_t enqueue_step(dsdna_ctx *c, int mode, int write_full, hipStream_t s)
 {
-    hipError_t e = launch_step(c->a, c->dA, c->prm.force_fp64, mode, write_full, s);
+    hipError_t e = hipSuccess;
+    if (mode != MODE_FROM_FORCES) e = launch_excl(c->a, c->dA, c->prm.force_fp64, 0, -1, s);
+    if (e == hipSuccess) e = launch_step(c->a, c->dA, c->prm.force_fp64, mode, write_full, s);
     if (e == hipSuccess) e = launch_scan(c->a, s);
     if (e == hipSuccess) e = launch_scatter(c->a, 1, s);
     return e;
@@ -497,26 +488,27 @@ static dsdna_status run_steps(dsdna_ctx *c, int64_t n_steps, std::vector<double>
         std::vector<hipEvent_t> evs;
         for (; k < launches; ++k) {
             const int mode = k == 0 ? first_mode : MODE_NORMAL;
-            hipEvent_t e0, e1, e2, e3;
+            hipEvent_t e0, e1, e2, e3, e4;
             HIPCHK(c, mark(&e0));
-            HIPCHK(c, launch_step(c->a, c->dA, c->prm.force_fp64, mode, k == launches - 1, c->stream));
+            if (mode != MODE_FROM_FORCES) HIPCHK(c, launch_excl(c->a, c->dA, c->prm.force_fp64, 0, -1, c->stream));
             HIPCHK(c, mark(&e1));
-            HIPCHK(c, launch_scan(c->a, c->stream));
+            HIPCHK(c, launch_step(c->a, c->dA, c->prm.force_fp64, mode, k == launches - 1, c->stream));
             HIPCHK(c, mark(&e2));
-            HIPCHK(c, launch_scatter(c->a, 1, c->stream));
+            HIPCHK(c, launch_scan(c->a, c->stream));
             HIPCHK(c, mark(&e3));
-            evs.insert(evs.end(), {e0, e1, e2, e3});
+            HIPCHK(c, launch_scatter(c->a, 1, c->stream));
+            HIPCHK(c, mark(&e4));
+            evs.insert(evs.end(), {e0, e1, e2, e3, e4});
         }
         HIPCHK(c, hipStreamSynchronize(c->stream));
         prof->assign(DSDNA_NKERNELS, 0.0);
-        for (size_t q = 0; q + 3 < evs.size(); q += 4) {
-            float t0, t1, t2;
-            HIPCHK(c, hipEventElapsedTime(&t0, evs[q], evs[q + 1]));
-            HIPCHK(c, hipEventElapsedTime(&t1, evs[q + 1], evs[q + 2]));
-            HIPCHK(c, hipEventElapsedTime(&t2, evs[q + 2], evs[q + 3]));
-            (*prof)[DSDNA_KERNEL_STEP] += t0;
-            (*prof)[DSDNA_KERNEL_SCAN] += t1;
-            (*prof)[DSDNA_KERNEL_SCATTER] += t2;
+        for (size_t q = 0; q + 4 < evs.size(); q += 5) {
+            float t[4];
+            for (int m = 0; m < 4; ++m) HIPCHK(c, hipEventElapsedTime(&t[m], evs[q + m], evs[q + m + 1]));
+            (*prof)[DSDNA_KERNEL_EXCL] += t[0];
+            (*prof)[DSDNA_KERNEL_STEP] += t[1];
+            (*prof)[DSDNA_KERNEL_SCAN] += t[2];
+            (*prof)[DSDNA_KERNEL_SCATTER] += t[3];
         }
         for (auto &x : *prof) x /= (double)launches;
         for (hipEvent_t e : evs) (void)hipEventDestroy(e);
@@ -561,6 +553,7 @@ static dsdna_status run_diag(dsdna_ctx *c, uint32_t mask)
     if (c->binned_buf != which) {
         if ((st = rebin(c, which))) return st;
     }
+    HIPCHK(c, launch_excl(c->a, c->dA, c->prm.force_fp64, 1, which, c->stream));
     HIPCHK(c, launch_diag(c->a, c->dA, which, c->prm.force_fp64, mask, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     Ctl h;
@@ -573,7 +566,7 @@ static dsdna_status run_diag(dsdna_ctx *c, uint32_t mask)
         clr.code = 0;
         if ((st = copy(c, c->a.b.ctl, &clr, sizeof clr, hipMemcpyHostToDevice))) return st;
         // the failed evaluation may have left histogram entries behind
-        HIPCHK(c, hipMemsetAsync(c->a.b.count, 0, sizeof(int32_t) * 2 * (size_t)c->a.g.nbucket, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->a.b.count, 0, sizeof(int32_t) * (size_t)c->a.g.nbucket, c->stream));
         c->binned_buf = -1;
         return fail(c, code, "invalid state: error %d at nucleotide %lld", (int)code, (long long)h.err_id);
     }
@@ -702,8 +695,14 @@ dsdna_status dsdna_set_topology(dsdna_ctx *c, int32_t n_rep, const int32_t *n_bp
     HIPCHK(c, dalloc(&b.Vf, n3)); HIPCHK(c, dalloc(&b.Lf, n3));
     HIPCHK(c, dalloc(&b.Fb, n3)); HIPCHK(c, dalloc(&b.Fp, n3));
     HIPCHK(c, dalloc(&b.key, (size_t)N)); HIPCHK(c, dalloc(&b.slot, (size_t)N));
-    HIPCHK(c, dalloc(&b.rec, (size_t)N));
-    HIPCHK(c, dalloc(&b.srec, (size_t)N)); HIPCHK(c, dalloc(&b.sid, (size_t)N));
+    HIPCHK(c, dalloc(&b.rec, (size_t)N)); HIPCHK(c, dalloc(&b.rcell, (size_t)N));
+    HIPCHK(c, dalloc(&b.srec, (size_t)N)); HIPCHK(c, dalloc(&b.sinfo, (size_t)N));
+    {
+        double *fex = nullptr;
+        HIPCHK(c, dalloc(&fex, 4 * (size_t)N));  // double4 per nt (float4 in FP32 mode)
+        b.fex = fex;
+    }
+    HIPCHK(c, dalloc(&b.eex, (size_t)N));
     HIPCHK(c, dalloc(&b.rep, (size_t)n_rep));
     HIPCHK(c, dalloc(&b.tiles, c->tiles_h.size()));
     HIPCHK(c, dalloc(&b.eacc, (size_t)a.n_tiles * DSDNA_NTERMS));

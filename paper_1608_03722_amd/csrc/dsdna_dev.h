@@ -7,9 +7,12 @@
 
 namespace dsdna {
 
-// Base pairs per tile: one workgroup of 2*TILE_BP threads owns the
-// nucleotides of TILE_BP consecutive base pairs of one replica.
-constexpr int TILE_BP = 128;
+// Base pairs per tile: one workgroup of WG_THREADS threads owns the
+// nucleotides of TILE_BP consecutive base pairs of one replica.  124 base
+// pairs keep every per-tile phase (sites with halo, backbone steps, bending
+// centres) within one item per thread.
+constexpr int WG_THREADS = 256;
+constexpr int TILE_BP = 124;
 constexpr int TILE_NT = 2 * TILE_BP;
 constexpr int HALO_BP = 2;  // bending reaches two base pairs away
 constexpr int SCAN_CHUNK = 4096;  // histogram entries per scan workgroup
@@ -46,7 +49,7 @@ struct RepInfo {
     int64_t off;        // first nucleotide
     int32_t n_bp;
     uint32_t flags;     // REP_*
-    double lo[3];       // box low corner: origin of the single-precision records
+    double lo[3];       // box low corner: origin of the cell grid
     double len[3];      // box edge (periodic dims)
     double inv_len[3];
     double pull[3], torque[3];
@@ -54,17 +57,19 @@ struct RepInfo {
     int32_t ncell[3];   // cells per periodic dim (0 for open dims)
     int32_t pad;
     double inv_h[3];    // cells per unit length per dim
-    float q[3];         // length of one unit of the 16-bit neighbour coordinates
-    int32_t qsame;      // 1 when q is the same along x, y and z
-    int32_t t2_same;    // (same-strand cutoff + slack)^2 in units of q^2
-    int32_t t2_cross;   // (cross-strand cutoff + slack)^2 in units of q^2
+    float qlen[3];      // length of one fixed-point coordinate unit
+    int32_t pad2;
 };
 
-// 16-bit neighbour coordinates: periodic dims map [lo, lo + L) onto the full
-// 16-bit range (q = L / 65536) so that wrapped 16-bit differences are minimum
-// images; open dims use q = 1/256 (differences of nearby beads are exact
-// modulo 256 nm, which is all the cell search needs).
-constexpr double OPEN_Q_INV = 256.0;
+// A bead in the cell list: 32-bit fixed-point coordinates and a tag word
+// (bit 0 strand, bit 1 steric, bits 2..31 replica).  Periodic dims map the
+// box edge onto the full 32-bit range, so the wrapped difference of two
+// coordinates is the minimum image; open dims use 2^-24 length units, so
+// differences of beads less than 128 apart are exact.
+struct alignas(16) BeadRec {
+    uint32_t x, y, z, tag;
+};
+constexpr double OPEN_QINV = 16777216.0;  // 2^24
 
 struct Tile {
     int32_t rep;
@@ -85,13 +90,13 @@ struct Ctl {
 // Hash of cell (cx, cy, cz) of replica r into [0, nbucket): linear in the
 // cell coordinates so that the three cells cx-1, cx, cx+1 of a row are three
 // consecutive buckets.  The host chooses A, B, C such that the 27 cells
-// around any cell fall in 27 distinct buckets.  The counting sort keys are
-// bucket + strand * nbucket: one plane of buckets per strand.
+// around any cell fall in 27 distinct buckets.  The bucket is the counting
+// sort key.
 struct Grid {
     uint32_t A, B, C, mask;  // mask = nbucket - 1
     double h;                // cell edge for open dims
-    float margin;            // slack of the 16-bit pre-check (length units)
-    int32_t nbucket;         // buckets per strand plane
+    int32_t nbucket;
+    int32_t any_open;        // some replica has an open edge
 };
 
 // Device buffers of one context.
@@ -99,11 +104,14 @@ struct Bufs {
     double *R[2], *u[2], *V[2], *L[2];  // SoA [3][N] (x block, y block, z block)
     double *Vf, *Lf;                    // full-step velocities of the last step
     double *Fb, *Fp;                    // full-step site forces (SoA [3][N])
-    uint2 *rec;                         // bead record (16-bit x, y, z, tag), per nt
+    BeadRec *rec;                       // bead record per nucleotide
+    int4 *rcell;                        // cell (x, y, z) of each bead
     int32_t *key, *slot;                // counting-sort key and slot of each bead
-    uint2 *srec;                        // records in key order (counting sort)
-    int32_t *sid;                       // nucleotide of each sorted record
-    int32_t *count, *start, *bsum;      // per key: 2 * nbucket (start: +1)
+    BeadRec *srec;                      // records in key order (counting sort)
+    int4 *sinfo;                        // per sorted record: nucleotide, cell x, y, z
+    int32_t *count, *start, *bsum;      // per key (start: nbucket + 1)
+    void *fex;                          // excluded-volume force per nt: float4 or double4
+    double *eex;                        // excluded-volume energy per nt (diagnostics)
     RepInfo *rep;
     Tile *tiles;
     Ctl *ctl;
@@ -133,6 +141,10 @@ hipError_t launch_bin(const StepArgs &a, const StepArgs *dA, int which, hipStrea
 hipError_t launch_scan(const StepArgs &a, hipStream_t s);
 hipError_t launch_scatter(const StepArgs &a, int inc_step, hipStream_t s);
 hipError_t launch_step(const StepArgs &a, const StepArgs *dA, int fp64, int mode, int write_full, hipStream_t s);
+// Excluded-volume force (and with `energy`, energy) of every bead from the
+// sorted records, written to b.fex (b.eex) by nucleotide.  `which`: position
+// buffer the records describe (-1: the control block's current buffer).
+hipError_t launch_excl(const StepArgs &a, const StepArgs *dA, int fp64, int energy, int which, hipStream_t s);
 hipError_t launch_thermalize(const StepArgs &a, const StepArgs *dA, double kT, uint64_t seed, hipStream_t s);
 // term_mask: bit t selects term t; writes per-term forces (AoS doubles) to
 // b.diag_fb / b.diag_fp, energies per tile to b.eacc[tile][DSDNA_NTERMS] and

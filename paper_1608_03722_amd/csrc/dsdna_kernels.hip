@@ -3,14 +3,15 @@
 //
 // Per step (all kernels read the step index and the buffer parity from the
 // device control block, so a captured graph replays unchanged):
+//   k_excl     excluded volume of every bead from the key-sorted cell list
+//              (one thread per sorted record, neighbours from 27 cells)
 //   k_step     one workgroup per tile of TILE_BP base pairs of one replica:
 //              stage the tile's FP64 sites in LDS, evaluate every
 //              fixed-topology term once into LDS outboxes, gather them per
-//              site (no atomics), add each bead's excluded volume from the
-//              cell list (fixed-point accumulation, order independent), the
-//              external loads and the Langevin forces, then integrate the
-//              rigid body (FP64) and bin its new bead position (histogram
-//              atomics: the counting-sort count phase).
+//              site (no atomics), add the excluded volume, the external
+//              loads and the Langevin forces, then integrate the rigid body
+//              (FP64) and bin its new bead position (histogram atomics: the
+//              counting-sort count phase).
 //   k_scan_*   exclusive scan of the histogram (counting-sort offsets)
 //   k_scatter  counting-sort scatter of the bead records into key order;
 //              clears the histogram for the next step.
@@ -192,10 +193,10 @@ __device__ __forceinline__ void raise_error(Ctl *ctl, int code, int64_t step, in
 
 // --------------------------------------------------------------- cell list
 
-// Cell of a bead and its 16-bit neighbour coordinates.  Periodic dims:
-// wrapped into [0, L), cell = floor(frac * ncell), coordinate = frac * 2^16;
-// open dims: relative to the replica origin, cell = floor(x / h), coordinate
-// = x * 256 modulo 2^16.  Returns false if the position is not finite or too
+// Cell of a bead and its fixed-point coordinates.  Periodic dims: wrapped
+// into [0, L), cell = floor(frac * ncell), coordinate = frac * 2^32; open
+// dims: relative to the replica origin, cell = floor(x / h), coordinate =
+// x * 2^24 modulo 2^32.  Returns false if the position is not finite or too
 // far from the origin to be binned.
 __device__ __forceinline__ bool cell_of(const RepInfo &ri, D3 p, int c[3], uint32_t qc[3])
 {
@@ -207,15 +208,14 @@ __device__ __forceinline__ bool cell_of(const RepInfo &ri, D3 p, int c[3], uint3
             double t = x[k] * ri.inv_len[k];
             ok = ok && isfinite(t);
             t = ok ? t - floor(t) : 0.0;
-            int ci = (int)(t * (double)ri.ncell[k]);
-            ci = ci >= ri.ncell[k] ? ri.ncell[k] - 1 : (ci < 0 ? 0 : ci);
-            c[k] = ci;
-            qc[k] = (uint32_t)(t * 65536.0) & 0xFFFFu;
+            const int ci = (int)(t * (double)ri.ncell[k]);
+            c[k] = ci >= ri.ncell[k] ? ri.ncell[k] - 1 : (ci < 0 ? 0 : ci);
+            qc[k] = (uint32_t)(uint64_t)(t * 4294967296.0);
         } else {
             ok = ok && (fabs(x[k]) < 1.0e6);  // also rejects NaN
             const double xs = ok ? x[k] : 0.0;
             c[k] = (int)floor(xs * ri.inv_h[k]);
-            qc[k] = (uint32_t)(long long)rint(xs * OPEN_Q_INV) & 0xFFFFu;
+            qc[k] = (uint32_t)(uint64_t)(int64_t)rint(xs * OPEN_QINV);
         }
     }
     return ok;
@@ -226,14 +226,15 @@ __device__ __forceinline__ uint32_t bucket_of(const Grid &g, int cx, int cy, int
     return ((uint32_t)cx + g.A * (uint32_t)cy + g.B * (uint32_t)cz + g.C * (uint32_t)rep) & g.mask;
 }
 
-// 16-bit tag: strand (bit 0), steric (bit 1), replica modulo 2^14 (bits 2..15).
+// Tag word of a bead record: strand, steric flag (every third base pair,
+// Sec. 2), replica.
 __device__ __forceinline__ uint32_t make_tag(int rep, int n, int s)
 {
-    return (((uint32_t)rep & 0x3FFFu) << 2) | ((n % 3 == 0) ? 2u : 0u) | (uint32_t)s;
+    return (uint32_t)s | ((n % 3) == 0 ? 2u : 0u) | ((uint32_t)rep << 2);
 }
 
-// Bin one bead: record, counting-sort key (bucket in its strand's plane) and
-// slot within the key (histogram).
+// Bin one bead: record, cell, counting-sort key (its bucket) and slot
+// within the key (histogram count phase).
 __device__ __forceinline__ void insert_bead(const StepArgs &a, const RepInfo &ri, int rep, int n, int s,
                                             int64_t i, D3 bead, int64_t step)
 {
@@ -243,8 +244,14 @@ __device__ __forceinline__ void insert_bead(const StepArgs &a, const RepInfo &ri
         raise_error(a.b.ctl, isfinite(bead.x + bead.y + bead.z) ? DSDNA_EDOMAIN : DSDNA_ENAN, step, i);
         c[0] = c[1] = c[2] = 0;
     }
-    const uint32_t key = bucket_of(a.g, c[0], c[1], c[2], rep) + (uint32_t)s * (uint32_t)a.g.nbucket;
-    a.b.rec[i] = make_uint2(qc[0] | (qc[1] << 16), qc[2] | (make_tag(rep, n, s) << 16));
+    const uint32_t key = bucket_of(a.g, c[0], c[1], c[2], rep);
+    BeadRec r;
+    r.x = qc[0];
+    r.y = qc[1];
+    r.z = qc[2];
+    r.tag = make_tag(rep, n, s);
+    a.b.rec[i] = r;
+    a.b.rcell[i] = make_int4(c[0], c[1], c[2], 0);
     a.b.key[i] = (int32_t)key;
     a.b.slot[i] = atomicAdd(&a.b.count[key], 1);
 }
@@ -258,10 +265,7 @@ struct TileLds {
     real oStep[2][TILE_BP + 1][4][3];      // per strand, per backbone step m
     real oBend[2][TILE_BP + 2][3][3];      // per strand, per bending centre
     real oHb[TILE_BP][3];                  // force on strand-0 patch
-    uint8_t sOpen[TILE_BP + 2 * HALO_BP];  // open flags of bp n0-2 .. n0+129
-    real sW[TILE_NT][3];                   // excluded-volume force per nucleotide
-    uint8_t perm[TILE_NT];                 // search order: steric beads first
-    int wcnt[2][TILE_NT / 64];             // per-wave steric / ghost counts
+    uint8_t sOpen[TILE_BP + 2 * HALO_BP];  // open flags of bp n0-2 .. n0+TILE_BP+1
 };
 
 template <typename real>
@@ -281,36 +285,69 @@ template <typename real>
 __device__ __forceinline__ V3<real> get3(const real *src) { return v3(src[0], src[1], src[2]); }
 
 constexpr uint32_t ALL_TERMS = (1u << DSDNA_NTERMS) - 1u;
+static_assert(WG_THREADS - TILE_NT == 4 * HALO_BP, "the spare threads of a tile stage its halo");
 
-typedef short short2v __attribute__((ext_vector_type(2)));
+// The rigid body a thread loads and stages in LDS (index l <-> bp
+// n0 - 2 + l/2, strand l & 1): its own nucleotide for t < TILE_NT, a halo
+// site for the spare threads.
+struct StagedSite {
+    int l;         // LDS site index
+    bool valid;    // the site exists in the replica
+    int64_t i;     // nucleotide index
+    D3 R, u;
+};
 
-// All conservative and external site forces of the calling thread's
-// nucleotide, restricted to the terms in `mask`.  Must be called by all
-// threads of the workgroup (it synchronises).  With energies != nullptr the
-// per-term energies owned by this thread are added there (diagnostics only).
-template <typename real>
-__device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileLds<real> &S, const RepInfo &ri, int rep, int n0,
-                                        int cur, uint32_t mask, int64_t step, double *energies)
+__device__ __forceinline__ StagedSite load_site(const StepArgs &a, const RepInfo &ri, int n0, int buf)
 {
     const int t = threadIdx.x;
-    const int64_t N = a.n_nt;
+    StagedSite st;
+    st.l = t < TILE_NT ? t + 2 * HALO_BP : (t - TILE_NT < 2 * HALO_BP ? t - TILE_NT : t);
+    const int bp = n0 - HALO_BP + (st.l >> 1);
+    st.valid = bp >= 0 && bp < ri.n_bp;
+    st.i = ri.off + 2 * (int64_t)bp + (st.l & 1);
+    st.R = v3(0.0, 0.0, 0.0);
+    st.u = st.R;
+    if (st.valid) {
+        st.R = ld3(a.b.R[buf], a.n_nt, st.i);
+        st.u = ld3(a.b.u[buf], a.n_nt, st.i);
+    }
+    return st;
+}
+
+template <typename real>
+__device__ __forceinline__ void stage_site(const StepArgs &a, TileLds<real> &S, const StagedSite &st)
+{
+    if (!st.valid) return;
+    const D3 b = bead_of(st.R, st.u, a.ph.db), p = patch_of(st.R, st.u, a.ph.dp);
+    S.sB[st.l][0] = b.x; S.sB[st.l][1] = b.y; S.sB[st.l][2] = b.z;
+    S.sP[st.l][0] = p.x; S.sP[st.l][1] = p.y; S.sP[st.l][2] = p.z;
+}
+
+// Excluded-volume force of nucleotide i computed by k_excl.
+template <typename real>
+__device__ __forceinline__ V3<real> load_fex(const StepArgs &a, int64_t i)
+{
+    if (sizeof(real) == sizeof(double)) {
+        const double4 w = reinterpret_cast<const double4 *>(a.b.fex)[i];
+        return v3<real>((real)w.x, (real)w.y, (real)w.z);
+    }
+    const float4 w = reinterpret_cast<const float4 *>(a.b.fex)[i];
+    return v3<real>((real)w.x, (real)w.y, (real)w.z);
+}
+
+// All conservative and external site forces of the calling thread's
+// nucleotide, restricted to the terms in `mask`, from the sites every thread
+// has staged (stage_site) beforehand; `fex` is the thread's excluded-volume
+// force.  Must be called by all threads of the workgroup (it synchronises).
+// With energies != nullptr the per-term energies owned by this thread are
+// added there (diagnostics only).
+template <typename real>
+__device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileLds<real> &S, const RepInfo &ri, int rep, int n0,
+                                        V3<real> fex, uint32_t mask, int64_t step, double *energies)
+{
+    const int t = threadIdx.x;
     const Phys &ph = a.ph;
     const int nbp = ri.n_bp;
-    const double *Rc = a.b.R[cur];
-    const double *uc = a.b.u[cur];
-
-    // --- stage FP64 sites of the tile and its halo (LDS index l <-> bp
-    //     n0 - 2 + l/2, strand l & 1)
-    for (int l = t; l < TILE_NT + 4 * HALO_BP; l += blockDim.x) {
-        const int bp = n0 - HALO_BP + (l >> 1);
-        if (bp >= 0 && bp < nbp) {
-            const int64_t i = ri.off + 2 * (int64_t)bp + (l & 1);
-            const D3 R = ld3(Rc, N, i), u = ld3(uc, N, i);
-            const D3 b = bead_of(R, u, ph.db), p = patch_of(R, u, ph.dp);
-            S.sB[l][0] = b.x; S.sB[l][1] = b.y; S.sB[l][2] = b.z;
-            S.sP[l][0] = p.x; S.sP[l][1] = p.y; S.sP[l][2] = p.z;
-        }
-    }
     __syncthreads();
 
     // --- hydrogen bonds and open flags (truncated harmonic between the
@@ -459,9 +496,10 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
     }
     __syncthreads();
 
-    // --- gather per site (fixed order, no atomics)
-    const int s = t & 1, bl = t >> 1, n = n0 + bl;
-    const int nbp_tile = min(TILE_BP, nbp - n0);
+    // --- gather per site (fixed order, no atomics); threads past the tile
+    //     own no nucleotide
+    const int s = t & 1, bl = t >> 1;
+    const int n = t < TILE_NT ? n0 + bl : nbp;
     SiteForces<real> out;
     out.b = v3<real>(0, 0, 0);
     out.p = out.b;
@@ -473,177 +511,10 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
         out.p = s == 0 ? out.p + hb : out.p - hb;
     }
 
-    // --- excluded volume (WCA, steric/ghost rule of Sec. 2).  Every bead
-    //     scans the other strand's bucket plane (cross-strand pairs, any bead
-    //     type); steric beads also scan their own strand's plane (steric
-    //     pairs).  Searched in an order that puts the steric beads in the
-    //     first waves; forces go back to the natural order through LDS.
-    if (mask & (1u << DSDNA_TERM_EXCL)) {
-        {
-            const bool valid = bl < nbp_tile;
-            const bool st = valid && ((n % 3) == 0);
-            const uint64_t bs = __ballot(st), bg = __ballot(valid && !st);
-            const int lane = t & 63, w = t >> 6;
-            const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-            if (lane == 0) {
-                S.wcnt[0][w] = __popcll(bs);
-                S.wcnt[1][w] = __popcll(bg);
-            }
-            __syncthreads();
-            int os = 0, og = 0, nst = 0;
-            for (int k = 0; k < TILE_NT / 64; ++k) {
-                if (k < w) { os += S.wcnt[0][k]; og += S.wcnt[1][k]; }
-                nst += S.wcnt[0][k];
-            }
-            if (st) S.perm[os + __popcll(bs & below)] = (uint8_t)t;
-            else if (valid) S.perm[nst + og + __popcll(bg & below)] = (uint8_t)t;
-        }
-        __syncthreads();
-        if (t < 2 * nbp_tile) {
-            const int lw = S.perm[t];
-            const int sw = lw & 1, nw = n0 + (lw >> 1);
-            const int64_t iw = ri.off + 2 * (int64_t)nw + sw;
-            const D3 bw = lds3(S.sB, lw + 2 * HALO_BP);
-            int c[3];
-            uint32_t mq[3];
-            cell_of(ri, bw, c, mq);
-            const bool mysteric = (nw % 3) == 0;
-            const uint32_t myrep = (uint32_t)rep & 0x3FFFu;
-            const float rs = (float)ph.rc_s + a.g.margin, rx = (float)ph.rc_x + a.g.margin;
-            const float rs2 = rs * rs, rx2 = rx * rx;
-            const real rcs2 = (real)(ph.rc_s * ph.rc_s), rcx2 = (real)(ph.rc_x * ph.rc_x);
-            const real sig_s2 = (real)(ph.sig_s * ph.sig_s), sig_x2 = (real)(ph.sig_x * ph.sig_x);
-            const bool px = ri.flags & REP_PER_X, py = ri.flags & REP_PER_Y, pz = ri.flags & REP_PER_Z;
-            const float qx = ri.q[0], qy = ri.q[1], qz = ri.q[2];
-            const bool qint = ri.qsame != 0;
-            const int64_t jlo = ri.off, jhi = ri.off + 2 * (int64_t)nbp;
-            const short2v mxy = __builtin_bit_cast(short2v, mq[0] | (mq[1] << 16));
-            long long ax = 0, ay = 0, az = 0;  // fixed point, 2^-32 units: order independent
-            double e_excl = 0.0;
-            const double *Rcj = a.b.R[cur], *ucj = a.b.u[cur];
-            const uint2 *__restrict__ srec = a.b.srec;
-
-            // exact test and force for a candidate that passed the 16-bit
-            // pre-check (rare: true contacts and the slack shell)
-            auto refine = [&](int p, bool same) {
-                const int j = a.b.sid[p];
-                if (j == (int)iw || j < jlo || j >= jhi) return;   // itself, other replica
-                const D3 bj = bead_of(ld3(Rcj, N, j), ld3(ucj, N, j), ph.db);
-                D3 d64 = bj - bw;
-                if (px) d64.x -= ri.len[0] * rint(d64.x * ri.inv_len[0]);
-                if (py) d64.y -= ri.len[1] * rint(d64.y * ri.inv_len[1]);
-                if (pz) d64.z -= ri.len[2] * rint(d64.z * ri.inv_len[2]);
-                const V3<real> d = cvt<real>(d64);
-                const real r2 = dot(d, d);
-                if (r2 >= (same ? rcs2 : rcx2)) return;
-                const real ir2 = rcp(r2);
-                const real sr2 = (same ? sig_s2 : sig_x2) * ir2;
-                const real sr6 = sr2 * sr2 * sr2;
-                const real g = (real)(24.0 * ph.eps) * ((real)2 * sr6 * sr6 - sr6) * ir2;
-                const double fx = (double)(g * d.x), fy = (double)(g * d.y), fz = (double)(g * d.z);
-                if (!(fabs(fx) + fabs(fy) + fabs(fz) < 1.0e9)) {  // overlapping beads: out of range
-                    raise_error(a.b.ctl, DSDNA_ENAN, step, iw);
-                    return;
-                }
-                // force on the bead = -g d (repulsive)
-                ax -= __double2ll_rn(fx * 4294967296.0);
-                ay -= __double2ll_rn(fy * 4294967296.0);
-                az -= __double2ll_rn(fz * 4294967296.0);
-                if (energies) {
-                    const double s2 = (same ? ph.sig_s * ph.sig_s : ph.sig_x * ph.sig_x) / dot(d64, d64);
-                    const double s6 = s2 * s2 * s2;
-                    e_excl += 0.5 * 4.0 * ph.eps * (s6 * s6 - s6 + 0.25);
-                }
-            };
-            // 16-bit pre-check of one record: replica and type, then the
-            // squared distance in coordinate units (integer when the unit is
-            // the same along x, y and z)
-            auto precheck = [&](const uint2 o, bool same, int t2) -> bool {
-                const uint32_t tj = o.y >> 16;
-                if ((tj >> 2) != myrep) return false;
-                if (same && !(tj & 2u)) return false;
-                if (qint) {
-                    const short2v dxy = __builtin_bit_cast(short2v, o.x) - mxy;
-                    const int dz = (int)(short)(uint16_t)(o.y - mq[2]);
-                    return __builtin_amdgcn_sdot2(dxy, dxy, dz * dz, false) < t2;
-                }
-                const float dx = (float)(int16_t)(uint16_t)((o.x & 0xFFFFu) - mq[0]) * qx;
-                const float dy = (float)(int16_t)(uint16_t)((o.x >> 16) - mq[1]) * qy;
-                const float dz = (float)(int16_t)(uint16_t)((o.y & 0xFFFFu) - mq[2]) * qz;
-                return dx * dx + dy * dy + dz * dz < (same ? rs2 : rx2);
-            };
-
-            // nine rows of three cells (dz, dy; cx-1..cx+1): three consecutive
-            // buckets each unless the row wraps (periodic x or bucket index)
-            const int ncx = ri.ncell[0], ncy = ri.ncell[1], ncz = ri.ncell[2];
-            const bool xwrap = px && (c[0] == 0 || c[0] == ncx - 1);
-            uint32_t kr[9];
-#pragma unroll
-            for (int q = 0; q < 9; ++q) {
-                int cy = c[1] + (q % 3) - 1, cz = c[2] + (q / 3) - 1;
-                if (py) cy = cy < 0 ? cy + ncy : (cy >= ncy ? cy - ncy : cy);
-                if (pz) cz = cz < 0 ? cz + ncz : (cz >= ncz ? cz - ncz : cz);
-                kr[q] = bucket_of(a.g, c[0] - 1, cy, cz, rep);
-            }
-            // pass 0: the other strand's plane (every bead); pass 1: the own
-            // strand's plane (steric beads only)
-            for (int pass = 0; pass < (mysteric ? 2 : 1); ++pass) {
-                const bool same = pass == 1;
-                const int t2 = same ? ri.t2_same : ri.t2_cross;
-                const uint32_t plane = (uint32_t)(same ? sw : 1 - sw) * (uint32_t)a.g.nbucket;
-                // stream position k of range q sits at k + sh[q] in the sorted
-                // records; pre[q] = first stream position of range q
-                int sh[9], pre[9];
-                int total = 0;
-#pragma unroll
-                for (int q = 0; q < 9; ++q) {
-                    const bool reg = !xwrap && kr[q] + 2u <= a.g.mask;
-                    const int l0 = reg ? a.b.start[plane + kr[q]] : 0;
-                    const int h0 = reg ? a.b.start[plane + kr[q] + 3] : 0;
-                    pre[q] = total;
-                    sh[q] = l0 - total;
-                    total += h0 - l0;
-                }
-                // the nine ranges as one candidate stream, four independent
-                // loads per trip (the wave runs max over lanes of the total)
-                constexpr int U = 4;
-                for (int k0 = 0; k0 < total; k0 += U) {
-                    uint2 o[U];
-                    int pp[U];
-#pragma unroll
-                    for (int v = 0; v < U; ++v) {
-                        const int k = k0 + v < total ? k0 + v : total - 1;
-                        int d = sh[0];
-#pragma unroll
-                        for (int r = 1; r < 9; ++r) d = (k >= pre[r]) ? sh[r] : d;
-                        pp[v] = k + d;
-                        o[v] = srec[pp[v]];
-                    }
-#pragma unroll
-                    for (int v = 0; v < U; ++v)
-                        if (k0 + v < total && precheck(o[v], same, t2)) refine(pp[v], same);
-                }
-                // rows that wrap: cell by cell (rare)
-                for (int q = 0; q < 9; ++q) {
-                    int cy = c[1] + (q % 3) - 1, cz = c[2] + (q / 3) - 1;
-                    if (py) cy = cy < 0 ? cy + ncy : (cy >= ncy ? cy - ncy : cy);
-                    if (pz) cz = cz < 0 ? cz + ncz : (cz >= ncz ? cz - ncz : cz);
-                    if (!xwrap && bucket_of(a.g, c[0] - 1, cy, cz, rep) + 2u <= a.g.mask) continue;
-                    for (int dx = -1; dx <= 1; ++dx) {
-                        int cx = c[0] + dx;
-                        if (px) cx = cx < 0 ? cx + ncx : (cx >= ncx ? cx - ncx : cx);
-                        const uint32_t kb = plane + bucket_of(a.g, cx, cy, cz, rep);
-                        for (int p = a.b.start[kb]; p < a.b.start[kb + 1]; ++p)
-                            if (precheck(srec[p], same, t2)) refine(p, same);
-                    }
-                }
-            }
-            put3(S.sW[lw], v3<real>((real)((double)ax * 0x1p-32), (real)((double)ay * 0x1p-32),
-                                    (real)((double)az * 0x1p-32)));
-            if (energies) energies[DSDNA_TERM_EXCL] += e_excl;
-        }
-        __syncthreads();
-        if (n < nbp) out.b = out.b + get3(S.sW[t]);
+    // --- excluded volume: computed per bead from the cell list beforehand
+    if (n < nbp && (mask & (1u << DSDNA_TERM_EXCL))) {
+        out.b = out.b + fex;
+        if (energies) energies[DSDNA_TERM_EXCL] += a.b.eex[ri.off + 2 * (int64_t)n + s];
     }
     if (n >= nbp) return out;
 
@@ -720,7 +591,7 @@ __device__ __forceinline__ D3 rotate(D3 u, D3 k, double th)
 // ---------------------------------------------------------------- k_step
 
 template <typename real>
-__global__ void __launch_bounds__(TILE_NT, 4) k_step(const StepArgs *__restrict__ A, int mode, int write_full)
+__global__ void __launch_bounds__(WG_THREADS, 4) k_step(const StepArgs *__restrict__ A, int mode, int write_full)
 {
     __shared__ TileLds<real> S;
     const StepArgs &a = *A;
@@ -735,17 +606,44 @@ __global__ void __launch_bounds__(TILE_NT, 4) k_step(const StepArgs *__restrict_
     const int64_t N = a.n_nt;
     const Phys &ph = a.ph;
 
+    // every global load of this thread up front: its body (or halo site),
+    // velocities and excluded-volume force
+    const StagedSite site = load_site(a, ri, tile.n0, cur);
+    const int s = threadIdx.x & 1;
+    const int n = threadIdx.x < TILE_NT ? tile.n0 + (int)(threadIdx.x >> 1) : ri.n_bp;
+    const bool own = n < ri.n_bp;
+    const int64_t i = site.i;
+    D3 R = site.R, u = site.u;
+    D3 V = v3(0.0, 0.0, 0.0), L = V;
+    V3<real> fexv = v3<real>(0, 0, 0);
+    if (own) {
+        V = ld3(a.b.V[cur], N, i);
+        L = ld3(a.b.L[cur], N, i);
+        if (mode != MODE_FROM_FORCES) fexv = load_fex<real>(a, i);
+    }
+    // the thread's noise numbers while the loads are in flight
+    real xi[6] = {0, 0, 0, 0, 0, 0};
+    const bool frozen = (ri.flags & REP_TETHER) && n == 0;
+    const bool langevin = own && !frozen && ph.gamma > 0.0 && mode != MODE_FROM_FORCES;
+    if (langevin) {
+        if (sizeof(real) == sizeof(double)) {
+            double x64[6];
+            noise6(ph.seed, ph.noise_kind, (uint64_t)step, (uint32_t)i, 0u, x64);
+            for (int k = 0; k < 6; ++k) xi[k] = (real)x64[k];
+        } else {
+            float x32[6];
+            noise6f(ph.seed, ph.noise_kind, (uint64_t)step, (uint32_t)i, 0u, x32);
+            for (int k = 0; k < 6; ++k) xi[k] = (real)x32[k];
+        }
+    }
     SiteForces<real> f;
     f.b = v3<real>(0, 0, 0);
     f.p = f.b;
-    if (mode != MODE_FROM_FORCES) f = tile_forces<real>(a, S, ri, tile.rep, tile.n0, cur, ALL_TERMS, step, nullptr);
-
-    const int s = threadIdx.x & 1, n = tile.n0 + (threadIdx.x >> 1);
-    if (n >= ri.n_bp) return;
-    const int64_t i = ri.off + 2 * (int64_t)n + s;
-    D3 R = ld3(a.b.R[cur], N, i), u = ld3(a.b.u[cur], N, i);
-    D3 V = ld3(a.b.V[cur], N, i), L = ld3(a.b.L[cur], N, i);
-    const bool frozen = (ri.flags & REP_TETHER) && n == 0;
+    if (mode != MODE_FROM_FORCES) {
+        stage_site(a, S, site);
+        f = tile_forces<real>(a, S, ri, tile.rep, tile.n0, fexv, ALL_TERMS, step, nullptr);
+    }
+    if (!own) return;
 
     D3 fb, fp;  // total site forces of this step
     if (mode == MODE_FROM_FORCES) {
@@ -753,19 +651,15 @@ __global__ void __launch_bounds__(TILE_NT, 4) k_step(const StepArgs *__restrict_
         fp = ld3(a.b.Fp, N, i);
     } else {
         V3<real> lb = v3<real>(0, 0, 0), lp = lb;
-        if (!frozen && ph.gamma > 0.0) {
+        if (langevin) {
             // Langevin forces (Appendix A) per site: friction on the site's
             // velocity on the rigid body plus counter-based noise
             const D3 w = L * (1.0 / ph.I);
             const D3 vb = V + cross(w, u * (-ph.db)), vp = V + cross(w, u * ph.dp);
             if (sizeof(real) == sizeof(double)) {
-                double xi[6];
-                noise6(ph.seed, ph.noise_kind, (uint64_t)step, (uint32_t)i, 0u, xi);
-                lb = cvt<real>(vb * (-ph.gamma) + v3(xi[0], xi[1], xi[2]) * ph.noise_amp);
-                lp = cvt<real>(vp * (-ph.gamma) + v3(xi[3], xi[4], xi[5]) * ph.noise_amp);
+                lb = cvt<real>(vb * (-ph.gamma) + v3((double)xi[0], (double)xi[1], (double)xi[2]) * ph.noise_amp);
+                lp = cvt<real>(vp * (-ph.gamma) + v3((double)xi[3], (double)xi[4], (double)xi[5]) * ph.noise_amp);
             } else {
-                float xi[6];
-                noise6f(ph.seed, ph.noise_kind, (uint64_t)step, (uint32_t)i, 0u, xi);
                 const real amp = (real)ph.noise_amp;
                 lb = cvt<real>(vb * (-ph.gamma)) + v3<real>(xi[0], xi[1], xi[2]) * amp;
                 lp = cvt<real>(vp * (-ph.gamma)) + v3<real>(xi[3], xi[4], xi[5]) * amp;
@@ -826,11 +720,236 @@ __global__ void __launch_bounds__(256) k_bin(const StepArgs *__restrict__ A, int
     if (tix >= a.n_tiles) return;
     const Tile tile = a.b.tiles[tix];
     const RepInfo &ri = a.b.rep[tile.rep];
-    const int s = threadIdx.x & 1, n = tile.n0 + (threadIdx.x >> 1);
+    const int s = threadIdx.x & 1, n = threadIdx.x < TILE_NT ? tile.n0 + (int)(threadIdx.x >> 1) : ri.n_bp;
     if (n >= ri.n_bp) return;
     const int64_t i = ri.off + 2 * (int64_t)n + s;
     const D3 R = ld3(a.b.R[which], a.n_nt, i), u = ld3(a.b.u[which], a.n_nt, i);
     insert_bead(a, ri, tile.rep, n, s, i, bead_of(R, u, a.ph.db), a.b.ctl->step);
+}
+
+// ------------------------------------------------------- excluded volume
+
+// Order-independent accumulation of force components, so that a bead's
+// total does not depend on the order of its contacts in the cell list.
+// FP32 forces: each contribution is rounded to a multiple of 2^-24 (adding
+// and removing 1.5 * 2^28 in FP64 does exactly that for |f| < 2^27) and FP64
+// sums of such values are exact while |sum| < 2^29.  FP64 forces: 64-bit
+// integer sums in 2^-36 units.  A contact force beyond the limits
+// (overlapping beads; at most 16 such contacts keep the sums in range) is
+// reported as an error.
+constexpr double FIX_ROUND = 402653184.0;         // 1.5 * 2^28
+constexpr double PAIR_FORCE_MAX_F32 = 33554432.0;  // 2^25 (|fx| + |fy| + |fz|)
+constexpr double PAIR_FORCE_MAX_F64 = 8388608.0;   // 2^23
+constexpr double FIX64_UNIT = 68719476736.0;       // 2^36
+
+__device__ __forceinline__ double fix_round(double f) { return (f + FIX_ROUND) - FIX_ROUND; }
+
+// Excluded volume (WCA, steric/ghost rule of Sec. 2) of every bead, one
+// thread per record of the key-sorted cell list, so the lanes of a wave hold
+// beads of neighbouring cells and read overlapping candidate ranges.  A bead
+// interacts with every bead of the other strand (sigma_x) and, if steric,
+// with the steric beads of its own strand (sigma_s).  Candidates come from
+// the 27 cells around the bead's cell: nine rows of three consecutive
+// buckets, walked as one stream.  With FP32 forces the distance comes from
+// the fixed-point coordinates; with FP64 forces those only pre-select, and
+// the distance is taken from the FP64 positions (minimum image along
+// periodic edges).
+template <typename real, bool energy, bool any_open>
+__global__ void __launch_bounds__(256) k_excl(const StepArgs *__restrict__ A, const BeadRec *__restrict__ srec,
+                                              const int4 *__restrict__ sinfo, const int *__restrict__ start, int which)
+{
+    const StepArgs &a = *A;
+    if (a.b.ctl->code != 0) return;
+    const int per = (int)(gridDim.x >> 3);
+    const int blk = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    const int p = blk * (int)blockDim.x + (int)threadIdx.x;
+    if (p >= a.n_nt) return;
+    constexpr bool F64 = sizeof(real) == sizeof(double);
+    const Phys &ph = a.ph;
+    const BeadRec me = srec[p];
+    const int4 info = sinfo[p];
+    const int64_t i = info.x;
+    const int c[3] = {info.y, info.z, info.w};
+    const uint32_t rep = me.tag >> 2;
+    const uint32_t mt = me.tag & 3u;
+    // partner types (bit 0 strand, bit 1 steric) this bead interacts with:
+    // the other strand always, its own strand steric-steric only
+    const uint32_t accept = (mt & 1u ? 0x5u : 0xAu) | (mt & 2u ? (mt & 1u ? 0x8u : 0x4u) : 0u);
+    const RepInfo &ri = a.b.rep[rep];
+    const float qx = ri.qlen[0], qy = ri.qlen[1], qz = ri.qlen[2];
+    const int64_t N = a.n_nt;
+    const int buf = which < 0 ? a.b.ctl->par : which;
+    const double *Rc = a.b.R[buf], *uc = a.b.u[buf];
+    D3 bw = v3(0.0, 0.0, 0.0);
+    if (F64) bw = bead_of(ld3(Rc, N, i), ld3(uc, N, i), ph.db);
+    const bool px = ri.flags & REP_PER_X, py = ri.flags & REP_PER_Y, pz = ri.flags & REP_PER_Z;
+    // any_open: some replica has an open edge
+    const bool open_any = any_open && !(px && py && pz);
+    // FP64 forces: pre-select with a slack that covers the fixed-point error
+    const float rcs2 = (float)(F64 ? (ph.rc_s + 1e-3) * (ph.rc_s + 1e-3) : ph.rc_s * ph.rc_s);
+    const float rcx2 = (float)(F64 ? (ph.rc_x + 1e-3) * (ph.rc_x + 1e-3) : ph.rc_x * ph.rc_x);
+    const real sig_s2 = (real)(ph.sig_s * ph.sig_s), sig_x2 = (real)(ph.sig_x * ph.sig_x);
+    const real e24 = (real)(24.0 * ph.eps);
+    double ax = 0.0, ay = 0.0, az = 0.0;   // FP32 forces
+    long long lx = 0, ly = 0, lz = 0;     // FP64 forces
+    double e_excl = 0.0;
+    bool overflow = false;
+
+    auto pair = [&](const BeadRec &o, int q, bool valid) {
+        // distance first (keeps the record load whole), then the type,
+        // replica and self tests in one predicate
+        const uint32_t ot = o.tag & 3u;
+        const bool same = ((ot ^ mt) & 1u) == 0u;
+        const float dx = (float)(int32_t)(o.x - me.x) * qx;
+        const float dy = (float)(int32_t)(o.y - me.y) * qy;
+        const float dz = (float)(int32_t)(o.z - me.z) * qz;
+        const float r2f = dx * dx + dy * dy + dz * dz;
+        if (!(valid && r2f < (same ? rcs2 : rcx2) && ((accept >> ot) & 1u) && (o.tag >> 2) == rep && q != p))
+            return;
+        // open edges: the fixed-point difference is exact only modulo 2^32
+        // units, so a record of a far cell that shares a bucket with a
+        // neighbour cell is rejected by its cell coordinates
+        int4 oinfo = make_int4(0, 0, 0, 0);
+        if (F64 || any_open) oinfo = sinfo[q];
+        if (any_open && open_any &&
+            ((!px && abs(oinfo.y - c[0]) > 1) || (!py && abs(oinfo.z - c[1]) > 1) || (!pz && abs(oinfo.w - c[2]) > 1)))
+            return;
+        V3<real> d = v3<real>(dx, dy, dz);
+        real r2 = r2f;
+        D3 d64 = v3(0.0, 0.0, 0.0);
+        if (F64) {
+            const int j = oinfo.x;
+            d64 = bead_of(ld3(Rc, N, j), ld3(uc, N, j), ph.db) - bw;
+            if (px) d64.x = __fma_rn(-ri.len[0], rint(d64.x * ri.inv_len[0]), d64.x);
+            if (py) d64.y = __fma_rn(-ri.len[1], rint(d64.y * ri.inv_len[1]), d64.y);
+            if (pz) d64.z = __fma_rn(-ri.len[2], rint(d64.z * ri.inv_len[2]), d64.z);
+            d = cvt<real>(d64);
+            r2 = dot(d, d);
+            if (r2 >= (real)(same ? ph.rc_s * ph.rc_s : ph.rc_x * ph.rc_x)) return;
+        }
+        const real ir2 = rcp(r2);
+        const real sr2 = (same ? sig_s2 : sig_x2) * ir2;
+        const real sr6 = sr2 * sr2 * sr2;
+        const real g = e24 * ((real)2 * sr6 * sr6 - sr6) * ir2;
+        const real fx = g * d.x, fy = g * d.y, fz = g * d.z;
+        if (!(fabs(fx) + fabs(fy) + fabs(fz) < (real)(F64 ? PAIR_FORCE_MAX_F64 : PAIR_FORCE_MAX_F32))) {
+            overflow = true;
+            return;
+        }
+        // force on this bead: -g d (repulsive)
+        if (F64) {
+            lx -= __double2ll_rn((double)fx * FIX64_UNIT);
+            ly -= __double2ll_rn((double)fy * FIX64_UNIT);
+            lz -= __double2ll_rn((double)fz * FIX64_UNIT);
+        } else {
+            ax -= fix_round((double)fx);
+            ay -= fix_round((double)fy);
+            az -= fix_round((double)fz);
+        }
+        if (energy) {
+            const double s2 = (same ? ph.sig_s * ph.sig_s : ph.sig_x * ph.sig_x) / (F64 ? dot(d64, d64) : (double)r2);
+            const double s6 = s2 * s2 * s2;
+            e_excl += 0.5 * 4.0 * ph.eps * (s6 * s6 - s6 + 0.25);
+        }
+    };
+
+    // nine rows of three cells (dz, dy; cx-1..cx+1): three consecutive
+    // buckets each unless the row wraps (periodic x or bucket index)
+    const int ncx = ri.ncell[0], ncy = ri.ncell[1], ncz = ri.ncell[2];
+    const bool xwrap = px && (c[0] == 0 || c[0] == ncx - 1);
+    // stream position k of row q sits at k + sh[q] in the sorted records;
+    // pre[q] = first stream position of row q.  sh lives in LDS; the row of
+    // k < 127 is found by counting the bytes of the packed pre[1..8] that are
+    // <= k (one subtract per four rows, no borrow between bytes while
+    // k, pre < 128); larger k take the plain search.
+    __shared__ int s_sh[9][256];
+    __shared__ int s_pre[9][256];
+    const int t = threadIdx.x;
+    int total = 0;
+    uint32_t wrapped = 0;  // bit q: row q wraps
+    uint32_t pk0 = 0, pk1 = 0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        int cy = c[1] + (q % 3) - 1, cz = c[2] + (q / 3) - 1;
+        if (py) cy = cy < 0 ? cy + ncy : (cy >= ncy ? cy - ncy : cy);
+        if (pz) cz = cz < 0 ? cz + ncz : (cz >= ncz ? cz - ncz : cz);
+        const uint32_t k0 = bucket_of(a.g, c[0] - 1, cy, cz, (int)rep);
+        const bool wr = xwrap || k0 + 2u > a.g.mask;
+        wrapped |= (uint32_t)wr << q;
+        const int l0 = wr ? 0 : start[k0];
+        const int h0 = wr ? 0 : start[k0 + 3];
+        s_pre[q][t] = total;
+        s_sh[q][t] = l0 - total;
+        const uint32_t pc = (uint32_t)min(total, 127);
+        if (q >= 1 && q <= 4) pk0 |= pc << (8 * (q - 1));
+        if (q >= 5) pk1 |= pc << (8 * (q - 5));
+        total += h0 - l0;
+    }
+    // no barrier needed: each thread reads only its own LDS column
+    const int nfast = min(total, 127);
+    // sorted position of stream entry k (clamped into the stream; entries
+    // past the end are fetched again and ignored)
+    auto locate = [&](int k) -> int {
+        k = k < nfast ? k : nfast - 1;
+        const uint32_t kb = ((uint32_t)k | 0x80u) * 0x01010101u;
+        const int q = __popc((kb - pk0) & 0x80808080u) + __popc((kb - pk1) & 0x80808080u);
+        return k + s_sh[q][t];
+    };
+    // software pipeline: the records of the next U entries are in flight
+    // while the current U are evaluated
+    constexpr int U = 2;
+    if (nfast > 0) {
+        BeadRec o[U];
+        int pp[U];
+#pragma unroll
+        for (int v = 0; v < U; ++v) {
+            pp[v] = locate(v);
+            o[v] = srec[pp[v]];
+        }
+        for (int k0 = 0; k0 < nfast; k0 += U) {
+            BeadRec on[U];
+            int pn[U];
+#pragma unroll
+            for (int v = 0; v < U; ++v) {
+                pn[v] = locate(k0 + U + v);
+                on[v] = srec[pn[v]];
+            }
+#pragma unroll
+            for (int v = 0; v < U; ++v) pair(o[v], pp[v], k0 + v < nfast);
+#pragma unroll
+            for (int v = 0; v < U; ++v) {
+                o[v] = on[v];
+                pp[v] = pn[v];
+            }
+        }
+    }
+    for (int k = nfast; k < total; ++k) {
+        int q = 0;
+        for (int r = 1; r < 9; ++r) q = (k >= s_pre[r][t]) ? r : q;
+        const int pq = k + s_sh[q][t];
+        pair(srec[pq], pq, true);
+    }
+    // rows that wrap: cell by cell (rare)
+#pragma unroll 1
+    for (int q = 0; q < 9; ++q) {
+        if (!((wrapped >> q) & 1u)) continue;
+        int cy = c[1] + (q % 3) - 1, cz = c[2] + (q / 3) - 1;
+        if (py) cy = cy < 0 ? cy + ncy : (cy >= ncy ? cy - ncy : cy);
+        if (pz) cz = cz < 0 ? cz + ncz : (cz >= ncz ? cz - ncz : cz);
+        for (int dx = -1; dx <= 1; ++dx) {
+            int cx = c[0] + dx;
+            if (px) cx = cx < 0 ? cx + ncx : (cx >= ncx ? cx - ncx : cx);
+            const uint32_t kb = bucket_of(a.g, cx, cy, cz, (int)rep);
+            for (int q2 = start[kb]; q2 < start[kb + 1]; ++q2) pair(srec[q2], q2, true);
+        }
+    }
+    if (overflow) raise_error(a.b.ctl, DSDNA_ENAN, a.b.ctl->step, i);
+    if (F64)
+        reinterpret_cast<double4 *>(a.b.fex)[i] =
+            make_double4((double)lx / FIX64_UNIT, (double)ly / FIX64_UNIT, (double)lz / FIX64_UNIT, 0.0);
+    else
+        reinterpret_cast<float4 *>(a.b.fex)[i] = make_float4((float)ax, (float)ay, (float)az, 0.0f);
+    if (energy) a.b.eex[i] = e_excl;
 }
 
 // ------------------------------------------------------------------- scan
@@ -912,13 +1031,14 @@ __global__ void __launch_bounds__(256) k_scan_down(const int *__restrict__ count
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == blockDim.x - 1) start[nkeys] = run;
 }
 
-// Counting-sort scatter: bead records (and their nucleotide ids) into key
-// order; clears the histogram entries it used.  inc: also advance the step
-// and flip the position buffers.
+// Counting-sort scatter: bead records into key order; clears the histogram
+// entries it used.  inc: also advance the step and flip the position
+// buffers.
 __global__ void __launch_bounds__(256) k_scatter(const int *__restrict__ key, const int *__restrict__ slot,
-                                                 const int *__restrict__ start, const uint2 *__restrict__ rec,
-                                                 uint2 *__restrict__ srec, int *__restrict__ sid,
-                                                 int *__restrict__ count, Ctl *ctl, int64_t n, int inc)
+                                                 const int *__restrict__ start, const BeadRec *__restrict__ rec,
+                                                 const int4 *__restrict__ rcell, BeadRec *__restrict__ srec,
+                                                 int4 *__restrict__ sinfo, int *__restrict__ count, Ctl *ctl,
+                                                 int64_t n, int inc)
 {
     if (ctl->code != 0) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -926,7 +1046,8 @@ __global__ void __launch_bounds__(256) k_scatter(const int *__restrict__ key, co
         const int k = key[i];
         const int p = start[k] + slot[i];
         srec[p] = rec[i];
-        sid[p] = (int)i;
+        const int4 c = rcell[i];
+        sinfo[p] = make_int4((int)i, c.x, c.y, c.z);
         count[k] = 0;
     }
     if (inc && i == 0) {
@@ -944,7 +1065,7 @@ __global__ void __launch_bounds__(256) k_thermalize(const StepArgs *__restrict__
     if (tix >= a.n_tiles) return;
     const Tile tile = a.b.tiles[tix];
     const RepInfo &ri = a.b.rep[tile.rep];
-    const int s = threadIdx.x & 1, n = tile.n0 + (threadIdx.x >> 1);
+    const int s = threadIdx.x & 1, n = threadIdx.x < TILE_NT ? tile.n0 + (int)(threadIdx.x >> 1) : ri.n_bp;
     if (n >= ri.n_bp) return;
     const int64_t i = ri.off + 2 * (int64_t)n + s;
     const int cur = a.b.ctl->par;
@@ -968,10 +1089,10 @@ __global__ void __launch_bounds__(256) k_thermalize(const StepArgs *__restrict__
 // --------------------------------------------------------------- diagnostics
 
 template <typename real>
-__global__ void __launch_bounds__(TILE_NT) k_diag(const StepArgs *__restrict__ A, int which, uint32_t mask)
+__global__ void __launch_bounds__(WG_THREADS) k_diag(const StepArgs *__restrict__ A, int which, uint32_t mask)
 {
     __shared__ TileLds<real> S;
-    __shared__ double red[DSDNA_NTERMS][TILE_NT / 64];
+    __shared__ double red[DSDNA_NTERMS][WG_THREADS / 64];
     const StepArgs &a = *A;
     // the cell list is only valid when the binning before this launch
     // completed without error
@@ -983,8 +1104,11 @@ __global__ void __launch_bounds__(TILE_NT) k_diag(const StepArgs *__restrict__ A
     double e[DSDNA_NTERMS];
     for (int k = 0; k < DSDNA_NTERMS; ++k) e[k] = 0.0;
     const int64_t step = a.b.ctl->step;
-    SiteForces<real> f = tile_forces<real>(a, S, ri, tile.rep, tile.n0, which, mask, step, e);
-    const int s = threadIdx.x & 1, bl = threadIdx.x >> 1, n = tile.n0 + bl;
+    const StagedSite site = load_site(a, ri, tile.n0, which);
+    const int s = threadIdx.x & 1, bl = threadIdx.x >> 1, n = threadIdx.x < TILE_NT ? tile.n0 + bl : ri.n_bp;
+    const V3<real> fexv = n < ri.n_bp ? load_fex<real>(a, site.i) : v3<real>(0, 0, 0);
+    stage_site(a, S, site);
+    SiteForces<real> f = tile_forces<real>(a, S, ri, tile.rep, tile.n0, fexv, mask, step, e);
     if (n < ri.n_bp) {
         const int64_t i = ri.off + 2 * (int64_t)n + s;
         a.b.diag_fb[3 * i] = (double)f.b.x;
@@ -1004,7 +1128,7 @@ __global__ void __launch_bounds__(TILE_NT) k_diag(const StepArgs *__restrict__ A
     __syncthreads();
     if (threadIdx.x < DSDNA_NTERMS) {
         double v = 0.0;
-        for (int w = 0; w < TILE_NT / 64; ++w) v += red[threadIdx.x][w];
+        for (int w = 0; w < WG_THREADS / 64; ++w) v += red[threadIdx.x][w];
         a.b.eacc[(int64_t)tix * DSDNA_NTERMS + threadIdx.x] = v;
     }
 }
@@ -1015,13 +1139,13 @@ static dim3 tiles_grid(const StepArgs &a) { return dim3((unsigned)a.n_tiles_pad)
 
 hipError_t launch_bin(const StepArgs &a, const StepArgs *dA, int which, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_bin, tiles_grid(a), dim3(TILE_NT), 0, s, dA, which);
+    hipLaunchKernelGGL(k_bin, tiles_grid(a), dim3(WG_THREADS), 0, s, dA, which);
     return hipGetLastError();
 }
 
 hipError_t launch_scan(const StepArgs &a, hipStream_t s)
 {
-    const int nkeys = 2 * a.g.nbucket;  // one plane of buckets per strand
+    const int nkeys = a.g.nbucket;
     const int nchunk = nkeys / SCAN_CHUNK;
     hipLaunchKernelGGL(k_scan_reduce, dim3(nchunk), dim3(256), 0, s, a.b.count, a.b.bsum, a.b.ctl);
     hipLaunchKernelGGL(k_scan_down, dim3(nchunk), dim3(256), 0, s, a.b.count, a.b.bsum, a.b.start, nkeys,
@@ -1032,23 +1156,49 @@ hipError_t launch_scan(const StepArgs &a, hipStream_t s)
 hipError_t launch_scatter(const StepArgs &a, int inc_step, hipStream_t s)
 {
     const unsigned nb = (unsigned)((a.n_nt + 255) / 256);
-    hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, s, a.b.key, a.b.slot, a.b.start, a.b.rec, a.b.srec,
-                       a.b.sid, a.b.count, a.b.ctl, a.n_nt, inc_step);
+    hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, s, a.b.key, a.b.slot, a.b.start, a.b.rec, a.b.rcell,
+                       a.b.srec, a.b.sinfo, a.b.count, a.b.ctl, a.n_nt, inc_step);
     return hipGetLastError();
 }
 
 hipError_t launch_step(const StepArgs &a, const StepArgs *dA, int fp64, int mode, int write_full, hipStream_t s)
 {
     if (fp64)
-        hipLaunchKernelGGL(k_step<double>, tiles_grid(a), dim3(TILE_NT), 0, s, dA, mode, write_full);
+        hipLaunchKernelGGL(k_step<double>, tiles_grid(a), dim3(WG_THREADS), 0, s, dA, mode, write_full);
     else
-        hipLaunchKernelGGL(k_step<float>, tiles_grid(a), dim3(TILE_NT), 0, s, dA, mode, write_full);
+        hipLaunchKernelGGL(k_step<float>, tiles_grid(a), dim3(WG_THREADS), 0, s, dA, mode, write_full);
+    return hipGetLastError();
+}
+
+template <typename real, bool energy>
+static void launch_excl_t(const StepArgs &a, const StepArgs *dA, int which, unsigned nb, hipStream_t s)
+{
+    if (a.g.any_open)
+        hipLaunchKernelGGL((k_excl<real, energy, true>), dim3(nb), dim3(256), 0, s, dA, a.b.srec, a.b.sinfo,
+                           a.b.start, which);
+    else
+        hipLaunchKernelGGL((k_excl<real, energy, false>), dim3(nb), dim3(256), 0, s, dA, a.b.srec, a.b.sinfo,
+                           a.b.start, which);
+}
+
+hipError_t launch_excl(const StepArgs &a, const StepArgs *dA, int fp64, int energy, int which, hipStream_t s)
+{
+    // whole groups of 8 workgroups: the kernel hands each XCD one contiguous
+    // eighth of the sorted records
+    const unsigned nb = (unsigned)(((a.n_nt + 255) / 256 + 7) / 8 * 8);
+    if (fp64) {
+        if (energy) launch_excl_t<double, true>(a, dA, which, nb, s);
+        else launch_excl_t<double, false>(a, dA, which, nb, s);
+    } else {
+        if (energy) launch_excl_t<float, true>(a, dA, which, nb, s);
+        else launch_excl_t<float, false>(a, dA, which, nb, s);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_thermalize(const StepArgs &a, const StepArgs *dA, double kT, uint64_t seed, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_thermalize, tiles_grid(a), dim3(TILE_NT), 0, s, dA, kT, seed);
+    hipLaunchKernelGGL(k_thermalize, tiles_grid(a), dim3(WG_THREADS), 0, s, dA, kT, seed);
     return hipGetLastError();
 }
 
@@ -1056,9 +1206,9 @@ hipError_t launch_diag(const StepArgs &a, const StepArgs *dA, int which, int fp6
                        hipStream_t s)
 {
     if (fp64)
-        hipLaunchKernelGGL(k_diag<double>, tiles_grid(a), dim3(TILE_NT), 0, s, dA, which, term_mask);
+        hipLaunchKernelGGL(k_diag<double>, tiles_grid(a), dim3(WG_THREADS), 0, s, dA, which, term_mask);
     else
-        hipLaunchKernelGGL(k_diag<float>, tiles_grid(a), dim3(TILE_NT), 0, s, dA, which, term_mask);
+        hipLaunchKernelGGL(k_diag<float>, tiles_grid(a), dim3(WG_THREADS), 0, s, dA, which, term_mask);
     return hipGetLastError();
 }
 

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EBOND", 5: 
 TERMS = ("excl", "bond", "stack", "hbond", "twist", "planar", "bend", "ext")
 NTERMS = len(TERMS)
 NENERGY = NTERMS + 2
-KERNELS = ("step", "scan", "scatter")
+KERNELS = ("step", "scan", "scatter", "excl")
 
 # every symbol include/dsdna.h declares
 EXPORTS = (

@@ -134,6 +134,36 @@ def test_forces_periodic_box(D):
             sim.close()
 
 
+@pytest.mark.parametrize("fp64", [0, 1])
+def test_open_box_far_records(D, fp64):
+    """Open edges: the 32-bit neighbour coordinates repeat every 256 length
+    units.  In a straight compressed duplex (rise 0.30, radius 0.3) steric
+    beads 17,070 bp apart sit at the same helical phase 5121.0 apart along the
+    axis; with cell edge 1.25 and 2^12 buckets many of their cells (4096 apart)
+    share a bucket, and their wrapped coordinates are 1.0 apart, inside the
+    steric cutoff.  No force may come from such a record."""
+    n, gap = 17200, 17070
+    bead, patch = synth.ideal_helix(n, rise=0.30, radius=0.3)
+    assert abs((bead[2 * gap, 2] - bead[0, 2]) - 5121.0) < 1e-6 and gap % 30 == 0
+    cfg = dict(n_bp=np.array([n]), bead=bead, patch=patch)
+    P = O.default_params()
+    S = O.System([n])
+    R, u = O.bodies_from_sites(P, bead, patch)
+    b, p = O.sites_from_bodies(P, R, u)
+    cz = np.floor(b[:, 2] / 1.25).astype(np.int64)
+    assert np.sum(cz[2 * gap::6] - cz[:2 * (n - gap):6] == 4096) >= 5  # steric strand-0 pairs
+    st, _, fb, fp, _, _ = O.forces(P, S, b, p, use_cells=True)
+    assert st == O.OK
+    sim = _gpu(D, cfg, cell_size=1.25, hash_log2=12, force_fp64=fp64)
+    gb, gp = sim.forces("excl")
+    ref = fb[O.T["excl"]]
+    scale = np.abs(ref).max()
+    assert scale > 0.1
+    assert np.abs(gb - ref).max() <= (1e-10 if fp64 else 1e-5) * max(scale, 1.0)
+    assert np.abs(gp).max() == 0.0
+    sim.close()
+
+
 def test_replicas_with_loads(D):
     """Uneven replicas stacked in the same region of space (they must not
     interact), tethered to a wall, pulled and twisted, with K2 scales."""

@@ -3,15 +3,18 @@
 Workload (default): 1 Mbp linear dsDNA (2e6 nucleotides) pre-coiled as a
 random-walk helix in a periodic cube at 2% bead volume fraction, FP32 forces
 with FP64 positions and integrator.  A step is one pass of the whole hot path:
-cell-list binning (histogram, scan, scatter), excluded volume, every bonded
-term, external loads, Langevin forces and the rigid-body velocity-Verlet
-update.  Prints one JSON line.
+excluded volume from the cell list, every bonded term, external loads,
+Langevin forces, the rigid-body velocity-Verlet update and the re-binning
+(histogram, scan, scatter).  Also measures the batched-replica path against
+one context per replica on the 256-replica tethered workload, and times the
+FP64 oracle on a bounded sample on the host.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 1mbp|100bp|10kbp|replicas|denat]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,11 +26,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor peak
-# Algorithmic bytes per nucleotide of one launch of the fused step kernel:
-# FP64 body state R, u, V, L read (96) and written (96), the bead's record in
-# the bucket-sorted copy read once (16), the new record, bucket key and slot
-# written (16 + 4 + 4).
-STEP_KERNEL_BYTES_PER_NT = 96 + 96 + 16 + 16 + 4 + 4
+# Algorithmic bytes per nucleotide of one launch of each kernel (every byte
+# the kernel must move once; see the design doc for the derivation):
+KERNEL_BYTES_PER_NT = {
+    # R, u, V, L read (96) and written (96); excluded-volume force read (16);
+    # bead record (16) and cell (16) written; bucket key and slot (4 + 4)
+    "step": 96 + 96 + 16 + 16 + 16 + 4 + 4,
+    # own sorted record and info (16 + 16); every record read once as a
+    # candidate (16); force written (16)
+    "excl": 16 + 16 + 16 + 16,
+    # key, slot, start[key] (12); record and cell read (32); sorted record
+    # and info written (32); histogram entry cleared (4)
+    "scatter": 12 + 32 + 32 + 4,
+}
+SCAN_BYTES_PER_KEY = 4 + 4 + 4  # histogram read by both passes, offsets written
+KERNEL_SOURCES = ("paper_1608_03722_amd/csrc/dsdna_kernels.hip", "paper_1608_03722_amd/csrc/dsdna_dev.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_1mbp_traffic.json")
 
 
 def log(msg):
@@ -57,7 +71,7 @@ def _build_workload(name):
     import synth
     if name == "1mbp":
         cfg = synth.config_1mbp(seed=0)
-        desc = "1 Mbp linear dsDNA, random-walk helix, periodic cube at 2% bead volume fraction"
+        desc = "1 Mbp linear dsDNA (2e6 nucleotides), random-walk helix, periodic cube at 2% bead volume fraction"
     elif name == "100bp":
         cfg = synth.config_100bp()
         desc = "100 bp ideal B-helix, open 200 sigma box"
@@ -66,13 +80,45 @@ def _build_workload(name):
         desc = "10 kbp ideal helix, periodic cube at 1% bead volume fraction"
     elif name == "replicas":
         cfg = synth.config_tethered_replicas()
-        desc = "256 tethered replicas 500-5000 bp, pulled, 64 under torque"
+        desc = "256 tethered replicas 500-5000 bp, pulled 0.05-20 pN, 64 under end torque"
     elif name == "denat":
         cfg = synth.config_denaturation()
-        desc = "64 x 2 kbp, K2 scaled 0.5-1.0, ssDNA rule"
+        desc = "64 x 2 kbp, base-pair attraction scaled 0.5-1.0, single-strand rule"
     else:
         raise SystemExit("unknown config " + name)
     return cfg, desc
+
+
+def subset(cfg, r):
+    """Replica r of a multi-replica config as a config of its own."""
+    off = 2 * int(np.sum(cfg["n_bp"][:r]))
+    n = 2 * int(cfg["n_bp"][r])
+    out = {"n_bp": cfg["n_bp"][r:r + 1], "bead": cfg["bead"][off:off + n], "patch": cfg["patch"][off:off + n]}
+    for k in ("box", "periodic", "pull", "torque", "tether", "wall_z", "k2_scale"):
+        if k in cfg:
+            out[k] = cfg[k][r:r + 1]
+    return out
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the step kernel from the committed counter
+    summary, if it was taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != source_digest():
+        return None
+    return t.get("bytes_per_launch")
 
 
 def cpu_baseline(cfg, steps, seed=0):
@@ -94,6 +140,38 @@ def cpu_baseline(cfg, steps, seed=0):
     return S.n_nt * steps / dt, dt
 
 
+def timed_steps(D, sim, steps, sync):
+    sync()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sync()
+    return time.perf_counter() - t0
+
+
+def batched_vs_single(D, sync, steps, graph_steps):
+    """256-replica tethered workload: one batched context against one context
+    per replica run one after another, same steps and parameters."""
+    cfg, desc = workload("replicas")
+    n_nt = int(2 * np.sum(cfg["n_bp"]))
+    prm = D.dsdna_default_params(seed=0, graph_steps=graph_steps)
+    sim = D.DsDNA(cfg, prm, device=0)
+    sim.thermalize(1.0, 0)
+    sim.step(steps)
+    t_b = timed_steps(D, sim, steps, sync)
+    sim.close()
+    t_s = 0.0
+    for r in range(len(cfg["n_bp"])):
+        one = D.DsDNA(subset(cfg, r), prm, device=0)
+        one.thermalize(1.0, 0)
+        one.step(steps)
+        t_s += timed_steps(D, one, steps, sync)
+        one.close()
+    v_b, v_s = n_nt * steps / t_b, n_nt * steps / t_s
+    log("replicas: batched %.4g, one context per replica %.4g nt-steps/s" % (v_b, v_s))
+    return {"workload": desc, "n_nt": n_nt, "steps": steps, "batched": v_b, "single": v_s,
+            "unit": "nucleotide-timesteps/s", "speedup": v_b / v_s}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,14 +182,16 @@ def main():
     ap.add_argument("--hash-log2", type=int, default=0)
     ap.add_argument("--graph-steps", type=int, default=50)
     ap.add_argument("--profile-steps", type=int, default=200)
-    ap.add_argument("--cpu-steps", type=int, default=5)
+    ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--replica-steps", type=int, default=200)
+    ap.add_argument("--no-replicas", action="store_true")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: there is no multi-GPU path in this library "
+              "(DESIGN.md describes how the step would shard)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -120,7 +200,7 @@ def main():
     t0 = time.perf_counter()
     cfg, desc = workload(args.config)
     n_nt = int(2 * np.sum(cfg["n_bp"]))
-    log("workload %s: %d nucleotides, built in %.1f s" % (args.config, n_nt, time.perf_counter() - t0))
+    log("workload %s: %d nucleotides, ready in %.1f s" % (args.config, n_nt, time.perf_counter() - t0))
 
     torch.cuda.init()
     dev = torch.device("cuda:0")
@@ -165,26 +245,40 @@ def main():
     ms_step = 1e3 * elapsed / args.steps
     log("timed %d steps in %.3f s: %.4g nt-steps/s" % (args.steps, elapsed, value))
 
-    # per-kernel durations with HIP events around every launch (same stream)
+    # per-kernel durations with HIP events around every launch, on the
+    # stream the kernels run on
     prof = sim.profile(args.profile_steps)
     log("kernel means (ms): %s" % {k: round(v, 5) for k, v in prof.items()})
-    achieved = STEP_KERNEL_BYTES_PER_NT * n_nt / (prof["step"] * 1e-3) / 1e9
+    kernels = {}
+    for k, ms in prof.items():
+        bpn = KERNEL_BYTES_PER_NT.get(k)
+        nbytes = bpn * n_nt if bpn is not None else SCAN_BYTES_PER_KEY * nb
+        kernels[k] = {"ms": round(ms, 5), "bytes": int(nbytes), "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+    dom = max(("step", "excl"), key=lambda k: prof[k])
+    achieved = kernels[dom]["bytes"] / (prof[dom] * 1e-3) / 1e9
+    traffic = measured_traffic() if (dom == "step" and args.config == "1mbp") else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_step", "bytes_per_nt": STEP_KERNEL_BYTES_PER_NT,
-            "kernel_ms": {k: round(v, 5) for k, v in prof.items()}}
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "k_step<float>" if dom == "step" else "k_excl<float>",
+            "bytes_per_nt": KERNEL_BYTES_PER_NT[dom], "kernels": kernels}
+    sim.close()
+
+    batch = None
+    if not args.no_replicas and args.config == "1mbp":
+        batch = batched_vs_single(D, torch.cuda.synchronize, args.replica_steps, args.graph_steps)
 
     cpu = None
     if not args.no_cpu:
         log("oracle baseline: %d steps of the same workload on one host core" % args.cpu_steps)
         v, dt = cpu_baseline(cfg, args.cpu_steps)
         cpu = {"value": v, "unit": "nucleotide-timesteps/s", "cores": 1, "kind": "oracle",
-               "sample": "%d steps of the full %d-nucleotide workload (%.1f s)" % (args.cpu_steps, n_nt, dt)}
+               "sample": "%d steps of the full %d-nucleotide workload, one thread (%.1f s)"
+                         % (args.cpu_steps, n_nt, dt)}
         log("oracle: %.4g nt-steps/s" % v)
 
     out = {
-        "metric": "nucleotide-timesteps/s at 1 Mbp (1 GPU)" if args.config == "1mbp"
-        else "nucleotide-timesteps/s (%s)" % args.config,
+        "metric": "nucleotide-timesteps/s at 1 Mbp (1 GPU) + % peak HBM; batched vs single"
+        if args.config == "1mbp" else "nucleotide-timesteps/s (%s)" % args.config,
         "value": value,
         "unit": "nucleotide-timesteps/s",
         "n_gpus": 1,
@@ -200,9 +294,9 @@ def main():
                    "forces": "f32", "state": "f64", "cell_size": h, "buckets": nb,
                    "graph_steps": args.graph_steps, "parallelism": "single GPU"},
         "roofline": roof,
+        "batched_vs_single": batch,
         "cpu_baseline": cpu,
     }
-    sim.close()
     print(json.dumps(out), flush=True)
 
 

@@ -105,8 +105,10 @@ typedef struct {
                                        inside bubbles > 2 bp (Sec. 5)        */
     int32_t hb_depth_convention;    /* 0: H-bond prefactor K2/(2(r0-rc)^2)
                                        as printed; 1: K2/(r0-rc)^2           */
-    double cell_size;               /* cell edge; 0 selects the default      */
-    int32_t hash_log2;              /* log2 of cell-hash buckets; 0 = auto   */
+    double cell_size;               /* cell edge; 0: 1.001 x largest cutoff  */
+    int32_t hash_log2;              /* log2 of cell-hash buckets; 0: the
+                                       power of two >= 4 x nucleotides,
+                                       within [12, 24]                      */
     int32_t graph_steps;            /* steps per captured HIP graph; 0 = off */
 } dsdna_params;
 

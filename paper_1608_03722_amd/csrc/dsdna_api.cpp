@@ -177,7 +177,8 @@ static double rc_max(const dsdna_ctx *c) { return TWO_16 * std::max(c->prm.sig_s
 
 static double cell_edge(const dsdna_ctx *c)
 {
-    return c->prm.cell_size > 0.0 ? c->prm.cell_size : 1.3;
+    // default: just above the largest cutoff (fewest candidates per bead)
+    return c->prm.cell_size > 0.0 ? c->prm.cell_size : rc_max(c) * 1.001;
 }
 
 // The 27 cells around any cell must hash to 27 distinct buckets, also across
@@ -239,7 +240,9 @@ static dsdna_status configure_grid(dsdna_ctx *c)
     }
     int lg = c->prm.hash_log2;
     if (lg <= 0) {
-        int64_t want = std::max<int64_t>(SCAN_CHUNK, 2 * c->N);
+        // about four buckets per bead: few records of far cells share the
+        // buckets of a bead's neighbourhood
+        int64_t want = std::max<int64_t>(SCAN_CHUNK, 4 * c->N);
         lg = 12;
         while ((int64_t(1) << lg) < want && lg < 24) ++lg;
     }

@@ -48,7 +48,10 @@ typedef enum {
     DSDNA_EDEVICE = 3,  /* HIP runtime error                                 */
     DSDNA_EBOND = 4,    /* backbone bond reached R0: the FENE energy is
                            infinite (Appendix A, U_bb for r >= R0)           */
-    DSDNA_ENAN = 5,     /* non-finite position or orientation                */
+    DSDNA_ENAN = 5,     /* non-finite position or orientation, or an
+                           excluded-volume contact force beyond the exact
+                           accumulation range (2^25 with FP32 forces, 2^23
+                           with FP64 forces: overlapping beads)             */
     DSDNA_ESTATE = 6,   /* call out of order                                 */
     DSDNA_EWALL = 7,    /* a bead of a tethered replica reached its wall     */
     DSDNA_EDOMAIN = 8   /* a bead left the representable coordinate range   */

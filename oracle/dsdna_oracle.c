@@ -14,6 +14,15 @@
  * the paper is silent the reading used is named in the comment (readings are
  * listed with their reasons in the design notes of the repository).
  *
+ * Pins: every function is checked by the tests against closed forms, finite
+ * differences of its own energy, invariants, brute force or a library
+ * routine.  Parity unpinned: whether the readings of what the paper leaves
+ * open (unit masses, friction 1, the noise distribution, the hydrogen-bond
+ * depth convention, the planarity triple, the bubble rule, the tether and
+ * the placement of the pulling force) are the ones of the authors' own
+ * input scripts, which are not published; the paper gives no worked
+ * numerical example of a force or a step.
+ *
  * Conventions
  *   - reduced units of Table 3: sigma = 1 nm, epsilon = k_B T, tau_Br.
  *   - replica r holds n_bp[r] base pairs; nucleotide (strand s, bp n) of

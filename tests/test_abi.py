@@ -62,16 +62,32 @@ def test_params_struct_layout_matches_c(D, tmp_path):
     assert (nt, ne, nk) == (D.NTERMS, D.NENERGY, len(D.KERNELS))
 
 
+def _golden(name):
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    out = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            key, val = line.split()[:2]
+            out[key] = float(val)
+    return out
+
+
 def test_default_params_are_table2(D):
+    """Library defaults equal Table 2 and the time step of Appendix A (the
+    printed values, tests/golden/table2_parameters.txt), plus the readings of
+    what the paper leaves open (cross-strand sigma 0.5, bead-patch distance
+    0.5)."""
     import math
+    g = _golden("table2_parameters.txt")
+    u = _golden("table3_units.txt")
     p = D.dsdna_default_params()
-    assert (p.K1, p.R0, p.eps_bb, p.sig_bb) == (30.0, 0.6825, 1.0, 0.443)
-    assert (p.K2, p.r0_hb, p.rc_hb) == (6.0, 0.0, 0.3)
-    assert (p.eps, p.sig_s, p.sig_x) == (1.0, 1.0, 0.5)
-    assert p.K3 == 50.0 and p.d_dih == pytest.approx(math.radians(-144.0))
-    assert (p.K4, p.lam, p.r0_m) == (30.0, 8.0, 0.34)
-    assert p.K5 == 200.0 and p.a0 == pytest.approx(math.pi / 2)
-    assert p.K6 == 52.0 and p.ell == 0.5 and p.dt == 0.005
+    for k in ("K1", "R0", "eps_bb", "sig_bb", "K2", "r0_hb", "rc_hb", "eps", "sig_s", "K3", "K4", "lam", "r0_m",
+              "K5", "K6"):
+        assert getattr(p, k) == g[k], k
+    assert p.d_dih == pytest.approx(math.radians(g["d_dih_deg"]), abs=1e-15)
+    assert p.a0 == pytest.approx(math.radians(g["a0_deg"]), abs=1e-15)
+    assert p.dt == u["dt_tau"]
+    assert p.sig_x == 0.5 and p.ell == 0.5
 
 
 def test_argument_checks_without_device(D):

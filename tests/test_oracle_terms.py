@@ -393,3 +393,30 @@ def test_bubble_statistics(orc):
     frac, hist = orc.bubbles(op, nhist=8)
     assert frac == pytest.approx(8 / 20)
     assert hist[1] == 2 and hist[2] == 1 and hist[4] == 1 and hist.sum() == 4
+
+
+def _golden(name):
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    out = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            key, val = line.split()[:2]
+            out[key] = float(val)
+    return out
+
+
+def test_oracle_defaults_are_table2(orc):
+    """Oracle defaults equal the values printed in Table 2 and Appendix A
+    (tests/golden), and the pN conversion of the input generator is Table 3's
+    force unit."""
+    g = _golden("table2_parameters.txt")
+    u = _golden("table3_units.txt")
+    P = orc.default_params()
+    for k in ("K1", "R0", "eps_bb", "sig_bb", "K2", "r0_hb", "rc_hb", "eps", "sig_s", "K3", "K4", "lam", "r0_m",
+              "K5", "K6"):
+        assert getattr(P, k) == g[k], k
+    assert P.d_dih == pytest.approx(math.radians(g["d_dih_deg"]), abs=1e-15)
+    assert P.a0 == pytest.approx(math.radians(g["a0_deg"]), abs=1e-15)
+    assert P.dt == u["dt_tau"]
+    assert synth.PN_PER_UNIT == pytest.approx(u["force_N"] * 1e12)

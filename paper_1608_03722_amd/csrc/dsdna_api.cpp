@@ -105,7 +105,7 @@ static void free_state(dsdna_ctx *c)
     }
     dfree(b.Vf); dfree(b.Lf); dfree(b.Fb); dfree(b.Fp);
     dfree(b.rec); dfree(b.rcell); dfree(b.key); dfree(b.slot); dfree(b.srec); dfree(b.sinfo);
-    dfree(b.fex); dfree(b.eex);
+    dfree(b.fex); dfree(b.tflag); dfree(b.eex);
     dfree(b.rep); dfree(b.tiles); dfree(b.eacc); dfree(b.open);
     dfree(b.diag_fb); dfree(b.diag_fp);
     Ctl *ctl = b.ctl;
@@ -293,6 +293,18 @@ static dsdna_status configure_grid(dsdna_ctx *c)
     return DSDNA_OK;
 }
 
+// Clear the cell histogram and the sparse excluded-volume accumulators (a
+// halted step or evaluation may leave entries behind).  Not used during graph
+// capture.
+static dsdna_status clear_accumulators(dsdna_ctx *c)
+{
+    Bufs &b = c->a.b;
+    HIPCHK(c, hipMemsetAsync(b.count, 0, sizeof(int32_t) * (size_t)c->a.g.nbucket, c->stream));
+    HIPCHK(c, hipMemsetAsync(b.fex, 0, sizeof(unsigned long long) * 4 * (size_t)c->N, c->stream));
+    HIPCHK(c, hipMemsetAsync(b.tflag, 0, sizeof(uint32_t) * (size_t)c->a.n_tiles, c->stream));
+    return DSDNA_OK;
+}
+
 static dsdna_status upload_reps(dsdna_ctx *c)
 {
     HIPCHK(c, hipMemcpyAsync(c->a.b.rep, c->rep_h.data(), sizeof(RepInfo) * c->n_rep, hipMemcpyHostToDevice,
@@ -385,8 +397,8 @@ static dsdna_status upload_full_state(dsdna_ctx *c, const double *R, const doubl
     }
     HIPCHK(c, hipMemcpyAsync(b.Vf, b.V[0], sizeof(double) * 3 * c->N, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(b.Lf, b.L[0], sizeof(double) * 3 * c->N, hipMemcpyDeviceToDevice, c->stream));
-    // a halted step may have left histogram entries behind
-    HIPCHK(c, hipMemsetAsync(b.count, 0, sizeof(int32_t) * (size_t)c->a.g.nbucket, c->stream));
+    // a halted step may have left histogram or accumulator entries behind
+    if ((st = clear_accumulators(c))) return st;
     if ((st = write_ctl(c, step, 0))) return st;
     c->full_par = 0;
     c->full_step = step;
@@ -406,8 +418,9 @@ static dsdna_status to_full(dsdna_ctx *c)
         HIPCHK(c, hipMemcpyAsync(b.V[p], b.Vf, sizeof(double) * 3 * c->N, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(b.L[p], b.Lf, sizeof(double) * 3 * c->N, hipMemcpyDeviceToDevice, c->stream));
     }
-    HIPCHK(c, hipMemsetAsync(b.count, 0, sizeof(int32_t) * (size_t)c->a.g.nbucket, c->stream));
-    dsdna_status st = write_ctl(c, c->full_step, p);
+    dsdna_status st = clear_accumulators(c);
+    if (st) return st;
+    st = write_ctl(c, c->full_step, p);
     if (st) return st;
     c->binned_buf = -1;
     c->phase = PH_FULL;
@@ -568,8 +581,8 @@ static dsdna_status run_diag(dsdna_ctx *c, uint32_t mask)
         Ctl clr = h;
         clr.code = 0;
         if ((st = copy(c, c->a.b.ctl, &clr, sizeof clr, hipMemcpyHostToDevice))) return st;
-        // the failed evaluation may have left histogram entries behind
-        HIPCHK(c, hipMemsetAsync(c->a.b.count, 0, sizeof(int32_t) * (size_t)c->a.g.nbucket, c->stream));
+        // the failed evaluation may have left histogram or accumulator entries
+        if ((st = clear_accumulators(c))) return st;
         c->binned_buf = -1;
         return fail(c, code, "invalid state: error %d at nucleotide %lld", (int)code, (long long)h.err_id);
     }
@@ -682,6 +695,7 @@ dsdna_status dsdna_set_topology(dsdna_ctx *c, int32_t n_rep, const int32_t *n_bp
             ri.len[k] = 1.0;
             ri.inv_len[k] = 1.0;
         }
+        ri.tile0 = (int32_t)c->tiles_h.size();
         for (int n0 = 0; n0 < n_bp[r]; n0 += TILE_BP) c->tiles_h.push_back(Tile{r, n0});
         o += 2 * (int64_t)n_bp[r];
     }
@@ -700,11 +714,8 @@ dsdna_status dsdna_set_topology(dsdna_ctx *c, int32_t n_rep, const int32_t *n_bp
     HIPCHK(c, dalloc(&b.key, (size_t)N)); HIPCHK(c, dalloc(&b.slot, (size_t)N));
     HIPCHK(c, dalloc(&b.rec, (size_t)N)); HIPCHK(c, dalloc(&b.rcell, (size_t)N));
     HIPCHK(c, dalloc(&b.srec, (size_t)N)); HIPCHK(c, dalloc(&b.sinfo, (size_t)N));
-    {
-        double *fex = nullptr;
-        HIPCHK(c, dalloc(&fex, 4 * (size_t)N));  // double4 per nt (float4 in FP32 mode)
-        b.fex = fex;
-    }
+    HIPCHK(c, dalloc(&b.fex, 4 * (size_t)N));
+    HIPCHK(c, dalloc(&b.tflag, (size_t)a.n_tiles));
     HIPCHK(c, dalloc(&b.eex, (size_t)N));
     HIPCHK(c, dalloc(&b.rep, (size_t)n_rep));
     HIPCHK(c, dalloc(&b.tiles, c->tiles_h.size()));

@@ -55,7 +55,7 @@ struct RepInfo {
     double pull[3], torque[3];
     double wall_z, k2_scale;
     int32_t ncell[3];   // cells per periodic dim (0 for open dims)
-    int32_t pad;
+    int32_t tile0;      // index of the replica's first tile
     double inv_h[3];    // cells per unit length per dim
     float qlen[3];      // length of one fixed-point coordinate unit
     int32_t pad2;
@@ -110,7 +110,11 @@ struct Bufs {
     BeadRec *srec;                      // records in key order (counting sort)
     int4 *sinfo;                        // per sorted record: nucleotide, cell x, y, z
     int32_t *count, *start, *bsum;      // per key (start: nbucket + 1)
-    void *fex;                          // excluded-volume force per nt: float4 or double4
+    // excluded-volume force per nt as exact fixed-point sums (x, y, z, unused;
+    // units FIX32_UNIT or FIX64_UNIT), zero except beads with contacts;
+    // consumers read and clear the entries of flagged tiles
+    unsigned long long *fex;
+    uint32_t *tflag;                    // per tile: some fex entry of the tile is nonzero
     double *eex;                        // excluded-volume energy per nt (diagnostics)
     RepInfo *rep;
     Tile *tiles;
@@ -121,6 +125,11 @@ struct Bufs {
 };
 
 enum StepMode : int { MODE_NORMAL = 0, MODE_FIRST = 1, MODE_FROM_FORCES = 2 };
+
+// Units of the fixed-point excluded-volume sums: 2^24 per force unit with
+// FP32 forces, 2^36 with FP64 forces.
+constexpr double FIX32_UNIT = 16777216.0;
+constexpr double FIX64_UNIT = 68719476736.0;
 
 // Everything the kernels read that does not change from launch to launch.
 // The host keeps a copy in device memory and passes its address, so the

@@ -256,6 +256,17 @@ __device__ __forceinline__ void insert_bead(const StepArgs &a, const RepInfo &ri
     a.b.slot[i] = atomicAdd(&a.b.count[key], 1);
 }
 
+// ------------------------------------------------------------------- tiles
+
+__device__ __forceinline__ int tile_index(int n_tiles, int n_tiles_pad)
+{
+    // consecutive workgroups go to the 8 XCDs in turn; give each XCD a
+    // contiguous run of tiles so chain neighbours share an L2
+    const int per = n_tiles_pad >> 3;
+    const int b = blockIdx.x;
+    return (b & 7) * per + (b >> 3);
+}
+
 // ------------------------------------------------------------- tile stage
 
 template <typename real>
@@ -323,16 +334,20 @@ __device__ __forceinline__ void stage_site(const StepArgs &a, TileLds<real> &S, 
     S.sP[st.l][0] = p.x; S.sP[st.l][1] = p.y; S.sP[st.l][2] = p.z;
 }
 
-// Excluded-volume force of nucleotide i computed by k_excl.
+// Excluded-volume force of nucleotide i accumulated by k_excl (only read
+// when its tile is flagged); the entry is cleared for the next step.
 template <typename real>
-__device__ __forceinline__ V3<real> load_fex(const StepArgs &a, int64_t i)
+__device__ __forceinline__ V3<real> take_fex(const StepArgs &a, int64_t i)
 {
-    if (sizeof(real) == sizeof(double)) {
-        const double4 w = reinterpret_cast<const double4 *>(a.b.fex)[i];
-        return v3<real>((real)w.x, (real)w.y, (real)w.z);
+    unsigned long long *f = a.b.fex + 4 * i;
+    const long long x = (long long)f[0], y = (long long)f[1], z = (long long)f[2];
+    if (x | y | z) {
+        f[0] = 0ull;
+        f[1] = 0ull;
+        f[2] = 0ull;
     }
-    const float4 w = reinterpret_cast<const float4 *>(a.b.fex)[i];
-    return v3<real>((real)w.x, (real)w.y, (real)w.z);
+    const double s = 1.0 / (sizeof(real) == sizeof(double) ? FIX64_UNIT : FIX32_UNIT);
+    return v3<real>((real)((double)x * s), (real)((double)y * s), (real)((double)z * s));
 }
 
 // All conservative and external site forces of the calling thread's
@@ -349,6 +364,9 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
     const Phys &ph = a.ph;
     const int nbp = ri.n_bp;
     __syncthreads();
+    // every thread has read (and consumed) the tile's accumulator flag
+    // before this barrier
+    if (t == 0) a.b.tflag[tile_index(a.n_tiles, a.n_tiles_pad)] = 0u;
 
     // --- hydrogen bonds and open flags (truncated harmonic between the
     //     patches of a base pair, Appendix A)
@@ -560,16 +578,6 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
     return out;
 }
 
-// ------------------------------------------------------------------- tiles
-
-__device__ __forceinline__ int tile_index(int n_tiles, int n_tiles_pad)
-{
-    // consecutive workgroups go to the 8 XCDs in turn; give each XCD a
-    // contiguous run of tiles so chain neighbours share an L2
-    const int per = n_tiles_pad >> 3;
-    const int b = blockIdx.x;
-    return (b & 7) * per + (b >> 3);
-}
 
 // Rotation of the axis of a free linear rotor by th about unit k:
 // u cos th + (k x u) sin th + k (k.u)(1 - cos th).  cos and sin come from
@@ -616,10 +624,11 @@ __global__ void __launch_bounds__(WG_THREADS, 4) k_step(const StepArgs *__restri
     D3 R = site.R, u = site.u;
     D3 V = v3(0.0, 0.0, 0.0), L = V;
     V3<real> fexv = v3<real>(0, 0, 0);
+    const bool flagged = mode != MODE_FROM_FORCES && a.b.tflag[tix] != 0u;
     if (own) {
         V = ld3(a.b.V[cur], N, i);
         L = ld3(a.b.L[cur], N, i);
-        if (mode != MODE_FROM_FORCES) fexv = load_fex<real>(a, i);
+        if (flagged) fexv = take_fex<real>(a, i);
     }
     // the thread's noise numbers while the loads are in flight
     real xi[6] = {0, 0, 0, 0, 0, 0};
@@ -729,31 +738,43 @@ __global__ void __launch_bounds__(256) k_bin(const StepArgs *__restrict__ A, int
 
 // ------------------------------------------------------- excluded volume
 
-// Order-independent accumulation of force components, so that a bead's
-// total does not depend on the order of its contacts in the cell list.
-// FP32 forces: each contribution is rounded to a multiple of 2^-24 (adding
-// and removing 1.5 * 2^28 in FP64 does exactly that for |f| < 2^27) and FP64
-// sums of such values are exact while |sum| < 2^29.  FP64 forces: 64-bit
-// integer sums in 2^-36 units.  A contact force beyond the limits
-// (overlapping beads; at most 16 such contacts keep the sums in range) is
-// reported as an error.
-constexpr double FIX_ROUND = 402653184.0;         // 1.5 * 2^28
+// Excluded-volume sums are exact and order independent: every contact force
+// component is rounded to the fixed-point grid (FIX32_UNIT or FIX64_UNIT per
+// force unit) and summed as a 64-bit integer, so a bead's total does not
+// depend on which thread evaluated a pair or in what order.  A contact force
+// beyond the limits (overlapping beads; at most 16 such contacts keep the
+// sums in range) is reported as an error.
 constexpr double PAIR_FORCE_MAX_F32 = 33554432.0;  // 2^25 (|fx| + |fy| + |fz|)
 constexpr double PAIR_FORCE_MAX_F64 = 8388608.0;   // 2^23
-constexpr double FIX64_UNIT = 68719476736.0;       // 2^36
 
-__device__ __forceinline__ double fix_round(double f) { return (f + FIX_ROUND) - FIX_ROUND; }
+__device__ __forceinline__ int tile_of(const RepInfo &ri, int64_t j)
+{
+    return ri.tile0 + (int)((j - ri.off) >> 1) / TILE_BP;
+}
 
-// Excluded volume (WCA, steric/ghost rule of Sec. 2) of every bead, one
-// thread per record of the key-sorted cell list, so the lanes of a wave hold
-// beads of neighbouring cells and read overlapping candidate ranges.  A bead
+// Add a fixed-point force to nucleotide j and flag its tile.
+__device__ __forceinline__ void fex_add(const StepArgs &a, const RepInfo &ri, int64_t j, long long fx, long long fy,
+                                        long long fz)
+{
+    unsigned long long *f = a.b.fex + 4 * j;
+    if (fx) atomicAdd(f, (unsigned long long)fx);
+    if (fy) atomicAdd(f + 1, (unsigned long long)fy);
+    if (fz) atomicAdd(f + 2, (unsigned long long)fz);
+    a.b.tflag[tile_of(ri, j)] = 1u;  // every writer stores the same value
+}
+
+// Excluded volume (WCA, steric/ghost rule of Sec. 2), one thread per record
+// of the key-sorted cell list, so the lanes of a wave hold beads of
+// neighbouring cells and read overlapping candidate ranges.  A bead
 // interacts with every bead of the other strand (sigma_x) and, if steric,
-// with the steric beads of its own strand (sigma_s).  Candidates come from
-// the 27 cells around the bead's cell: nine rows of three consecutive
-// buckets, walked as one stream.  With FP32 forces the distance comes from
-// the fixed-point coordinates; with FP64 forces those only pre-select, and
-// the distance is taken from the FP64 positions (minimum image along
-// periodic edges).
+// with the steric beads of its own strand (sigma_s).  Each pair is evaluated
+// once (half stencil): the thread of a bead scans the later records of its
+// own bucket, the next cell of its row, the row above (dy = +1) and the three
+// rows of the next layer (dz = +1), as one stream of five record ranges.
+// Contacts are rare, so forces go to the sparse accumulators by atomics.
+// With FP32 forces the distance comes from the fixed-point coordinates; with
+// FP64 forces those only pre-select, and the distance is taken from the FP64
+// positions (minimum image along periodic edges).
 template <typename real, bool energy, bool any_open>
 __global__ void __launch_bounds__(256) k_excl(const StepArgs *__restrict__ A, const BeadRec *__restrict__ srec,
                                               const int4 *__restrict__ sinfo, const int *__restrict__ start, int which)
@@ -765,6 +786,7 @@ __global__ void __launch_bounds__(256) k_excl(const StepArgs *__restrict__ A, co
     const int p = blk * (int)blockDim.x + (int)threadIdx.x;
     if (p >= a.n_nt) return;
     constexpr bool F64 = sizeof(real) == sizeof(double);
+    const double unit = F64 ? FIX64_UNIT : FIX32_UNIT;
     const Phys &ph = a.ph;
     const BeadRec me = srec[p];
     const int4 info = sinfo[p];
@@ -780,8 +802,6 @@ __global__ void __launch_bounds__(256) k_excl(const StepArgs *__restrict__ A, co
     const int64_t N = a.n_nt;
     const int buf = which < 0 ? a.b.ctl->par : which;
     const double *Rc = a.b.R[buf], *uc = a.b.u[buf];
-    D3 bw = v3(0.0, 0.0, 0.0);
-    if (F64) bw = bead_of(ld3(Rc, N, i), ld3(uc, N, i), ph.db);
     const bool px = ri.flags & REP_PER_X, py = ri.flags & REP_PER_Y, pz = ri.flags & REP_PER_Z;
     // any_open: some replica has an open edge
     const bool open_any = any_open && !(px && py && pz);
@@ -790,8 +810,7 @@ __global__ void __launch_bounds__(256) k_excl(const StepArgs *__restrict__ A, co
     const float rcx2 = (float)(F64 ? (ph.rc_x + 1e-3) * (ph.rc_x + 1e-3) : ph.rc_x * ph.rc_x);
     const real sig_s2 = (real)(ph.sig_s * ph.sig_s), sig_x2 = (real)(ph.sig_x * ph.sig_x);
     const real e24 = (real)(24.0 * ph.eps);
-    double ax = 0.0, ay = 0.0, az = 0.0;   // FP32 forces
-    long long lx = 0, ly = 0, lz = 0;     // FP64 forces
+    long long ox = 0, oy = 0, oz = 0;  // this bead's own sum
     double e_excl = 0.0;
     bool overflow = false;
 
@@ -806,20 +825,19 @@ __global__ void __launch_bounds__(256) k_excl(const StepArgs *__restrict__ A, co
         const float r2f = dx * dx + dy * dy + dz * dz;
         if (!(valid && r2f < (same ? rcs2 : rcx2) && ((accept >> ot) & 1u) && (o.tag >> 2) == rep && q != p))
             return;
+        const int4 oinfo = sinfo[q];
         // open edges: the fixed-point difference is exact only modulo 2^32
         // units, so a record of a far cell that shares a bucket with a
         // neighbour cell is rejected by its cell coordinates
-        int4 oinfo = make_int4(0, 0, 0, 0);
-        if (F64 || any_open) oinfo = sinfo[q];
         if (any_open && open_any &&
             ((!px && abs(oinfo.y - c[0]) > 1) || (!py && abs(oinfo.z - c[1]) > 1) || (!pz && abs(oinfo.w - c[2]) > 1)))
             return;
+        const int64_t j = oinfo.x;
         V3<real> d = v3<real>(dx, dy, dz);
         real r2 = r2f;
         D3 d64 = v3(0.0, 0.0, 0.0);
         if (F64) {
-            const int j = oinfo.x;
-            d64 = bead_of(ld3(Rc, N, j), ld3(uc, N, j), ph.db) - bw;
+            d64 = bead_of(ld3(Rc, N, j), ld3(uc, N, j), ph.db) - bead_of(ld3(Rc, N, i), ld3(uc, N, i), ph.db);
             if (px) d64.x = __fma_rn(-ri.len[0], rint(d64.x * ri.inv_len[0]), d64.x);
             if (py) d64.y = __fma_rn(-ri.len[1], rint(d64.y * ri.inv_len[1]), d64.y);
             if (pz) d64.z = __fma_rn(-ri.len[2], rint(d64.z * ri.inv_len[2]), d64.z);
@@ -836,53 +854,58 @@ __global__ void __launch_bounds__(256) k_excl(const StepArgs *__restrict__ A, co
             overflow = true;
             return;
         }
-        // force on this bead: -g d (repulsive)
-        if (F64) {
-            lx -= __double2ll_rn((double)fx * FIX64_UNIT);
-            ly -= __double2ll_rn((double)fy * FIX64_UNIT);
-            lz -= __double2ll_rn((double)fz * FIX64_UNIT);
-        } else {
-            ax -= fix_round((double)fx);
-            ay -= fix_round((double)fy);
-            az -= fix_round((double)fz);
-        }
+        // repulsive: -g d on this bead, +g d on the partner
+        const long long lx = __double2ll_rn((double)fx * unit);
+        const long long ly = __double2ll_rn((double)fy * unit);
+        const long long lz = __double2ll_rn((double)fz * unit);
+        ox -= lx;
+        oy -= ly;
+        oz -= lz;
+        fex_add(a, ri, j, lx, ly, lz);
         if (energy) {
             const double s2 = (same ? ph.sig_s * ph.sig_s : ph.sig_x * ph.sig_x) / (F64 ? dot(d64, d64) : (double)r2);
             const double s6 = s2 * s2 * s2;
-            e_excl += 0.5 * 4.0 * ph.eps * (s6 * s6 - s6 + 0.25);
+            e_excl += 4.0 * ph.eps * (s6 * s6 - s6 + 0.25);
         }
     };
 
-    // nine rows of three cells (dz, dy; cx-1..cx+1): three consecutive
-    // buckets each unless the row wraps (periodic x or bucket index)
+    // rows of three cells (dz, dy; cx-1..cx+1) are three consecutive buckets
+    // unless the row wraps (periodic x or bucket index)
     const int ncx = ri.ncell[0], ncy = ri.ncell[1], ncz = ri.ncell[2];
-    const bool xwrap = px && (c[0] == 0 || c[0] == ncx - 1);
-    // stream position k of row q sits at k + sh[q] in the sorted records;
-    // pre[q] = first stream position of row q.  sh lives in LDS; the row of
-    // k < 127 is found by counting the bytes of the packed pre[1..8] that are
-    // <= k (one subtract per four rows, no borrow between bytes while
-    // k, pre < 128); larger k take the plain search.
-    __shared__ int s_sh[9][256];
-    __shared__ int s_pre[9][256];
+    auto wrap = [&](int v, int n, bool per_) { return per_ ? (v < 0 ? v + n : (v >= n ? v - n : v)) : v; };
+    // stream position k of range q sits at k + sh[q] in the sorted records;
+    // pre[q] = first stream position of range q.  Range 0: the rest of the
+    // own bucket and the next cell; ranges 1..4: rows (dy, dz) = (+1, 0),
+    // (-1, +1), (0, +1), (+1, +1).  The range of k < 127 is found by counting
+    // the bytes of the packed pre[1..4] that are <= k (no borrow between
+    // bytes while k, pre < 128); larger k take the plain search.
+    __shared__ int s_sh[5][256];
+    __shared__ int s_pre[5][256];
     const int t = threadIdx.x;
     int total = 0;
-    uint32_t wrapped = 0;  // bit q: row q wraps
-    uint32_t pk0 = 0, pk1 = 0;
+    uint32_t wrapped = 0;  // bit q: range q is walked cell by cell
+    uint32_t pk = 0;
+    const uint32_t kown = bucket_of(a.g, c[0], c[1], c[2], (int)rep);
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
-        int cy = c[1] + (q % 3) - 1, cz = c[2] + (q / 3) - 1;
-        if (py) cy = cy < 0 ? cy + ncy : (cy >= ncy ? cy - ncy : cy);
-        if (pz) cz = cz < 0 ? cz + ncz : (cz >= ncz ? cz - ncz : cz);
-        const uint32_t k0 = bucket_of(a.g, c[0] - 1, cy, cz, (int)rep);
-        const bool wr = xwrap || k0 + 2u > a.g.mask;
+    for (int q = 0; q < 5; ++q) {
+        int l0, h0;
+        bool wr;
+        if (q == 0) {
+            wr = (px && c[0] == ncx - 1) || kown + 1u > a.g.mask;
+            l0 = p + 1;
+            h0 = wr ? p + 1 : start[kown + 2];
+        } else {
+            const int dy = q == 1 ? 1 : q - 3, dz = q == 1 ? 0 : 1;
+            const int cy = wrap(c[1] + dy, ncy, py), cz = wrap(c[2] + dz, ncz, pz);
+            const uint32_t k0 = bucket_of(a.g, c[0] - 1, cy, cz, (int)rep);
+            wr = (px && (c[0] == 0 || c[0] == ncx - 1)) || k0 + 2u > a.g.mask;
+            l0 = wr ? 0 : start[k0];
+            h0 = wr ? 0 : start[k0 + 3];
+        }
         wrapped |= (uint32_t)wr << q;
-        const int l0 = wr ? 0 : start[k0];
-        const int h0 = wr ? 0 : start[k0 + 3];
         s_pre[q][t] = total;
         s_sh[q][t] = l0 - total;
-        const uint32_t pc = (uint32_t)min(total, 127);
-        if (q >= 1 && q <= 4) pk0 |= pc << (8 * (q - 1));
-        if (q >= 5) pk1 |= pc << (8 * (q - 5));
+        if (q >= 1) pk |= (uint32_t)min(total, 127) << (8 * (q - 1));
         total += h0 - l0;
     }
     // no barrier needed: each thread reads only its own LDS column
@@ -891,8 +914,10 @@ __global__ void __launch_bounds__(256) k_excl(const StepArgs *__restrict__ A, co
     // past the end are fetched again and ignored)
     auto locate = [&](int k) -> int {
         k = k < nfast ? k : nfast - 1;
-        const uint32_t kb = ((uint32_t)k | 0x80u) * 0x01010101u;
-        const int q = __popc((kb - pk0) & 0x80808080u) + __popc((kb - pk1) & 0x80808080u);
+        uint32_t kb = (uint32_t)k | 0x80u;
+        kb |= kb << 8;
+        kb |= kb << 16;
+        const int q = __popc((kb - pk) & 0x80808080u);
         return k + s_sh[q][t];
     };
     // software pipeline: the records of the next U entries are in flight
@@ -925,30 +950,29 @@ __global__ void __launch_bounds__(256) k_excl(const StepArgs *__restrict__ A, co
     }
     for (int k = nfast; k < total; ++k) {
         int q = 0;
-        for (int r = 1; r < 9; ++r) q = (k >= s_pre[r][t]) ? r : q;
+        for (int r = 1; r < 5; ++r) q = (k >= s_pre[r][t]) ? r : q;
         const int pq = k + s_sh[q][t];
         pair(srec[pq], pq, true);
     }
-    // rows that wrap: cell by cell (rare)
+    // ranges that wrap: cell by cell (rare)
 #pragma unroll 1
-    for (int q = 0; q < 9; ++q) {
+    for (int q = 0; q < 5; ++q) {
         if (!((wrapped >> q) & 1u)) continue;
-        int cy = c[1] + (q % 3) - 1, cz = c[2] + (q / 3) - 1;
-        if (py) cy = cy < 0 ? cy + ncy : (cy >= ncy ? cy - ncy : cy);
-        if (pz) cz = cz < 0 ? cz + ncz : (cz >= ncz ? cz - ncz : cz);
+        if (q == 0) {
+            for (int q2 = p + 1; q2 < start[kown + 1]; ++q2) pair(srec[q2], q2, true);
+            const uint32_t kb = bucket_of(a.g, wrap(c[0] + 1, ncx, px), c[1], c[2], (int)rep);
+            for (int q2 = start[kb]; q2 < start[kb + 1]; ++q2) pair(srec[q2], q2, true);
+            continue;
+        }
+        const int dy = q == 1 ? 1 : q - 3, dz = q == 1 ? 0 : 1;
+        const int cy = wrap(c[1] + dy, ncy, py), cz = wrap(c[2] + dz, ncz, pz);
         for (int dx = -1; dx <= 1; ++dx) {
-            int cx = c[0] + dx;
-            if (px) cx = cx < 0 ? cx + ncx : (cx >= ncx ? cx - ncx : cx);
-            const uint32_t kb = bucket_of(a.g, cx, cy, cz, (int)rep);
+            const uint32_t kb = bucket_of(a.g, wrap(c[0] + dx, ncx, px), cy, cz, (int)rep);
             for (int q2 = start[kb]; q2 < start[kb + 1]; ++q2) pair(srec[q2], q2, true);
         }
     }
     if (overflow) raise_error(a.b.ctl, DSDNA_ENAN, a.b.ctl->step, i);
-    if (F64)
-        reinterpret_cast<double4 *>(a.b.fex)[i] =
-            make_double4((double)lx / FIX64_UNIT, (double)ly / FIX64_UNIT, (double)lz / FIX64_UNIT, 0.0);
-    else
-        reinterpret_cast<float4 *>(a.b.fex)[i] = make_float4((float)ax, (float)ay, (float)az, 0.0f);
+    if (ox | oy | oz) fex_add(a, ri, i, ox, oy, oz);
     if (energy) a.b.eex[i] = e_excl;
 }
 
@@ -1106,7 +1130,8 @@ __global__ void __launch_bounds__(WG_THREADS) k_diag(const StepArgs *__restrict_
     const int64_t step = a.b.ctl->step;
     const StagedSite site = load_site(a, ri, tile.n0, which);
     const int s = threadIdx.x & 1, bl = threadIdx.x >> 1, n = threadIdx.x < TILE_NT ? tile.n0 + bl : ri.n_bp;
-    const V3<real> fexv = n < ri.n_bp ? load_fex<real>(a, site.i) : v3<real>(0, 0, 0);
+    const bool flagged = a.b.tflag[tix] != 0u;
+    const V3<real> fexv = (n < ri.n_bp && flagged) ? take_fex<real>(a, site.i) : v3<real>(0, 0, 0);
     stage_site(a, S, site);
     SiteForces<real> f = tile_forces<real>(a, S, ri, tile.rep, tile.n0, fexv, mask, step, e);
     if (n < ri.n_bp) {

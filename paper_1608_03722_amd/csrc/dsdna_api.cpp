@@ -168,6 +168,9 @@ static void fill_phys(dsdna_ctx *c)
     h.cos_d = std::cos(p.d_dih);
     h.sin_d = std::sin(p.d_dih);
     h.kick = 0.5 * p.dt;
+    h.inv_I = 1.0 / h.I;
+    h.kick_M = h.kick / h.M;
+    h.inv_R0sq = 1.0 / (p.R0 * p.R0);
     h.seed = p.seed;
     h.noise_kind = p.noise_kind;
     h.ssdna_rule = p.ssdna_rule;

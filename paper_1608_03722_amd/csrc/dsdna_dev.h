@@ -32,6 +32,8 @@ struct Phys {
     double rc_bb, rc_s, rc_x; // WCA cutoffs 2^(1/6) sigma
     double cos_d, sin_d;      // cos and sin of the dihedral phase
     double kick;              // dt / 2
+    double inv_I, kick_M;     // 1 / I, (dt / 2) / M
+    double inv_R0sq;          // 1 / R0^2
     uint64_t seed;
     int32_t noise_kind, ssdna_rule;
 };

@@ -274,7 +274,7 @@ struct TileLds {
     double sB[TILE_NT + 4 * HALO_BP][3];   // FP64 sites, halo of 2 bp each side
     double sP[TILE_NT + 4 * HALO_BP][3];
     real oStep[2][TILE_BP + 1][4][3];      // per strand, per backbone step m
-    real oBend[2][TILE_BP + 2][3][3];      // per strand, per bending centre
+    real oBend[2][TILE_BP + 2][2][3];      // per strand, per bending centre: end forces
     real oHb[TILE_BP][3];                  // force on strand-0 patch
     uint8_t sOpen[TILE_BP + 2 * HALO_BP];  // open flags of bp n0-2 .. n0+TILE_BP+1
 };
@@ -412,7 +412,7 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
                 } else {
                     // FENE attraction and the WCA core cancel to a few percent
                     // near the bond minimum, so (dU/dr)/r is formed in FP64
-                    const double x = 1.0 - r2 / (ph.R0 * ph.R0);
+                    const double x = 1.0 - r2 * ph.inv_R0sq;
                     double g = ph.K1 / x;
                     double e = 0.0;
                     if (energies && own) e = -0.5 * ph.K1 * ph.R0 * ph.R0 * log(x);
@@ -493,7 +493,7 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
     // --- Kratky-Porod bending on patches (s, m-1), (s, m), (s, m+1)
     for (int q = t; q < 2 * (TILE_BP + 2); q += blockDim.x) {
         const int s = q & 1, mi = q >> 1, m = n0 - 1 + mi;
-        V3<real> f0 = v3<real>(0, 0, 0), f1 = f0, f2 = f0;
+        V3<real> f0 = v3<real>(0, 0, 0), f2 = f0;
         const bool masked = rule && S.sOpen[mi] && S.sOpen[mi + 1] && S.sOpen[mi + 2];
         if ((mask & (1u << DSDNA_TERM_BEND)) && m >= 1 && m + 1 < nbp && !masked) {
             const int la = 2 * mi + s;
@@ -505,12 +505,10 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
             const real K6 = (real)ph.K6;
             f0 = (r2 * il - r1 * (c * rcp(l11))) * (-K6);
             f2 = (r1 * il - r2 * (c * rcp(l22))) * (-K6);
-            f1 = -(f0 + f2);
             if (energies && mi >= 1 && mi <= TILE_BP) energies[DSDNA_TERM_BEND] += ph.K6 * (1.0 + (double)c);
         }
         put3(S.oBend[s][mi][0], f0);
-        put3(S.oBend[s][mi][1], f1);
-        put3(S.oBend[s][mi][2], f2);
+        put3(S.oBend[s][mi][1], f2);
     }
     __syncthreads();
 
@@ -523,8 +521,10 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
     out.p = out.b;
     if (n < nbp) {
         out.b = get3(S.oStep[s][bl][2]) + get3(S.oStep[s][bl + 1][0]);
-        out.p = get3(S.oStep[s][bl][3]) + get3(S.oStep[s][bl + 1][1]) + get3(S.oBend[s][bl][2]) +
-                get3(S.oBend[s][bl + 1][1]) + get3(S.oBend[s][bl + 2][0]);
+        // middle patch of a bending triple: minus the sum of the end forces
+        const V3<real> mid = -(get3(S.oBend[s][bl + 1][0]) + get3(S.oBend[s][bl + 1][1]));
+        out.p = get3(S.oStep[s][bl][3]) + get3(S.oStep[s][bl + 1][1]) + get3(S.oBend[s][bl][1]) + mid +
+                get3(S.oBend[s][bl + 2][0]);
         const V3<real> hb = get3(S.oHb[bl]);
         out.p = s == 0 ? out.p + hb : out.p - hb;
     }
@@ -580,16 +580,33 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
 
 
 // Rotation of the axis of a free linear rotor by th about unit k:
-// u cos th + (k x u) sin th + k (k.u)(1 - cos th).  cos and sin come from
-// their Taylor series through th^10 for th < 1/32 (error below 1e-19),
-// otherwise from sincos.
+// u cos th + (k x u) sin th + k (k.u)(1 - cos th).  For th < 1/4 (angular
+// speeds below 50 per unit time at dt = 0.005, far in the tail of the
+// thermal distribution) cos and sin come from their Taylor series through
+// th^16 and th^17, whose remainders are below 1e-25; otherwise sincos.
 __device__ __forceinline__ D3 rotate(D3 u, D3 k, double th)
 {
     double sn, cs;
-    if (th < 0.03125) {
+    if (th < 0.25) {
         const double t2 = th * th;
-        cs = 1.0 - t2 * (1.0 / 2 - t2 * (1.0 / 24 - t2 * (1.0 / 720 - t2 * (1.0 / 40320 - t2 * (1.0 / 3628800)))));
-        sn = th * (1.0 - t2 * (1.0 / 6 - t2 * (1.0 / 120 - t2 * (1.0 / 5040 - t2 * (1.0 / 362880)))));
+        double c = 1.0 / 20922789888000.0;            // 1/16!
+        double s = 1.0 / 355687428096000.0;           // 1/17!
+        c = 1.0 / 87178291200.0 - t2 * c;             // 1/14!
+        s = 1.0 / 1307674368000.0 - t2 * s;           // 1/15!
+        c = 1.0 / 479001600.0 - t2 * c;               // 1/12!
+        s = 1.0 / 6227020800.0 - t2 * s;              // 1/13!
+        c = 1.0 / 3628800.0 - t2 * c;                 // 1/10!
+        s = 1.0 / 39916800.0 - t2 * s;                // 1/11!
+        c = 1.0 / 40320.0 - t2 * c;                   // 1/8!
+        s = 1.0 / 362880.0 - t2 * s;                  // 1/9!
+        c = 1.0 / 720.0 - t2 * c;
+        s = 1.0 / 5040.0 - t2 * s;
+        c = 1.0 / 24.0 - t2 * c;
+        s = 1.0 / 120.0 - t2 * s;
+        c = 0.5 - t2 * c;
+        s = 1.0 / 6.0 - t2 * s;
+        cs = 1.0 - t2 * c;
+        sn = th * (1.0 - t2 * s);
     } else {
         sincos(th, &sn, &cs);
     }
@@ -599,7 +616,7 @@ __device__ __forceinline__ D3 rotate(D3 u, D3 k, double th)
 // ---------------------------------------------------------------- k_step
 
 template <typename real>
-__global__ void __launch_bounds__(WG_THREADS, 4) k_step(const StepArgs *__restrict__ A, int mode, int write_full)
+__global__ void __launch_bounds__(WG_THREADS, 5) k_step(const StepArgs *__restrict__ A, int mode, int write_full)
 {
     __shared__ TileLds<real> S;
     const StepArgs &a = *A;
@@ -663,7 +680,7 @@ __global__ void __launch_bounds__(WG_THREADS, 4) k_step(const StepArgs *__restri
         if (langevin) {
             // Langevin forces (Appendix A) per site: friction on the site's
             // velocity on the rigid body plus counter-based noise
-            const D3 w = L * (1.0 / ph.I);
+            const D3 w = L * ph.inv_I;
             const D3 vb = V + cross(w, u * (-ph.db)), vp = V + cross(w, u * ph.dp);
             if (sizeof(real) == sizeof(double)) {
                 lb = cvt<real>(vb * (-ph.gamma) + v3((double)xi[0], (double)xi[1], (double)xi[2]) * ph.noise_amp);
@@ -690,7 +707,7 @@ __global__ void __launch_bounds__(WG_THREADS, 4) k_step(const StepArgs *__restri
     } else {
         const D3 F = fb + fp;
         const D3 tau = cross(u, fp * ph.dp - fb * ph.db);
-        const double km = ph.kick / ph.M;
+        const double km = ph.kick_M;
         if (mode == MODE_NORMAL) {  // second half kick of the previous step
             V = V + F * km;
             L = L + tau * ph.kick;
@@ -705,10 +722,12 @@ __global__ void __launch_bounds__(WG_THREADS, 4) k_step(const StepArgs *__restri
         V = V + F * km;
         L = L + tau * ph.kick;
         R = R + V * ph.dt;
-        const D3 w = L * (1.0 / ph.I);
+        const D3 w = L * ph.inv_I;
         const double wl = sqrt(dot(w, w));
         if (wl > 0.0) u = rotate(u, w * (1.0 / wl), wl * ph.dt);
-        u = u * (1.0 / sqrt(dot(u, u)));
+        // renormalise: |u|^2 = 1 up to rounding, so one Newton step from 1
+        // gives 1/|u| to double precision
+        u = u * (1.5 - 0.5 * dot(u, u));
         L = L - u * dot(L, u);
     }
     st3(a.b.R[nxt], N, i, R);

@@ -104,8 +104,10 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k)
             k.x += 0x9E3779B9u;
             k.y += 0xBB67AE85u;
         }
-        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        // one 32 x 32 -> 64-bit product per multiplier
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
     }
     return c;
@@ -152,7 +154,9 @@ __device__ __forceinline__ void noise6(uint64_t seed, int kind, uint64_t step, u
 
 // The same numbers evaluated in FP32 (forces in FP32).  For u > 1/2, ln u
 // is taken as log1p(-(1 - u)) with 1 - u formed exactly from the integer,
-// so the radius keeps its relative accuracy near u = 1.
+// so the radius keeps its relative accuracy near u = 1; below 1/2 the
+// hardware base-2 logarithm is used.  The angle 2 pi u goes to the hardware
+// sine and cosine, which take their argument in turns (u itself).
 __device__ __forceinline__ void noise6f(uint64_t seed, int kind, uint64_t step, uint32_t id, uint32_t stream,
                                         float xi[6])
 {
@@ -170,14 +174,12 @@ __device__ __forceinline__ void noise6f(uint64_t seed, int kind, uint64_t step, 
 #pragma unroll
     for (int k = 0; k < 6; k += 2) {
         const uint32_t a = w[k];
-        const float lnu = a < 0x80000000u ? logf(((float)a + 0.5f) * 0x1p-32f)
+        const float lnu = a < 0x80000000u ? __logf(((float)a + 0.5f) * 0x1p-32f)
                                           : log1pf(-(((float)(0xFFFFFFFFu - a) + 0.5f) * 0x1p-32f));
         const float rad = sqrtf(-2.0f * lnu);
-        const float ang = 6.28318530717958648f * (((float)w[k + 1] + 0.5f) * 0x1p-32f);
-        float s, c;
-        sincosf(ang, &s, &c);
-        xi[k] = rad * c;
-        xi[k + 1] = rad * s;
+        const float turns = ((float)w[k + 1] + 0.5f) * 0x1p-32f;
+        xi[k] = rad * __builtin_amdgcn_cosf(turns);
+        xi[k + 1] = rad * __builtin_amdgcn_sinf(turns);
     }
 }
 

@@ -258,6 +258,54 @@ __device__ __forceinline__ void insert_bead(const StepArgs &a, const RepInfo &ri
     a.b.slot[i] = atomicAdd(&a.b.count[key], 1);
 }
 
+// Bin the new bead positions of a tile (all threads of the workgroup call
+// this): record, cell and key per bead, then the slots.  The keys of the tile
+// are first counted in an LDS hash table (at most WG_THREADS distinct keys in
+// WG_THREADS slots, so every probe sequence ends), then one histogram atomic
+// per distinct key returns its base slot; a bead's slot is base + its rank
+// within the tile.  tab, cnt, base: WG_THREADS entries each of LDS.
+__device__ __forceinline__ void bin_tile(const StepArgs &a, uint32_t *tab, uint32_t *cnt, int *base,
+                                         const RepInfo &ri, int rep, int n, int s, int64_t i, bool own, D3 bead,
+                                         int64_t step)
+{
+    constexpr uint32_t EMPTY = 0xFFFFFFFFu;  // keys are below 2^28
+    const int t = threadIdx.x;
+    __syncthreads();
+    tab[t] = EMPTY;
+    cnt[t] = 0u;
+    __syncthreads();
+    int e = 0;
+    uint32_t rank = 0;
+    if (own) {
+        int c[3];
+        uint32_t qc[3];
+        if (!cell_of(ri, bead, c, qc)) {
+            raise_error(a.b.ctl, isfinite(bead.x + bead.y + bead.z) ? DSDNA_EDOMAIN : DSDNA_ENAN, step, i);
+            c[0] = c[1] = c[2] = 0;
+        }
+        const uint32_t key = bucket_of(a.g, c[0], c[1], c[2], rep);
+        BeadRec r;
+        r.x = qc[0];
+        r.y = qc[1];
+        r.z = qc[2];
+        r.tag = make_tag(rep, n, s);
+        a.b.rec[i] = r;
+        a.b.rcell[i] = make_int4(c[0], c[1], c[2], 0);
+        a.b.key[i] = (int32_t)key;
+        e = (int)((key * 2654435761u) >> 24) & (WG_THREADS - 1);
+        for (;;) {
+            const uint32_t old = atomicCAS(&tab[e], EMPTY, key);
+            if (old == EMPTY || old == key) break;
+            e = (e + 1) & (WG_THREADS - 1);
+        }
+        rank = atomicAdd(&cnt[e], 1u);
+    }
+    __syncthreads();
+    if (tab[t] != EMPTY) base[t] = atomicAdd(&a.b.count[tab[t]], (int)cnt[t]);
+    __syncthreads();
+    if (own) a.b.slot[i] = base[e] + (int)rank;
+}
+
 // ------------------------------------------------------------------- tiles
 
 __device__ __forceinline__ int tile_index(int n_tiles, int n_tiles_pad)
@@ -671,73 +719,78 @@ __global__ void __launch_bounds__(WG_THREADS, 5) k_step(const StepArgs *__restri
         stage_site(a, S, site);
         f = tile_forces<real>(a, S, ri, tile.rep, tile.n0, fexv, ALL_TERMS, step, nullptr);
     }
-    if (!own) return;
-
-    D3 fb, fp;  // total site forces of this step
-    if (mode == MODE_FROM_FORCES) {
-        fb = ld3(a.b.Fb, N, i);
-        fp = ld3(a.b.Fp, N, i);
-    } else {
-        V3<real> lb = v3<real>(0, 0, 0), lp = lb;
-        if (langevin) {
-            // Langevin forces (Appendix A) per site: friction on the site's
-            // velocity on the rigid body plus counter-based noise
-            const D3 w = L * ph.inv_I;
-            const D3 vb = V + cross(w, u * (-ph.db)), vp = V + cross(w, u * ph.dp);
-            if (sizeof(real) == sizeof(double)) {
-                lb = cvt<real>(vb * (-ph.gamma) + v3((double)xi[0], (double)xi[1], (double)xi[2]) * ph.noise_amp);
-                lp = cvt<real>(vp * (-ph.gamma) + v3((double)xi[3], (double)xi[4], (double)xi[5]) * ph.noise_amp);
-            } else {
-                const real amp = (real)ph.noise_amp;
-                lb = cvt<real>(vb * (-ph.gamma)) + v3<real>(xi[0], xi[1], xi[2]) * amp;
-                lp = cvt<real>(vp * (-ph.gamma)) + v3<real>(xi[3], xi[4], xi[5]) * amp;
+    D3 bead_new = v3(0.0, 0.0, 0.0);
+    if (own) {
+        D3 fb, fp;  // total site forces of this step
+        if (mode == MODE_FROM_FORCES) {
+            fb = ld3(a.b.Fb, N, i);
+            fp = ld3(a.b.Fp, N, i);
+        } else {
+            V3<real> lb = v3<real>(0, 0, 0), lp = lb;
+            if (langevin) {
+                // Langevin forces (Appendix A) per site: friction on the site's
+                // velocity on the rigid body plus counter-based noise
+                const D3 w = L * ph.inv_I;
+                const D3 vb = V + cross(w, u * (-ph.db)), vp = V + cross(w, u * ph.dp);
+                if (sizeof(real) == sizeof(double)) {
+                    lb = cvt<real>(vb * (-ph.gamma) + v3((double)xi[0], (double)xi[1], (double)xi[2]) * ph.noise_amp);
+                    lp = cvt<real>(vp * (-ph.gamma) + v3((double)xi[3], (double)xi[4], (double)xi[5]) * ph.noise_amp);
+                } else {
+                    const real amp = (real)ph.noise_amp;
+                    lb = cvt<real>(vb * (-ph.gamma)) + v3<real>(xi[0], xi[1], xi[2]) * amp;
+                    lp = cvt<real>(vp * (-ph.gamma)) + v3<real>(xi[3], xi[4], xi[5]) * amp;
+                }
             }
+            fb = cvt<double>(f.b + lb);
+            fp = cvt<double>(f.p + lp);
         }
-        fb = cvt<double>(f.b + lb);
-        fp = cvt<double>(f.p + lp);
-    }
 
-    if (frozen) {
-        V = v3(0.0, 0.0, 0.0);
-        L = V;
-        if (write_full) {
-            st3(a.b.Vf, N, i, V);
-            st3(a.b.Lf, N, i, L);
-            st3(a.b.Fb, N, i, fb);
-            st3(a.b.Fp, N, i, fp);
-        }
-    } else {
-        const D3 F = fb + fp;
-        const D3 tau = cross(u, fp * ph.dp - fb * ph.db);
-        const double km = ph.kick_M;
-        if (mode == MODE_NORMAL) {  // second half kick of the previous step
+        if (frozen) {
+            V = v3(0.0, 0.0, 0.0);
+            L = V;
+            if (write_full) {
+                st3(a.b.Vf, N, i, V);
+                st3(a.b.Lf, N, i, L);
+                st3(a.b.Fb, N, i, fb);
+                st3(a.b.Fp, N, i, fp);
+            }
+        } else {
+            const D3 F = fb + fp;
+            const D3 tau = cross(u, fp * ph.dp - fb * ph.db);
+            const double km = ph.kick_M;
+            if (mode == MODE_NORMAL) {  // second half kick of the previous step
+                V = V + F * km;
+                L = L + tau * ph.kick;
+            }
+            if (write_full) {
+                st3(a.b.Vf, N, i, V);
+                st3(a.b.Lf, N, i, L);
+                st3(a.b.Fb, N, i, fb);
+                st3(a.b.Fp, N, i, fp);
+            }
+            // first half kick, drift, free rotation of the linear rotor
             V = V + F * km;
             L = L + tau * ph.kick;
+            R = R + V * ph.dt;
+            const D3 w = L * ph.inv_I;
+            const double wl = sqrt(dot(w, w));
+            if (wl > 0.0) u = rotate(u, w * (1.0 / wl), wl * ph.dt);
+            // renormalise: |u|^2 = 1 up to rounding, so one Newton step from 1
+            // gives 1/|u| to double precision
+            u = u * (1.5 - 0.5 * dot(u, u));
+            L = L - u * dot(L, u);
         }
-        if (write_full) {
-            st3(a.b.Vf, N, i, V);
-            st3(a.b.Lf, N, i, L);
-            st3(a.b.Fb, N, i, fb);
-            st3(a.b.Fp, N, i, fp);
-        }
-        // first half kick, drift, free rotation of the linear rotor
-        V = V + F * km;
-        L = L + tau * ph.kick;
-        R = R + V * ph.dt;
-        const D3 w = L * ph.inv_I;
-        const double wl = sqrt(dot(w, w));
-        if (wl > 0.0) u = rotate(u, w * (1.0 / wl), wl * ph.dt);
-        // renormalise: |u|^2 = 1 up to rounding, so one Newton step from 1
-        // gives 1/|u| to double precision
-        u = u * (1.5 - 0.5 * dot(u, u));
-        L = L - u * dot(L, u);
+        st3(a.b.R[nxt], N, i, R);
+        st3(a.b.u[nxt], N, i, u);
+        st3(a.b.V[nxt], N, i, V);
+        st3(a.b.L[nxt], N, i, L);
+        if (!(isfinite(R.x + R.y + R.z) && isfinite(u.x + u.y + u.z))) raise_error(a.b.ctl, DSDNA_ENAN, step + 1, i);
+        bead_new = bead_of(R, u, ph.db);
     }
-    st3(a.b.R[nxt], N, i, R);
-    st3(a.b.u[nxt], N, i, u);
-    st3(a.b.V[nxt], N, i, V);
-    st3(a.b.L[nxt], N, i, L);
-    if (!(isfinite(R.x + R.y + R.z) && isfinite(u.x + u.y + u.z))) raise_error(a.b.ctl, DSDNA_ENAN, step + 1, i);
-    insert_bead(a, ri, tile.rep, n, s, i, bead_of(R, u, ph.db), step + 1);
+    // the force phase is over: its LDS outboxes hold the binning table
+    uint32_t *lds = reinterpret_cast<uint32_t *>(&S.oStep[0][0][0][0]);
+    bin_tile(a, lds, lds + WG_THREADS, reinterpret_cast<int *>(lds + 2 * WG_THREADS), ri, tile.rep, n, s, i, own,
+             bead_new, step + 1);
 }
 
 // ------------------------------------------------------------ binning only

@@ -104,7 +104,7 @@ static void free_state(dsdna_ctx *c)
         dfree(b.R[k]); dfree(b.u[k]); dfree(b.V[k]); dfree(b.L[k]);
     }
     dfree(b.Vf); dfree(b.Lf); dfree(b.Fb); dfree(b.Fp);
-    dfree(b.rec); dfree(b.rcell); dfree(b.key); dfree(b.slot); dfree(b.srec); dfree(b.sinfo);
+    dfree(b.rec); dfree(b.rcell); dfree(b.key); dfree(b.slot); dfree(b.srec); dfree(b.sid); dfree(b.scell);
     dfree(b.fex); dfree(b.tflag); dfree(b.eex);
     dfree(b.rep); dfree(b.tiles); dfree(b.eacc); dfree(b.open);
     dfree(b.diag_fb); dfree(b.diag_fp);
@@ -230,6 +230,10 @@ static dsdna_status configure_grid(dsdna_ctx *c)
                     return fail(c, DSDNA_EINVAL, "replica %d: periodic edge %g holds fewer than 3 cells of %g", r,
                                 ri.len[k], h);
                 if (n > (1 << 20)) return fail(c, DSDNA_EINVAL, "replica %d: periodic edge too long", r);
+                // cells are cut on the 32-bit coordinates (unit L / 2^32): a
+                // cell must stay wider than the cutoff plus a few units
+                if (ri.len[k] / (double)n < rc_max(c) + 4.0 * ri.len[k] / 4294967296.0)
+                    return fail(c, DSDNA_EINVAL, "replica %d: periodic edge %g too long for cell %g", r, ri.len[k], h);
                 ri.ncell[k] = (int32_t)n;
                 ri.inv_h[k] = (double)n / ri.len[k];
             } else {
@@ -716,7 +720,7 @@ dsdna_status dsdna_set_topology(dsdna_ctx *c, int32_t n_rep, const int32_t *n_bp
     HIPCHK(c, dalloc(&b.Fb, n3)); HIPCHK(c, dalloc(&b.Fp, n3));
     HIPCHK(c, dalloc(&b.key, (size_t)N)); HIPCHK(c, dalloc(&b.slot, (size_t)N));
     HIPCHK(c, dalloc(&b.rec, (size_t)N)); HIPCHK(c, dalloc(&b.rcell, (size_t)N));
-    HIPCHK(c, dalloc(&b.srec, (size_t)N)); HIPCHK(c, dalloc(&b.sinfo, (size_t)N));
+    HIPCHK(c, dalloc(&b.srec, (size_t)N)); HIPCHK(c, dalloc(&b.sid, (size_t)N)); HIPCHK(c, dalloc(&b.scell, (size_t)N));
     HIPCHK(c, dalloc(&b.fex, 4 * (size_t)N));
     HIPCHK(c, dalloc(&b.tflag, (size_t)a.n_tiles));
     HIPCHK(c, dalloc(&b.eex, (size_t)N));

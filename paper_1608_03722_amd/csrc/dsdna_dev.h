@@ -107,10 +107,11 @@ struct Bufs {
     double *Vf, *Lf;                    // full-step velocities of the last step
     double *Fb, *Fp;                    // full-step site forces (SoA [3][N])
     BeadRec *rec;                       // bead record per nucleotide
-    int4 *rcell;                        // cell (x, y, z) of each bead
+    int4 *rcell;                        // cell (x, y, z) of each bead (open edges only)
     int32_t *key, *slot;                // counting-sort key and slot of each bead
     BeadRec *srec;                      // records in key order (counting sort)
-    int4 *sinfo;                        // per sorted record: nucleotide, cell x, y, z
+    int32_t *sid;                       // nucleotide of each sorted record
+    int4 *scell;                        // cell of each sorted record (open edges only)
     int32_t *count, *start, *bsum;      // per key (start: nbucket + 1)
     // excluded-volume force per nt as exact fixed-point sums (x, y, z, unused;
     // units FIX32_UNIT or FIX64_UNIT), zero except beads with contacts;

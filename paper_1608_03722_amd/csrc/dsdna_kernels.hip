@@ -196,10 +196,16 @@ __device__ __forceinline__ void raise_error(Ctl *ctl, int code, int64_t step, in
 // --------------------------------------------------------------- cell list
 
 // Cell of a bead and its fixed-point coordinates.  Periodic dims: wrapped
-// into [0, L), cell = floor(frac * ncell), coordinate = frac * 2^32; open
-// dims: relative to the replica origin, cell = floor(x / h), coordinate =
-// x * 2^24 modulo 2^32.  Returns false if the position is not finite or too
+// into [0, L), coordinate = floor(frac * 2^32), cell = floor(coordinate *
+// ncell / 2^32) (a function of the coordinate alone, so the neighbour search
+// can recompute it from the record); open dims: relative to the replica
+// origin, cell = floor(x / h), coordinate = x * 2^24 modulo 2^32.  Returns false if the position is not finite or too
 // far from the origin to be binned.
+__device__ __forceinline__ int periodic_cell(uint32_t q, int ncell)
+{
+    return (int)(((uint64_t)q * (uint64_t)(uint32_t)ncell) >> 32);
+}
+
 __device__ __forceinline__ bool cell_of(const RepInfo &ri, D3 p, int c[3], uint32_t qc[3])
 {
     const double x[3] = {p.x - ri.lo[0], p.y - ri.lo[1], p.z - ri.lo[2]};
@@ -210,9 +216,8 @@ __device__ __forceinline__ bool cell_of(const RepInfo &ri, D3 p, int c[3], uint3
             double t = x[k] * ri.inv_len[k];
             ok = ok && isfinite(t);
             t = ok ? t - floor(t) : 0.0;
-            const int ci = (int)(t * (double)ri.ncell[k]);
-            c[k] = ci >= ri.ncell[k] ? ri.ncell[k] - 1 : (ci < 0 ? 0 : ci);
             qc[k] = (uint32_t)(uint64_t)(t * 4294967296.0);
+            c[k] = periodic_cell(qc[k], ri.ncell[k]);
         } else {
             ok = ok && (fabs(x[k]) < 1.0e6);  // also rejects NaN
             const double xs = ok ? x[k] : 0.0;
@@ -253,7 +258,7 @@ __device__ __forceinline__ void insert_bead(const StepArgs &a, const RepInfo &ri
     r.z = qc[2];
     r.tag = make_tag(rep, n, s);
     a.b.rec[i] = r;
-    a.b.rcell[i] = make_int4(c[0], c[1], c[2], 0);
+    if (a.g.any_open) a.b.rcell[i] = make_int4(c[0], c[1], c[2], 0);
     a.b.key[i] = (int32_t)key;
     a.b.slot[i] = atomicAdd(&a.b.count[key], 1);
 }
@@ -290,7 +295,7 @@ __device__ __forceinline__ void bin_tile(const StepArgs &a, uint32_t *tab, uint3
         r.z = qc[2];
         r.tag = make_tag(rep, n, s);
         a.b.rec[i] = r;
-        a.b.rcell[i] = make_int4(c[0], c[1], c[2], 0);
+        if (a.g.any_open) a.b.rcell[i] = make_int4(c[0], c[1], c[2], 0);
         a.b.key[i] = (int32_t)key;
         e = (int)((key * 2654435761u) >> 24) & (WG_THREADS - 1);
         for (;;) {
@@ -851,7 +856,8 @@ __device__ __forceinline__ void fex_add(const StepArgs &a, const RepInfo &ri, in
 // positions (minimum image along periodic edges).
 template <typename real, bool energy, bool any_open>
 __global__ void __launch_bounds__(256) k_excl(const StepArgs *__restrict__ A, const BeadRec *__restrict__ srec,
-                                              const int4 *__restrict__ sinfo, const int *__restrict__ start, int which)
+                                              const int *__restrict__ sid, const int4 *__restrict__ scell,
+                                              const int *__restrict__ start, int which)
 {
     const StepArgs &a = *A;
     if (a.b.ctl->code != 0) return;
@@ -863,9 +869,7 @@ __global__ void __launch_bounds__(256) k_excl(const StepArgs *__restrict__ A, co
     const double unit = F64 ? FIX64_UNIT : FIX32_UNIT;
     const Phys &ph = a.ph;
     const BeadRec me = srec[p];
-    const int4 info = sinfo[p];
-    const int64_t i = info.x;
-    const int c[3] = {info.y, info.z, info.w};
+    const int64_t i = sid[p];
     const uint32_t rep = me.tag >> 2;
     const uint32_t mt = me.tag & 3u;
     // partner types (bit 0 strand, bit 1 steric) this bead interacts with:
@@ -877,8 +881,20 @@ __global__ void __launch_bounds__(256) k_excl(const StepArgs *__restrict__ A, co
     const int buf = which < 0 ? a.b.ctl->par : which;
     const double *Rc = a.b.R[buf], *uc = a.b.u[buf];
     const bool px = ri.flags & REP_PER_X, py = ri.flags & REP_PER_Y, pz = ri.flags & REP_PER_Z;
-    // any_open: some replica has an open edge
+    // any_open: some replica has an open edge; cells were stored by the
+    // binning.  Otherwise they follow from the periodic coordinates.
     const bool open_any = any_open && !(px && py && pz);
+    int c[3];
+    if (any_open) {
+        const int4 cc = scell[p];
+        c[0] = cc.x;
+        c[1] = cc.y;
+        c[2] = cc.z;
+    } else {
+        c[0] = periodic_cell(me.x, ri.ncell[0]);
+        c[1] = periodic_cell(me.y, ri.ncell[1]);
+        c[2] = periodic_cell(me.z, ri.ncell[2]);
+    }
     // FP64 forces: pre-select with a slack that covers the fixed-point error
     const float rcs2 = (float)(F64 ? (ph.rc_s + 1e-3) * (ph.rc_s + 1e-3) : ph.rc_s * ph.rc_s);
     const float rcx2 = (float)(F64 ? (ph.rc_x + 1e-3) * (ph.rc_x + 1e-3) : ph.rc_x * ph.rc_x);
@@ -899,14 +915,15 @@ __global__ void __launch_bounds__(256) k_excl(const StepArgs *__restrict__ A, co
         const float r2f = dx * dx + dy * dy + dz * dz;
         if (!(valid && r2f < (same ? rcs2 : rcx2) && ((accept >> ot) & 1u) && (o.tag >> 2) == rep && q != p))
             return;
-        const int4 oinfo = sinfo[q];
         // open edges: the fixed-point difference is exact only modulo 2^32
         // units, so a record of a far cell that shares a bucket with a
         // neighbour cell is rejected by its cell coordinates
-        if (any_open && open_any &&
-            ((!px && abs(oinfo.y - c[0]) > 1) || (!py && abs(oinfo.z - c[1]) > 1) || (!pz && abs(oinfo.w - c[2]) > 1)))
-            return;
-        const int64_t j = oinfo.x;
+        if (any_open && open_any) {
+            const int4 oc = scell[q];
+            if ((!px && abs(oc.x - c[0]) > 1) || (!py && abs(oc.y - c[1]) > 1) || (!pz && abs(oc.z - c[2]) > 1))
+                return;
+        }
+        const int64_t j = sid[q];
         V3<real> d = v3<real>(dx, dy, dz);
         real r2 = r2f;
         D3 d64 = v3(0.0, 0.0, 0.0);
@@ -1135,8 +1152,8 @@ __global__ void __launch_bounds__(256) k_scan_down(const int *__restrict__ count
 __global__ void __launch_bounds__(256) k_scatter(const int *__restrict__ key, const int *__restrict__ slot,
                                                  const int *__restrict__ start, const BeadRec *__restrict__ rec,
                                                  const int4 *__restrict__ rcell, BeadRec *__restrict__ srec,
-                                                 int4 *__restrict__ sinfo, int *__restrict__ count, Ctl *ctl,
-                                                 int64_t n, int inc)
+                                                 int *__restrict__ sid, int4 *__restrict__ scell,
+                                                 int *__restrict__ count, Ctl *ctl, int64_t n, int inc, int any_open)
 {
     if (ctl->code != 0) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1144,8 +1161,8 @@ __global__ void __launch_bounds__(256) k_scatter(const int *__restrict__ key, co
         const int k = key[i];
         const int p = start[k] + slot[i];
         srec[p] = rec[i];
-        const int4 c = rcell[i];
-        sinfo[p] = make_int4((int)i, c.x, c.y, c.z);
+        sid[p] = (int)i;
+        if (any_open) scell[p] = rcell[i];
         count[k] = 0;
     }
     if (inc && i == 0) {
@@ -1256,7 +1273,7 @@ hipError_t launch_scatter(const StepArgs &a, int inc_step, hipStream_t s)
 {
     const unsigned nb = (unsigned)((a.n_nt + 255) / 256);
     hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, s, a.b.key, a.b.slot, a.b.start, a.b.rec, a.b.rcell,
-                       a.b.srec, a.b.sinfo, a.b.count, a.b.ctl, a.n_nt, inc_step);
+                       a.b.srec, a.b.sid, a.b.scell, a.b.count, a.b.ctl, a.n_nt, inc_step, a.g.any_open);
     return hipGetLastError();
 }
 
@@ -1273,11 +1290,11 @@ template <typename real, bool energy>
 static void launch_excl_t(const StepArgs &a, const StepArgs *dA, int which, unsigned nb, hipStream_t s)
 {
     if (a.g.any_open)
-        hipLaunchKernelGGL((k_excl<real, energy, true>), dim3(nb), dim3(256), 0, s, dA, a.b.srec, a.b.sinfo,
-                           a.b.start, which);
+        hipLaunchKernelGGL((k_excl<real, energy, true>), dim3(nb), dim3(256), 0, s, dA, a.b.srec, a.b.sid,
+                           a.b.scell, a.b.start, which);
     else
-        hipLaunchKernelGGL((k_excl<real, energy, false>), dim3(nb), dim3(256), 0, s, dA, a.b.srec, a.b.sinfo,
-                           a.b.start, which);
+        hipLaunchKernelGGL((k_excl<real, energy, false>), dim3(nb), dim3(256), 0, s, dA, a.b.srec, a.b.sid,
+                           a.b.scell, a.b.start, which);
 }
 
 hipError_t launch_excl(const StepArgs &a, const StepArgs *dA, int fp64, int energy, int which, hipStream_t s)

@@ -26,19 +26,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor peak
-# Algorithmic bytes per nucleotide of one launch of each kernel (every byte
-# the kernel must move once; see the design doc for the derivation):
+# Algorithmic bytes per nucleotide of one launch of each kernel in a fully
+# periodic box (every byte the kernel must move once).  The
+# excluded-volume forces travel through sparse accumulators touched only by
+# beads in contact (about 1e-3 of them), so they add no bytes per nucleotide.
 KERNEL_BYTES_PER_NT = {
-    # R, u, V, L read (96) and written (96); excluded-volume force read (16);
-    # bead record (16) and cell (16) written; bucket key and slot (4 + 4)
-    "step": 96 + 96 + 16 + 16 + 16 + 4 + 4,
-    # own sorted record and info (16 + 16); every record read once as a
-    # candidate (16); force written (16)
-    "excl": 16 + 16 + 16 + 16,
-    # key, slot, start[key] (12); record and cell read (32); sorted record
-    # and info written (32); histogram entry cleared (4)
-    "scatter": 12 + 32 + 32 + 4,
+    # R, u, V, L read (96) and written (96); bead record (16), bucket key and
+    # slot (4 + 4) written
+    "step": 96 + 96 + 16 + 4 + 4,
+    # own sorted record and nucleotide id (16 + 4); every record read once as
+    # a candidate (16)
+    "excl": 16 + 4 + 16,
+    # key, slot, start[key] (12); record read (16); sorted record and id
+    # written (16 + 4); histogram entry cleared (4)
+    "scatter": 12 + 16 + 16 + 4 + 4,
 }
+# With an open edge the cell of every bead is stored and sorted as well.
+OPEN_EXTRA_BYTES_PER_NT = {"step": 16, "excl": 16, "scatter": 16 + 16}
 SCAN_BYTES_PER_KEY = 4 + 4 + 4  # histogram read by both passes, offsets written
 KERNEL_SOURCES = ("paper_1608_03722_amd/csrc/dsdna_kernels.hip", "paper_1608_03722_amd/csrc/dsdna_dev.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_1mbp_traffic.json")
@@ -172,6 +176,101 @@ def batched_vs_single(D, sync, steps, graph_steps):
             "unit": "nucleotide-timesteps/s", "speedup": v_b / v_s}
 
 
+def _per_term_error(D, sim32, sim64):
+    """Per term t: ||F32_t - F64_t|| / ||F64_t|| over all sites (same state)."""
+    out = {}
+    for t, name in enumerate(D.TERMS):
+        b32, p32 = sim32.forces(t)
+        b64, p64 = sim64.forces(t)
+        ref = np.concatenate([b64, p64])
+        d = np.linalg.norm(np.concatenate([b32, p32]) - ref)
+        nr = np.linalg.norm(ref)
+        out[name] = float(d / nr) if nr > 0 else float(d)
+    e32, e64 = sim32.energies(), sim64.energies()
+    for t, name in enumerate(D.TERMS):
+        out["energy_" + name] = float(np.abs(e32[:, t] - e64[:, t]).max() / max(1.0, np.abs(e64[:, t]).max()))
+    return out
+
+
+def denaturation_report(D, cfg, sim32, args):
+    """64 x 2 kbp with scaled base-pair attraction: an all-FP64 run beside the
+    FP32-force run from the same state and noise; fraction unpaired and bubble
+    histogram of both every `sample_every` steps, and the per-term force and
+    energy difference FP32 vs FP64 on the shared start state and on the FP64
+    run's last sampled state.  A run the model's dynamics stops (a backbone
+    bond reaching R0) is reported with its step."""
+    extra = {"dt": args.dt} if args.dt > 0 else {}
+    prm64 = D.dsdna_default_params(seed=0, force_fp64=1, ssdna_rule=1, graph_steps=args.graph_steps, **extra)
+    prm32 = D.dsdna_default_params(seed=0, ssdna_rule=1, graph_steps=args.graph_steps, **extra)
+    sim64 = D.DsDNA(cfg, prm64, device=0)
+    R, V, u, L, k = sim32.state()
+    sim64.set_state(R, V, u, L, k)
+
+    def term_error(state):
+        probe = D.DsDNA(cfg, prm32, device=0)
+        probe.set_state(*state)
+        ref = D.DsDNA(cfg, prm64, device=0)
+        ref.set_state(*state)
+        err = _per_term_error(D, probe, ref)
+        probe.close()
+        ref.close()
+        return err
+
+    err_start = term_error((R, V, u, L, k))
+    rows, stopped = [], {}
+    n_samples = max(1, args.samples)
+    for q in range(n_samples):
+        row = {}
+        for name, sim in (("fp32", sim32), ("fp64", sim64)):
+            if name in stopped:
+                continue
+            try:
+                sim.step(args.sample_every)
+            except D.DsdnaError as e:
+                stopped[name] = str(e)
+                continue
+            f, h = sim.bubbles(16)
+            row["unpaired_" + name] = float(np.mean(f))
+            row["bubbles_" + name] = [int(x) for x in np.sum(h, 0)]
+            row["step"] = int(sim.state()[4])
+        if not row:
+            break
+        rows.append(row)
+    err_last = None
+    if "fp64" not in stopped and rows:
+        err_last = term_error(sim64.state())
+    sim64.close()
+    k2 = np.asarray(cfg["k2_scale"])
+    log("denaturation: %d samples, stopped: %s" % (len(rows), stopped or "none"))
+    return {"k2_scale_range": [float(k2.min()), float(k2.max())], "dt": args.dt or 0.005, "samples": rows,
+            "stopped": stopped, "fp32_vs_fp64_start": err_start, "fp32_vs_fp64_last": err_last}
+
+
+def chain_report(D, cfg, sim, args):
+    """Single chain: end-to-end distance (unwrapped FP64 positions) and mean
+    twist per base-pair step every `sample_every` steps."""
+    ree, tw = [], []
+    n_samples = max(2, args.samples)
+    for _ in range(n_samples):
+        sim.step(args.sample_every)
+        b, p = sim.sites()
+        c = 0.5 * (p[0::2] + p[1::2])
+        ree.append(float(np.linalg.norm(c[-1] - c[0])))
+        t = c[1:] - c[:-1]
+        t /= np.linalg.norm(t, axis=1, keepdims=True)
+        bb = b[0::2] - b[1::2]
+        f0 = bb[:-1] - t * np.sum(bb[:-1] * t, 1, keepdims=True)
+        f1 = bb[1:] - t * np.sum(bb[1:] * t, 1, keepdims=True)
+        phi = np.arctan2(np.sum(np.cross(f0, f1) * t, 1), np.sum(f0 * f1, 1))
+        tw.append(float(np.degrees(phi[5:-5]).mean()))
+    ree, tw = np.array(ree), np.array(tw)
+    log("chain: <R_ee> %.2f, twist %.3f deg/bp over %d samples" % (ree.mean(), tw.mean(), len(ree)))
+    return {"end_to_end": {"mean": float(ree.mean()), "sem": float(ree.std(ddof=1) / np.sqrt(len(ree))),
+                           "samples": ree.tolist()},
+            "twist_deg_per_bp": {"mean": float(tw.mean()), "sem": float(tw.std(ddof=1) / np.sqrt(len(tw)))},
+            "sample_every": args.sample_every}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -186,6 +285,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--replica-steps", type=int, default=200)
     ap.add_argument("--no-replicas", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--dt", type=float, default=0.0, help="time step (0: the paper's 0.005)")
+    ap.add_argument("--sample-every", type=int, default=1000,
+                    help="denat / 10kbp: observables every this many steps")
+    ap.add_argument("--samples", type=int, default=20, help="denat / 10kbp: number of samples")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a counter calibration)")
     args = ap.parse_args()
@@ -213,11 +317,23 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy: %d MiB read + %d MiB written" % (args.calib_copy_mb, args.calib_copy_mb))
         del src, dst
+    extra = {"dt": args.dt} if args.dt > 0 else {}
     prm = D.dsdna_default_params(seed=0, cell_size=args.cell, hash_log2=args.hash_log2,
                                  graph_steps=args.graph_steps,
-                                 ssdna_rule=1 if args.config == "denat" else 0)
+                                 ssdna_rule=1 if args.config == "denat" else 0, **extra)
     sim = D.DsDNA(cfg, prm, device=0, stream=stream.cuda_stream)
     sim.thermalize(1.0, 0)
+    tuned = None
+    if not args.no_autotune and args.cell == 0.0 and args.hash_log2 == 0:
+        # cell edges from just above the largest cutoff, bucket counts around
+        # four per bead; the trial steps are part of the warm-up
+        base = int(np.ceil(np.log2(4 * n_nt)))
+        lgs = [lg for lg in (base - 1, base, base + 1) if 12 <= lg <= 24]
+        cells_try = [1.1236, 1.2, 1.35]
+        t0 = time.perf_counter()
+        bc, bl = sim.autotune(cells_try, lgs, 30)
+        tuned = {"cells": cells_try, "hash_log2": lgs, "trial_steps": 30, "cell": bc, "hash_log2_best": bl}
+        log("autotune: cell %.4f, 2^%d buckets (%.1f s)" % (bc, bl, time.perf_counter() - t0))
     h, nb, cells = sim.grid()
     log("grid: cell %.4f, %d buckets, cells %s" % (h, nb, list(cells)))
 
@@ -234,24 +350,40 @@ def main():
     t0 = time.perf_counter()
     left = args.steps
     chunk = max(1, min(args.steps, 5000))
+    failure = None
     while left > 0:
         k = min(left, chunk)
-        sim.step(k)
+        try:
+            sim.step(k)
+        except D.DsdnaError as e:
+            # the model's dynamics stopped (e.g. a backbone bond reached R0):
+            # outside the default workload this is reported, not hidden
+            if args.config == "1mbp":
+                raise
+            failure = {"status": int(e.status), "message": str(e)}
+            log("stopped: %s" % e)
+            break
         left -= k
         log("  %d steps left" % left)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    value = n_nt * args.steps / elapsed
-    ms_step = 1e3 * elapsed / args.steps
-    log("timed %d steps in %.3f s: %.4g nt-steps/s" % (args.steps, elapsed, value))
+    done = args.steps - left
+    value = n_nt * done / elapsed if done > 0 else 0.0
+    ms_step = 1e3 * elapsed / max(done, 1)
+    log("timed %d steps in %.3f s: %.4g nt-steps/s" % (done, elapsed, value))
 
     # per-kernel durations with HIP events around every launch, on the
     # stream the kernels run on
-    prof = sim.profile(args.profile_steps)
+    if failure is not None:
+        R, V, u, L, kk = sim.state()   # the state at the failing step: restart from it
+        sim.set_state(R, V, u, L, kk)
+    prof = sim.profile(args.profile_steps) if failure is None else {k: float("nan") for k in D.KERNELS}
     log("kernel means (ms): %s" % {k: round(v, 5) for k, v in prof.items()})
     kernels = {}
+    any_open = "periodic" not in cfg or not np.all(np.asarray(cfg["periodic"]))
+    bytes_per_nt = {k: v + (OPEN_EXTRA_BYTES_PER_NT[k] if any_open else 0) for k, v in KERNEL_BYTES_PER_NT.items()}
     for k, ms in prof.items():
-        bpn = KERNEL_BYTES_PER_NT.get(k)
+        bpn = bytes_per_nt.get(k)
         nbytes = bpn * n_nt if bpn is not None else SCAN_BYTES_PER_KEY * nb
         kernels[k] = {"ms": round(ms, 5), "bytes": int(nbytes), "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1)}
     dom = max(("step", "excl"), key=lambda k: prof[k])
@@ -260,7 +392,14 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "k_step<float>" if dom == "step" else "k_excl<float>",
-            "bytes_per_nt": KERNEL_BYTES_PER_NT[dom], "kernels": kernels}
+            "bytes_per_nt": bytes_per_nt[dom], "kernels": kernels}
+    observables = None
+    if failure is not None:
+        observables = {"stopped": failure}
+    elif args.config == "denat":
+        observables = denaturation_report(D, cfg, sim, args)
+    elif args.config == "10kbp":
+        observables = chain_report(D, cfg, sim, args)
     sim.close()
 
     batch = None
@@ -282,7 +421,7 @@ def main():
         "value": value,
         "unit": "nucleotide-timesteps/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": args.steps if failure is None else done,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True,
@@ -294,6 +433,8 @@ def main():
                    "forces": "f32", "state": "f64", "cell_size": h, "buckets": nb,
                    "graph_steps": args.graph_steps, "parallelism": "single GPU"},
         "roofline": roof,
+        "autotune": tuned,
+        "observables": observables,
         "batched_vs_single": batch,
         "cpu_baseline": cpu,
     }

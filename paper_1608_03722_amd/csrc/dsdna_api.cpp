@@ -167,6 +167,8 @@ static void fill_phys(dsdna_ctx *c)
     h.rc_x = TWO_16 * p.sig_x;
     h.cos_d = std::cos(p.d_dih);
     h.sin_d = std::sin(p.d_dih);
+    h.cos_a0 = std::cos(p.a0);
+    h.sin_a0 = std::sin(p.a0);
     h.kick = 0.5 * p.dt;
     h.inv_I = 1.0 / h.I;
     h.kick_M = h.kick / h.M;

@@ -31,6 +31,7 @@ struct Phys {
     double hb_pref;           // H-bond prefactor before the per-replica scale
     double rc_bb, rc_s, rc_x; // WCA cutoffs 2^(1/6) sigma
     double cos_d, sin_d;      // cos and sin of the dihedral phase
+    double cos_a0, sin_a0;    // cos and sin of the planarity angle
     double kick;              // dt / 2
     double inv_I, kick_M;     // 1 / I, (dt / 2) / M
     double inv_R0sq;          // 1 / R0^2

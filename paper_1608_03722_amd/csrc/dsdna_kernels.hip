@@ -486,12 +486,14 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
             }
             // stacking: Morse between consecutive patches
             if (mask & (1u << DSDNA_TERM_STACK)) {
+                // distance in FP64 and 1 - e^{-x} as -expm1(-x): near the
+                // minimum both factors would otherwise cancel in FP32
                 const D3 d64 = Pb - Pa;
                 const V3<real> d = cvt<real>(d64);
-                const real ir = rsq(dot(d, d));
-                const real r = dot(d, d) * ir;
-                const real ex = exp(-(real)ph.lam * (r - (real)ph.r0_m));
-                const V3<real> f = d * ((real)(2.0 * ph.K4 * ph.lam) * ex * ((real)1 - ex) * ir);
+                const double r64 = sqrt(dot(d64, d64));
+                const real em1 = expm1(-(real)ph.lam * (real)(r64 - ph.r0_m));
+                const real ir = rcp((real)r64);
+                const V3<real> f = d * ((real)(2.0 * ph.K4 * ph.lam) * ((real)1 + em1) * (-em1) * ir);
                 fPa = fPa + f;
                 fPb = fPb - f;
                 if (energies && own) {
@@ -529,15 +531,18 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
                 const real il = rsq(l11 * l22);
                 real c = dot(r1, r2) * il;
                 c = c > (real)1 ? (real)1 : (c < (real)-1 ? (real)-1 : c);
-                const real al = acos(c);
                 const real sn = sqrt((real)1 - c * c);
-                const real dUdc = -(real)ph.K5 * (al - (real)ph.a0) * rcp(sn);
+                // alpha - a0 as the angle of (cos, sin)(alpha - a0): no
+                // cancellation near the minimum
+                const real ca0 = (real)ph.cos_a0, sa0 = (real)ph.sin_a0;
+                const real da = atan2(sn * ca0 - c * sa0, c * ca0 + sn * sa0);
+                const real dUdc = -(real)ph.K5 * da * rcp(sn);
                 const V3<real> dca = r2 * il - r1 * (c * rcp(l11)), dcc = r1 * il - r2 * (c * rcp(l22));
                 const V3<real> fa = dca * (-dUdc), fc = dcc * (-dUdc);
                 fPa = fPa + fa;
                 fBb = fBb + fc;
                 fPb = fPb - (fa + fc);
-                if (energies && own) energies[DSDNA_TERM_PLANAR] += 0.5 * ph.K5 * ((double)al - ph.a0) * ((double)al - ph.a0);
+                if (energies && own) energies[DSDNA_TERM_PLANAR] += 0.5 * ph.K5 * (double)da * (double)da;
             }
         }
         put3(S.oStep[s][mi][0], fBa);

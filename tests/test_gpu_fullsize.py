@@ -87,3 +87,69 @@ def test_fp64_steps_1mbp(run):
     assert kg == k + 2
     assert np.abs(Rg - st.R).max() < 1e-9
     assert np.abs(Vg - st.V).max() < 1e-7 * max(1.0, np.abs(st.V).max())
+
+
+def _compare(D, sim, P, S, R, u, tol=1e-5):
+    b, p = O.sites_from_bodies(P, R, u)
+    st, _, fb, fp, E, op = O.forces(P, S, b, p, use_cells=True)
+    assert st == O.OK
+    for t, name in enumerate(D.TERMS):
+        gb, gp = sim.forces(t)
+        ref = np.concatenate([fb[t], fp[t]])
+        nr = np.linalg.norm(ref)
+        got = np.concatenate([gb, gp])
+        if nr < 1e-12:
+            assert np.abs(got).max() < 1e-7, name
+        else:
+            assert np.linalg.norm(got - ref) / nr <= tol, name
+    gb, gp = sim.forces(-1)
+    scale = np.concatenate([np.linalg.norm(fb, axis=2).sum(0), np.linalg.norm(fp, axis=2).sum(0)])
+    err = np.linalg.norm(np.concatenate([gb - fb.sum(0), gp - fp.sum(0)]), axis=1)
+    assert (err / np.maximum(scale, 1.0)).max() <= tol
+    return op
+
+
+def test_tethered_replicas_full_size():
+    """The 256 tethered replicas (500-5000 bp, pulled, 64 under end torque) in
+    one batched context: forces against the oracle on a thermal state, and
+    the forces of single replicas in contexts of their own are bit for bit
+    those of the batched context."""
+    from paper_1608_03722_amd import dsdna as D
+    cfg = synth.config_tethered_replicas()
+    keys = ("box", "periodic", "pull", "torque", "tether", "wall_z")
+    sim = D.DsDNA(cfg, D.dsdna_default_params(seed=0, graph_steps=50))
+    sim.thermalize(1.0, 0)
+    sim.step(200)
+    R, V, u, L, k = sim.state()
+    P = O.default_params(seed=0)
+    S = O.System(cfg["n_bp"], **{key: cfg[key] for key in keys})
+    _compare(D, sim, P, S, R, u)
+    fb_all, fp_all = sim.forces(-1)
+    off = np.concatenate([[0], np.cumsum(2 * cfg["n_bp"].astype(np.int64))])
+    for r in (0, 63, 64, 255):
+        sub = {"n_bp": cfg["n_bp"][r:r + 1], "bead": cfg["bead"][off[r]:off[r + 1]],
+               "patch": cfg["patch"][off[r]:off[r + 1]]}
+        sub.update({key: cfg[key][r:r + 1] for key in keys})
+        one = D.DsDNA(sub, D.dsdna_default_params(seed=0))
+        one.set_state(R[off[r]:off[r + 1]], V[off[r]:off[r + 1]], u[off[r]:off[r + 1]], L[off[r]:off[r + 1]], k)
+        gb, gp = one.forces(-1)
+        one.close()
+        assert np.array_equal(gb, fb_all[off[r]:off[r + 1]]) and np.array_equal(gp, fp_all[off[r]:off[r + 1]]), r
+    sim.close()
+
+
+def test_denaturation_full_size():
+    """64 x 2 kbp with scaled base-pair attraction and the single-strand rule:
+    forces and open flags against the oracle on a thermal state."""
+    from paper_1608_03722_amd import dsdna as D
+    cfg = synth.config_denaturation()
+    sim = D.DsDNA(cfg, D.dsdna_default_params(seed=0, ssdna_rule=1, graph_steps=50))
+    sim.thermalize(1.0, 0)
+    sim.step(1000)
+    R, V, u, L, k = sim.state()
+    P = O.default_params(seed=0, ssdna_rule=1)
+    S = O.System(cfg["n_bp"], box=cfg["box"], periodic=cfg["periodic"], k2_scale=cfg["k2_scale"])
+    op = _compare(D, sim, P, S, R, u)
+    assert np.array_equal(sim.bp_open(), op)
+    assert op.sum() > 0  # frayed ends and bubbles are present
+    sim.close()

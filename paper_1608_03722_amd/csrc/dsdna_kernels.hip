@@ -405,6 +405,38 @@ __device__ __forceinline__ V3<real> take_fex(const StepArgs &a, int64_t i)
     return v3<real>((real)((double)x * s), (real)((double)y * s), (real)((double)z * s));
 }
 
+// exp(x) - 1 and atan2(y, x) where the thermal arguments fall: Taylor
+// series on |x| < 1/2 (remainder below 6e-9 relative) and for |y| <= x / 4
+// (remainder below 1e-10 relative), the library functions elsewhere.
+template <typename real>
+__device__ __forceinline__ real expm1_small(real x)
+{
+    if (sizeof(real) == sizeof(double) || !(fabs(x) < (real)0.5)) return expm1(x);
+    const real h = x * (real)0.125;
+    real p = (real)1 + h;
+    p = (real)1 + x * ((real)1 / 7) * p;
+    p = (real)1 + x * ((real)1 / 6) * p;
+    p = (real)1 + x * (real)0.2 * p;
+    p = (real)1 + x * (real)0.25 * p;
+    p = (real)1 + x * ((real)1 / 3) * p;
+    p = (real)1 + x * (real)0.5 * p;
+    return x * p;
+}
+
+template <typename real>
+__device__ __forceinline__ real atan2_small(real y, real x)
+{
+    if (sizeof(real) == sizeof(double) || !(fabs(y) <= (real)0.25 * x)) return atan2(y, x);
+    const real t = y * rcp(x), t2 = t * t;
+    real p = (real)1 / 13;
+    p = (real)1 / 11 - t2 * p;
+    p = (real)1 / 9 - t2 * p;
+    p = (real)1 / 7 - t2 * p;
+    p = (real)0.2 - t2 * p;
+    p = (real)1 / 3 - t2 * p;
+    return t * ((real)1 - t2 * p);
+}
+
 // All conservative and external site forces of the calling thread's
 // nucleotide, restricted to the terms in `mask`, from the sites every thread
 // has staged (stage_site) beforehand; `fex` is the thread's excluded-volume
@@ -488,11 +520,14 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
             if (mask & (1u << DSDNA_TERM_STACK)) {
                 // distance in FP64 and 1 - e^{-x} as -expm1(-x): near the
                 // minimum both factors would otherwise cancel in FP32
+                // r - r0 = (r^2 - r0^2) / (r + r0) with the numerator in FP64
                 const D3 d64 = Pb - Pa;
                 const V3<real> d = cvt<real>(d64);
-                const double r64 = sqrt(dot(d64, d64));
-                const real em1 = expm1(-(real)ph.lam * (real)(r64 - ph.r0_m));
-                const real ir = rcp((real)r64);
+                const double r2_64 = dot(d64, d64);
+                const real r = sqrt((real)r2_64);
+                const real dlt = (real)(r2_64 - ph.r0_m * ph.r0_m) * rcp(r + (real)ph.r0_m);
+                const real em1 = expm1_small(-(real)ph.lam * dlt);
+                const real ir = rcp(r);
                 const V3<real> f = d * ((real)(2.0 * ph.K4 * ph.lam) * ((real)1 + em1) * (-em1) * ir);
                 fPa = fPa + f;
                 fPb = fPb - f;
@@ -535,7 +570,7 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
                 // alpha - a0 as the angle of (cos, sin)(alpha - a0): no
                 // cancellation near the minimum
                 const real ca0 = (real)ph.cos_a0, sa0 = (real)ph.sin_a0;
-                const real da = atan2(sn * ca0 - c * sa0, c * ca0 + sn * sa0);
+                const real da = atan2_small(sn * ca0 - c * sa0, c * ca0 + sn * sa0);
                 const real dUdc = -(real)ph.K5 * da * rcp(sn);
                 const V3<real> dca = r2 * il - r1 * (c * rcp(l11)), dcc = r1 * il - r2 * (c * rcp(l22));
                 const V3<real> fa = dca * (-dUdc), fc = dcc * (-dUdc);

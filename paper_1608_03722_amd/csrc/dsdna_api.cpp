@@ -105,7 +105,7 @@ static void free_state(dsdna_ctx *c)
     }
     dfree(b.Vf); dfree(b.Lf); dfree(b.Fb); dfree(b.Fp);
     dfree(b.rec); dfree(b.rcell); dfree(b.key); dfree(b.slot); dfree(b.srec); dfree(b.sid); dfree(b.scell);
-    dfree(b.fex); dfree(b.tflag); dfree(b.eex);
+    dfree(b.fex); dfree(b.cmask); dfree(b.eex);
     dfree(b.rep); dfree(b.tiles); dfree(b.eacc); dfree(b.open);
     dfree(b.diag_fb); dfree(b.diag_fp);
     Ctl *ctl = b.ctl;
@@ -310,7 +310,7 @@ static dsdna_status clear_accumulators(dsdna_ctx *c)
     Bufs &b = c->a.b;
     HIPCHK(c, hipMemsetAsync(b.count, 0, sizeof(int32_t) * (size_t)c->a.g.nbucket, c->stream));
     HIPCHK(c, hipMemsetAsync(b.fex, 0, sizeof(unsigned long long) * 4 * (size_t)c->N, c->stream));
-    HIPCHK(c, hipMemsetAsync(b.tflag, 0, sizeof(uint32_t) * (size_t)c->a.n_tiles, c->stream));
+    HIPCHK(c, hipMemsetAsync(b.cmask, 0, sizeof(uint32_t) * CMASK_WORDS * (size_t)c->a.n_tiles, c->stream));
     return DSDNA_OK;
 }
 
@@ -381,6 +381,9 @@ static dsdna_status rebin(dsdna_ctx *c, int which)
 {
     dsdna_status st = sync_args(c);
     if (st) return st;
+    // the histogram is cleared by the excluded-volume pass of a step, which
+    // may not have run since the last binning
+    HIPCHK(c, hipMemsetAsync(c->a.b.count, 0, sizeof(int32_t) * (size_t)c->a.g.nbucket, c->stream));
     HIPCHK(c, launch_bin(c->a, c->dA, which, c->stream));
     HIPCHK(c, launch_scan(c->a, c->stream));
     HIPCHK(c, launch_scatter(c->a, 0, c->stream));
@@ -455,7 +458,10 @@ static dsdna_status status_from_ctl(dsdna_ctx *c, const Ctl &h)
 static hipError_t enqueue_step(dsdna_ctx *c, int mode, int write_full, hipStream_t s)
 {
     hipError_t e = hipSuccess;
+    // the excluded-volume pass clears the histogram; without it (resume from
+    // stored forces, never captured in a graph) a memset does
     if (mode != MODE_FROM_FORCES) e = launch_excl(c->a, c->dA, c->prm.force_fp64, 0, -1, s);
+    else e = hipMemsetAsync(c->a.b.count, 0, sizeof(int32_t) * (size_t)c->a.g.nbucket, s);
     if (e == hipSuccess) e = launch_step(c->a, c->dA, c->prm.force_fp64, mode, write_full, s);
     if (e == hipSuccess) e = launch_scan(c->a, s);
     if (e == hipSuccess) e = launch_scatter(c->a, 1, s);
@@ -516,6 +522,7 @@ static dsdna_status run_steps(dsdna_ctx *c, int64_t n_steps, std::vector<double>
             hipEvent_t e0, e1, e2, e3, e4;
             HIPCHK(c, mark(&e0));
             if (mode != MODE_FROM_FORCES) HIPCHK(c, launch_excl(c->a, c->dA, c->prm.force_fp64, 0, -1, c->stream));
+            else HIPCHK(c, hipMemsetAsync(c->a.b.count, 0, sizeof(int32_t) * (size_t)c->a.g.nbucket, c->stream));
             HIPCHK(c, mark(&e1));
             HIPCHK(c, launch_step(c->a, c->dA, c->prm.force_fp64, mode, k == launches - 1, c->stream));
             HIPCHK(c, mark(&e2));
@@ -724,7 +731,7 @@ dsdna_status dsdna_set_topology(dsdna_ctx *c, int32_t n_rep, const int32_t *n_bp
     HIPCHK(c, dalloc(&b.rec, (size_t)N)); HIPCHK(c, dalloc(&b.rcell, (size_t)N));
     HIPCHK(c, dalloc(&b.srec, (size_t)N)); HIPCHK(c, dalloc(&b.sid, (size_t)N)); HIPCHK(c, dalloc(&b.scell, (size_t)N));
     HIPCHK(c, dalloc(&b.fex, 4 * (size_t)N));
-    HIPCHK(c, dalloc(&b.tflag, (size_t)a.n_tiles));
+    HIPCHK(c, dalloc(&b.cmask, CMASK_WORDS * (size_t)a.n_tiles));
     HIPCHK(c, dalloc(&b.eex, (size_t)N));
     HIPCHK(c, dalloc(&b.rep, (size_t)n_rep));
     HIPCHK(c, dalloc(&b.tiles, c->tiles_h.size()));

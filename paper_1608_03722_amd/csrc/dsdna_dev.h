@@ -15,6 +15,7 @@ constexpr int WG_THREADS = 256;
 constexpr int TILE_BP = 124;
 constexpr int TILE_NT = 2 * TILE_BP;
 constexpr int HALO_BP = 2;  // bending reaches two base pairs away
+constexpr int CMASK_WORDS = WG_THREADS / 32;  // contact-bit words per tile
 constexpr int SCAN_CHUNK = 4096;  // histogram entries per scan workgroup
 
 // Physics constants as the kernels use them (double; the force precision is
@@ -113,12 +114,14 @@ struct Bufs {
     BeadRec *srec;                      // records in key order (counting sort)
     int32_t *sid;                       // nucleotide of each sorted record
     int4 *scell;                        // cell of each sorted record (open edges only)
-    int32_t *count, *start, *bsum;      // per key (start: nbucket + 1)
+    int32_t *count, *start, *bsum;      // per key (start: nbucket + 1); per scan chunk
     // excluded-volume force per nt as exact fixed-point sums (x, y, z, unused;
     // units FIX32_UNIT or FIX64_UNIT), zero except beads with contacts;
-    // consumers read and clear the entries of flagged tiles
+    // consumers read and clear the entries whose contact bit is set
     unsigned long long *fex;
-    uint32_t *tflag;                    // per tile: some fex entry of the tile is nonzero
+    // contact bits, CMASK_WORDS words per tile: bit t of the tile's mask is
+    // set when tile thread t's nucleotide (2 (n - n0) + s) has a fex entry
+    uint32_t *cmask;
     double *eex;                        // excluded-volume energy per nt (diagnostics)
     RepInfo *rep;
     Tile *tiles;

@@ -13,8 +13,7 @@
 //              (FP64) and bin its new bead position (histogram atomics: the
 //              counting-sort count phase).
 //   k_scan_*   exclusive scan of the histogram (counting-sort offsets)
-//   k_scatter  counting-sort scatter of the bead records into key order;
-//              clears the histogram for the next step.
+//   k_scatter  counting-sort scatter of the bead records into key order
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -206,26 +205,45 @@ __device__ __forceinline__ int periodic_cell(uint32_t q, int ncell)
     return (int)(((uint64_t)q * (uint64_t)(uint32_t)ncell) >> 32);
 }
 
+// One dimension of cell_of: cell index and fixed-point coordinate of the
+// offset x from the replica origin; ok = false if x cannot be binned.
+struct CellDim {
+    int c;
+    uint32_t q;
+    bool ok;
+};
+
+__device__ __forceinline__ CellDim cell_dim(const RepInfo &ri, int k, double x)
+{
+    CellDim r;
+    if (ri.flags & (REP_PER_X << k)) {
+        double t = x * ri.inv_len[k];
+        r.ok = isfinite(t);
+        t = r.ok ? t - floor(t) : 0.0;
+        r.q = (uint32_t)(uint64_t)(t * 4294967296.0);
+        r.c = periodic_cell(r.q, ri.ncell[k]);
+    } else {
+        r.ok = fabs(x) < 1.0e6;  // also rejects NaN
+        const double xs = r.ok ? x : 0.0;
+        r.c = (int)floor(xs * ri.inv_h[k]);
+        r.q = (uint32_t)(uint64_t)(int64_t)rint(xs * OPEN_QINV);
+    }
+    return r;
+}
+
 __device__ __forceinline__ bool cell_of(const RepInfo &ri, D3 p, int c[3], uint32_t qc[3])
 {
-    const double x[3] = {p.x - ri.lo[0], p.y - ri.lo[1], p.z - ri.lo[2]};
-    bool ok = true;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        if (ri.flags & (REP_PER_X << k)) {
-            double t = x[k] * ri.inv_len[k];
-            ok = ok && isfinite(t);
-            t = ok ? t - floor(t) : 0.0;
-            qc[k] = (uint32_t)(uint64_t)(t * 4294967296.0);
-            c[k] = periodic_cell(qc[k], ri.ncell[k]);
-        } else {
-            ok = ok && (fabs(x[k]) < 1.0e6);  // also rejects NaN
-            const double xs = ok ? x[k] : 0.0;
-            c[k] = (int)floor(xs * ri.inv_h[k]);
-            qc[k] = (uint32_t)(uint64_t)(int64_t)rint(xs * OPEN_QINV);
-        }
-    }
-    return ok;
+    // values, not stores, merge across the branches: the arrays stay in
+    // registers
+    const CellDim X = cell_dim(ri, 0, p.x - ri.lo[0]), Y = cell_dim(ri, 1, p.y - ri.lo[1]),
+                  Z = cell_dim(ri, 2, p.z - ri.lo[2]);
+    c[0] = X.c;
+    c[1] = Y.c;
+    c[2] = Z.c;
+    qc[0] = X.q;
+    qc[1] = Y.q;
+    qc[2] = Z.q;
+    return X.ok && Y.ok && Z.ok;
 }
 
 __device__ __forceinline__ uint32_t bucket_of(const Grid &g, int cx, int cy, int cz, int rep)
@@ -389,8 +407,16 @@ __device__ __forceinline__ void stage_site(const StepArgs &a, TileLds<real> &S, 
     S.sP[st.l][0] = p.x; S.sP[st.l][1] = p.y; S.sP[st.l][2] = p.z;
 }
 
+// Contact bit of the calling thread's nucleotide in tile tix: its
+// excluded-volume accumulator may be nonzero.
+__device__ __forceinline__ bool contact_flag(const StepArgs &a, int tix)
+{
+    const uint32_t w = a.b.cmask[(int64_t)tix * CMASK_WORDS + (threadIdx.x >> 5)];
+    return (w >> (threadIdx.x & 31)) & 1u;
+}
+
 // Excluded-volume force of nucleotide i accumulated by k_excl (only read
-// when its tile is flagged); the entry is cleared for the next step.
+// when its contact bit is set); the entry is cleared for the next step.
 template <typename real>
 __device__ __forceinline__ V3<real> take_fex(const StepArgs &a, int64_t i)
 {
@@ -451,9 +477,9 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
     const Phys &ph = a.ph;
     const int nbp = ri.n_bp;
     __syncthreads();
-    // every thread has read (and consumed) the tile's accumulator flag
-    // before this barrier
-    if (t == 0) a.b.tflag[tile_index(a.n_tiles, a.n_tiles_pad)] = 0u;
+    // every thread has read (and consumed) its accumulator flag before this
+    // barrier
+    if (t < CMASK_WORDS) a.b.cmask[tile_index(a.n_tiles, a.n_tiles_pad) * CMASK_WORDS + t] = 0u;
 
     // --- hydrogen bonds and open flags (truncated harmonic between the
     //     patches of a base pair, Appendix A)
@@ -736,7 +762,7 @@ __global__ void __launch_bounds__(WG_THREADS, 5) k_step(const StepArgs *__restri
     D3 R = site.R, u = site.u;
     D3 V = v3(0.0, 0.0, 0.0), L = V;
     V3<real> fexv = v3<real>(0, 0, 0);
-    const bool flagged = mode != MODE_FROM_FORCES && a.b.tflag[tix] != 0u;
+    const bool flagged = mode != MODE_FROM_FORCES && contact_flag(a, tix);
     if (own) {
         V = ld3(a.b.V[cur], N, i);
         L = ld3(a.b.L[cur], N, i);
@@ -866,12 +892,8 @@ __global__ void __launch_bounds__(256) k_bin(const StepArgs *__restrict__ A, int
 constexpr double PAIR_FORCE_MAX_F32 = 33554432.0;  // 2^25 (|fx| + |fy| + |fz|)
 constexpr double PAIR_FORCE_MAX_F64 = 8388608.0;   // 2^23
 
-__device__ __forceinline__ int tile_of(const RepInfo &ri, int64_t j)
-{
-    return ri.tile0 + (int)((j - ri.off) >> 1) / TILE_BP;
-}
-
-// Add a fixed-point force to nucleotide j and flag its tile.
+// Add a fixed-point force to nucleotide j and set its contact bit (bit
+// 2 (n - n0) + s of its tile's mask, the tile thread that owns it).
 __device__ __forceinline__ void fex_add(const StepArgs &a, const RepInfo &ri, int64_t j, long long fx, long long fy,
                                         long long fz)
 {
@@ -879,7 +901,10 @@ __device__ __forceinline__ void fex_add(const StepArgs &a, const RepInfo &ri, in
     if (fx) atomicAdd(f, (unsigned long long)fx);
     if (fy) atomicAdd(f + 1, (unsigned long long)fy);
     if (fz) atomicAdd(f + 2, (unsigned long long)fz);
-    a.b.tflag[tile_of(ri, j)] = 1u;  // every writer stores the same value
+    const int64_t jj = j - ri.off;
+    const int tb = (int)(jj >> 1) / TILE_BP;
+    const int lt = (int)(jj - 2 * (int64_t)TILE_BP * tb);
+    atomicOr(&a.b.cmask[(int64_t)(ri.tile0 + tb) * CMASK_WORDS + (lt >> 5)], 1u << (lt & 31));
 }
 
 // Excluded volume (WCA, steric/ghost rule of Sec. 2), one thread per record
@@ -904,6 +929,13 @@ __global__ void __launch_bounds__(256) k_excl(const StepArgs *__restrict__ A, co
     const int per = (int)(gridDim.x >> 3);
     const int blk = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
     const int p = blk * (int)blockDim.x + (int)threadIdx.x;
+    // the histogram has served this cell list: clear it for the next
+    // binning (streaming stores while this kernel is bound by arithmetic)
+    {
+        int4 *c4 = reinterpret_cast<int4 *>(a.b.count);
+        const int n4 = a.g.nbucket >> 2, stride = (int)(gridDim.x * blockDim.x);
+        for (int k = (int)(blockIdx.x * blockDim.x + threadIdx.x); k < n4; k += stride) c4[k] = make_int4(0, 0, 0, 0);
+    }
     if (p >= a.n_nt) return;
     constexpr bool F64 = sizeof(real) == sizeof(double);
     const double unit = F64 ? FIX64_UNIT : FIX32_UNIT;
@@ -1135,6 +1167,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int *total)
     return base + incl - v;
 }
 
+// Total of each chunk of SCAN_CHUNK histogram entries.
 __global__ void __launch_bounds__(256) k_scan_reduce(const int *__restrict__ count, int *__restrict__ bsum,
                                                      const Ctl *ctl)
 {
@@ -1151,6 +1184,7 @@ __global__ void __launch_bounds__(256) k_scan_reduce(const int *__restrict__ cou
     if (threadIdx.x == 0) bsum[blockIdx.x] = total;
 }
 
+// Offsets of one chunk of SCAN_CHUNK keys from the preceding chunk totals.
 __global__ void __launch_bounds__(256) k_scan_down(const int *__restrict__ count, const int *__restrict__ bsum,
                                                    int *__restrict__ start, int nkeys, const Ctl *ctl)
 {
@@ -1186,14 +1220,13 @@ __global__ void __launch_bounds__(256) k_scan_down(const int *__restrict__ count
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == blockDim.x - 1) start[nkeys] = run;
 }
 
-// Counting-sort scatter: bead records into key order; clears the histogram
-// entries it used.  inc: also advance the step and flip the position
-// buffers.
+// Counting-sort scatter: bead records into key order.  inc: also advance
+// the step and flip the position buffers.
 __global__ void __launch_bounds__(256) k_scatter(const int *__restrict__ key, const int *__restrict__ slot,
                                                  const int *__restrict__ start, const BeadRec *__restrict__ rec,
                                                  const int4 *__restrict__ rcell, BeadRec *__restrict__ srec,
-                                                 int *__restrict__ sid, int4 *__restrict__ scell,
-                                                 int *__restrict__ count, Ctl *ctl, int64_t n, int inc, int any_open)
+                                                 int *__restrict__ sid, int4 *__restrict__ scell, Ctl *ctl,
+                                                 int64_t n, int inc, int any_open)
 {
     if (ctl->code != 0) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1203,7 +1236,6 @@ __global__ void __launch_bounds__(256) k_scatter(const int *__restrict__ key, co
         srec[p] = rec[i];
         sid[p] = (int)i;
         if (any_open) scell[p] = rcell[i];
-        count[k] = 0;
     }
     if (inc && i == 0) {
         ctl->step += 1;
@@ -1261,7 +1293,7 @@ __global__ void __launch_bounds__(WG_THREADS) k_diag(const StepArgs *__restrict_
     const int64_t step = a.b.ctl->step;
     const StagedSite site = load_site(a, ri, tile.n0, which);
     const int s = threadIdx.x & 1, bl = threadIdx.x >> 1, n = threadIdx.x < TILE_NT ? tile.n0 + bl : ri.n_bp;
-    const bool flagged = a.b.tflag[tix] != 0u;
+    const bool flagged = contact_flag(a, tix);
     const V3<real> fexv = (n < ri.n_bp && flagged) ? take_fex<real>(a, site.i) : v3<real>(0, 0, 0);
     stage_site(a, S, site);
     SiteForces<real> f = tile_forces<real>(a, S, ri, tile.rep, tile.n0, fexv, mask, step, e);
@@ -1313,7 +1345,7 @@ hipError_t launch_scatter(const StepArgs &a, int inc_step, hipStream_t s)
 {
     const unsigned nb = (unsigned)((a.n_nt + 255) / 256);
     hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, s, a.b.key, a.b.slot, a.b.start, a.b.rec, a.b.rcell,
-                       a.b.srec, a.b.sid, a.b.scell, a.b.count, a.b.ctl, a.n_nt, inc_step, a.g.any_open);
+                       a.b.srec, a.b.sid, a.b.scell, a.b.ctl, a.n_nt, inc_step, a.g.any_open);
     return hipGetLastError();
 }
 

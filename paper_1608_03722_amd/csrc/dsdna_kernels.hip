@@ -1086,29 +1086,30 @@ __global__ void __launch_bounds__(256) k_excl(const StepArgs *__restrict__ A, co
     // software pipeline: the records of the next U entries are in flight
     // while the current U are evaluated
     constexpr int U = 2;
+    // (two register sets, so the pipeline needs no copies)
     if (nfast > 0) {
-        BeadRec o[U];
-        int pp[U];
+        BeadRec oa[U], ob[U];
+        int pa[U], pb[U];
 #pragma unroll
         for (int v = 0; v < U; ++v) {
-            pp[v] = locate(v);
-            o[v] = srec[pp[v]];
+            pa[v] = locate(v);
+            oa[v] = srec[pa[v]];
         }
-        for (int k0 = 0; k0 < nfast; k0 += U) {
-            BeadRec on[U];
-            int pn[U];
+        for (int k0 = 0; k0 < nfast; k0 += 2 * U) {
 #pragma unroll
             for (int v = 0; v < U; ++v) {
-                pn[v] = locate(k0 + U + v);
-                on[v] = srec[pn[v]];
+                pb[v] = locate(k0 + U + v);
+                ob[v] = srec[pb[v]];
             }
 #pragma unroll
-            for (int v = 0; v < U; ++v) pair(o[v], pp[v], k0 + v < nfast);
+            for (int v = 0; v < U; ++v) pair(oa[v], pa[v], k0 + v < nfast);
 #pragma unroll
             for (int v = 0; v < U; ++v) {
-                o[v] = on[v];
-                pp[v] = pn[v];
+                pa[v] = locate(k0 + 2 * U + v);
+                oa[v] = srec[pa[v]];
             }
+#pragma unroll
+            for (int v = 0; v < U; ++v) pair(ob[v], pb[v], k0 + U + v < nfast);
         }
     }
     for (int k = nfast; k < total; ++k) {

@@ -907,6 +907,64 @@ __device__ __forceinline__ void fex_add(const StepArgs &a, const RepInfo &ri, in
     atomicOr(&a.b.cmask[(int64_t)(ri.tile0 + tb) * CMASK_WORDS + (lt >> 5)], 1u << (lt & 31));
 }
 
+// A bead of the sorted cell list as the excluded-volume search sees it.
+struct ExclBead {
+    BeadRec me;
+    uint32_t rep, mt, accept;
+    const RepInfo *ri;
+    bool px, py, pz;
+    int c[3];       // its cell
+    uint32_t kown;  // its bucket
+};
+
+template <bool any_open>
+__device__ __forceinline__ ExclBead excl_bead(const StepArgs &a, const BeadRec *__restrict__ srec,
+                                              const int4 *__restrict__ scell, int p)
+{
+    ExclBead B;
+    B.me = srec[p];
+    B.rep = B.me.tag >> 2;
+    B.mt = B.me.tag & 3u;
+    // partner types (bit 0 strand, bit 1 steric) this bead interacts with:
+    // the other strand always, its own strand steric-steric only
+    B.accept = (B.mt & 1u ? 0x5u : 0xAu) | (B.mt & 2u ? (B.mt & 1u ? 0x8u : 0x4u) : 0u);
+    B.ri = &a.b.rep[B.rep];
+    B.px = B.ri->flags & REP_PER_X;
+    B.py = B.ri->flags & REP_PER_Y;
+    B.pz = B.ri->flags & REP_PER_Z;
+    // any_open: some replica has an open edge; cells were stored by the
+    // binning.  Otherwise they follow from the periodic coordinates.
+    if (any_open) {
+        const int4 cc = scell[p];
+        B.c[0] = cc.x;
+        B.c[1] = cc.y;
+        B.c[2] = cc.z;
+    } else {
+        B.c[0] = periodic_cell(B.me.x, B.ri->ncell[0]);
+        B.c[1] = periodic_cell(B.me.y, B.ri->ncell[1]);
+        B.c[2] = periodic_cell(B.me.z, B.ri->ncell[2]);
+    }
+    B.kown = bucket_of(a.g, B.c[0], B.c[1], B.c[2], (int)B.rep);
+    return B;
+}
+
+// Does a ghost bead (cross-strand partners only, within rc_x) need the
+// neighbour cells below / above it along dimension k?  Periodic dims: from
+// its position inside the cell (the low 32 bits of q * ncell); open dims:
+// always.
+__device__ __forceinline__ void ghost_reach(const RepInfo &ri, int k, uint32_t q, double rc, bool &lo, bool &hi)
+{
+    if (!(ri.flags & (REP_PER_X << k))) {
+        lo = hi = true;
+        return;
+    }
+    const uint64_t frac = (uint64_t)(uint32_t)((uint64_t)q * (uint64_t)(uint32_t)ri.ncell[k]);
+    // rc in fractions of the cell, in 2^-32 units (the cell is wider than rc)
+    const uint64_t T = (uint64_t)(rc * (double)ri.ncell[k] * ri.inv_len[k] * 4294967296.0);
+    lo = frac < T;
+    hi = 4294967296ull - frac < T;
+}
+
 // Excluded volume (WCA, steric/ghost rule of Sec. 2), one thread per record
 // of the key-sorted cell list, so the lanes of a wave hold beads of
 // neighbouring cells and read overlapping candidate ranges.  A bead
@@ -914,11 +972,16 @@ __device__ __forceinline__ void fex_add(const StepArgs &a, const RepInfo &ri, in
 // with the steric beads of its own strand (sigma_s).  Each pair is evaluated
 // once (half stencil): the thread of a bead scans the later records of its
 // own bucket, the next cell of its row, the row above (dy = +1) and the three
-// rows of the next layer (dz = +1), as one stream of five record ranges.
-// Contacts are rare, so forces go to the sparse accumulators by atomics.
-// With FP32 forces the distance comes from the fixed-point coordinates; with
-// FP64 forces those only pre-select, and the distance is taken from the FP64
-// positions (minimum image along periodic edges).
+// rows of the next layer (dz = +1), as one stream of five record ranges.  A
+// ghost bead has only cross-strand partners, within rc_x of it, so it skips
+// the neighbour cells farther than rc_x from its position (exact: a skipped
+// cell holds no bead that close).  The candidate counts of a workgroup's
+// records vary a lot, so the records are handed to the threads in order of
+// decreasing count (a counting sort in LDS) and each wave's lanes carry
+// similar loads.  Contacts are rare, so forces go to the sparse accumulators
+// by atomics.  With FP32 forces the distance comes from the fixed-point
+// coordinates; with FP64 forces those only pre-select, and the distance is
+// taken from the FP64 positions (minimum image along periodic edges).
 template <typename real, bool energy, bool any_open>
 __global__ void __launch_bounds__(256) k_excl(const StepArgs *__restrict__ A, const BeadRec *__restrict__ srec,
                                               const int *__restrict__ sid, const int4 *__restrict__ scell,
@@ -928,7 +991,8 @@ __global__ void __launch_bounds__(256) k_excl(const StepArgs *__restrict__ A, co
     if (a.b.ctl->code != 0) return;
     const int per = (int)(gridDim.x >> 3);
     const int blk = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-    const int p = blk * (int)blockDim.x + (int)threadIdx.x;
+    const int p0 = blk * (int)blockDim.x;
+    const int t = threadIdx.x;
     // the histogram has served this cell list: clear it for the next
     // binning (streaming stores while this kernel is bound by arithmetic)
     {
@@ -936,37 +1000,110 @@ __global__ void __launch_bounds__(256) k_excl(const StepArgs *__restrict__ A, co
         const int n4 = a.g.nbucket >> 2, stride = (int)(gridDim.x * blockDim.x);
         for (int k = (int)(blockIdx.x * blockDim.x + threadIdx.x); k < n4; k += stride) c4[k] = make_int4(0, 0, 0, 0);
     }
-    if (p >= a.n_nt) return;
     constexpr bool F64 = sizeof(real) == sizeof(double);
-    const double unit = F64 ? FIX64_UNIT : FIX32_UNIT;
     const Phys &ph = a.ph;
-    const BeadRec me = srec[p];
+
+    // --- the candidate stream of record p0 + t: stream position k of range
+    // q sits at k + s_sh[q] in the sorted records; s_pre[q] = first stream
+    // position of range q.  Range 0: the rest of the own bucket and the next
+    // cell; ranges 1..4: rows (dy, dz) = (+1, 0), (-1, +1), (0, +1), (+1, +1)
+    // over the needed dx.  A range that wraps (periodic x or bucket index)
+    // is empty here and walked cell by cell later (bit q of s_wr).
+    __shared__ int s_sh[5][256];
+    __shared__ int s_pre[5][256];
+    __shared__ uint32_t s_pk[256];
+    __shared__ int s_tot[256];
+    __shared__ uint8_t s_wr[256];
+    __shared__ int s_hist[64];
+    __shared__ int s_order[256];
+    int key = 0;
+    {
+        int total = 0;
+        uint32_t wrapped = 0, pk = 0;
+        if (p0 + t < a.n_nt) {
+            const int p = p0 + t;
+            const ExclBead B = excl_bead<any_open>(a, srec, scell, p);
+            const RepInfo &ri = *B.ri;
+            const int ncx = ri.ncell[0], ncy = ri.ncell[1], ncz = ri.ncell[2];
+            auto wrap = [&](int v, int n, bool per_) { return per_ ? (v < 0 ? v + n : (v >= n ? v - n : v)) : v; };
+            bool xm = true, xp = true, ym = true, yp = true, zm = true, zp = true;
+            if (!(B.mt & 2u)) {
+                const double rc = ph.rc_x + 1e-3;
+                ghost_reach(ri, 0, B.me.x, rc, xm, xp);
+                ghost_reach(ri, 1, B.me.y, rc, ym, yp);
+                ghost_reach(ri, 2, B.me.z, rc, zm, zp);
+            }
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                int l0 = 0, h0 = 0;
+                bool wr = false;
+                if (q == 0) {
+                    wr = xp && ((B.px && B.c[0] == ncx - 1) || B.kown + 1u > a.g.mask);
+                    l0 = p + 1;
+                    h0 = wr ? p + 1 : start[B.kown + (xp ? 2 : 1)];
+                } else {
+                    const int dy = q == 1 ? 1 : q - 3, dz = q == 1 ? 0 : 1;
+                    const bool need = (dy > 0 ? yp : (dy < 0 ? ym : true)) && (dz == 0 || zp);
+                    if (need) {
+                        const int cy = wrap(B.c[1] + dy, ncy, B.py), cz = wrap(B.c[2] + dz, ncz, B.pz);
+                        const uint32_t k0 = bucket_of(a.g, B.c[0] - 1, cy, cz, (int)B.rep);
+                        wr = (B.px && (B.c[0] == 0 || B.c[0] == ncx - 1)) || k0 + 2u > a.g.mask;
+                        l0 = wr ? 0 : start[k0 + (xm ? 0 : 1)];
+                        h0 = wr ? 0 : start[k0 + (xp ? 3 : 2)];
+                    }
+                }
+                wrapped |= (uint32_t)wr << q;
+                s_pre[q][t] = total;
+                s_sh[q][t] = l0 - total;
+                if (q >= 1) pk |= (uint32_t)min(total, 127) << (8 * (q - 1));
+                total += h0 - l0;
+            }
+            // the dx reach (a ghost's) for the cell-by-cell walk
+            wrapped |= (xm ? 0x20u : 0u) | (xp ? 0x40u : 0u);
+            (void)zm;
+        }
+        s_pk[t] = pk;
+        s_tot[t] = total;
+        s_wr[t] = (uint8_t)wrapped;
+        key = min(total, 63);
+    }
+
+    // --- counting sort of the workgroup's records by decreasing count
+    if (t < 64) s_hist[t] = 0;
+    __syncthreads();
+    const int rank = atomicAdd(&s_hist[63 - key], 1);
+    __syncthreads();
+    if (t < 64) {
+        const int v = s_hist[t];
+        int x = v;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int o = __shfl_up(x, d, 64);
+            if (t >= d) x += o;
+        }
+        s_hist[t] = x - v;
+    }
+    __syncthreads();
+    s_order[s_hist[63 - key] + rank] = t;
+    __syncthreads();
+    const int src = s_order[t];
+    const int p = p0 + src;
+    if (p >= a.n_nt) return;
+
+    // --- the candidates of record p (its stream is LDS column src)
+    const double unit = F64 ? FIX64_UNIT : FIX32_UNIT;
+    const ExclBead B = excl_bead<any_open>(a, srec, scell, p);
+    const BeadRec me = B.me;
+    const uint32_t rep = B.rep, mt = B.mt, accept = B.accept;
+    const RepInfo &ri = *B.ri;
     const int64_t i = sid[p];
-    const uint32_t rep = me.tag >> 2;
-    const uint32_t mt = me.tag & 3u;
-    // partner types (bit 0 strand, bit 1 steric) this bead interacts with:
-    // the other strand always, its own strand steric-steric only
-    const uint32_t accept = (mt & 1u ? 0x5u : 0xAu) | (mt & 2u ? (mt & 1u ? 0x8u : 0x4u) : 0u);
-    const RepInfo &ri = a.b.rep[rep];
     const float qx = ri.qlen[0], qy = ri.qlen[1], qz = ri.qlen[2];
     const int64_t N = a.n_nt;
     const int buf = which < 0 ? a.b.ctl->par : which;
     const double *Rc = a.b.R[buf], *uc = a.b.u[buf];
-    const bool px = ri.flags & REP_PER_X, py = ri.flags & REP_PER_Y, pz = ri.flags & REP_PER_Z;
-    // any_open: some replica has an open edge; cells were stored by the
-    // binning.  Otherwise they follow from the periodic coordinates.
+    const bool px = B.px, py = B.py, pz = B.pz;
     const bool open_any = any_open && !(px && py && pz);
-    int c[3];
-    if (any_open) {
-        const int4 cc = scell[p];
-        c[0] = cc.x;
-        c[1] = cc.y;
-        c[2] = cc.z;
-    } else {
-        c[0] = periodic_cell(me.x, ri.ncell[0]);
-        c[1] = periodic_cell(me.y, ri.ncell[1]);
-        c[2] = periodic_cell(me.z, ri.ncell[2]);
-    }
+    const int *c = B.c;
     // FP64 forces: pre-select with a slack that covers the fixed-point error
     const float rcs2 = (float)(F64 ? (ph.rc_s + 1e-3) * (ph.rc_s + 1e-3) : ph.rc_s * ph.rc_s);
     const float rcx2 = (float)(F64 ? (ph.rc_x + 1e-3) * (ph.rc_x + 1e-3) : ph.rc_x * ph.rc_x);
@@ -1032,46 +1169,12 @@ __global__ void __launch_bounds__(256) k_excl(const StepArgs *__restrict__ A, co
         }
     };
 
-    // rows of three cells (dz, dy; cx-1..cx+1) are three consecutive buckets
-    // unless the row wraps (periodic x or bucket index)
-    const int ncx = ri.ncell[0], ncy = ri.ncell[1], ncz = ri.ncell[2];
-    auto wrap = [&](int v, int n, bool per_) { return per_ ? (v < 0 ? v + n : (v >= n ? v - n : v)) : v; };
-    // stream position k of range q sits at k + sh[q] in the sorted records;
-    // pre[q] = first stream position of range q.  Range 0: the rest of the
-    // own bucket and the next cell; ranges 1..4: rows (dy, dz) = (+1, 0),
-    // (-1, +1), (0, +1), (+1, +1).  The range of k < 127 is found by counting
-    // the bytes of the packed pre[1..4] that are <= k (no borrow between
-    // bytes while k, pre < 128); larger k take the plain search.
-    __shared__ int s_sh[5][256];
-    __shared__ int s_pre[5][256];
-    const int t = threadIdx.x;
-    int total = 0;
-    uint32_t wrapped = 0;  // bit q: range q is walked cell by cell
-    uint32_t pk = 0;
-    const uint32_t kown = bucket_of(a.g, c[0], c[1], c[2], (int)rep);
-#pragma unroll
-    for (int q = 0; q < 5; ++q) {
-        int l0, h0;
-        bool wr;
-        if (q == 0) {
-            wr = (px && c[0] == ncx - 1) || kown + 1u > a.g.mask;
-            l0 = p + 1;
-            h0 = wr ? p + 1 : start[kown + 2];
-        } else {
-            const int dy = q == 1 ? 1 : q - 3, dz = q == 1 ? 0 : 1;
-            const int cy = wrap(c[1] + dy, ncy, py), cz = wrap(c[2] + dz, ncz, pz);
-            const uint32_t k0 = bucket_of(a.g, c[0] - 1, cy, cz, (int)rep);
-            wr = (px && (c[0] == 0 || c[0] == ncx - 1)) || k0 + 2u > a.g.mask;
-            l0 = wr ? 0 : start[k0];
-            h0 = wr ? 0 : start[k0 + 3];
-        }
-        wrapped |= (uint32_t)wr << q;
-        s_pre[q][t] = total;
-        s_sh[q][t] = l0 - total;
-        if (q >= 1) pk |= (uint32_t)min(total, 127) << (8 * (q - 1));
-        total += h0 - l0;
-    }
-    // no barrier needed: each thread reads only its own LDS column
+    const int total = s_tot[src];
+    const uint32_t pk = s_pk[src];
+    const uint32_t wrapped = s_wr[src];
+    // the range of stream entry k < 127 is found by counting the bytes of the
+    // packed s_pre[1..4] that are <= k (no borrow between bytes while k, pre
+    // < 128); larger k take the plain search
     const int nfast = min(total, 127);
     // sorted position of stream entry k (clamped into the stream; entries
     // past the end are fetched again and ignored)
@@ -1081,12 +1184,12 @@ __global__ void __launch_bounds__(256) k_excl(const StepArgs *__restrict__ A, co
         kb |= kb << 8;
         kb |= kb << 16;
         const int q = __popc((kb - pk) & 0x80808080u);
-        return k + s_sh[q][t];
+        return k + s_sh[q][src];
     };
     // software pipeline: the records of the next U entries are in flight
-    // while the current U are evaluated
+    // while the current U are evaluated (two register sets, so the pipeline
+    // needs no copies)
     constexpr int U = 2;
-    // (two register sets, so the pipeline needs no copies)
     if (nfast > 0) {
         BeadRec oa[U], ob[U];
         int pa[U], pb[U];
@@ -1114,25 +1217,30 @@ __global__ void __launch_bounds__(256) k_excl(const StepArgs *__restrict__ A, co
     }
     for (int k = nfast; k < total; ++k) {
         int q = 0;
-        for (int r = 1; r < 5; ++r) q = (k >= s_pre[r][t]) ? r : q;
-        const int pq = k + s_sh[q][t];
+        for (int r = 1; r < 5; ++r) q = (k >= s_pre[r][src]) ? r : q;
+        const int pq = k + s_sh[q][src];
         pair(srec[pq], pq, true);
     }
-    // ranges that wrap: cell by cell (rare)
+    // ranges that wrap: cell by cell (rare), over the dx a ghost needs
+    if (wrapped & 0x1Fu) {
+        const int ncx = ri.ncell[0], ncy = ri.ncell[1], ncz = ri.ncell[2];
+        auto wrap = [&](int v, int n, bool per_) { return per_ ? (v < 0 ? v + n : (v >= n ? v - n : v)) : v; };
+        const int dxlo = (wrapped & 0x20u) ? -1 : 0, dxhi = (wrapped & 0x40u) ? 1 : 0;
 #pragma unroll 1
-    for (int q = 0; q < 5; ++q) {
-        if (!((wrapped >> q) & 1u)) continue;
-        if (q == 0) {
-            for (int q2 = p + 1; q2 < start[kown + 1]; ++q2) pair(srec[q2], q2, true);
-            const uint32_t kb = bucket_of(a.g, wrap(c[0] + 1, ncx, px), c[1], c[2], (int)rep);
-            for (int q2 = start[kb]; q2 < start[kb + 1]; ++q2) pair(srec[q2], q2, true);
-            continue;
-        }
-        const int dy = q == 1 ? 1 : q - 3, dz = q == 1 ? 0 : 1;
-        const int cy = wrap(c[1] + dy, ncy, py), cz = wrap(c[2] + dz, ncz, pz);
-        for (int dx = -1; dx <= 1; ++dx) {
-            const uint32_t kb = bucket_of(a.g, wrap(c[0] + dx, ncx, px), cy, cz, (int)rep);
-            for (int q2 = start[kb]; q2 < start[kb + 1]; ++q2) pair(srec[q2], q2, true);
+        for (int q = 0; q < 5; ++q) {
+            if (!((wrapped >> q) & 1u)) continue;
+            if (q == 0) {
+                for (int q2 = p + 1; q2 < start[B.kown + 1]; ++q2) pair(srec[q2], q2, true);
+                const uint32_t kb = bucket_of(a.g, wrap(c[0] + 1, ncx, px), c[1], c[2], (int)rep);
+                for (int q2 = start[kb]; q2 < start[kb + 1]; ++q2) pair(srec[q2], q2, true);
+                continue;
+            }
+            const int dy = q == 1 ? 1 : q - 3, dz = q == 1 ? 0 : 1;
+            const int cy = wrap(c[1] + dy, ncy, py), cz = wrap(c[2] + dz, ncz, pz);
+            for (int dx = dxlo; dx <= dxhi; ++dx) {
+                const uint32_t kb = bucket_of(a.g, wrap(c[0] + dx, ncx, px), cy, cz, (int)rep);
+                for (int q2 = start[kb]; q2 < start[kb + 1]; ++q2) pair(srec[q2], q2, true);
+            }
         }
     }
     if (overflow) raise_error(a.b.ctl, DSDNA_ENAN, a.b.ctl->step, i);

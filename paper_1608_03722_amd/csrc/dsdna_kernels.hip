@@ -1298,11 +1298,7 @@ __global__ void __launch_bounds__(256) k_scan_down(const int *__restrict__ count
                                                    int *__restrict__ start, int nkeys, const Ctl *ctl)
 {
     if (ctl->code != 0) return;
-    // offset of this chunk: sum of the preceding chunks' totals
-    int pre = 0;
-    for (int k = threadIdx.x; k < (int)blockIdx.x; k += blockDim.x) pre += bsum[k];
-    int ptot;
-    block_excl_scan(pre, &ptot);
+    // the chunk's counts first (in flight while the offset is summed)
     const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + threadIdx.x * 16;
     const int4 *c4 = reinterpret_cast<const int4 *>(count + base);
     int v[16];
@@ -1311,6 +1307,21 @@ __global__ void __launch_bounds__(256) k_scan_down(const int *__restrict__ count
         const int4 q = c4[k];
         v[4 * k] = q.x; v[4 * k + 1] = q.y; v[4 * k + 2] = q.z; v[4 * k + 3] = q.w;
     }
+    // offset of this chunk: sum of the preceding chunks' totals
+    int pre = 0;
+    const int nb = (int)blockIdx.x;
+    for (int k0 = threadIdx.x; k0 < nb; k0 += 8 * (int)blockDim.x) {
+        int w[8];  // eight loads in flight per pass
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int k = k0 + r * (int)blockDim.x;
+            w[r] = k < nb ? bsum[k] : 0;
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) pre += w[r];
+    }
+    int ptot;
+    block_excl_scan(pre, &ptot);
     int sum = 0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) sum += v[k];

@@ -982,8 +982,10 @@ __device__ __forceinline__ void ghost_reach(const RepInfo &ri, int k, uint32_t q
 // by atomics.  With FP32 forces the distance comes from the fixed-point
 // coordinates; with FP64 forces those only pre-select, and the distance is
 // taken from the FP64 positions (minimum image along periodic edges).
+constexpr int EXCL_THREADS = 256;  // records per workgroup (sorted by load together)
+
 template <typename real, bool energy, bool any_open>
-__global__ void __launch_bounds__(256) k_excl(const StepArgs *__restrict__ A, const BeadRec *__restrict__ srec,
+__global__ void __launch_bounds__(EXCL_THREADS) k_excl(const StepArgs *__restrict__ A, const BeadRec *__restrict__ srec,
                                               const int *__restrict__ sid, const int4 *__restrict__ scell,
                                               const int *__restrict__ start, int which)
 {
@@ -1009,13 +1011,13 @@ __global__ void __launch_bounds__(256) k_excl(const StepArgs *__restrict__ A, co
     // cell; ranges 1..4: rows (dy, dz) = (+1, 0), (-1, +1), (0, +1), (+1, +1)
     // over the needed dx.  A range that wraps (periodic x or bucket index)
     // is empty here and walked cell by cell later (bit q of s_wr).
-    __shared__ int s_sh[5][256];
-    __shared__ int s_pre[5][256];
-    __shared__ uint32_t s_pk[256];
-    __shared__ int s_tot[256];
-    __shared__ uint8_t s_wr[256];
+    __shared__ int s_sh[5][EXCL_THREADS];
+    __shared__ int s_pre[5][EXCL_THREADS];
+    __shared__ uint32_t s_pk[EXCL_THREADS];
+    __shared__ int s_tot[EXCL_THREADS];
+    __shared__ uint8_t s_wr[EXCL_THREADS];
     __shared__ int s_hist[64];
-    __shared__ int s_order[256];
+    __shared__ int s_order[EXCL_THREADS];
     int key = 0;
     {
         int total = 0;
@@ -1482,10 +1484,10 @@ template <typename real, bool energy>
 static void launch_excl_t(const StepArgs &a, const StepArgs *dA, int which, unsigned nb, hipStream_t s)
 {
     if (a.g.any_open)
-        hipLaunchKernelGGL((k_excl<real, energy, true>), dim3(nb), dim3(256), 0, s, dA, a.b.srec, a.b.sid,
+        hipLaunchKernelGGL((k_excl<real, energy, true>), dim3(nb), dim3(EXCL_THREADS), 0, s, dA, a.b.srec, a.b.sid,
                            a.b.scell, a.b.start, which);
     else
-        hipLaunchKernelGGL((k_excl<real, energy, false>), dim3(nb), dim3(256), 0, s, dA, a.b.srec, a.b.sid,
+        hipLaunchKernelGGL((k_excl<real, energy, false>), dim3(nb), dim3(EXCL_THREADS), 0, s, dA, a.b.srec, a.b.sid,
                            a.b.scell, a.b.start, which);
 }
 
@@ -1493,7 +1495,7 @@ hipError_t launch_excl(const StepArgs &a, const StepArgs *dA, int fp64, int ener
 {
     // whole groups of 8 workgroups: the kernel hands each XCD one contiguous
     // eighth of the sorted records
-    const unsigned nb = (unsigned)(((a.n_nt + 255) / 256 + 7) / 8 * 8);
+    const unsigned nb = (unsigned)(((a.n_nt + EXCL_THREADS - 1) / EXCL_THREADS + 7) / 8 * 8);
     if (fp64) {
         if (energy) launch_excl_t<double, true>(a, dA, which, nb, s);
         else launch_excl_t<double, false>(a, dA, which, nb, s);

@@ -35,15 +35,18 @@ KERNEL_BYTES_PER_NT = {
     # slot (4 + 4) written
     "step": 96 + 96 + 16 + 4 + 4,
     # own sorted record and nucleotide id (16 + 4); every record read once as
-    # a candidate (16)
+    # a candidate (16); plus the histogram it clears (per bucket, below)
     "excl": 16 + 4 + 16,
     # key, slot, start[key] (12); record read (16); sorted record and id
-    # written (16 + 4); histogram entry cleared (4)
-    "scatter": 12 + 16 + 16 + 4 + 4,
+    # written (16 + 4)
+    "scatter": 12 + 16 + 16 + 4,
 }
 # With an open edge the cell of every bead is stored and sorted as well.
 OPEN_EXTRA_BYTES_PER_NT = {"step": 16, "excl": 16, "scatter": 16 + 16}
-SCAN_BYTES_PER_KEY = 4 + 4 + 4  # histogram read by both passes, offsets written
+# Per bucket: the scan reads the histogram twice and writes the offsets; the
+# excluded-volume pass clears the histogram.
+SCAN_BYTES_PER_KEY = 4 + 4 + 4
+EXCL_BYTES_PER_KEY = 4
 KERNEL_SOURCES = ("paper_1608_03722_amd/csrc/dsdna_kernels.hip", "paper_1608_03722_amd/csrc/dsdna_dev.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_1mbp_traffic.json")
 
@@ -385,6 +388,8 @@ def main():
     for k, ms in prof.items():
         bpn = bytes_per_nt.get(k)
         nbytes = bpn * n_nt if bpn is not None else SCAN_BYTES_PER_KEY * nb
+        if k == "excl":
+            nbytes += EXCL_BYTES_PER_KEY * nb
         kernels[k] = {"ms": round(ms, 5), "bytes": int(nbytes), "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1)}
     dom = max(("step", "excl"), key=lambda k: prof[k])
     achieved = kernels[dom]["bytes"] / (prof[dom] * 1e-3) / 1e9

@@ -71,6 +71,22 @@ template <>
 __device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 template <>
 __device__ __forceinline__ double rcp<double>(double x) { return 1.0 / x; }
+// 1/sqrt(x) in FP64 for x > 0: the hardware estimate refined by two Newton
+// steps (each doubles the correct bits).
+__device__ __forceinline__ double rsq64(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    y = __fma_rn(0.5 * y, __fma_rn(-x * y, y, 1.0), y);
+    return __fma_rn(0.5 * y, __fma_rn(-x * y, y, 1.0), y);
+}
+
+// Square root: the hardware approximation in FP32 (forces), exact in FP64.
+template <typename T>
+__device__ __forceinline__ T fsqrt(T x);
+template <>
+__device__ __forceinline__ float fsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+template <>
+__device__ __forceinline__ double fsqrt<double>(double x) { return sqrt(x); }
 template <typename T>
 __device__ __forceinline__ T rsq(T x);
 template <>
@@ -172,10 +188,18 @@ __device__ __forceinline__ void noise6f(uint64_t seed, int kind, uint64_t step, 
     }
 #pragma unroll
     for (int k = 0; k < 6; k += 2) {
+        // ln u without a branch.  Below 1/2: the log of u.  From 1/2 up,
+        // u = 1 - t with t = (2^32 - 1 - a + 1/2) 2^-32 formed exactly, and
+        // ln(1 - t) = log(y) t / (1 - y) for y = 1 - t rounded (Goldberg's
+        // log1p identity: exact up to the log's and reciprocal's own
+        // errors, 5e-7 relative at worst), -t where y rounds to 1.
         const uint32_t a = w[k];
-        const float lnu = a < 0x80000000u ? __logf(((float)a + 0.5f) * 0x1p-32f)
-                                          : log1pf(-(((float)(0xFFFFFFFFu - a) + 0.5f) * 0x1p-32f));
-        const float rad = sqrtf(-2.0f * lnu);
+        const bool up = a >= 0x80000000u;
+        const float t = ((float)(up ? ~a : a) + 0.5f) * 0x1p-32f;
+        const float y = up ? 1.0f - t : t;
+        const float L = __logf(y);
+        const float lnu = !up ? L : (y == 1.0f ? -t : L * t * __builtin_amdgcn_rcpf(1.0f - y));
+        const float rad = __builtin_amdgcn_sqrtf(-2.0f * lnu);
         const float turns = ((float)w[k + 1] + 0.5f) * 0x1p-32f;
         xi[k] = rad * __builtin_amdgcn_cosf(turns);
         xi[k + 1] = rad * __builtin_amdgcn_sinf(turns);
@@ -494,7 +518,8 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
             open = r > ph.rc_hb;
             if (!open && (mask & (1u << DSDNA_TERM_HBOND))) {
                 const real pref = (real)(ph.hb_pref * k2s);
-                const real c = (ph.r0_hb == 0.0) ? (real)2 * pref : (real)2 * pref * ((real)1 - (real)(ph.r0_hb / r));
+                real c = (real)2 * pref;
+                if (ph.r0_hb != 0.0) c *= (real)1 - (real)(ph.r0_hb / r);  // uniform: no division at r0 = 0
                 f = cvt<real>(d64) * c;
                 if (energies && q >= HALO_BP && q < TILE_BP + HALO_BP)
                     energies[DSDNA_TERM_HBOND] += ph.hb_pref * k2s *
@@ -507,8 +532,8 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
     __syncthreads();
 
     const bool rule = ph.ssdna_rule != 0;
-    // --- backbone steps: FENE + WCA core, Morse, dihedral, planarity on the
-    //     pair of nucleotides (s, m), (s, m+1), m = n0 - 1 + mi
+    // --- backbone steps: FENE + WCA core, Morse, planarity on the pair of
+    //     nucleotides (s, m), (s, m+1), m = n0 - 1 + mi
     for (int q = t; q < 2 * (TILE_BP + 1); q += blockDim.x) {
         const int s = q & 1, mi = q >> 1, m = n0 - 1 + mi;
         V3<real> fBa = v3<real>(0, 0, 0), fPa = fBa, fBb = fBa, fPb = fBa;
@@ -550,7 +575,7 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
                 const D3 d64 = Pb - Pa;
                 const V3<real> d = cvt<real>(d64);
                 const double r2_64 = dot(d64, d64);
-                const real r = sqrt((real)r2_64);
+                const real r = fsqrt((real)r2_64);
                 const real dlt = (real)(r2_64 - ph.r0_m * ph.r0_m) * rcp(r + (real)ph.r0_m);
                 const real em1 = expm1_small(-(real)ph.lam * dlt);
                 const real ir = rcp(r);
@@ -562,41 +587,21 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
                     energies[DSDNA_TERM_STACK] += ph.K4 * (1.0 - e64) * (1.0 - e64);
                 }
             }
-            const V3<real> b1 = cvt<real>(Pa - Ba), b2 = cvt<real>(Pb - Pa), b3 = cvt<real>(Bb - Pb);
-            // helical twist: dihedral of (B_m, P_m, P_m+1, B_m+1); gradient as in
-            // Blondel & Karplus (1996), free of the 1/sin(phi) singularity
-            const bool masked = rule && S.sOpen[mi + 1] && S.sOpen[mi + 2] && (S.sOpen[mi] || S.sOpen[mi + 3]);
-            if ((mask & (1u << DSDNA_TERM_TWIST)) && !masked) {
-                const V3<real> A = cross(b1, b2), B = cross(b2, b3);
-                const real AA = dot(A, A), BB = dot(B, B), GG = dot(b2, b2);
-                const real iG = rsq(GG), lG = GG * iG;
-                const real inv = rsq(AA * BB);
-                const real cphi = dot(A, B) * inv, sphi = lG * dot(b1, B) * inv;
-                const real cd = (real)ph.cos_d, sd = (real)ph.sin_d;
-                // -dU/dphi = K3 sin(phi - d)
-                const real mdU = (real)ph.K3 * (sphi * cd - cphi * sd);
-                const real FG = dot(b1, b2), HG = -dot(b3, b2);
-                const real iAA = rcp(AA), iBB = rcp(BB);
-                const V3<real> tA = A * (lG * iAA), tB = B * (lG * iBB);
-                const V3<real> sA = A * (FG * iAA * iG), sB = B * (HG * iBB * iG);
-                fBa = fBa + (-tA) * mdU;
-                fPa = fPa + (tA + sA - sB) * mdU;
-                fPb = fPb + (-tB - sA + sB) * mdU;
-                fBb = fBb + tB * mdU;
-                if (energies && own) energies[DSDNA_TERM_TWIST] += ph.K3 * (1.0 + (double)cphi * ph.cos_d + (double)sphi * ph.sin_d);
-            }
             // planarity: angle at P_m+1 between P_m and B_m+1, (K5/2)(alpha - a0)^2
             if (mask & (1u << DSDNA_TERM_PLANAR)) {
-                const V3<real> r1 = -b2, r2 = b3;
-                const real l11 = dot(r1, r1), l22 = dot(r2, r2);
-                const real il = rsq(l11 * l22);
-                real c = dot(r1, r2) * il;
-                c = c > (real)1 ? (real)1 : (c < (real)-1 ? (real)-1 : c);
-                const real sn = sqrt((real)1 - c * c);
-                // alpha - a0 as the angle of (cos, sin)(alpha - a0): no
-                // cancellation near the minimum
-                const real ca0 = (real)ph.cos_a0, sa0 = (real)ph.sin_a0;
-                const real da = atan2_small(sn * ca0 - c * sa0, c * ca0 + sn * sa0);
+                // cos and sin of the angle in FP64 (alpha - a0 is small near
+                // the minimum), then alpha - a0 as the angle of (cos, sin)
+                // rotated by -a0: no cancellation
+                const D3 r1d = Pa - Pb, r2d = Bb - Pb;
+                const double l11d = dot(r1d, r1d), l22d = dot(r2d, r2d);
+                const double ild = rsq64(l11d * l22d);
+                double cd = dot(r1d, r2d) * ild;
+                cd = cd > 1.0 ? 1.0 : (cd < -1.0 ? -1.0 : cd);
+                const double s2 = 1.0 - cd * cd, snd = s2 > 0.0 ? s2 * rsq64(s2) : 0.0;
+                const real da = atan2_small((real)(snd * ph.cos_a0 - cd * ph.sin_a0),
+                                            (real)(cd * ph.cos_a0 + snd * ph.sin_a0));
+                const V3<real> r1 = cvt<real>(r1d), r2 = cvt<real>(r2d);
+                const real l11 = (real)l11d, l22 = (real)l22d, il = (real)ild, c = (real)cd, sn = (real)snd;
                 const real dUdc = -(real)ph.K5 * da * rcp(sn);
                 const V3<real> dca = r2 * il - r1 * (c * rcp(l11)), dcc = r1 * il - r2 * (c * rcp(l22));
                 const V3<real> fa = dca * (-dUdc), fc = dcc * (-dUdc);
@@ -610,6 +615,48 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
         put3(S.oStep[s][mi][1], fPa);
         put3(S.oStep[s][mi][2], fBb);
         put3(S.oStep[s][mi][3], fPb);
+    }
+    // --- helical twist of the same backbone steps in a pass of its own (its
+    //     FP64 intermediates are not live with the other terms'); each
+    //     thread adds to the outboxes of the step it wrote above
+    for (int q = t; q < 2 * (TILE_BP + 1); q += blockDim.x) {
+        const int s = q & 1, mi = q >> 1, m = n0 - 1 + mi;
+        if (!(m >= 0 && m + 1 < nbp)) continue;
+        const int la = 2 * (mi + 1) + s, lb = la + 2;
+        const D3 Ba = lds3(S.sB, la), Pa = lds3(S.sP, la), Bb = lds3(S.sB, lb), Pb = lds3(S.sP, lb);
+        const bool own = mi >= 1;
+        const D3 b1d = Pa - Ba, b2d = Pb - Pa, b3d = Bb - Pb;
+        V3<real> fBa = v3<real>(0, 0, 0), fPa = fBa, fBb = fBa, fPb = fBa;
+        // helical twist: dihedral of (B_m, P_m, P_m+1, B_m+1); gradient as in
+        // Blondel & Karplus (1996), free of the 1/sin(phi) singularity
+        const bool masked = rule && S.sOpen[mi + 1] && S.sOpen[mi + 2] && (S.sOpen[mi] || S.sOpen[mi + 3]);
+        if ((mask & (1u << DSDNA_TERM_TWIST)) && !masked) {
+            // the angle in FP64: near the minimum sin(phi - d) is a small
+            // difference of O(1) products; the gradient directions in the
+            // force precision
+            const D3 Ad = cross(b1d, b2d), Bd = cross(b2d, b3d);
+            const double AAd = dot(Ad, Ad), BBd = dot(Bd, Bd), GGd = dot(b2d, b2d);
+            const double iGd = rsq64(GGd), lGd = GGd * iGd;
+            const double inv = rsq64(AAd * BBd);
+            const double cphi = dot(Ad, Bd) * inv, sphi = lGd * dot(b1d, Bd) * inv;
+            // -dU/dphi = K3 sin(phi - d)
+            const real mdU = (real)(ph.K3 * (sphi * ph.cos_d - cphi * ph.sin_d));
+            const V3<real> A = cvt<real>(Ad), B = cvt<real>(Bd);
+            const real AA = (real)AAd, BB = (real)BBd, iG = (real)iGd, lG = (real)lGd;
+            const real FG = (real)dot(b1d, b2d), HG = (real)(-dot(b3d, b2d));
+            const real iAA = rcp(AA), iBB = rcp(BB);
+            const V3<real> tA = A * (lG * iAA), tB = B * (lG * iBB);
+            const V3<real> sA = A * (FG * iAA * iG), sB = B * (HG * iBB * iG);
+            fBa = fBa + (-tA) * mdU;
+            fPa = fPa + (tA + sA - sB) * mdU;
+            fPb = fPb + (-tB - sA + sB) * mdU;
+            fBb = fBb + tB * mdU;
+            if (energies && own) energies[DSDNA_TERM_TWIST] += ph.K3 * (1.0 + cphi * ph.cos_d + sphi * ph.sin_d);
+        }
+        put3(S.oStep[s][mi][0], get3(S.oStep[s][mi][0]) + fBa);
+        put3(S.oStep[s][mi][1], get3(S.oStep[s][mi][1]) + fPa);
+        put3(S.oStep[s][mi][2], get3(S.oStep[s][mi][2]) + fBb);
+        put3(S.oStep[s][mi][3], get3(S.oStep[s][mi][3]) + fPb);
     }
     // --- Kratky-Porod bending on patches (s, m-1), (s, m), (s, m+1)
     for (int q = t; q < 2 * (TILE_BP + 2); q += blockDim.x) {
@@ -760,18 +807,26 @@ __global__ void __launch_bounds__(WG_THREADS, 5) k_step(const StepArgs *__restri
     const bool own = n < ri.n_bp;
     const int64_t i = site.i;
     D3 R = site.R, u = site.u;
-    D3 V = v3(0.0, 0.0, 0.0), L = V;
     V3<real> fexv = v3<real>(0, 0, 0);
     const bool flagged = mode != MODE_FROM_FORCES && contact_flag(a, tix);
+    if (own && flagged) fexv = take_fex<real>(a, i);
+    const bool frozen = (ri.flags & REP_TETHER) && n == 0;
+    const bool langevin = own && !frozen && ph.gamma > 0.0 && mode != MODE_FROM_FORCES;
+    SiteForces<real> f;
+    f.b = v3<real>(0, 0, 0);
+    f.p = f.b;
+    if (mode != MODE_FROM_FORCES) {
+        stage_site(a, S, site);
+        f = tile_forces<real>(a, S, ri, tile.rep, tile.n0, fexv, ALL_TERMS, step, nullptr);
+    }
+    // velocities and noise only now: they are not live through the force
+    // phase, and the noise is drawn while the velocity loads are in flight
+    D3 V = v3(0.0, 0.0, 0.0), L = V;
     if (own) {
         V = ld3(a.b.V[cur], N, i);
         L = ld3(a.b.L[cur], N, i);
-        if (flagged) fexv = take_fex<real>(a, i);
     }
-    // the thread's noise numbers while the loads are in flight
     real xi[6] = {0, 0, 0, 0, 0, 0};
-    const bool frozen = (ri.flags & REP_TETHER) && n == 0;
-    const bool langevin = own && !frozen && ph.gamma > 0.0 && mode != MODE_FROM_FORCES;
     if (langevin) {
         if (sizeof(real) == sizeof(double)) {
             double x64[6];
@@ -782,13 +837,6 @@ __global__ void __launch_bounds__(WG_THREADS, 5) k_step(const StepArgs *__restri
             noise6f(ph.seed, ph.noise_kind, (uint64_t)step, (uint32_t)i, 0u, x32);
             for (int k = 0; k < 6; ++k) xi[k] = (real)x32[k];
         }
-    }
-    SiteForces<real> f;
-    f.b = v3<real>(0, 0, 0);
-    f.p = f.b;
-    if (mode != MODE_FROM_FORCES) {
-        stage_site(a, S, site);
-        f = tile_forces<real>(a, S, ri, tile.rep, tile.n0, fexv, ALL_TERMS, step, nullptr);
     }
     D3 bead_new = v3(0.0, 0.0, 0.0);
     if (own) {
@@ -844,8 +892,16 @@ __global__ void __launch_bounds__(WG_THREADS, 5) k_step(const StepArgs *__restri
             L = L + tau * ph.kick;
             R = R + V * ph.dt;
             const D3 w = L * ph.inv_I;
-            const double wl = sqrt(dot(w, w));
-            if (wl > 0.0) u = rotate(u, w * (1.0 / wl), wl * ph.dt);
+            const double w2 = dot(w, w);
+            if (w2 > 0.0) {
+                // 1/|w| from the hardware estimate refined by two Newton
+                // steps (each doubles the correct bits), then the unit axis
+                // and |w| dt from it
+                double ri = __builtin_amdgcn_rsq(w2);
+                ri = __fma_rn(0.5 * ri, __fma_rn(-w2 * ri, ri, 1.0), ri);
+                ri = __fma_rn(0.5 * ri, __fma_rn(-w2 * ri, ri, 1.0), ri);
+                u = rotate(u, w * ri, w2 * ri * ph.dt);
+            }
             // renormalise: |u|^2 = 1 up to rounding, so one Newton step from 1
             // gives 1/|u| to double precision
             u = u * (1.5 - 0.5 * dot(u, u));

@@ -1123,7 +1123,9 @@ __global__ void __launch_bounds__(EXCL_THREADS) k_excl(const StepArgs *__restric
         s_pk[t] = pk;
         s_tot[t] = total;
         s_wr[t] = (uint8_t)wrapped;
-        key = min(total, 63);
+        // (clamped: every key is a histogram bin, so s_order below is always a
+        // full permutation of the workgroup's threads)
+        key = min(max(total, 0), 63);
     }
 
     // --- counting sort of the workgroup's records by decreasing count

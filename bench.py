@@ -43,10 +43,10 @@ KERNEL_BYTES_PER_NT = {
 }
 # With an open edge the cell of every bead is stored and sorted as well.
 OPEN_EXTRA_BYTES_PER_NT = {"step": 16, "excl": 16, "scatter": 16 + 16}
-# Per bucket: the scan reads the histogram twice and writes the offsets; the
-# excluded-volume pass clears the histogram.
-SCAN_BYTES_PER_KEY = 4 + 4 + 4
-EXCL_BYTES_PER_KEY = 4
+# Per bucket: the scan reads the 16-bit histogram twice and writes the 32-bit
+# offsets; the excluded-volume pass clears the histogram.
+SCAN_BYTES_PER_KEY = 2 + 2 + 4
+EXCL_BYTES_PER_KEY = 2
 KERNEL_SOURCES = ("paper_1608_03722_amd/csrc/dsdna_kernels.hip", "paper_1608_03722_amd/csrc/dsdna_dev.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_1mbp_traffic.json")
 

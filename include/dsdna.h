@@ -26,7 +26,7 @@
  *     not thread-safe.  Functions that return data synchronise the stream.
  *   - Every function returns a dsdna_status; DSDNA_OK is 0.  On failure
  *     dsdna_last_error() describes the cause (with step and nucleotide for
- *     DSDNA_EBOND, DSDNA_ENAN, DSDNA_EWALL).
+ *     DSDNA_EBOND, DSDNA_ENAN, DSDNA_EWALL, DSDNA_EDOMAIN, DSDNA_ECELL).
  *   - Call order: create -> set_topology -> (set_box, set_external,
  *     set_k2_scale) -> set_sites or set_state -> (thermalize or
  *     set_velocities) -> step ...  Out-of-order calls return DSDNA_ESTATE.
@@ -54,7 +54,9 @@ typedef enum {
                            with FP64 forces: overlapping beads)             */
     DSDNA_ESTATE = 6,   /* call out of order                                 */
     DSDNA_EWALL = 7,    /* a bead of a tethered replica reached its wall     */
-    DSDNA_EDOMAIN = 8   /* a bead left the representable coordinate range   */
+    DSDNA_EDOMAIN = 8,  /* a bead left the representable coordinate range   */
+    DSDNA_ECELL = 9     /* more than 65535 beads in one cell-list bucket
+                           (raise hash_log2)                                 */
 } dsdna_status;
 
 /* Slots of the per-term force and energy arrays. */
@@ -171,8 +173,8 @@ dsdna_status dsdna_thermalize(dsdna_ctx *ctx, double kT, uint64_t seed);
 
 /* Advance n_steps >= 0 time steps.  Enqueued on the stream; returns after
  * reading the device status word once.  On DSDNA_EBOND / DSDNA_ENAN /
- * DSDNA_EWALL / DSDNA_EDOMAIN the remaining steps are skipped and the state
- * is left at the step where the error was found. */
+ * DSDNA_EWALL / DSDNA_EDOMAIN / DSDNA_ECELL the remaining steps are skipped and
+ * the state is left at the step where the error was found. */
 dsdna_status dsdna_step(dsdna_ctx *ctx, int64_t n_steps);
 
 /* Current full-step state: body centres R, velocities V, axes u, angular

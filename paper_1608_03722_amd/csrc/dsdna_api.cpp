@@ -109,7 +109,8 @@ static void free_state(dsdna_ctx *c)
     dfree(b.rep); dfree(b.tiles); dfree(b.eacc); dfree(b.open);
     dfree(b.diag_fb); dfree(b.diag_fp);
     Ctl *ctl = b.ctl;
-    int32_t *count = b.count, *start = b.start, *bsum = b.bsum;
+    uint32_t *count = b.count;
+    int32_t *start = b.start, *bsum = b.bsum;
     std::memset(&b, 0, sizeof b);
     b.ctl = ctl;
     b.count = count; b.start = start; b.bsum = bsum;
@@ -118,7 +119,8 @@ static void free_state(dsdna_ctx *c)
 static void free_grid(dsdna_ctx *c)
 {
     dfree(c->a.b.count); dfree(c->a.b.start); dfree(c->a.b.bsum);
-    c->a.b.count = c->a.b.start = c->a.b.bsum = nullptr;
+    c->a.b.count = nullptr;
+    c->a.b.start = c->a.b.bsum = nullptr;
 }
 
 // Upload the argument block if it changed since the last upload.  Never
@@ -256,6 +258,9 @@ static dsdna_status configure_grid(dsdna_ctx *c)
         while ((int64_t(1) << lg) < want && lg < 24) ++lg;
     }
     if (lg < 12 || lg > 28) return fail(c, DSDNA_EINVAL, "hash_log2 %d out of [12, 28]", lg);
+    // bucket counters are 16 bits: keep the mean load far below that
+    if (c->N > ((int64_t)1 << lg) * 4096)
+        return fail(c, DSDNA_EINVAL, "hash_log2 %d too small for %lld nucleotides", lg, (long long)c->N);
     const uint32_t nb = 1u << lg, mask = nb - 1u;
     uint32_t A = 1031u, B = 1031u * 1031u;
     if (all_per_same) {
@@ -289,10 +294,10 @@ static dsdna_status configure_grid(dsdna_ctx *c)
     }
     if (g.nbucket != (int32_t)nb || !c->a.b.count) {
         free_grid(c);
-        HIPCHK(c, dalloc(&c->a.b.count, (size_t)nb));
+        HIPCHK(c, dalloc(&c->a.b.count, (size_t)nb / 2));
         HIPCHK(c, dalloc(&c->a.b.start, (size_t)nb + 1));
         HIPCHK(c, dalloc(&c->a.b.bsum, (size_t)nb / SCAN_CHUNK));
-        HIPCHK(c, hipMemsetAsync(c->a.b.count, 0, sizeof(int32_t) * nb, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->a.b.count, 0, sizeof(uint32_t) * (nb / 2), c->stream));
         g.nbucket = (int32_t)nb;
     }
     HIPCHK(c, hipMemcpyAsync(c->a.b.rep, c->rep_h.data(), sizeof(RepInfo) * c->n_rep, hipMemcpyHostToDevice,
@@ -308,7 +313,7 @@ static dsdna_status configure_grid(dsdna_ctx *c)
 static dsdna_status clear_accumulators(dsdna_ctx *c)
 {
     Bufs &b = c->a.b;
-    HIPCHK(c, hipMemsetAsync(b.count, 0, sizeof(int32_t) * (size_t)c->a.g.nbucket, c->stream));
+    HIPCHK(c, hipMemsetAsync(b.count, 0, sizeof(uint32_t) * ((size_t)c->a.g.nbucket / 2), c->stream));
     HIPCHK(c, hipMemsetAsync(b.fex, 0, sizeof(unsigned long long) * 4 * (size_t)c->N, c->stream));
     HIPCHK(c, hipMemsetAsync(b.cmask, 0, sizeof(uint32_t) * CMASK_WORDS * (size_t)c->a.n_tiles, c->stream));
     return DSDNA_OK;
@@ -383,7 +388,7 @@ static dsdna_status rebin(dsdna_ctx *c, int which)
     if (st) return st;
     // the histogram is cleared by the excluded-volume pass of a step, which
     // may not have run since the last binning
-    HIPCHK(c, hipMemsetAsync(c->a.b.count, 0, sizeof(int32_t) * (size_t)c->a.g.nbucket, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->a.b.count, 0, sizeof(uint32_t) * ((size_t)c->a.g.nbucket / 2), c->stream));
     HIPCHK(c, launch_bin(c->a, c->dA, which, c->stream));
     HIPCHK(c, launch_scan(c->a, c->stream));
     HIPCHK(c, launch_scatter(c->a, 0, c->stream));
@@ -449,6 +454,7 @@ static dsdna_status status_from_ctl(dsdna_ctx *c, const Ctl &h)
                        : h.code == DSDNA_ENAN   ? "non-finite position or orientation"
                        : h.code == DSDNA_EWALL  ? "bead reached the anchoring wall"
                        : h.code == DSDNA_EDOMAIN ? "bead left the representable coordinate range"
+                       : h.code == DSDNA_ECELL  ? "more than 65535 beads in one cell-list bucket (raise hash_log2)"
                                                  : "device error";
     return fail(c, (dsdna_status)h.code, "%s at step %lld, nucleotide %lld", what, (long long)h.err_step,
                 (long long)h.err_id);
@@ -461,7 +467,7 @@ static hipError_t enqueue_step(dsdna_ctx *c, int mode, int write_full, hipStream
     // the excluded-volume pass clears the histogram; without it (resume from
     // stored forces, never captured in a graph) a memset does
     if (mode != MODE_FROM_FORCES) e = launch_excl(c->a, c->dA, c->prm.force_fp64, 0, -1, s);
-    else e = hipMemsetAsync(c->a.b.count, 0, sizeof(int32_t) * (size_t)c->a.g.nbucket, s);
+    else e = hipMemsetAsync(c->a.b.count, 0, sizeof(uint32_t) * ((size_t)c->a.g.nbucket / 2), s);
     if (e == hipSuccess) e = launch_step(c->a, c->dA, c->prm.force_fp64, mode, write_full, s);
     if (e == hipSuccess) e = launch_scan(c->a, s);
     if (e == hipSuccess) e = launch_scatter(c->a, 1, s);
@@ -522,7 +528,7 @@ static dsdna_status run_steps(dsdna_ctx *c, int64_t n_steps, std::vector<double>
             hipEvent_t e0, e1, e2, e3, e4;
             HIPCHK(c, mark(&e0));
             if (mode != MODE_FROM_FORCES) HIPCHK(c, launch_excl(c->a, c->dA, c->prm.force_fp64, 0, -1, c->stream));
-            else HIPCHK(c, hipMemsetAsync(c->a.b.count, 0, sizeof(int32_t) * (size_t)c->a.g.nbucket, c->stream));
+            else HIPCHK(c, hipMemsetAsync(c->a.b.count, 0, sizeof(uint32_t) * ((size_t)c->a.g.nbucket / 2), c->stream));
             HIPCHK(c, mark(&e1));
             HIPCHK(c, launch_step(c->a, c->dA, c->prm.force_fp64, mode, k == launches - 1, c->stream));
             HIPCHK(c, mark(&e2));

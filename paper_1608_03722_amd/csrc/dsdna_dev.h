@@ -114,7 +114,10 @@ struct Bufs {
     BeadRec *srec;                      // records in key order (counting sort)
     int32_t *sid;                       // nucleotide of each sorted record
     int4 *scell;                        // cell of each sorted record (open edges only)
-    int32_t *count, *start, *bsum;      // per key (start: nbucket + 1); per scan chunk
+    // histogram: two 16-bit bucket counts per word (bucket k in bits
+    // 16 (k & 1) .. 16 (k & 1) + 15 of word k >> 1)
+    uint32_t *count;
+    int32_t *start, *bsum;              // per key (start: nbucket + 1); per scan chunk
     // excluded-volume force per nt as exact fixed-point sums (x, y, z, unused;
     // units FIX32_UNIT or FIX64_UNIT), zero except beads with contacts;
     // consumers read and clear the entries whose contact bit is set

@@ -282,6 +282,18 @@ __device__ __forceinline__ uint32_t make_tag(int rep, int n, int s)
     return (uint32_t)s | ((n % 3) == 0 ? 2u : 0u) | ((uint32_t)rep << 2);
 }
 
+// Add n beads to bucket `key` of the histogram and return its previous
+// count (16-bit counters, two per word; a bucket past 65535 beads is an
+// error, reported for nucleotide i).
+__device__ __forceinline__ int hist_add(const StepArgs &a, uint32_t key, int n, int64_t i, int64_t step)
+{
+    const uint32_t sh = (key & 1u) << 4;
+    const uint32_t old = atomicAdd(&a.b.count[key >> 1], (uint32_t)n << sh);
+    const int base = (int)((old >> sh) & 0xFFFFu);
+    if (base + n > 0xFFFF) raise_error(a.b.ctl, DSDNA_ECELL, step, i);
+    return base;
+}
+
 // Bin one bead: record, cell, counting-sort key (its bucket) and slot
 // within the key (histogram count phase).
 __device__ __forceinline__ void insert_bead(const StepArgs &a, const RepInfo &ri, int rep, int n, int s,
@@ -302,7 +314,7 @@ __device__ __forceinline__ void insert_bead(const StepArgs &a, const RepInfo &ri
     a.b.rec[i] = r;
     if (a.g.any_open) a.b.rcell[i] = make_int4(c[0], c[1], c[2], 0);
     a.b.key[i] = (int32_t)key;
-    a.b.slot[i] = atomicAdd(&a.b.count[key], 1);
+    a.b.slot[i] = hist_add(a, key, 1, i, step);
 }
 
 // Bin the new bead positions of a tile (all threads of the workgroup call
@@ -348,7 +360,7 @@ __device__ __forceinline__ void bin_tile(const StepArgs &a, uint32_t *tab, uint3
         rank = atomicAdd(&cnt[e], 1u);
     }
     __syncthreads();
-    if (tab[t] != EMPTY) base[t] = atomicAdd(&a.b.count[tab[t]], (int)cnt[t]);
+    if (tab[t] != EMPTY) base[t] = hist_add(a, tab[t], (int)cnt[t], i, step);
     __syncthreads();
     if (own) a.b.slot[i] = base[e] + (int)rank;
 }
@@ -1055,7 +1067,7 @@ __global__ void __launch_bounds__(EXCL_THREADS) k_excl(const StepArgs *__restric
     // binning (streaming stores while this kernel is bound by arithmetic)
     {
         int4 *c4 = reinterpret_cast<int4 *>(a.b.count);
-        const int n4 = a.g.nbucket >> 2, stride = (int)(gridDim.x * blockDim.x);
+        const int n4 = a.g.nbucket >> 3, stride = (int)(gridDim.x * blockDim.x);
         for (int k = (int)(blockIdx.x * blockDim.x + threadIdx.x); k < n4; k += stride) c4[k] = make_int4(0, 0, 0, 0);
     }
     constexpr bool F64 = sizeof(real) == sizeof(double);
@@ -1337,16 +1349,18 @@ __device__ __forceinline__ int block_excl_scan(int v, int *total)
 }
 
 // Total of each chunk of SCAN_CHUNK histogram entries.
-__global__ void __launch_bounds__(256) k_scan_reduce(const int *__restrict__ count, int *__restrict__ bsum,
+__global__ void __launch_bounds__(256) k_scan_reduce(const uint32_t *__restrict__ count, int *__restrict__ bsum,
                                                      const Ctl *ctl)
 {
     if (ctl->code != 0) return;
-    const int4 *c4 = reinterpret_cast<const int4 *>(count + (int64_t)blockIdx.x * SCAN_CHUNK) + threadIdx.x * 4;
+    // 16 buckets (8 words) per thread
+    const uint4 *c4 = reinterpret_cast<const uint4 *>(count + (int64_t)blockIdx.x * (SCAN_CHUNK / 2)) + threadIdx.x * 2;
     int v = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int4 q = c4[k];
-        v += q.x + q.y + q.z + q.w;
+    for (int k = 0; k < 2; ++k) {
+        const uint4 q = c4[k];
+        v += (int)((q.x & 0xFFFFu) + (q.x >> 16) + (q.y & 0xFFFFu) + (q.y >> 16) + (q.z & 0xFFFFu) + (q.z >> 16) +
+                   (q.w & 0xFFFFu) + (q.w >> 16));
     }
     int total;
     block_excl_scan(v, &total);
@@ -1354,18 +1368,24 @@ __global__ void __launch_bounds__(256) k_scan_reduce(const int *__restrict__ cou
 }
 
 // Offsets of one chunk of SCAN_CHUNK keys from the preceding chunk totals.
-__global__ void __launch_bounds__(256) k_scan_down(const int *__restrict__ count, const int *__restrict__ bsum,
+__global__ void __launch_bounds__(256) k_scan_down(const uint32_t *__restrict__ count, const int *__restrict__ bsum,
                                                    int *__restrict__ start, int nkeys, const Ctl *ctl)
 {
     if (ctl->code != 0) return;
-    // the chunk's counts first (in flight while the offset is summed)
+    // the chunk's counts first (in flight while the offset is summed): 16
+    // buckets in 8 words per thread
     const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + threadIdx.x * 16;
-    const int4 *c4 = reinterpret_cast<const int4 *>(count + base);
+    const uint4 *c4 = reinterpret_cast<const uint4 *>(count + base / 2);
     int v[16];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int4 q = c4[k];
-        v[4 * k] = q.x; v[4 * k + 1] = q.y; v[4 * k + 2] = q.z; v[4 * k + 3] = q.w;
+    for (int k = 0; k < 2; ++k) {
+        const uint4 q = c4[k];
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v[8 * k + 2 * j] = (int)(w[j] & 0xFFFFu);
+            v[8 * k + 2 * j + 1] = (int)(w[j] >> 16);
+        }
     }
     // offset of this chunk: sum of the preceding chunks' totals
     int pre = 0;

@@ -15,9 +15,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdsdna.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, EBOND, ENAN, ESTATE, EWALL, EDOMAIN = range(9)
+OK, EINVAL, ENOMEM, EDEVICE, EBOND, ENAN, ESTATE, EWALL, EDOMAIN, ECELL = range(10)
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EBOND", 5: "ENAN", 6: "ESTATE",
-                7: "EWALL", 8: "EDOMAIN"}
+                7: "EWALL", 8: "EDOMAIN", 9: "ECELL"}
 TERMS = ("excl", "bond", "stack", "hbond", "twist", "planar", "bend", "ext")
 NTERMS = len(TERMS)
 NENERGY = NTERMS + 2

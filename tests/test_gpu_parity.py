@@ -328,3 +328,21 @@ def test_error_paths(D):
     with pytest.raises(D.DsdnaError) as ei:
         D.dsdna_step(sim.ctx, -1)
     assert ei.value.status == D.EINVAL
+
+
+def test_full_bucket_is_reported(D):
+    """More than 65535 beads in one cell-list bucket (every nucleotide of a
+    40 kbp chain placed on the same bead and patch positions) stops the run
+    with ECELL before any force is evaluated; the context stays usable."""
+    n = 40000
+    bead = np.zeros((2 * n, 3))
+    patch = np.tile([0.0, 0.0, 0.5], (2 * n, 1))
+    sim = _gpu(D, dict(n_bp=np.array([n]), bead=bead, patch=patch), hash_log2=12)
+    with pytest.raises(D.DsdnaError) as ei:
+        sim.step(1)
+    assert ei.value.status == D.ECELL and "bucket" in str(ei.value)
+    b2, p2 = synth.ideal_helix(n)
+    D.dsdna_set_sites(sim.ctx, b2, p2)
+    sim.step(2)
+    assert sim.state()[4] == 2
+    sim.close()

@@ -1185,6 +1185,17 @@ __global__ void __launch_bounds__(EXCL_THREADS) k_excl(const StepArgs *__restric
     double e_excl = 0.0;
     bool overflow = false;
 
+    // contact test of candidate o (sorted position q): every test evaluated,
+    // no branch
+    auto test = [&](const BeadRec &o, int q) -> bool {
+        const uint32_t ot = o.tag & 3u;
+        const bool same = ((ot ^ mt) & 1u) == 0u;
+        const float dx = (float)(int32_t)(o.x - me.x) * qx;
+        const float dy = (float)(int32_t)(o.y - me.y) * qy;
+        const float dz = (float)(int32_t)(o.z - me.z) * qz;
+        const float r2f = dx * dx + dy * dy + dz * dz;
+        return (r2f < (same ? rcs2 : rcx2)) & (((accept >> ot) & 1u) != 0u) & ((o.tag >> 2) == rep) & (q != p);
+    };
     auto pair = [&](const BeadRec &o, int q, bool valid) {
         // distance first (keeps the record load whole), then the type,
         // replica and self tests in one predicate
@@ -1262,6 +1273,14 @@ __global__ void __launch_bounds__(EXCL_THREADS) k_excl(const StepArgs *__restric
     // while the current U are evaluated (two register sets, so the pipeline
     // needs no copies)
     constexpr int U = 2;
+    // The stream is screened without branches: a contact sets bit k of the
+    // hit masks (k < 128), and the (rare) contacts are evaluated afterwards.
+    uint64_t hit0 = 0, hit1 = 0;
+    auto mark = [&](int k, bool h) {
+        const uint64_t bit = (uint64_t)h << (k & 63);
+        if (k < 64) hit0 |= bit;  // k is the same in every lane
+        else hit1 |= bit;
+    };
     if (nfast > 0) {
         BeadRec oa[U], ob[U];
         int pa[U], pb[U];
@@ -1277,15 +1296,23 @@ __global__ void __launch_bounds__(EXCL_THREADS) k_excl(const StepArgs *__restric
                 ob[v] = srec[pb[v]];
             }
 #pragma unroll
-            for (int v = 0; v < U; ++v) pair(oa[v], pa[v], k0 + v < nfast);
+            for (int v = 0; v < U; ++v) mark(k0 + v, (k0 + v < nfast) & test(oa[v], pa[v]));
 #pragma unroll
             for (int v = 0; v < U; ++v) {
                 pa[v] = locate(k0 + 2 * U + v);
                 oa[v] = srec[pa[v]];
             }
 #pragma unroll
-            for (int v = 0; v < U; ++v) pair(ob[v], pb[v], k0 + U + v < nfast);
+            for (int v = 0; v < U; ++v) mark(k0 + U + v, (k0 + U + v < nfast) & test(ob[v], pb[v]));
         }
+    }
+    for (uint64_t h = hit0; h; h &= h - 1) {
+        const int pq = locate(__builtin_ctzll(h));
+        pair(srec[pq], pq, true);
+    }
+    for (uint64_t h = hit1; h; h &= h - 1) {
+        const int pq = locate(64 + __builtin_ctzll(h));
+        pair(srec[pq], pq, true);
     }
     for (int k = nfast; k < total; ++k) {
         int q = 0;

@@ -541,9 +541,12 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
         S.sOpen[q] = open;
         if (q >= HALO_BP && q < TILE_BP + HALO_BP) put3(S.oHb[q - HALO_BP], f);
     }
-    __syncthreads();
-
+    // the open flags are read below only under the single-strand rule (the
+    // H-bond outboxes are read after the next barrier); the condition is the
+    // same for the whole workgroup
     const bool rule = ph.ssdna_rule != 0;
+    if (rule) __syncthreads();
+
     // --- backbone steps: FENE + WCA core, Morse, planarity on the pair of
     //     nucleotides (s, m), (s, m+1), m = n0 - 1 + mi
     for (int q = t; q < 2 * (TILE_BP + 1); q += blockDim.x) {

@@ -9,7 +9,7 @@ Langevin forces, the rigid-body velocity-Verlet update and the re-binning
 one context per replica on the 256-replica tethered workload, and times the
 FP64 oracle on a bounded sample on the host.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 1mbp|100bp|10kbp|replicas|denat]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 1mbp|100bp|10kbp|replicas|denat|lp300]
 """
 from __future__ import annotations
 
@@ -91,6 +91,15 @@ def _build_workload(name):
     elif name == "denat":
         cfg = synth.config_denaturation()
         desc = "64 x 2 kbp, base-pair attraction scaled 0.5-1.0, single-strand rule"
+    elif name == "lp300":
+        # half straight ideal helices, half pre-bent random-walk helices (axis
+        # persistence ~150 bp): equal correlators afterwards mean the bending
+        # modes have equilibrated from both sides
+        parts = [synth.ideal_helix(300) for _ in range(64)]
+        parts += [synth.random_walk_helix(300, 500.0, seed=100 + r) for r in range(64)]
+        bead, patch = synth.concat_replicas(parts)
+        cfg = dict(n_bp=np.full(128, 300, np.int32), bead=bead, patch=patch)
+        desc = "128 x 300 bp (64 straight, 64 pre-bent), open box: persistence length"
     else:
         raise SystemExit("unknown config " + name)
     return cfg, desc
@@ -274,6 +283,57 @@ def chain_report(D, cfg, sim, args):
             "sample_every": args.sample_every}
 
 
+def persistence_report(D, cfg, sim, args):
+    """Bending persistence length from the tangent correlator of the patch
+    centreline (Sec. 3.1): t(n) along the midpoints of the paired patches,
+    5 bp dropped at each end, <t(n).t(n+m)> averaged over positions and
+    samples per replica, l_p from straight-line fits of its logarithm over
+    windows of m.  Errors from 8 groups of replicas; the straight and the
+    pre-bent halves are reported apart."""
+    n_rep, n_bp = len(cfg["n_bp"]), int(cfg["n_bp"][0])
+    done = 0
+    while done < args.equil_steps:
+        k = min(1000000, args.equil_steps - done)
+        sim.step(k)
+        done += k
+        log("equilibration: %d of %d steps" % (done, args.equil_steps))
+    M = 151
+    acc = np.zeros((n_rep, M))
+    cnt = np.zeros((n_rep, M))
+    for k in range(max(2, args.samples)):
+        sim.step(args.sample_every)
+        _, p = sim.sites()
+        p = p.reshape(n_rep, 2 * n_bp, 3)
+        c = 0.5 * (p[:, 0::2] + p[:, 1::2])
+        t = c[:, 1:] - c[:, :-1]
+        t /= np.linalg.norm(t, axis=2, keepdims=True)
+        t = t[:, 5:-5]
+        n = t.shape[1]
+        for m in range(M):
+            d = np.sum(t[:, :n - m] * t[:, m:], axis=2)
+            acc[:, m] += d.sum(1)
+            cnt[:, m] += d.shape[1]
+        if k % 100 == 0:
+            log("sample %d of %d" % (k, args.samples))
+    corr = acc / cnt
+    out = {"equilibration_steps": args.equil_steps, "samples": args.samples, "sample_every": args.sample_every}
+    groups = 8
+    for name, sl in (("straight_start", slice(0, n_rep // 2)), ("bent_start", slice(n_rep // 2, n_rep)),
+                     ("all", slice(0, n_rep))):
+        cr = corr[sl]
+        g = cr.reshape(groups, -1, M).mean(1)
+        fits = {}
+        for lo, hi in ((1, 30), (5, 50), (10, 100), (1, 150)):
+            ms = np.arange(lo, hi + 1)
+            fit = lambda c: float(-1.0 / np.polyfit(ms, np.log(c[lo:hi + 1]), 1)[0])
+            vals = np.array([fit(x) for x in g])
+            fits["m_%d_%d" % (lo, hi)] = {"lp_bp": fit(cr.mean(0)), "sem": float(vals.std(ddof=1) / np.sqrt(groups))}
+        out[name] = {"lp_fits": fits, "corr": {str(m): float(cr.mean(0)[m]) for m in (1, 10, 50, 100, 150)}}
+    log("persistence length (bp): %s" % {k: round(v["lp_fits"]["m_5_50"]["lp_bp"], 1)
+                                         for k, v in out.items() if isinstance(v, dict)})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -291,8 +351,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--dt", type=float, default=0.0, help="time step (0: the paper's 0.005)")
     ap.add_argument("--sample-every", type=int, default=1000,
-                    help="denat / 10kbp: observables every this many steps")
-    ap.add_argument("--samples", type=int, default=20, help="denat / 10kbp: number of samples")
+                    help="denat / 10kbp / lp300: observables every this many steps")
+    ap.add_argument("--samples", type=int, default=20, help="denat / 10kbp / lp300: number of samples")
+    ap.add_argument("--equil-steps", type=int, default=0, help="lp300: steps before the first sample")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a counter calibration)")
     args = ap.parse_args()
@@ -405,6 +466,8 @@ def main():
         observables = denaturation_report(D, cfg, sim, args)
     elif args.config == "10kbp":
         observables = chain_report(D, cfg, sim, args)
+    elif args.config == "lp300":
+        observables = persistence_report(D, cfg, sim, args)
     sim.close()
 
     batch = None

@@ -80,6 +80,15 @@ __device__ __forceinline__ double rsq64(double x)
     return __fma_rn(0.5 * y, __fma_rn(-x * y, y, 1.0), y);
 }
 
+// 1/x in FP64 for normal x: the hardware estimate refined by two Newton
+// steps.
+__device__ __forceinline__ double rcp64(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    y = __fma_rn(y, __fma_rn(-x, y, 1.0), y);
+    return __fma_rn(y, __fma_rn(-x, y, 1.0), y);
+}
+
 // Square root: the hardware approximation in FP32 (forces), exact in FP64.
 template <typename T>
 __device__ __forceinline__ T fsqrt(T x);
@@ -681,14 +690,16 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
         if ((mask & (1u << DSDNA_TERM_BEND)) && m >= 1 && m + 1 < nbp && !masked) {
             const int la = 2 * mi + s;
             const D3 Pa = lds3(S.sP, la), Pc = lds3(S.sP, la + 2), Pe = lds3(S.sP, la + 4);
-            const V3<real> r1 = cvt<real>(Pa - Pc), r2 = cvt<real>(Pe - Pc);
-            const real l11 = dot(r1, r1), l22 = dot(r2, r2);
-            const real il = rsq(l11 * l22);
-            const real c = dot(r1, r2) * il;
-            const real K6 = (real)ph.K6;
-            f0 = (r2 * il - r1 * (c * rcp(l11))) * (-K6);
-            f2 = (r1 * il - r2 * (c * rcp(l22))) * (-K6);
-            if (energies && mi >= 1 && mi <= TILE_BP) energies[DSDNA_TERM_BEND] += ph.K6 * (1.0 + (double)c);
+            const D3 r1 = Pa - Pc, r2 = Pe - Pc;
+            const double l11 = dot(r1, r1), l22 = dot(r2, r2), d12 = dot(r1, r2);
+            const double il = rsq64(l11 * l22);
+            // -dU/dr1 = -K6 il (r2 - r1 (r1.r2) / |r1|^2): the part of r2
+            // across r1, a small difference of nearly parallel vectors for a
+            // nearly straight triple, so formed in FP64
+            const double k = -ph.K6 * il;
+            f0 = cvt<real>((r2 - r1 * (d12 * rcp64(l11))) * k);
+            f2 = cvt<real>((r1 - r2 * (d12 * rcp64(l22))) * k);
+            if (energies && mi >= 1 && mi <= TILE_BP) energies[DSDNA_TERM_BEND] += ph.K6 * (1.0 + d12 * il);
         }
         put3(S.oBend[s][mi][0], f0);
         put3(S.oBend[s][mi][1], f2);

@@ -9,7 +9,7 @@ Langevin forces, the rigid-body velocity-Verlet update and the re-binning
 one context per replica on the 256-replica tethered workload, and times the
 FP64 oracle on a bounded sample on the host.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 1mbp|100bp|10kbp|replicas|denat|lp300]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 1mbp|100bp|10kbp|replicas|denat|lp300|rings]
 """
 from __future__ import annotations
 
@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor peak
+FP64_PEAK_GFLOPS = 78600.0  # MI355X FP64 vector, vendor peak
 # Algorithmic bytes per nucleotide of one launch of each kernel in a fully
 # periodic box (every byte the kernel must move once).  The
 # excluded-volume forces travel through sparse accumulators touched only by
@@ -100,6 +101,14 @@ def _build_workload(name):
         bead, patch = synth.concat_replicas(parts)
         cfg = dict(n_bp=np.full(128, 300, np.int32), bead=bead, patch=patch)
         desc = "128 x 300 bp (64 straight, 64 pre-bent), open box: persistence length"
+    elif name == "rings":
+        # circular DNA (Sec. 4.2): 128 planar rings of 510 bp wound 48 times
+        # (Lk = 48 against the relaxed 51, i.e. Delta Lk = -3), stacked 5 apart
+        parts = [synth.ideal_ring(510, 48, center=(0.0, 0.0, 5.0 * r)) for r in range(128)]
+        bead, patch = synth.concat_replicas(parts)
+        cfg = dict(n_bp=np.full(128, 510, np.int32), bead=bead, patch=patch,
+                   circular=np.ones(128, np.uint8))
+        desc = "128 rings x 510 bp, Lk 48 (Delta Lk = -3), open box: linking number and writhe"
     else:
         raise SystemExit("unknown config " + name)
     return cfg, desc
@@ -141,7 +150,7 @@ def cpu_baseline(cfg, steps, seed=0):
     """The FP64 oracle (single thread) on the same workload for `steps` steps."""
     from oracle import oracle as O
     O.build(force=False)
-    keys = ("box", "periodic", "pull", "torque", "tether", "wall_z", "k2_scale")
+    keys = ("box", "periodic", "pull", "torque", "tether", "wall_z", "k2_scale", "circular")
     P = O.default_params(seed=seed)
     S = O.System(cfg["n_bp"], **{k: cfg[k] for k in keys if k in cfg})
     R, u = O.bodies_from_sites(P, cfg["bead"], cfg["patch"])
@@ -334,6 +343,41 @@ def persistence_report(D, cfg, sim, args):
     return out
 
 
+# FP64 operations of one segment-pair solid angle as the kernel writes it:
+# four difference vectors (12), four squared lengths (20), two triangles of
+# (cross 9 + triple 5 + denominator 23 + 1), one sum; the 4 square roots and
+# 2 atan2 calls are counted as one operation each, so this figure is a floor
+# on the arithmetic issued.
+PAIR_FLOPS = 115
+
+
+def supercoil_report(D, cfg, sim, args):
+    """Linking number of the strands and writhe of the centreline of every
+    ring (Gauss's double integral, appendix on the closure procedure) every
+    sample_every steps, with the duration of the segment-pair kernel."""
+    n_bp = np.asarray(cfg["n_bp"], np.int64)
+    lk0, wr0 = sim.linking()
+    series, times = [], []
+    lk_dev = float(np.abs(lk0 - 48).max())
+    for k in range(max(1, args.samples)):
+        sim.step(args.sample_every)
+        lk, wr, ms = sim.linking(timed=True)
+        lk_dev = max(lk_dev, float(np.abs(lk - 48).max()))
+        series.append({"step": (k + 1) * args.sample_every, "wr_mean": float(wr.mean()),
+                       "wr_sem": float(wr.std(ddof=1) / np.sqrt(len(wr))), "lk_mean": float(lk.mean())})
+        times.append(ms)
+        log("sample %d: Lk %.6f .. %.6f, <Wr> %.4f (pair kernel %.3f ms)" % (k, lk.min(), lk.max(), wr.mean(), ms))
+    pairs = int(np.sum(2 * n_bp * n_bp))   # Lk and Wr rows, all ordered segment pairs
+    ms = float(np.median(times))
+    return {"lk_target": 48, "lk_max_abs_dev": lk_dev, "writhe": series,
+            "pair_kernel": {"ms_median": ms, "pairs_per_launch": pairs,
+                            "pairs_per_s": pairs / (ms * 1e-3),
+                            "fp64_gflops": pairs * PAIR_FLOPS / (ms * 1e-3) / 1e9,
+                            "fp64_peak_gflops": FP64_PEAK_GFLOPS,
+                            "frac": pairs * PAIR_FLOPS / (ms * 1e-3) / 1e9 / FP64_PEAK_GFLOPS,
+                            "bound": "alu", "flops_per_pair": PAIR_FLOPS}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -468,6 +512,8 @@ def main():
         observables = chain_report(D, cfg, sim, args)
     elif args.config == "lp300":
         observables = persistence_report(D, cfg, sim, args)
+    elif args.config == "rings":
+        observables = supercoil_report(D, cfg, sim, args)
     sim.close()
 
     batch = None

@@ -150,6 +150,31 @@ dsdna_status dsdna_set_box(dsdna_ctx *ctx, const double *lo_hi, const uint8_t *p
 dsdna_status dsdna_set_external(dsdna_ctx *ctx, int32_t rep, const double F[3],
                                 const double G[3], int32_t tether, double wall_z);
 
+/* Close replicas into rings (Sec. 4.2, circular DNA): circular[n_rep], 1 for
+ * a ring, in which base pair n_bp-1 is bonded to base pair 0 on both
+ * strands.  Every backbone step (FENE + core, stacking, dihedral,
+ * planarity) then includes the seam step n_bp-1 -> 0, there is a bending
+ * triple centred on every base pair, and the single-strand rule reads
+ * bubbles cyclically.  A ring needs n_bp >= 6 and n_bp a multiple of 3 (the
+ * steric beads, every third base pair, stay every third across the seam)
+ * and takes no external loads; either is DSDNA_EINVAL.  The flag of every
+ * replica is replaced by this call; set_topology clears all of them.
+ * Placing the sites so that the ring closes is the caller's concern. */
+dsdna_status dsdna_set_circular(dsdna_ctx *ctx, const uint8_t *circular);
+
+/* Topology of every ring from the current state (appendix on the closure
+ * procedure, Gauss's double integral): lk[n_rep] = linking number of the
+ * closed curves of the strand 0 and strand 1 beads, both oriented along
+ * increasing base pair (a relaxed right-handed duplex has Lk ~ +n_bp/10);
+ * wr[n_rep] = writhe of the centreline through the midpoints of the paired
+ * patches (Sec. 3.1).  The twist is Lk - Wr.  Both are computed exactly for
+ * the polygons (the sum over segment pairs of signed solid angles, FP64),
+ * so lk is an integer up to rounding while the strands do not cross.
+ * Linear replicas get NaN.  pair_ms (may be NULL) receives the duration of
+ * the segment-pair kernel in milliseconds.  Runs on the context's stream
+ * after the steps already queued. */
+dsdna_status dsdna_get_linking(dsdna_ctx *ctx, double *lk, double *wr, double *pair_ms);
+
 /* Multiply K2 of each replica by scale[n_rep] (denaturation, Sec. 5). */
 dsdna_status dsdna_set_k2_scale(dsdna_ctx *ctx, const double *scale);
 

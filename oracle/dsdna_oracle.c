@@ -67,6 +67,8 @@ typedef struct {
     const uint8_t *tether;    /* [n_rep]: first bp anchored + bead wall    */
     const double *wall_z;     /* [n_rep]: wall plane z                     */
     const double *k2_scale;   /* [n_rep]: multiplies K2                    */
+    const uint8_t *circular;  /* [n_rep]: closed ring (bp n_bp-1 bonded to
+                                 bp 0), may be NULL                         */
 } orc_system;
 
 typedef struct {
@@ -408,6 +410,30 @@ static void bubble_mask(const uint8_t *open, int64_t nbp, uint8_t *in_bubble)
     }
 }
 
+/* The same on a ring, where bp nbp-1 and bp 0 are neighbours: runs are
+ * cyclic, and a ring with every base pair open is one bubble. */
+static void bubble_mask_ring(const uint8_t *open, int64_t nbp, uint8_t *in_bubble)
+{
+    int64_t c = 0;
+    while (c < nbp && open[c]) ++c;
+    if (c == nbp) {
+        for (int64_t k = 0; k < nbp; ++k) in_bubble[k] = nbp >= 3;
+        return;
+    }
+    /* walk once round the ring from the closed base pair c */
+    int64_t k = 1;
+    in_bubble[c] = 0;
+    while (k < nbp) {
+        int64_t n = (c + k) % nbp;
+        if (!open[n]) { in_bubble[n] = 0; ++k; continue; }
+        int64_t e = k;
+        while (e < nbp && open[(c + e) % nbp]) ++e;
+        uint8_t big = (e - k) >= 3;
+        for (int64_t q = k; q < e; ++q) in_bubble[(c + q) % nbp] = big;
+        k = e;
+    }
+}
+
 /* ---------------------------------------------------------------- forces */
 
 /*
@@ -443,6 +469,12 @@ int orc_forces(const orc_params *P, const orc_system *sys, const double *bead,
         int64_t nbp = sys->n_bp[r];
         int64_t off = rep_offset(sys, r);
         double k2s = sys->k2_scale ? sys->k2_scale[r] : 1.0;
+        /* a ring has a backbone step from every bp n to n+1 (mod nbp) and a
+         * bending triple centred on every bp; a linear chain has nbp - 1
+         * steps and the triples centred on bp 1 .. nbp-2 */
+        int ring = sys->circular && sys->circular[r];
+        int64_t nstep = ring ? nbp : nbp - 1;
+        int64_t b_first = ring ? 0 : 1, b_end = ring ? nbp : nbp - 1;
 
         /* --- hydrogen bond (Appendix A, U_hb): patches of (0,n) and (1,n) */
         uint8_t *open = (uint8_t *)calloc((size_t)nbp + 1, 1);
@@ -468,12 +500,15 @@ int orc_forces(const orc_params *P, const orc_system *sys, const double *bead,
             EN(r, T_HBOND) += U;
         }
         if (open_out) memcpy(open_out + bp_base, open, (size_t)nbp);
-        if (P->ssdna_rule) bubble_mask(open, nbp, inb);
+        if (P->ssdna_rule) {
+            if (ring) bubble_mask_ring(open, nbp, inb);
+            else bubble_mask(open, nbp, inb);
+        }
 
         for (int s = 0; s < 2; ++s) {
             /* --- backbone: FENE + WCA(eps_bb, sig_bb) between consecutive beads */
-            for (int64_t n = 0; n + 1 < nbp; ++n) {
-                int64_t i = nt_index(off, s, n), j = nt_index(off, s, n + 1);
+            for (int64_t n = 0; n < nstep; ++n) {
+                int64_t i = nt_index(off, s, n), j = nt_index(off, s, (n + 1) % nbp);
                 v3 d = v3_sub(v3_ld(bead + 3 * j), v3_ld(bead + 3 * i));
                 double rr = v3_len(d);
                 if (rr >= P->R0) {
@@ -488,8 +523,8 @@ int orc_forces(const orc_params *P, const orc_system *sys, const double *bead,
                 EN(r, T_BOND) += U;
             }
             /* --- Morse stacking between consecutive patches */
-            for (int64_t n = 0; n + 1 < nbp; ++n) {
-                int64_t i = nt_index(off, s, n), j = nt_index(off, s, n + 1);
+            for (int64_t n = 0; n < nstep; ++n) {
+                int64_t i = nt_index(off, s, n), j = nt_index(off, s, (n + 1) % nbp);
                 v3 d = v3_sub(v3_ld(patch + 3 * j), v3_ld(patch + 3 * i));
                 double rr = v3_len(d);
                 double dudr;
@@ -501,9 +536,9 @@ int orc_forces(const orc_params *P, const orc_system *sys, const double *bead,
             }
             /* --- dihedral on (bead n, patch n, patch n+1, bead n+1),
              *     U = K3 [1 + cos(phi - d)] (Sec. 2, Appendix A) */
-            for (int64_t n = 0; n + 1 < nbp; ++n) {
-                if (P->ssdna_rule && inb[n] && inb[n + 1]) continue;
-                int64_t i = nt_index(off, s, n), j = nt_index(off, s, n + 1);
+            for (int64_t n = 0; n < nstep; ++n) {
+                if (P->ssdna_rule && inb[n] && inb[(n + 1) % nbp]) continue;
+                int64_t i = nt_index(off, s, n), j = nt_index(off, s, (n + 1) % nbp);
                 v3 g[4];
                 double phi = dihedral(v3_ld(bead + 3 * i), v3_ld(patch + 3 * i),
                                       v3_ld(patch + 3 * j), v3_ld(bead + 3 * j), g);
@@ -517,8 +552,8 @@ int orc_forces(const orc_params *P, const orc_system *sys, const double *bead,
             }
             /* --- planarity: angle at patch n+1 between patch n and bead n+1,
              *     U = (K5/2)(alpha - alpha0)^2 */
-            for (int64_t n = 0; n + 1 < nbp; ++n) {
-                int64_t i = nt_index(off, s, n), j = nt_index(off, s, n + 1);
+            for (int64_t n = 0; n < nstep; ++n) {
+                int64_t i = nt_index(off, s, n), j = nt_index(off, s, (n + 1) % nbp);
                 v3 dca, dcc;
                 double cs = angle_cos(v3_ld(patch + 3 * i), v3_ld(patch + 3 * j),
                                       v3_ld(bead + 3 * j), &dca, &dcc);
@@ -536,10 +571,11 @@ int orc_forces(const orc_params *P, const orc_system *sys, const double *bead,
             }
             /* --- Kratky-Porod: angle at patch n among patches n-1, n, n+1,
              *     U = K6 [1 + cos(theta)] */
-            for (int64_t n = 1; n + 1 < nbp; ++n) {
-                if (P->ssdna_rule && inb[n - 1] && inb[n] && inb[n + 1]) continue;
-                int64_t h = nt_index(off, s, n - 1), i = nt_index(off, s, n),
-                        j = nt_index(off, s, n + 1);
+            for (int64_t n = b_first; n < b_end; ++n) {
+                int64_t np = (n + nbp - 1) % nbp, nn = (n + 1) % nbp;
+                if (P->ssdna_rule && inb[np] && inb[n] && inb[nn]) continue;
+                int64_t h = nt_index(off, s, np), i = nt_index(off, s, n),
+                        j = nt_index(off, s, nn);
                 v3 dca, dcc;
                 double cs = angle_cos(v3_ld(patch + 3 * h), v3_ld(patch + 3 * i),
                                       v3_ld(patch + 3 * j), &dca, &dcc);
@@ -889,20 +925,32 @@ void orc_kinetic(const orc_params *P, const orc_system *sys, const orc_state *S,
 
 /* Bubble statistics of Sec. 5 for one open mask: fraction of open base pairs
  * and the histogram of maximal open-run lengths (hist[k] counts runs of
- * length k, k < nhist; longer runs land in hist[nhist-1]). */
-void orc_bubbles(const uint8_t *open, int64_t nbp, double *frac, int64_t *hist, int nhist)
+ * length k, k < nhist; longer runs land in hist[nhist-1]).  On a ring
+ * (ring != 0) runs are cyclic: a run through bp nbp-1 and bp 0 counts once,
+ * and a ring with every base pair open is one run of length nbp. */
+void orc_bubbles(const uint8_t *open, int64_t nbp, int ring, double *frac, int64_t *hist, int nhist)
 {
     int64_t nopen = 0;
     for (int k = 0; k < nhist; ++k) hist[k] = 0;
-    int64_t n = 0;
-    while (n < nbp) {
-        if (!open[n]) { ++n; continue; }
-        int64_t e = n;
-        while (e < nbp && open[e]) ++e;
-        int64_t len = e - n;
+    int64_t c = 0; /* runs are read starting after the closed bp c */
+    if (ring) {
+        while (c < nbp && open[c]) ++c;
+        if (c == nbp) {
+            if (nbp) hist[nbp < nhist ? nbp : nhist - 1] += 1;
+            *frac = nbp ? 1.0 : 0.0;
+            return;
+        }
+    }
+    int64_t k = 0;
+    while (k < nbp) {
+        int64_t n = ring ? (c + k) % nbp : k;
+        if (!open[n]) { ++k; continue; }
+        int64_t e = k;
+        while (e < nbp && open[ring ? (c + e) % nbp : e]) ++e;
+        int64_t len = e - k;
         nopen += len;
         hist[len < nhist ? len : nhist - 1] += 1;
-        n = e;
+        k = e;
     }
     *frac = nbp ? (double)nopen / (double)nbp : 0.0;
 }

@@ -70,7 +70,8 @@ def default_params(**over) -> Params:
 class _Sys(C.Structure):
     _fields_ = [("n_rep", C.c_int32), ("n_bp", C.c_void_p), ("box", C.c_void_p),
                 ("periodic", C.c_void_p), ("pull", C.c_void_p), ("torque", C.c_void_p),
-                ("tether", C.c_void_p), ("wall_z", C.c_void_p), ("k2_scale", C.c_void_p)]
+                ("tether", C.c_void_p), ("wall_z", C.c_void_p), ("k2_scale", C.c_void_p),
+                ("circular", C.c_void_p)]
 
 
 class _State(C.Structure):
@@ -102,7 +103,7 @@ def lib():
         L.orc_bodies_from_sites.argtypes = [vp, i64, vp, vp, vp, vp]
         L.orc_wca_pairs.argtypes = [vp, vp, vp, C.c_int, C.c_int, vp, i64]
         L.orc_wca_pairs.restype = i64
-        L.orc_bubbles.argtypes = [vp, i64, vp, vp, C.c_int]
+        L.orc_bubbles.argtypes = [vp, i64, C.c_int, vp, vp, C.c_int]
         L.orc_nterm.restype = C.c_int
         L.orc_sizeof_params.restype = C.c_size_t
         L.orc_sizeof_system.restype = C.c_size_t
@@ -123,7 +124,7 @@ class System:
     """Replica lengths, boxes and external loads (all host numpy arrays)."""
 
     def __init__(self, n_bp, box=None, periodic=None, pull=None, torque=None,
-                 tether=None, wall_z=None, k2_scale=None):
+                 tether=None, wall_z=None, k2_scale=None, circular=None):
         self.n_bp = np.ascontiguousarray(np.atleast_1d(n_bp), dtype=np.int32)
         R = len(self.n_bp)
         self.n_rep = R
@@ -142,10 +143,13 @@ class System:
             np.zeros(R) if wall_z is None else np.reshape(wall_z, (R,)), dtype=np.float64)
         self.k2_scale = np.ascontiguousarray(
             np.ones(R) if k2_scale is None else np.reshape(k2_scale, (R,)), dtype=np.float64)
+        self.circular = np.ascontiguousarray(
+            np.zeros(R) if circular is None else np.reshape(circular, (R,)), dtype=np.uint8)
         self.n_nt = int(2 * self.n_bp.astype(np.int64).sum())
         self.offsets = np.concatenate([[0], np.cumsum(2 * self.n_bp.astype(np.int64))])[:-1]
         self._c = _Sys(R, _ptr(self.n_bp), _ptr(self.box), _ptr(self.periodic), _ptr(self.pull),
-                       _ptr(self.torque), _ptr(self.tether), _ptr(self.wall_z), _ptr(self.k2_scale))
+                       _ptr(self.torque), _ptr(self.tether), _ptr(self.wall_z), _ptr(self.k2_scale),
+                       _ptr(self.circular))
 
     @property
     def ref(self):
@@ -279,9 +283,9 @@ def wca_pairs(P: Params, sysm: System, bead, rep=0, use_cells=False, cap=1 << 20
     return buf[:n].copy()
 
 
-def bubbles(open_mask, nhist=64):
+def bubbles(open_mask, nhist=64, ring=False):
     o = np.ascontiguousarray(open_mask, dtype=np.uint8)
     frac = C.c_double(0.0)
     hist = np.zeros(nhist, dtype=np.int64)
-    lib().orc_bubbles(_ptr(o), len(o), C.byref(frac), _ptr(hist), int(nhist))
+    lib().orc_bubbles(_ptr(o), len(o), int(bool(ring)), C.byref(frac), _ptr(hist), int(nhist))
     return frac.value, hist

@@ -19,6 +19,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -62,6 +63,15 @@ struct dsdna_ctx {
 
     hipGraphExec_t gexec = nullptr;
     int gsteps = 0;
+
+    // rings and the scratch of the linking-number kernels
+    std::vector<RingSeg> rings_h;
+    std::vector<int32_t> ring_rep;   // replica of each ring
+    RingSeg *d_rings = nullptr;
+    int2 *d_lkblk = nullptr;
+    double *d_curves = nullptr, *d_lkpart = nullptr, *d_lkout = nullptr;
+    int lk_blocks = 0, lk_pts = 0;
+    hipEvent_t lk_ev[2] = {nullptr, nullptr};
 };
 
 // ------------------------------------------------------------------ helpers
@@ -97,8 +107,18 @@ static void dfree(void *p)
     if (p) (void)hipFree(p);
 }
 
+static void free_rings(dsdna_ctx *c)
+{
+    dfree(c->d_rings); dfree(c->d_lkblk); dfree(c->d_curves); dfree(c->d_lkpart); dfree(c->d_lkout);
+    c->d_rings = nullptr; c->d_lkblk = nullptr; c->d_curves = c->d_lkpart = c->d_lkout = nullptr;
+    c->rings_h.clear();
+    c->ring_rep.clear();
+    c->lk_blocks = c->lk_pts = 0;
+}
+
 static void free_state(dsdna_ctx *c)
 {
+    free_rings(c);
     Bufs &b = c->a.b;
     for (int k = 0; k < 2; ++k) {
         dfree(b.R[k]); dfree(b.u[k]); dfree(b.V[k]); dfree(b.L[k]);
@@ -676,6 +696,8 @@ dsdna_status dsdna_destroy(dsdna_ctx *c)
     free_grid(c);
     dfree(c->a.b.ctl);
     dfree(c->dA);
+    for (hipEvent_t e : c->lk_ev)
+        if (e) (void)hipEventDestroy(e);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return DSDNA_OK;
@@ -718,7 +740,7 @@ dsdna_status dsdna_set_topology(dsdna_ctx *c, int32_t n_rep, const int32_t *n_bp
             ri.inv_len[k] = 1.0;
         }
         ri.tile0 = (int32_t)c->tiles_h.size();
-        for (int n0 = 0; n0 < n_bp[r]; n0 += TILE_BP) c->tiles_h.push_back(Tile{r, n0});
+        for (int n0 = 0; n0 < n_bp[r]; n0 += TILE_BP) c->tiles_h.push_back(Tile{r, n0, n_bp[r], 0});
         o += 2 * (int64_t)n_bp[r];
     }
     StepArgs &a = c->a;
@@ -779,6 +801,10 @@ dsdna_status dsdna_set_external(dsdna_ctx *c, int32_t rep, const double F[3], co
     if (st) return st;
     if (rep < 0 || rep >= c->n_rep) return fail(c, DSDNA_EINVAL, "replica %d out of range", rep);
     RepInfo &ri = c->rep_h[rep];
+    const bool any = tether || (F && (F[0] != 0.0 || F[1] != 0.0 || F[2] != 0.0)) ||
+                     (G && (G[0] != 0.0 || G[1] != 0.0 || G[2] != 0.0));
+    if ((ri.flags & REP_RING) && any)
+        return fail(c, DSDNA_EINVAL, "replica %d is a ring: it has no end to anchor, pull or twist", rep);
     ri.flags &= ~(uint32_t)(REP_TETHER | REP_PULL | REP_TORQUE);
     for (int k = 0; k < 3; ++k) {
         ri.pull[k] = F ? F[k] : 0.0;
@@ -798,6 +824,94 @@ dsdna_status dsdna_set_k2_scale(dsdna_ctx *c, const double *scale)
     if (!scale) return fail(c, DSDNA_EINVAL, "null scale");
     for (int r = 0; r < c->n_rep; ++r) c->rep_h[r].k2_scale = scale[r];
     return upload_reps(c);
+}
+
+dsdna_status dsdna_set_circular(dsdna_ctx *c, const uint8_t *circular)
+{
+    dsdna_status st = check_ready(c, false);
+    if (st) return st;
+    if (!circular) return fail(c, DSDNA_EINVAL, "null circular");
+    for (int r = 0; r < c->n_rep; ++r) {
+        if (!circular[r]) continue;
+        const int nb = c->n_bp[r];
+        if (nb < 6 || nb % 3 != 0)
+            return fail(c, DSDNA_EINVAL,
+                        "ring %d has %d base pairs: a ring needs at least 6 and a multiple of 3 (steric beads every "
+                        "third base pair on both sides of the seam)", r, nb);
+        if (c->rep_h[r].flags & (REP_TETHER | REP_PULL | REP_TORQUE))
+            return fail(c, DSDNA_EINVAL, "replica %d carries external loads and cannot be a ring", r);
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    free_rings(c);
+    std::vector<int2> blk;
+    int32_t pts = 0;
+    for (int r = 0; r < c->n_rep; ++r) {
+        RepInfo &ri = c->rep_h[r];
+        ri.flags &= ~(uint32_t)REP_RING;
+        if (!circular[r]) continue;
+        ri.flags |= REP_RING;
+        RingSeg g;
+        g.off = ri.off;
+        g.n_bp = ri.n_bp;
+        g.pt0 = pts;
+        g.blk0 = (int32_t)blk.size();
+        g.n_blk = (ri.n_bp + LK_THREADS - 1) / LK_THREADS;
+        for (int b = 0; b < g.n_blk; ++b) blk.push_back(int2{(int)c->rings_h.size(), b * LK_THREADS});
+        c->rings_h.push_back(g);
+        c->ring_rep.push_back(r);
+        pts += ri.n_bp;
+    }
+    for (Tile &t : c->tiles_h) t.ring = (c->rep_h[t.rep].flags & REP_RING) ? 1 : 0;
+    if ((st = copy(c, c->a.b.tiles, c->tiles_h.data(), sizeof(Tile) * c->tiles_h.size(), hipMemcpyHostToDevice)))
+        return st;
+    if (!c->rings_h.empty()) {
+        c->lk_blocks = (int)blk.size();
+        c->lk_pts = pts;
+        HIPCHK(c, dalloc(&c->d_rings, c->rings_h.size()));
+        HIPCHK(c, dalloc(&c->d_lkblk, blk.size()));
+        HIPCHK(c, dalloc(&c->d_curves, 9 * (size_t)pts));
+        HIPCHK(c, dalloc(&c->d_lkpart, 2 * blk.size()));
+        HIPCHK(c, dalloc(&c->d_lkout, 2 * c->rings_h.size()));
+        if ((st = copy(c, c->d_rings, c->rings_h.data(), sizeof(RingSeg) * c->rings_h.size(), hipMemcpyHostToDevice)))
+            return st;
+        if ((st = copy(c, c->d_lkblk, blk.data(), sizeof(int2) * blk.size(), hipMemcpyHostToDevice))) return st;
+    }
+    return upload_reps(c);
+}
+
+dsdna_status dsdna_get_linking(dsdna_ctx *c, double *lk, double *wr, double *pair_ms)
+{
+    dsdna_status st = check_ready(c, true);
+    if (st) return st;
+    if (!lk || !wr) return fail(c, DSDNA_EINVAL, "null lk or wr");
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    std::fill(lk, lk + c->n_rep, nan);
+    std::fill(wr, wr + c->n_rep, nan);
+    if (pair_ms) *pair_ms = 0.0;
+    if (c->rings_h.empty()) return DSDNA_OK;
+    if ((st = sync_args(c))) return st;
+    HIPCHK(c, hipSetDevice(c->device));
+    if (pair_ms)
+        for (hipEvent_t &e : c->lk_ev)
+            if (!e) HIPCHK(c, hipEventCreate(&e));
+    // the full-step positions (a stepping context holds them in the buffer
+    // behind the device's current one)
+    HIPCHK(c, launch_linking(c->dA, full_buffer(c), c->d_rings, (int)c->rings_h.size(), c->d_lkblk, c->lk_blocks,
+                             c->lk_pts, c->d_curves, c->d_lkpart, c->d_lkout, c->stream,
+                             pair_ms ? c->lk_ev[0] : nullptr, pair_ms ? c->lk_ev[1] : nullptr));
+    std::vector<double> out(2 * c->rings_h.size());
+    if ((st = copy(c, out.data(), c->d_lkout, sizeof(double) * out.size(), hipMemcpyDeviceToHost))) return st;
+    for (size_t k = 0; k < c->rings_h.size(); ++k) {
+        lk[c->ring_rep[k]] = out[2 * k];
+        wr[c->ring_rep[k]] = out[2 * k + 1];
+    }
+    if (pair_ms) {
+        float ms = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->lk_ev[0], c->lk_ev[1]));
+        *pair_ms = ms;
+    }
+    return DSDNA_OK;
 }
 
 dsdna_status dsdna_set_temperature(dsdna_ctx *c, double kT)
@@ -996,15 +1110,26 @@ dsdna_status dsdna_get_bubbles(dsdna_ctx *c, int32_t nhist, double *frac, int64_
     for (int r = 0; r < c->n_rep; ++r) {
         int64_t *h = hist + (size_t)r * nhist;
         std::fill(h, h + nhist, 0);
-        int64_t nopen = 0, n = 0;
+        int64_t nopen = 0, k = 0;
         const int64_t nb = c->n_bp[r];
-        while (n < nb) {
-            if (!op[base + n]) { ++n; continue; }
-            int64_t e = n;
-            while (e < nb && op[base + e]) ++e;
-            nopen += e - n;
-            h[std::min<int64_t>(e - n, nhist - 1)] += 1;
-            n = e;
+        // on a ring, runs are read from just after a closed base pair z, so
+        // a run through the seam counts once; an all-open ring is one run
+        const bool ring = c->rep_h[r].flags & REP_RING;
+        int64_t z = 0;
+        if (ring) while (z < nb && op[base + z]) ++z;
+        const auto at = [&](int64_t q) { return op[base + (ring ? (z + q) % nb : q)]; };
+        if (ring && z == nb) {
+            nopen = nb;
+            h[std::min<int64_t>(nb, nhist - 1)] += 1;
+            k = nb;
+        }
+        while (k < nb) {
+            if (!at(k)) { ++k; continue; }
+            int64_t e = k;
+            while (e < nb && at(e)) ++e;
+            nopen += e - k;
+            h[std::min<int64_t>(e - k, nhist - 1)] += 1;
+            k = e;
         }
         frac[r] = (double)nopen / (double)nb;
         base += nb;

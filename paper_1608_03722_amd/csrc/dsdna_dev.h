@@ -47,6 +47,7 @@ enum : uint32_t {
     REP_PER_Z = 8u,
     REP_PULL = 16u,
     REP_TORQUE = 32u,
+    REP_RING = 64u,   // closed ring: bp n_bp-1 is bonded to bp 0
 };
 
 struct RepInfo {
@@ -77,7 +78,9 @@ constexpr double OPEN_QINV = 16777216.0;  // 2^24
 
 struct Tile {
     int32_t rep;
-    int32_t n0;  // first base pair of the tile within its replica
+    int32_t n0;    // first base pair of the tile within its replica
+    int32_t n_bp;  // base pairs of the replica
+    int32_t ring;  // 1 if the replica is a ring (REP_RING)
 };
 
 // Control block in device memory.  `step` is the step index of the positions
@@ -154,6 +157,18 @@ struct StepArgs {
     int32_t n_tiles_pad;   // launched workgroups (multiple of 8)
 };
 
+// A ring for the linking-number kernels: its first nucleotide, length,
+// first point in the curve buffers and its workgroups (blocks of LK_THREADS
+// base pairs, first at blk0).
+constexpr int LK_THREADS = 256;
+struct RingSeg {
+    int64_t off;
+    int32_t n_bp;
+    int32_t pt0;
+    int32_t blk0;
+    int32_t n_blk;
+};
+
 // Launchers (defined in dsdna_kernels.hip).  `a` is the host copy (grid
 // sizes), `dA` the device copy the kernels read.
 hipError_t launch_bin(const StepArgs &a, const StepArgs *dA, int which, hipStream_t s);
@@ -170,5 +185,13 @@ hipError_t launch_thermalize(const StepArgs &a, const StepArgs *dA, double kT, u
 // open flags per bp to b.open.
 hipError_t launch_diag(const StepArgs &a, const StepArgs *dA, int which, int fp64, uint32_t term_mask,
                        hipStream_t s);
+// Linking number of the strands and writhe of the centreline of every ring
+// from the positions in buffer `which`: curves (3 curves x n_pts points x 3
+// doubles) and partial ([n_blocks][2]) are scratch, out[n_rings][2]
+// receives (Lk, Wr).  blocks[n_blocks] = (ring, first bp).  ev0/ev1 (may be
+// null) bracket the pair kernel.
+hipError_t launch_linking(const StepArgs *dA, int which, const RingSeg *rings, int n_rings, const int2 *blocks,
+                          int n_blocks, int n_pts, double *curves, double *partial, double *out, hipStream_t s,
+                          hipEvent_t ev0, hipEvent_t ev1);
 
 }  // namespace dsdna

@@ -416,6 +416,18 @@ __device__ __forceinline__ V3<real> get3(const real *src) { return v3(src[0], sr
 constexpr uint32_t ALL_TERMS = (1u << DSDNA_NTERMS) - 1u;
 static_assert(WG_THREADS - TILE_NT == 4 * HALO_BP, "the spare threads of a tile stage its halo");
 
+// Whether the tile slot of base pair bp (relative to the replica start,
+// possibly outside it) holds a site: on a ring the two base pairs either
+// side of the seam wrap round (bp -2, -1 are nbp-2, nbp-1; bp nbp, nbp+1
+// are 0, 1), so every backbone step and bending triple of a tile finds its
+// sites in the halo.
+// The tile record carries the chain length and the ring flag, so these tests
+// need no reload of the replica record.
+__device__ __forceinline__ bool site_exists(const Tile &tile, int bp)
+{
+    return tile.ring ? (bp >= -HALO_BP && bp < tile.n_bp + HALO_BP) : (bp >= 0 && bp < tile.n_bp);
+}
+
 // The rigid body a thread loads and stages in LDS (index l <-> bp
 // n0 - 2 + l/2, strand l & 1): its own nucleotide for t < TILE_NT, a halo
 // site for the spare threads.
@@ -426,13 +438,15 @@ struct StagedSite {
     D3 R, u;
 };
 
-__device__ __forceinline__ StagedSite load_site(const StepArgs &a, const RepInfo &ri, int n0, int buf)
+__device__ __forceinline__ StagedSite load_site(const StepArgs &a, const RepInfo &ri, const Tile &tile, int buf)
 {
+    const int n0 = tile.n0;
     const int t = threadIdx.x;
     StagedSite st;
     st.l = t < TILE_NT ? t + 2 * HALO_BP : (t - TILE_NT < 2 * HALO_BP ? t - TILE_NT : t);
-    const int bp = n0 - HALO_BP + (st.l >> 1);
-    st.valid = bp >= 0 && bp < ri.n_bp;
+    int bp = n0 - HALO_BP + (st.l >> 1);
+    st.valid = site_exists(tile, bp);
+    if (tile.ring) bp = bp < 0 ? bp + tile.n_bp : (bp >= tile.n_bp ? bp - tile.n_bp : bp);
     st.i = ri.off + 2 * (int64_t)bp + (st.l & 1);
     st.R = v3(0.0, 0.0, 0.0);
     st.u = st.R;
@@ -515,12 +529,12 @@ __device__ __forceinline__ real atan2_small(real y, real x)
 // With energies != nullptr the per-term energies owned by this thread are
 // added there (diagnostics only).
 template <typename real>
-__device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileLds<real> &S, const RepInfo &ri, int rep, int n0,
+__device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileLds<real> &S, const RepInfo &ri, const Tile &tile,
                                         V3<real> fex, uint32_t mask, int64_t step, double *energies)
 {
     const int t = threadIdx.x;
     const Phys &ph = a.ph;
-    const int nbp = ri.n_bp;
+    const int nbp = tile.n_bp, n0 = tile.n0;
     __syncthreads();
     // every thread has read (and consumed) its accumulator flag before this
     // barrier
@@ -533,7 +547,7 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
         const int bp = n0 - HALO_BP + q;
         uint8_t open = 0;
         V3<real> f = v3<real>(0, 0, 0);
-        if (bp >= 0 && bp < nbp) {
+        if (site_exists(tile, bp)) {
             const D3 d64 = lds3(S.sP, 2 * q + 1) - lds3(S.sP, 2 * q);
             const double r = sqrt(dot(d64, d64));
             open = r > ph.rc_hb;
@@ -542,7 +556,7 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
                 real c = (real)2 * pref;
                 if (ph.r0_hb != 0.0) c *= (real)1 - (real)(ph.r0_hb / r);  // uniform: no division at r0 = 0
                 f = cvt<real>(d64) * c;
-                if (energies && q >= HALO_BP && q < TILE_BP + HALO_BP)
+                if (energies && q >= HALO_BP && q < TILE_BP + HALO_BP && bp < nbp)
                     energies[DSDNA_TERM_HBOND] += ph.hb_pref * k2s *
                         ((r - ph.r0_hb) * (r - ph.r0_hb) - (ph.rc_hb - ph.r0_hb) * (ph.rc_hb - ph.r0_hb));
             }
@@ -556,12 +570,20 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
     const bool rule = ph.ssdna_rule != 0;
     if (rule) __syncthreads();
 
+    // backbone step m joins bp m and m+1: m = 0 .. nbp-2 on a linear chain,
+    // m = -1 .. nbp-1 on a ring (m = -1 and nbp-1 both being the seam step
+    // nbp-1 -> 0, seen from either side); a bending triple is centred on bp
+    // m = 1 .. nbp-2, or m = -1 .. nbp on a ring
+    const bool ring = tile.ring != 0;
+    const int step_lo = ring ? -1 : 0, step_hi = ring ? nbp : nbp - 1;
+    const int bend_lo = ring ? -1 : 1, bend_hi = ring ? nbp + 1 : nbp - 1;
+
     // --- backbone steps: FENE + WCA core, Morse, planarity on the pair of
     //     nucleotides (s, m), (s, m+1), m = n0 - 1 + mi
     for (int q = t; q < 2 * (TILE_BP + 1); q += blockDim.x) {
         const int s = q & 1, mi = q >> 1, m = n0 - 1 + mi;
         V3<real> fBa = v3<real>(0, 0, 0), fPa = fBa, fBb = fBa, fPb = fBa;
-        if (m >= 0 && m + 1 < nbp) {
+        if (m >= step_lo && m < step_hi) {
             const int la = 2 * (mi + 1) + s, lb = la + 2;
             const D3 Ba = lds3(S.sB, la), Pa = lds3(S.sP, la), Bb = lds3(S.sB, lb), Pb = lds3(S.sP, lb);
             const bool own = mi >= 1;  // step m belongs to the tile that holds nucleotide m
@@ -570,7 +592,7 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
                 const D3 d64 = Bb - Ba;
                 const double r2 = dot(d64, d64);
                 if (r2 >= ph.R0 * ph.R0) {
-                    raise_error(a.b.ctl, DSDNA_EBOND, step, ri.off + 2 * (int64_t)m + s);
+                    raise_error(a.b.ctl, DSDNA_EBOND, step, ri.off + 2 * (int64_t)(m < 0 ? m + nbp : m) + s);
                 } else {
                     // FENE attraction and the WCA core cancel to a few percent
                     // near the bond minimum, so (dU/dr)/r is formed in FP64
@@ -645,7 +667,7 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
     //     thread adds to the outboxes of the step it wrote above
     for (int q = t; q < 2 * (TILE_BP + 1); q += blockDim.x) {
         const int s = q & 1, mi = q >> 1, m = n0 - 1 + mi;
-        if (!(m >= 0 && m + 1 < nbp)) continue;
+        if (!(m >= step_lo && m < step_hi)) continue;
         const int la = 2 * (mi + 1) + s, lb = la + 2;
         const D3 Ba = lds3(S.sB, la), Pa = lds3(S.sP, la), Bb = lds3(S.sB, lb), Pb = lds3(S.sP, lb);
         const bool own = mi >= 1;
@@ -687,7 +709,7 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
         const int s = q & 1, mi = q >> 1, m = n0 - 1 + mi;
         V3<real> f0 = v3<real>(0, 0, 0), f2 = f0;
         const bool masked = rule && S.sOpen[mi] && S.sOpen[mi + 1] && S.sOpen[mi + 2];
-        if ((mask & (1u << DSDNA_TERM_BEND)) && m >= 1 && m + 1 < nbp && !masked) {
+        if ((mask & (1u << DSDNA_TERM_BEND)) && m >= bend_lo && m < bend_hi && !masked) {
             const int la = 2 * mi + s;
             const D3 Pa = lds3(S.sP, la), Pc = lds3(S.sP, la + 2), Pe = lds3(S.sP, la + 4);
             const D3 r1 = Pa - Pc, r2 = Pe - Pc;
@@ -699,7 +721,7 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
             const double k = -ph.K6 * il;
             f0 = cvt<real>((r2 - r1 * (d12 * rcp64(l11))) * k);
             f2 = cvt<real>((r1 - r2 * (d12 * rcp64(l22))) * k);
-            if (energies && mi >= 1 && mi <= TILE_BP) energies[DSDNA_TERM_BEND] += ph.K6 * (1.0 + d12 * il);
+            if (energies && mi >= 1 && mi <= TILE_BP && m < nbp) energies[DSDNA_TERM_BEND] += ph.K6 * (1.0 + d12 * il);
         }
         put3(S.oBend[s][mi][0], f0);
         put3(S.oBend[s][mi][1], f2);
@@ -827,10 +849,10 @@ __global__ void __launch_bounds__(WG_THREADS, 5) k_step(const StepArgs *__restri
 
     // every global load of this thread up front: its body (or halo site),
     // velocities and excluded-volume force
-    const StagedSite site = load_site(a, ri, tile.n0, cur);
+    const StagedSite site = load_site(a, ri, tile, cur);
     const int s = threadIdx.x & 1;
-    const int n = threadIdx.x < TILE_NT ? tile.n0 + (int)(threadIdx.x >> 1) : ri.n_bp;
-    const bool own = n < ri.n_bp;
+    const int n = threadIdx.x < TILE_NT ? tile.n0 + (int)(threadIdx.x >> 1) : tile.n_bp;
+    const bool own = n < tile.n_bp;
     const int64_t i = site.i;
     D3 R = site.R, u = site.u;
     V3<real> fexv = v3<real>(0, 0, 0);
@@ -843,7 +865,7 @@ __global__ void __launch_bounds__(WG_THREADS, 5) k_step(const StepArgs *__restri
     f.p = f.b;
     if (mode != MODE_FROM_FORCES) {
         stage_site(a, S, site);
-        f = tile_forces<real>(a, S, ri, tile.rep, tile.n0, fexv, ALL_TERMS, step, nullptr);
+        f = tile_forces<real>(a, S, ri, tile, fexv, ALL_TERMS, step, nullptr);
     }
     // velocities and noise only now: they are not live through the force
     // phase, and the noise is drawn while the velocity loads are in flight
@@ -956,8 +978,8 @@ __global__ void __launch_bounds__(256) k_bin(const StepArgs *__restrict__ A, int
     if (tix >= a.n_tiles) return;
     const Tile tile = a.b.tiles[tix];
     const RepInfo &ri = a.b.rep[tile.rep];
-    const int s = threadIdx.x & 1, n = threadIdx.x < TILE_NT ? tile.n0 + (int)(threadIdx.x >> 1) : ri.n_bp;
-    if (n >= ri.n_bp) return;
+    const int s = threadIdx.x & 1, n = threadIdx.x < TILE_NT ? tile.n0 + (int)(threadIdx.x >> 1) : tile.n_bp;
+    if (n >= tile.n_bp) return;
     const int64_t i = ri.off + 2 * (int64_t)n + s;
     const D3 R = ld3(a.b.R[which], a.n_nt, i), u = ld3(a.b.u[which], a.n_nt, i);
     insert_bead(a, ri, tile.rep, n, s, i, bead_of(R, u, a.ph.db), a.b.ctl->step);
@@ -1493,8 +1515,8 @@ __global__ void __launch_bounds__(256) k_thermalize(const StepArgs *__restrict__
     if (tix >= a.n_tiles) return;
     const Tile tile = a.b.tiles[tix];
     const RepInfo &ri = a.b.rep[tile.rep];
-    const int s = threadIdx.x & 1, n = threadIdx.x < TILE_NT ? tile.n0 + (int)(threadIdx.x >> 1) : ri.n_bp;
-    if (n >= ri.n_bp) return;
+    const int s = threadIdx.x & 1, n = threadIdx.x < TILE_NT ? tile.n0 + (int)(threadIdx.x >> 1) : tile.n_bp;
+    if (n >= tile.n_bp) return;
     const int64_t i = ri.off + 2 * (int64_t)n + s;
     const int cur = a.b.ctl->par;
     const int64_t N = a.n_nt;
@@ -1512,6 +1534,141 @@ __global__ void __launch_bounds__(256) k_thermalize(const StepArgs *__restrict__
     st3(a.b.L[cur], N, i, L);
     st3(a.b.Vf, N, i, V);
     st3(a.b.Lf, N, i, L);
+}
+
+// ------------------------------------------------ linking number, writhe
+
+// The closed curves of each ring from the positions in buffer `buf`:
+// strand 0 beads, strand 1 beads and the centreline through the midpoints of
+// the paired patches (Sec. 3.1), as FP64 points [n][3] per curve.  One
+// workgroup per block of LK_THREADS base pairs of one ring.
+__global__ void __launch_bounds__(LK_THREADS) k_curves(const StepArgs *__restrict__ A, const RingSeg *__restrict__ rings,
+                                                      const int2 *__restrict__ blocks, int n_pts, int buf,
+                                                      double *__restrict__ curves)
+{
+    const StepArgs &a = *A;
+    const int2 blk = blocks[blockIdx.x];
+    const RingSeg rg = rings[blk.x];
+    const int n = blk.y + (int)threadIdx.x;
+    if (n >= rg.n_bp) return;
+    const int64_t i0 = rg.off + 2 * (int64_t)n, i1 = i0 + 1;
+    const D3 R0 = ld3(a.b.R[buf], a.n_nt, i0), u0 = ld3(a.b.u[buf], a.n_nt, i0);
+    const D3 R1 = ld3(a.b.R[buf], a.n_nt, i1), u1 = ld3(a.b.u[buf], a.n_nt, i1);
+    const D3 b0 = bead_of(R0, u0, a.ph.db), b1 = bead_of(R1, u1, a.ph.db);
+    const D3 c = (patch_of(R0, u0, a.ph.dp) + patch_of(R1, u1, a.ph.dp)) * 0.5;
+    double *pA = curves + 3 * ((int64_t)rg.pt0 + n);
+    double *pB = pA + 3 * (int64_t)n_pts, *pC = pB + 3 * (int64_t)n_pts;
+    pA[0] = b0.x; pA[1] = b0.y; pA[2] = b0.z;
+    pB[0] = b1.x; pB[1] = b1.y; pB[2] = b1.z;
+    pC[0] = c.x; pC[1] = c.y; pC[2] = c.z;
+}
+
+// Signed solid angle of the spherical triangle with vertices along x, y, z
+// (lengths lx, ly, lz), from tan(Omega/2) = x.(y x z) / (lx ly lz +
+// (x.y) lz + (x.z) ly + (y.z) lx) (Van Oosterom and Strackee, IEEE Trans.
+// Biomed. Eng. 30, 125 (1983)).
+__device__ __forceinline__ double tri_omega(D3 x, D3 y, D3 z, double lx, double ly, double lz)
+{
+    const double num = dot(x, cross(y, z));
+    const double den = lx * ly * lz + dot(x, y) * lz + dot(x, z) * ly + dot(y, z) * lx;
+    return 2.0 * atan2(num, den);
+}
+
+// Gauss's double integral (appendix on the closure procedure) over segment
+// p1 -> p2 of one closed polygon and segment p3 -> p4 of another, times
+// 4 pi.  The integrand is the pull-back of the area form of the sphere by
+// (r_1 - r_2)/|r_1 - r_2| up to sign, so the pair integral is the signed
+// area of the geodesic quadrangle with corners p1-p3, p2-p3, p2-p4, p1-p4;
+// written with r_ij = p_j - p_i it is the fan of two triangles below.
+__device__ __forceinline__ double pair_omega(D3 p1, D3 p2, D3 p3, D3 p4)
+{
+    const D3 r13 = p3 - p1, r14 = p4 - p1, r23 = p3 - p2, r24 = p4 - p2;
+    const double l13 = sqrt(dot(r13, r13)), l14 = sqrt(dot(r14, r14));
+    const double l23 = sqrt(dot(r23, r23)), l24 = sqrt(dot(r24, r24));
+    return tri_omega(r13, r23, r24, l13, l23, l24) + tri_omega(r13, r24, r14, l13, l24, l14);
+}
+
+// Row sums of the segment-pair solid angles: thread i of a workgroup holds
+// segment i -> i+1 (mod n) of the strand 0 curve and of the centreline; the
+// strand 1 curve and the centreline stream through LDS in chunks of
+// LK_THREADS segments.  Per workgroup: sum over its rows of Omega(A_i, B_j)
+// over all j (the linking number) and of Omega(C_i, C_j) over every j whose
+// segment shares no vertex with segment i (the writhe, each unordered pair
+// twice), reduced in a fixed order to partial[block][2].
+__global__ void __launch_bounds__(LK_THREADS) k_gauss(const RingSeg *__restrict__ rings, const int2 *__restrict__ blocks,
+                                                     int n_pts, const double *__restrict__ curves,
+                                                     double *__restrict__ partial)
+{
+    __shared__ double sB[LK_THREADS + 1][3];
+    __shared__ double sC[LK_THREADS + 1][3];
+    __shared__ double red[LK_THREADS][2];
+    const int t = threadIdx.x;
+    const int2 blk = blocks[blockIdx.x];
+    const RingSeg rg = rings[blk.x];
+    const int n = rg.n_bp;
+    const double *cA = curves + 3 * (int64_t)rg.pt0;
+    const double *cB = cA + 3 * (int64_t)n_pts, *cC = cB + 3 * (int64_t)n_pts;
+    const int i = blk.y + t;
+    const bool row = i < n;
+    const int i1 = i + 1 == n ? 0 : i + 1;
+    D3 a0 = v3(0.0, 0.0, 0.0), a1 = a0, c0 = a0, c1 = a0;
+    if (row) {
+        a0 = v3(cA[3 * i], cA[3 * i + 1], cA[3 * i + 2]);
+        a1 = v3(cA[3 * i1], cA[3 * i1 + 1], cA[3 * i1 + 2]);
+        c0 = v3(cC[3 * i], cC[3 * i + 1], cC[3 * i + 2]);
+        c1 = v3(cC[3 * i1], cC[3 * i1 + 1], cC[3 * i1 + 2]);
+    }
+    double lk = 0.0, wr = 0.0;
+    for (int j0 = 0; j0 < n; j0 += LK_THREADS) {
+        const int m = min(LK_THREADS, n - j0);  // segments in this chunk
+        __syncthreads();
+        for (int q = t; q <= m; q += LK_THREADS) {  // m + 1 points, the last may wrap
+            const int j = j0 + q == n ? 0 : j0 + q;
+            sB[q][0] = cB[3 * j]; sB[q][1] = cB[3 * j + 1]; sB[q][2] = cB[3 * j + 2];
+            sC[q][0] = cC[3 * j]; sC[q][1] = cC[3 * j + 1]; sC[q][2] = cC[3 * j + 2];
+        }
+        __syncthreads();
+        if (!row) continue;
+        for (int q = 0; q < m; ++q) {
+            const D3 b0 = lds3(sB, q), b1 = lds3(sB, q + 1);
+            lk += pair_omega(a0, a1, b0, b1);
+            const int j = j0 + q;
+            const int j1 = j + 1 == n ? 0 : j + 1;
+            if (j != i && j != i1 && j1 != i) wr += pair_omega(c0, c1, lds3(sC, q), lds3(sC, q + 1));
+        }
+    }
+    red[t][0] = lk;
+    red[t][1] = wr;
+    for (int w = LK_THREADS / 2; w > 0; w >>= 1) {
+        __syncthreads();
+        if (t < w) {
+            red[t][0] += red[t + w][0];
+            red[t][1] += red[t + w][1];
+        }
+    }
+    if (t == 0) {
+        partial[2 * blockIdx.x] = red[0][0];
+        partial[2 * blockIdx.x + 1] = red[0][1];
+    }
+}
+
+// Per ring, in block order: Lk = (sum of its rows) / (4 pi) and Wr the same
+// for the centreline (whose rows count each pair twice, as the integral
+// over the torus does).
+__global__ void __launch_bounds__(64) k_gauss_sum(const RingSeg *__restrict__ rings, int n_rings,
+                                                 const double *__restrict__ partial, double *__restrict__ out)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rings) return;
+    const RingSeg rg = rings[r];
+    double lk = 0.0, wr = 0.0;
+    for (int b = 0; b < rg.n_blk; ++b) {
+        lk += partial[2 * (rg.blk0 + b)];
+        wr += partial[2 * (rg.blk0 + b) + 1];
+    }
+    const double k = 0.25 / 3.14159265358979323846;
+    out[2 * r] = lk * k;
+    out[2 * r + 1] = wr * k;
 }
 
 // --------------------------------------------------------------- diagnostics
@@ -1532,13 +1689,13 @@ __global__ void __launch_bounds__(WG_THREADS) k_diag(const StepArgs *__restrict_
     double e[DSDNA_NTERMS];
     for (int k = 0; k < DSDNA_NTERMS; ++k) e[k] = 0.0;
     const int64_t step = a.b.ctl->step;
-    const StagedSite site = load_site(a, ri, tile.n0, which);
-    const int s = threadIdx.x & 1, bl = threadIdx.x >> 1, n = threadIdx.x < TILE_NT ? tile.n0 + bl : ri.n_bp;
+    const StagedSite site = load_site(a, ri, tile, which);
+    const int s = threadIdx.x & 1, bl = threadIdx.x >> 1, n = threadIdx.x < TILE_NT ? tile.n0 + bl : tile.n_bp;
     const bool flagged = contact_flag(a, tix);
-    const V3<real> fexv = (n < ri.n_bp && flagged) ? take_fex<real>(a, site.i) : v3<real>(0, 0, 0);
+    const V3<real> fexv = (n < tile.n_bp && flagged) ? take_fex<real>(a, site.i) : v3<real>(0, 0, 0);
     stage_site(a, S, site);
-    SiteForces<real> f = tile_forces<real>(a, S, ri, tile.rep, tile.n0, fexv, mask, step, e);
-    if (n < ri.n_bp) {
+    SiteForces<real> f = tile_forces<real>(a, S, ri, tile, fexv, mask, step, e);
+    if (n < tile.n_bp) {
         const int64_t i = ri.off + 2 * (int64_t)n + s;
         a.b.diag_fb[3 * i] = (double)f.b.x;
         a.b.diag_fb[3 * i + 1] = (double)f.b.y;
@@ -1638,6 +1795,19 @@ hipError_t launch_diag(const StepArgs &a, const StepArgs *dA, int which, int fp6
         hipLaunchKernelGGL(k_diag<double>, tiles_grid(a), dim3(WG_THREADS), 0, s, dA, which, term_mask);
     else
         hipLaunchKernelGGL(k_diag<float>, tiles_grid(a), dim3(WG_THREADS), 0, s, dA, which, term_mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_linking(const StepArgs *dA, int which, const RingSeg *rings, int n_rings, const int2 *blocks,
+                          int n_blocks, int n_pts, double *curves, double *partial, double *out, hipStream_t s,
+                          hipEvent_t ev0, hipEvent_t ev1)
+{
+    if (n_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_curves, dim3(n_blocks), dim3(LK_THREADS), 0, s, dA, rings, blocks, n_pts, which, curves);
+    if (ev0) (void)hipEventRecord(ev0, s);
+    hipLaunchKernelGGL(k_gauss, dim3(n_blocks), dim3(LK_THREADS), 0, s, rings, blocks, n_pts, curves, partial);
+    if (ev1) (void)hipEventRecord(ev1, s);
+    hipLaunchKernelGGL(k_gauss_sum, dim3((n_rings + 63) / 64), dim3(64), 0, s, rings, n_rings, partial, out);
     return hipGetLastError();
 }
 

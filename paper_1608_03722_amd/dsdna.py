@@ -30,6 +30,7 @@ EXPORTS = (
     "dsdna_set_velocities", "dsdna_thermalize", "dsdna_step", "dsdna_get_state", "dsdna_set_state",
     "dsdna_get_resume", "dsdna_set_resume", "dsdna_get_sites", "dsdna_get_forces", "dsdna_get_energies",
     "dsdna_get_bp_open", "dsdna_get_bubbles", "dsdna_profile_kernels", "dsdna_get_grid", "dsdna_autotune",
+    "dsdna_set_circular", "dsdna_get_linking",
 )
 
 
@@ -86,6 +87,8 @@ def lib():
             "dsdna_profile_kernels": [vp, i64, vp],
             "dsdna_get_grid": [vp, vp, vp, vp],
             "dsdna_autotune": [vp, i32, vp, i32, vp, i64, vp, vp],
+            "dsdna_set_circular": [vp, vp],
+            "dsdna_get_linking": [vp, vp, vp, vp],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
@@ -160,6 +163,20 @@ def dsdna_set_external(ctx, rep, F=(0, 0, 0), G=(0, 0, 0), tether=0, wall_z=0.0)
 def dsdna_set_k2_scale(ctx, scale):
     s = _f64(np.atleast_1d(scale))
     _check(ctx, lib().dsdna_set_k2_scale(ctx, _p(s)))
+
+
+def dsdna_set_circular(ctx, circular):
+    c = np.ascontiguousarray(np.atleast_1d(circular), dtype=np.uint8)
+    _check(ctx, lib().dsdna_set_circular(ctx, _p(c)))
+
+
+def dsdna_get_linking(ctx, n_rep, timed=False):
+    """(lk[n_rep], wr[n_rep]) and, with timed, the pair kernel's duration in ms."""
+    lk = np.empty(n_rep)
+    wr = np.empty(n_rep)
+    ms = C.c_double(0.0)
+    _check(ctx, lib().dsdna_get_linking(ctx, _p(lk), _p(wr), C.byref(ms) if timed else None))
+    return (lk, wr, ms.value) if timed else (lk, wr)
 
 
 def dsdna_set_temperature(ctx, kT):
@@ -269,7 +286,7 @@ def dsdna_autotune(ctx, cell_sizes, hash_log2s, trial_steps):
 class DsDNA:
     """One context: topology, box, loads and positions from a dict such as
     those of the `synth` configs (keys n_bp, bead, patch and optionally box,
-    periodic, pull, torque, tether, wall_z, k2_scale)."""
+    periodic, circular, pull, torque, tether, wall_z, k2_scale)."""
 
     def __init__(self, cfg, params: Params | None = None, device=0, stream=None):
         self.params = params if params is not None else dsdna_default_params()
@@ -280,6 +297,8 @@ class DsDNA:
         dsdna_set_topology(self.ctx, self.n_bp)
         if "box" in cfg:
             dsdna_set_box(self.ctx, cfg["box"], cfg.get("periodic", np.zeros((self.n_rep, 3))))
+        if "circular" in cfg:
+            dsdna_set_circular(self.ctx, cfg["circular"])
         for r in range(self.n_rep):
             F = cfg["pull"][r] if "pull" in cfg else (0, 0, 0)
             G = cfg["torque"][r] if "torque" in cfg else (0, 0, 0)
@@ -328,6 +347,9 @@ class DsDNA:
 
     def bubbles(self, nhist=64):
         return dsdna_get_bubbles(self.ctx, self.n_rep, nhist)
+
+    def linking(self, timed=False):
+        return dsdna_get_linking(self.ctx, self.n_rep, timed)
 
     def resume_point(self):
         return dsdna_get_resume(self.ctx, self.n_nt)

@@ -75,6 +75,23 @@ def ideal_helix(n_bp, origin=(0.0, 0.0, 0.0), direction=(0.0, 0.0, 1.0), phase0=
     return helix_on_axis(axis, np.tile(t, (n_bp, 1)), np.tile(e1, (n_bp, 1)), phase0, twist, radius)
 
 
+def ideal_ring(n_bp, turns, center=(0.0, 0.0, 0.0), phase0=0.0, radius=RADIUS):
+    """Closed duplex on a planar circle in the xy plane: patch (s, n) at angle
+    2 pi n / n_bp on a circle whose chord between neighbours is the rise, and
+    the beads wound `turns` times round it (twist 2 pi turns / n_bp per bp,
+    about the radial / -z frame, which a planar circle transports without
+    rotation).  Both strands then close on themselves after n_bp base pairs;
+    with integer `turns` and the strands oriented along increasing n, they
+    link `turns` times (the axis has no writhe)."""
+    th = 2.0 * math.pi * np.arange(n_bp, dtype=np.float64) / n_bp
+    rho = RISE / (2.0 * math.sin(math.pi / n_bp))
+    c = np.asarray(center, dtype=np.float64)
+    axis = c[None, :] + rho * np.stack([np.cos(th), np.sin(th), np.zeros(n_bp)], axis=1)
+    tang = np.stack([-np.sin(th), np.cos(th), np.zeros(n_bp)], axis=1)
+    e1 = np.stack([np.cos(th), np.sin(th), np.zeros(n_bp)], axis=1)
+    return helix_on_axis(axis, tang, e1, phase0, 2.0 * math.pi * turns / n_bp, radius)
+
+
 def mirror_helix(n_bp, **kw):
     """Left-handed counterpart of ideal_helix (twist -36 deg per bp)."""
     return ideal_helix(n_bp, twist=-TWIST, **kw)

@@ -9,7 +9,7 @@ Langevin forces, the rigid-body velocity-Verlet update and the re-binning
 one context per replica on the 256-replica tethered workload, and times the
 FP64 oracle on a bounded sample on the host.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 1mbp|100bp|10kbp|replicas|denat|lp300|rings]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 1mbp|100bp|10kbp|replicas|denat|denat_seq|lp300|rings]
 """
 from __future__ import annotations
 
@@ -101,6 +101,10 @@ def _build_workload(name):
         bead, patch = synth.concat_replicas(parts)
         cfg = dict(n_bp=np.full(128, 300, np.int32), bead=bead, patch=patch)
         desc = "128 x 300 bp (64 straight, 64 pre-bent), open box: persistence length"
+    elif name == "denat_seq":
+        cfg = synth.config_denaturation_sequence()
+        desc = ("64 x 2 kbp, K2(CG) 1.0-1.4 kT, K2(AT) = 2/3 K2(CG), random sequence 50% AT, "
+                "single-strand rule, overstretched backbone bonds held (fene_clamp)")
     elif name == "rings":
         # circular DNA (Sec. 4.2): 128 planar rings of 510 bp wound 48 times
         # (Lk = 48 against the relaxed 51, i.e. Delta Lk = -3), stacked 5 apart
@@ -150,7 +154,7 @@ def cpu_baseline(cfg, steps, seed=0):
     """The FP64 oracle (single thread) on the same workload for `steps` steps."""
     from oracle import oracle as O
     O.build(force=False)
-    keys = ("box", "periodic", "pull", "torque", "tether", "wall_z", "k2_scale", "circular")
+    keys = ("box", "periodic", "pull", "torque", "tether", "wall_z", "k2_scale", "circular", "k2_bp")
     P = O.default_params(seed=seed)
     S = O.System(cfg["n_bp"], **{k: cfg[k] for k in keys if k in cfg})
     R, u = O.bodies_from_sites(P, cfg["bead"], cfg["patch"])
@@ -351,6 +355,32 @@ def persistence_report(D, cfg, sim, args):
 PAIR_FLOPS = 115
 
 
+def melting_report(D, cfg, sim, args):
+    """Fraction of open base pairs every sample_every steps, over all base
+    pairs and apart for AT and CG pairs and for the weakest and strongest
+    quarters of the replicas (Sec. 5).  A run the model's dynamics stops is
+    reported with its step."""
+    at = np.asarray(cfg["at"], bool)
+    n_rep, n_bp = len(cfg["n_bp"]), int(cfg["n_bp"][0])
+    q = n_rep // 4
+    rows, stopped = [], None
+    for k in range(max(1, args.samples)):
+        try:
+            sim.step(args.sample_every)
+        except D.DsdnaError as e:
+            stopped = str(e)
+            log("stopped: %s" % e)
+            break
+        op = sim.bp_open().astype(bool)
+        byrep = op.reshape(n_rep, n_bp).mean(1)
+        rows.append({"step": (k + 1) * args.sample_every, "open": float(op.mean()),
+                     "open_at": float(op[at].mean()), "open_cg": float(op[~at].mean()),
+                     "open_weakest_quarter": float(byrep[:q].mean()),
+                     "open_strongest_quarter": float(byrep[-q:].mean())})
+        log("sample %d: open %.4f (AT %.4f, CG %.4f)" % (k, rows[-1]["open"], rows[-1]["open_at"], rows[-1]["open_cg"]))
+    return {"samples": rows, "stopped": stopped}
+
+
 def supercoil_report(D, cfg, sim, args):
     """Linking number of the strands and writhe of the centreline of every
     ring (Gauss's double integral, appendix on the closure procedure) every
@@ -428,7 +458,8 @@ def main():
     extra = {"dt": args.dt} if args.dt > 0 else {}
     prm = D.dsdna_default_params(seed=0, cell_size=args.cell, hash_log2=args.hash_log2,
                                  graph_steps=args.graph_steps,
-                                 ssdna_rule=1 if args.config == "denat" else 0, **extra)
+                                 ssdna_rule=1 if args.config in ("denat", "denat_seq") else 0,
+                                 fene_clamp=1 if args.config == "denat_seq" else 0, **extra)
     sim = D.DsDNA(cfg, prm, device=0, stream=stream.cuda_stream)
     sim.thermalize(1.0, 0)
     tuned = None
@@ -447,18 +478,27 @@ def main():
 
     t0 = time.perf_counter()
     left = args.warmup
+    failure = None
     while left > 0:
         k = min(left, 500)
-        sim.step(k)
+        try:
+            sim.step(k)
+        except D.DsdnaError as e:
+            # as in the timed loop below: reported outside the default workload
+            if args.config == "1mbp":
+                raise
+            failure = {"status": int(e.status), "message": str(e), "during": "warm-up"}
+            log("stopped in the warm-up: %s" % e)
+            break
         left -= k
     torch.cuda.synchronize()
-    log("warm-up %d steps in %.2f s" % (args.warmup, time.perf_counter() - t0))
+    log("warm-up %d steps in %.2f s" % (args.warmup - left, time.perf_counter() - t0))
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    left = args.steps
+    to_time = args.steps if failure is None else 0
+    left = to_time
     chunk = max(1, min(args.steps, 5000))
-    failure = None
     while left > 0:
         k = min(left, chunk)
         try:
@@ -475,7 +515,7 @@ def main():
         log("  %d steps left" % left)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    done = args.steps - left
+    done = to_time - left
     value = n_nt * done / elapsed if done > 0 else 0.0
     ms_step = 1e3 * elapsed / max(done, 1)
     log("timed %d steps in %.3f s: %.4g nt-steps/s" % (done, elapsed, value))
@@ -514,6 +554,8 @@ def main():
         observables = persistence_report(D, cfg, sim, args)
     elif args.config == "rings":
         observables = supercoil_report(D, cfg, sim, args)
+    elif args.config == "denat_seq":
+        observables = melting_report(D, cfg, sim, args)
     sim.close()
 
     batch = None

@@ -115,6 +115,13 @@ typedef struct {
                                        power of two >= 4 x nucleotides,
                                        within [12, 24]                      */
     int32_t graph_steps;            /* steps per captured HIP graph; 0 = off */
+    int32_t fene_clamp;             /* 0: a backbone bond reaching R0 stops
+                                       the run (DSDNA_EBOND); 1: once
+                                       1 - r^2/R0^2 falls below 0.1 it is held
+                                       there (the force keeps growing with r,
+                                       the energy is capped), and only a bond
+                                       of 2 R0 stops the run               */
+    int32_t pad;
 } dsdna_params;
 
 /* Table 2 values plus the defaults for what the paper leaves open: unit
@@ -149,6 +156,13 @@ dsdna_status dsdna_set_box(dsdna_ctx *ctx, const double *lo_hi, const uint8_t *p
  * pair is fixed and every bead feels a WCA wall, sigma = sig_s, at z = wall_z). */
 dsdna_status dsdna_set_external(dsdna_ctx *ctx, int32_t rep, const double F[3],
                                 const double G[3], int32_t tether, double wall_z);
+
+/* Sequence-specific base pairing (Sec. 5, K2(AT) < K2(CG)): scale[n_bp_total]
+ * multiplies K2 of each base pair, in replica order then bp order, on top of
+ * the per-replica dsdna_set_k2_scale.  NULL removes the table (every base
+ * pair then has multiplier 1).  Entries must be finite and >= 0
+ * (DSDNA_EINVAL).  The table is copied; set_topology removes it. */
+dsdna_status dsdna_set_k2_bp(dsdna_ctx *ctx, const double *scale);
 
 /* Close replicas into rings (Sec. 4.2, circular DNA): circular[n_rep], 1 for
  * a ring, in which base pair n_bp-1 is bonded to base pair 0 on both

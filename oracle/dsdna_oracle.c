@@ -54,7 +54,8 @@ typedef struct {
     int32_t noise_kind;            /* 0 Gaussian (Box-Muller), 1 uniform   */
     int32_t ssdna_rule;            /* Sec. 5 rule for bubbles > 2 bp       */
     int32_t hb_depth_convention;   /* 0: prefactor K2/(2(r0-rc)^2)         */
-    int32_t pad;
+    int32_t fene_clamp;            /* 1: hold 1 - r^2/R0^2 at >= 0.1 (a
+                                      reading for overstretched bonds)     */
 } orc_params;
 
 typedef struct {
@@ -69,6 +70,8 @@ typedef struct {
     const double *k2_scale;   /* [n_rep]: multiplies K2                    */
     const uint8_t *circular;  /* [n_rep]: closed ring (bp n_bp-1 bonded to
                                  bp 0), may be NULL                         */
+    const double *k2_bp;      /* [sum n_bp]: multiplies K2 of each base
+                                 pair (sequence, Sec. 5), may be NULL       */
 } orc_system;
 
 typedef struct {
@@ -174,9 +177,12 @@ static double u_wca(double r, double eps, double sig, double *dudr)
 }
 
 /* Appendix A: FENE, U = -(K1 R0^2 / 2) ln[1 - (r/R0)^2] for r < R0. */
-static double u_fene(double r, double K1, double R0, double *dudr)
+static double u_fene(double r, double K1, double R0, int clamp, double *dudr)
 {
     double x = 1.0 - (r * r) / (R0 * R0);
+    /* the optional hold: past 1 - r^2/R0^2 = 0.1 the argument stays at 0.1,
+     * so the force grows linearly with r and the energy is capped */
+    if (clamp && x < 0.1) x = 0.1;
     *dudr = K1 * r / x;
     return -0.5 * K1 * R0 * R0 * log(x);
 }
@@ -488,12 +494,14 @@ int orc_forces(const orc_params *P, const orc_system *sys, const double *bead,
             v3 d = v3_sub(v3_ld(patch + 3 * j), v3_ld(patch + 3 * i));
             double rr = v3_len(d);
             if (rr > P->rc_hb) { open[n] = 1; continue; }
-            double U = pref * ((rr - P->r0_hb) * (rr - P->r0_hb) -
-                               (P->rc_hb - P->r0_hb) * (P->rc_hb - P->r0_hb));
+            /* the base pair's own stiffness: K2 x replica scale x bp scale */
+            double pn = sys->k2_bp ? pref * sys->k2_bp[bp_base + n] : pref;
+            double U = pn * ((rr - P->r0_hb) * (rr - P->r0_hb) -
+                             (P->rc_hb - P->r0_hb) * (P->rc_hb - P->r0_hb));
             /* -dU/dr along the unit vector from i to j, written without 1/r so
              * that r = 0 (coincident patches of the ideal helix) is regular:
              * f_i = 2 pref (r - r0)/r * d = 2 pref (1 - r0/r) d. */
-            double c = (P->r0_hb == 0.0) ? 2.0 * pref : 2.0 * pref * (1.0 - P->r0_hb / rr);
+            double c = (P->r0_hb == 0.0) ? 2.0 * pn : 2.0 * pn * (1.0 - P->r0_hb / rr);
             v3 f = v3_mul(d, c);
             v3_acc(FP(T_HBOND, i), f);
             v3_acc(FP(T_HBOND, j), v3_mul(f, -1.0));
@@ -511,12 +519,12 @@ int orc_forces(const orc_params *P, const orc_system *sys, const double *bead,
                 int64_t i = nt_index(off, s, n), j = nt_index(off, s, (n + 1) % nbp);
                 v3 d = v3_sub(v3_ld(bead + 3 * j), v3_ld(bead + 3 * i));
                 double rr = v3_len(d);
-                if (rr >= P->R0) {
+                if (P->fene_clamp ? rr >= 2.0 * P->R0 : rr >= P->R0) {
                     if (status == ORC_OK) { status = ORC_EBOND; if (err_id) *err_id = i; }
                     continue;
                 }
                 double d1, d2;
-                double U = u_fene(rr, P->K1, P->R0, &d1) + u_wca(rr, P->eps_bb, P->sig_bb, &d2);
+                double U = u_fene(rr, P->K1, P->R0, P->fene_clamp, &d1) + u_wca(rr, P->eps_bb, P->sig_bb, &d2);
                 v3 f = v3_mul(d, (d1 + d2) / rr);
                 v3_acc(FB(T_BOND, i), f);
                 v3_acc(FB(T_BOND, j), v3_mul(f, -1.0));

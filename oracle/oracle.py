@@ -47,7 +47,7 @@ class Params(C.Structure):
         "K3", "d_dih", "K4", "lam", "r0_m", "K5", "a0", "K6", "ell", "m_bead", "m_patch",
         "gamma", "kT", "dt")] + [
         ("seed", C.c_uint64), ("noise_kind", C.c_int32), ("ssdna_rule", C.c_int32),
-        ("hb_depth_convention", C.c_int32), ("pad", C.c_int32)]
+        ("hb_depth_convention", C.c_int32), ("fene_clamp", C.c_int32)]
 
 
 def default_params(**over) -> Params:
@@ -61,7 +61,7 @@ def default_params(**over) -> Params:
                K6=52.0,
                ell=0.5, m_bead=1.0, m_patch=1.0,
                gamma=1.0, kT=1.0, dt=0.005,
-               seed=0, noise_kind=0, ssdna_rule=0, hb_depth_convention=0, pad=0)
+               seed=0, noise_kind=0, ssdna_rule=0, hb_depth_convention=0, fene_clamp=0)
     for k, v in over.items():
         setattr(p, k, v)
     return p
@@ -71,7 +71,7 @@ class _Sys(C.Structure):
     _fields_ = [("n_rep", C.c_int32), ("n_bp", C.c_void_p), ("box", C.c_void_p),
                 ("periodic", C.c_void_p), ("pull", C.c_void_p), ("torque", C.c_void_p),
                 ("tether", C.c_void_p), ("wall_z", C.c_void_p), ("k2_scale", C.c_void_p),
-                ("circular", C.c_void_p)]
+                ("circular", C.c_void_p), ("k2_bp", C.c_void_p)]
 
 
 class _State(C.Structure):
@@ -124,7 +124,7 @@ class System:
     """Replica lengths, boxes and external loads (all host numpy arrays)."""
 
     def __init__(self, n_bp, box=None, periodic=None, pull=None, torque=None,
-                 tether=None, wall_z=None, k2_scale=None, circular=None):
+                 tether=None, wall_z=None, k2_scale=None, circular=None, k2_bp=None):
         self.n_bp = np.ascontiguousarray(np.atleast_1d(n_bp), dtype=np.int32)
         R = len(self.n_bp)
         self.n_rep = R
@@ -145,11 +145,13 @@ class System:
             np.ones(R) if k2_scale is None else np.reshape(k2_scale, (R,)), dtype=np.float64)
         self.circular = np.ascontiguousarray(
             np.zeros(R) if circular is None else np.reshape(circular, (R,)), dtype=np.uint8)
+        self.k2_bp = None if k2_bp is None else np.ascontiguousarray(
+            np.reshape(k2_bp, (int(self.n_bp.astype(np.int64).sum()),)), dtype=np.float64)
         self.n_nt = int(2 * self.n_bp.astype(np.int64).sum())
         self.offsets = np.concatenate([[0], np.cumsum(2 * self.n_bp.astype(np.int64))])[:-1]
         self._c = _Sys(R, _ptr(self.n_bp), _ptr(self.box), _ptr(self.periodic), _ptr(self.pull),
                        _ptr(self.torque), _ptr(self.tether), _ptr(self.wall_z), _ptr(self.k2_scale),
-                       _ptr(self.circular))
+                       _ptr(self.circular), _ptr(self.k2_bp))
 
     @property
     def ref(self):

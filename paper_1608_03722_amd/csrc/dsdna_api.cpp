@@ -128,6 +128,7 @@ static void free_state(dsdna_ctx *c)
     dfree(b.fex); dfree(b.cmask); dfree(b.eex);
     dfree(b.rep); dfree(b.tiles); dfree(b.eacc); dfree(b.open);
     dfree(b.diag_fb); dfree(b.diag_fp);
+    dfree(b.k2bp);
     Ctl *ctl = b.ctl;
     uint32_t *count = b.count;
     int32_t *start = b.start, *bsum = b.bsum;
@@ -198,6 +199,7 @@ static void fill_phys(dsdna_ctx *c)
     h.seed = p.seed;
     h.noise_kind = p.noise_kind;
     h.ssdna_rule = p.ssdna_rule;
+    h.fene_clamp = p.fene_clamp;
 }
 
 static double rc_max(const dsdna_ctx *c) { return TWO_16 * std::max(c->prm.sig_s, c->prm.sig_x); }
@@ -824,6 +826,25 @@ dsdna_status dsdna_set_k2_scale(dsdna_ctx *c, const double *scale)
     if (!scale) return fail(c, DSDNA_EINVAL, "null scale");
     for (int r = 0; r < c->n_rep; ++r) c->rep_h[r].k2_scale = scale[r];
     return upload_reps(c);
+}
+
+dsdna_status dsdna_set_k2_bp(dsdna_ctx *c, const double *scale)
+{
+    dsdna_status st = check_ready(c, false);
+    if (st) return st;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    Bufs &b = c->a.b;
+    if (!scale) {
+        dfree(b.k2bp);
+        b.k2bp = nullptr;
+        return DSDNA_OK;
+    }
+    for (int64_t n = 0; n < c->n_bp_total; ++n)
+        if (!(scale[n] >= 0.0 && std::isfinite(scale[n])))
+            return fail(c, DSDNA_EINVAL, "K2 multiplier of base pair %lld is %g", (long long)n, scale[n]);
+    if (!b.k2bp) HIPCHK(c, dalloc(&b.k2bp, (size_t)c->n_bp_total));
+    return copy(c, b.k2bp, scale, sizeof(double) * c->n_bp_total, hipMemcpyHostToDevice);
 }
 
 dsdna_status dsdna_set_circular(dsdna_ctx *c, const uint8_t *circular)

@@ -38,6 +38,7 @@ struct Phys {
     double inv_R0sq;          // 1 / R0^2
     uint64_t seed;
     int32_t noise_kind, ssdna_rule;
+    int32_t fene_clamp, pad_;
 };
 
 enum : uint32_t {
@@ -134,6 +135,7 @@ struct Bufs {
     Ctl *ctl;
     double *eacc;                       // per tile energy partials
     uint8_t *open;                      // per bp open flags (diagnostics)
+    double *k2bp;                       // per bp K2 multiplier, null if unset
     double *diag_fb, *diag_fp;          // per-term diagnostic forces (AoS [N][3])
 };
 

@@ -548,16 +548,23 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
         uint8_t open = 0;
         V3<real> f = v3<real>(0, 0, 0);
         if (site_exists(tile, bp)) {
+            // the base pair's own K2 multiplier (sequence), if any: a load
+            // only when the table is set
+            double k2n = k2s;
+            if (a.b.k2bp) {
+                const int bw = bp < 0 ? bp + nbp : (bp >= nbp ? bp - nbp : bp);
+                k2n *= a.b.k2bp[ri.off / 2 + bw];
+            }
             const D3 d64 = lds3(S.sP, 2 * q + 1) - lds3(S.sP, 2 * q);
             const double r = sqrt(dot(d64, d64));
             open = r > ph.rc_hb;
             if (!open && (mask & (1u << DSDNA_TERM_HBOND))) {
-                const real pref = (real)(ph.hb_pref * k2s);
+                const real pref = (real)(ph.hb_pref * k2n);
                 real c = (real)2 * pref;
                 if (ph.r0_hb != 0.0) c *= (real)1 - (real)(ph.r0_hb / r);  // uniform: no division at r0 = 0
                 f = cvt<real>(d64) * c;
                 if (energies && q >= HALO_BP && q < TILE_BP + HALO_BP && bp < nbp)
-                    energies[DSDNA_TERM_HBOND] += ph.hb_pref * k2s *
+                    energies[DSDNA_TERM_HBOND] += ph.hb_pref * k2n *
                         ((r - ph.r0_hb) * (r - ph.r0_hb) - (ph.rc_hb - ph.r0_hb) * (ph.rc_hb - ph.r0_hb));
             }
         }
@@ -591,12 +598,15 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
             if (mask & (1u << DSDNA_TERM_BOND)) {
                 const D3 d64 = Bb - Ba;
                 const double r2 = dot(d64, d64);
-                if (r2 >= ph.R0 * ph.R0) {
+                double x = 1.0 - r2 * ph.inv_R0sq;
+                // optional hold of 1 - r^2/R0^2 at 0.1 (fene_clamp); the run
+                // stops at R0, or at 2 R0 with the hold
+                if (ph.fene_clamp && x < 0.1) x = x <= -3.0 ? 0.0 : 0.1;
+                if (x <= 0.0) {
                     raise_error(a.b.ctl, DSDNA_EBOND, step, ri.off + 2 * (int64_t)(m < 0 ? m + nbp : m) + s);
                 } else {
                     // FENE attraction and the WCA core cancel to a few percent
                     // near the bond minimum, so (dU/dr)/r is formed in FP64
-                    const double x = 1.0 - r2 * ph.inv_R0sq;
                     double g = ph.K1 / x;
                     double e = 0.0;
                     if (energies && own) e = -0.5 * ph.K1 * ph.R0 * ph.R0 * log(x);

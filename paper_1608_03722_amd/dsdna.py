@@ -30,7 +30,7 @@ EXPORTS = (
     "dsdna_set_velocities", "dsdna_thermalize", "dsdna_step", "dsdna_get_state", "dsdna_set_state",
     "dsdna_get_resume", "dsdna_set_resume", "dsdna_get_sites", "dsdna_get_forces", "dsdna_get_energies",
     "dsdna_get_bp_open", "dsdna_get_bubbles", "dsdna_profile_kernels", "dsdna_get_grid", "dsdna_autotune",
-    "dsdna_set_circular", "dsdna_get_linking",
+    "dsdna_set_circular", "dsdna_get_linking", "dsdna_set_k2_bp",
 )
 
 
@@ -47,7 +47,7 @@ class Params(C.Structure):
         "gamma", "kT", "dt")] + [
         ("seed", C.c_uint64), ("noise_kind", C.c_int32), ("force_fp64", C.c_int32),
         ("ssdna_rule", C.c_int32), ("hb_depth_convention", C.c_int32), ("cell_size", C.c_double),
-        ("hash_log2", C.c_int32), ("graph_steps", C.c_int32)]
+        ("hash_log2", C.c_int32), ("graph_steps", C.c_int32), ("fene_clamp", C.c_int32), ("pad", C.c_int32)]
 
 
 _lib = None
@@ -88,6 +88,7 @@ def lib():
             "dsdna_get_grid": [vp, vp, vp, vp],
             "dsdna_autotune": [vp, i32, vp, i32, vp, i64, vp, vp],
             "dsdna_set_circular": [vp, vp],
+            "dsdna_set_k2_bp": [vp, vp],
             "dsdna_get_linking": [vp, vp, vp, vp],
         }
         for name, args in sigs.items():
@@ -163,6 +164,11 @@ def dsdna_set_external(ctx, rep, F=(0, 0, 0), G=(0, 0, 0), tether=0, wall_z=0.0)
 def dsdna_set_k2_scale(ctx, scale):
     s = _f64(np.atleast_1d(scale))
     _check(ctx, lib().dsdna_set_k2_scale(ctx, _p(s)))
+
+
+def dsdna_set_k2_bp(ctx, scale):
+    s = None if scale is None else _f64(np.ravel(scale))
+    _check(ctx, lib().dsdna_set_k2_bp(ctx, _p(s)))
 
 
 def dsdna_set_circular(ctx, circular):
@@ -286,7 +292,7 @@ def dsdna_autotune(ctx, cell_sizes, hash_log2s, trial_steps):
 class DsDNA:
     """One context: topology, box, loads and positions from a dict such as
     those of the `synth` configs (keys n_bp, bead, patch and optionally box,
-    periodic, circular, pull, torque, tether, wall_z, k2_scale)."""
+    periodic, circular, pull, torque, tether, wall_z, k2_scale, k2_bp)."""
 
     def __init__(self, cfg, params: Params | None = None, device=0, stream=None):
         self.params = params if params is not None else dsdna_default_params()
@@ -308,6 +314,8 @@ class DsDNA:
                 dsdna_set_external(self.ctx, r, F, G, te, wz)
         if "k2_scale" in cfg:
             dsdna_set_k2_scale(self.ctx, cfg["k2_scale"])
+        if "k2_bp" in cfg:
+            dsdna_set_k2_bp(self.ctx, cfg["k2_bp"])
         dsdna_set_sites(self.ctx, cfg["bead"], cfg["patch"])
 
     def close(self):

@@ -244,6 +244,26 @@ def config_tethered_replicas(n_rep=256, n_torque=64, lo=500, hi=5000, f_lo_pn=0.
                 tether=np.ones(n_rep, np.uint8), wall_z=np.zeros(n_rep))
 
 
+def config_denaturation_sequence(n_rep=64, n_bp=2000, k2_lo=1.0, k2_hi=1.4, at_ratio=2.0 / 3.0, at_frac=0.5,
+                                 seed=5, k2_table=6.0):
+    """Replicas of n_bp ideal helix at the paper's melting strengths: replica
+    k pairs its CG base pairs with K2 = k2_lo + (k2_hi - k2_lo) k/(n_rep-1)
+    (in kT) and its AT base pairs with at_ratio times that; the sequence is
+    random with an AT fraction at_frac.  Returned as per-replica multipliers
+    of the table value k2_table and per-bp multipliers (1 for CG, at_ratio
+    for AT), with the AT mask."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    k2 = k2_lo + (k2_hi - k2_lo) * np.arange(n_rep) / max(1, n_rep - 1)
+    at = rng.random(n_rep * n_bp) < at_frac
+    lens = np.full(n_rep, n_bp, dtype=np.int32)
+    bead, patch = concat_replicas([ideal_helix(n_bp) for _ in range(n_rep)])
+    big = 1e5
+    return dict(n_bp=lens, bead=bead, patch=patch,
+                box=np.tile([-big, -big, -big, big, big, big], (n_rep, 1)).astype(np.float64),
+                periodic=np.zeros((n_rep, 3), np.uint8), k2_scale=k2 / k2_table,
+                k2_bp=np.where(at, at_ratio, 1.0), at=at)
+
+
 def config_denaturation(n_rep=64, n_bp=2000, seed=4):
     """Replicas of n_bp ideal helix with the hydrogen-bond strength scaled by
     0.5 + 0.5 k/(n_rep-1), k = 0..n_rep-1, in a seeded permutation."""

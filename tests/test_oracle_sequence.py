@@ -1,0 +1,86 @@
+"""Pins of the oracle's sequence-specific base pairing (Sec. 5: two H-bond
+stiffnesses, K2(AT) < K2(CG)), as a per-base-pair K2 multiplier on top of the
+per-replica one: closed-form energies and linear scaling of the forces."""
+import numpy as np
+import pytest
+
+import synth
+
+
+def _opened(seps):
+    """An ideal helix whose strand 1 patch of bp n is moved seps[n] along x."""
+    b, p = synth.ideal_helix(len(seps))
+    p = p.copy()
+    for n, r in enumerate(seps):
+        p[2 * n + 1, 0] += r
+    return b, p
+
+
+def test_per_bp_k2_energy_closed_form(orc):
+    """U_hb = s_n K2/(2 (r0 - rc)^2) [(r - r0)^2 - (rc - r0)^2] per base pair:
+    with K2 = 6, r0 = 0, rc = 0.3 that is -3 s_n (1 - (r/0.3)^2) inside the
+    cutoff and 0 beyond."""
+    P = orc.default_params()
+    seps = [0.0, 0.1, 0.2, 0.35, 0.05]
+    s = np.array([1.0, 0.5, 2.0, 3.0, 0.0])
+    b, p = _opened(seps)
+    want = sum(-3.0 * sn * (1 - (r / 0.3) ** 2) for r, sn in zip(seps, s) if r <= 0.3)
+    st, _, fb, fp, E, op = orc.forces(P, orc.System([5], k2_bp=s), b, p)
+    assert st == orc.OK
+    assert E[0, orc.T["hbond"]] == pytest.approx(want, rel=1e-13)
+    assert list(op) == [0, 0, 0, 1, 0]          # the cutoff does not depend on K2
+    # on top of the per-replica multiplier
+    st, _, _, _, E2, _ = orc.forces(P, orc.System([5], k2_bp=s, k2_scale=[0.25]), b, p)
+    assert E2[0, orc.T["hbond"]] == pytest.approx(0.25 * want, rel=1e-13)
+
+
+def test_per_bp_k2_scales_each_pair_force(orc):
+    P = orc.default_params()
+    b, p = synth.ideal_helix(12)
+    b, p = synth.perturb(b, 0.04, 3), synth.perturb(p, 0.04, 4)
+    s = np.random.default_rng(1).uniform(0.2, 1.8, 12)
+    t = orc.T["hbond"]
+    _, _, fb1, fp1, E1, _ = orc.forces(P, orc.System([12]), b, p)
+    _, _, fbs, fps, Es, _ = orc.forces(P, orc.System([12], k2_bp=s), b, p)
+    np.testing.assert_allclose(fps[t], fp1[t] * np.repeat(s, 2)[:, None], rtol=1e-13, atol=1e-15)
+    assert np.all(fbs[t] == 0.0)
+    for other in ("bond", "stack", "twist", "planar", "bend", "excl"):
+        np.testing.assert_array_equal(fps[orc.T[other]], fp1[orc.T[other]])
+    # replicas take consecutive slices of the table
+    b2, p2 = synth.concat_replicas([(b, p), (b, p)])
+    s2 = np.concatenate([s, np.ones(12)])
+    _, _, _, fpr, Er, _ = orc.forces(P, orc.System([12, 12], k2_bp=s2), b2, p2)
+    assert Er[0, t] == pytest.approx(Es[0, t], rel=1e-13) and Er[1, t] == pytest.approx(E1[0, t], rel=1e-13)
+
+
+def _stretched(r):
+    """Two base pairs; the strand 0 bond stretched to r along x, the strand 1
+    bond at 0.46, strands 5 apart (no other contact)."""
+    bead = np.array([[0.0, 0.0, 0.0], [0.0, 5.0, 0.0], [r, 0.0, 0.0], [0.46, 5.0, 0.0]])
+    patch = bead + np.array([0.0, 0.0, 0.5])
+    return bead, patch
+
+
+@pytest.mark.parametrize("r", [0.5, 0.66, 0.7, 1.3])
+def test_fene_hold_reading(orc, r):
+    """fene_clamp = 1 holds 1 - r^2/R0^2 at 0.1 once it falls below: the bond
+    force is K1 r / 0.1 and the energy -K1 R0^2 ln(0.1) / 2 there; the run
+    stops only at 2 R0.  Without it a bond at R0 or beyond stops the run."""
+    K1, R0 = 30.0, 0.6825
+    b, p = _stretched(r)
+    x = 1 - r * r / R0 ** 2
+    t = orc.T["bond"]
+    for clamp in (0, 1):
+        P = orc.default_params(fene_clamp=clamp)
+        st, err, fb, fp, E, _ = orc.forces(P, orc.System([2]), b, p)
+        if not clamp and r >= R0:
+            assert st == orc.EBOND and err == 0
+            continue
+        assert st == orc.OK
+        xe = max(x, 0.1) if clamp else x
+        # force on the stretched bond's second bead, along -x (WCA core off: r > 0.497)
+        assert fb[t][2][0] == pytest.approx(-K1 * r / xe, rel=1e-12)
+        assert fb[t][2][1] == 0.0 and fb[t][2][2] == 0.0
+    P = orc.default_params(fene_clamp=1)
+    b, p = _stretched(2 * R0 + 0.01)
+    assert orc.forces(P, orc.System([2]), b, p)[0] == orc.EBOND

@@ -9,7 +9,7 @@ Langevin forces, the rigid-body velocity-Verlet update and the re-binning
 one context per replica on the 256-replica tethered workload, and times the
 FP64 oracle on a bounded sample on the host.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 1mbp|100bp|10kbp|replicas|denat|denat_seq|lp300|rings]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 1mbp|100bp|10kbp|replicas|denat|denat_seq|lp300|rings|sm]
 """
 from __future__ import annotations
 
@@ -104,7 +104,12 @@ def _build_workload(name):
     elif name == "denat_seq":
         cfg = synth.config_denaturation_sequence()
         desc = ("64 x 2 kbp, K2(CG) 1.0-1.4 kT, K2(AT) = 2/3 K2(CG), random sequence 50% AT, "
-                "single-strand rule, overstretched backbone bonds held (fene_clamp)")
+                "single-strand rule, overstretched backbone bonds held (fene_clamp), damped dihedral "
+                "(dihedral_damping)")
+    elif name == "sm":
+        cfg = synth.config_single_molecule()
+        desc = ("single-molecule set-ups of Sec. 4: 120 x 300 bp pulled by 0.1-10 pN (force-extension), "
+                "40 x 600 bp at 16 pN under -20..20 pN nm (twist response), anchored")
     elif name == "rings":
         # circular DNA (Sec. 4.2): 128 planar rings of 510 bp wound 48 times
         # (Lk = 48 against the relaxed 51, i.e. Delta Lk = -3), stacked 5 apart
@@ -381,6 +386,94 @@ def melting_report(D, cfg, sim, args):
     return {"samples": rows, "stopped": stopped}
 
 
+def single_molecule_report(D, cfg, sim, args):
+    """Force-extension (Sec. 4.1): R_z = (c(last bp) - c(first bp)) . e_z of
+    the centreline averaged per force, fitted to the Marko-Siggia
+    interpolation F l_p / kT = R_z/L + 1/(4 (1 - R_z/L)^2) - 1/4 for L and
+    l_p.  Twist response (Sec. 4.2): sigma = (<twist per bp> - 36 deg)/36 deg
+    per torque (the chain held straight by 16 pN has no writhe, so Lk - Lk0
+    is the excess twist), and C = (a0/theta0) dGamma/dsigma / kT from the
+    slope over the linear regime |sigma| < 0.1 (a torque that melts the
+    duplex leaves it).  The chains start straight, so a force enters the fit
+    only if the equilibration lasted 3 relaxation times of the slowest
+    bending mode at that tension, tau(F) = zeta / (kappa q^4 + F q^2) with
+    q = 4.73/L, zeta = 4 gamma per rise (four sites per base pair) and
+    kappa = 45 kT nm (the measured persistence length).  Errors: standard
+    errors of the per-replica means; the fit errors from the covariance of
+    the least-squares fit."""
+    from scipy.optimize import curve_fit
+    n_bp = np.asarray(cfg["n_bp"], np.int64)
+    off = np.concatenate([[0], np.cumsum(2 * n_bp)])
+    grp, fpn, gpn = cfg["group"], cfg["f_pn"], cfg["g_pnnm"]
+    done = 0
+    while done < args.equil_steps:
+        k = min(1000000, args.equil_steps - done)
+        sim.step(k)
+        done += k
+        log("equilibration: %d of %d steps" % (done, args.equil_steps))
+    rz = np.zeros(len(n_bp))
+    tw = np.zeros(len(n_bp))
+    ns = max(2, args.samples)
+    for q in range(ns):
+        sim.step(args.sample_every)
+        b, p = sim.sites()
+        for r in range(len(n_bp)):
+            bb, pp = b[off[r]:off[r + 1]], p[off[r]:off[r + 1]]
+            c = 0.5 * (pp[0::2] + pp[1::2])
+            rz[r] += (c[-1, 2] - c[0, 2]) / ns
+            if grp[r] == 1:
+                t = c[1:] - c[:-1]
+                t /= np.linalg.norm(t, axis=1, keepdims=True)
+                v = bb[0::2] - bb[1::2]
+                f0 = v[:-1] - t * np.sum(v[:-1] * t, 1, keepdims=True)
+                f1 = v[1:] - t * np.sum(v[1:] * t, 1, keepdims=True)
+                phi = np.arctan2(np.sum(np.cross(f0, f1) * t, 1), np.sum(f0 * f1, 1))
+                tw[r] += np.degrees(phi[5:-5]).mean() / ns
+        if q % 50 == 0:
+            log("sample %d of %d" % (q, ns))
+    kT = 4.1419  # pN nm
+    fe = grp == 0
+    forces = np.unique(fpn[fe])
+    Lc = 0.34 * n_bp[fe][0]
+    q = 4.73 / Lc
+    zeta = 4.0 * sim.params.gamma / 0.34
+    t_eq = args.equil_steps * sim.params.dt
+    tau = zeta / (45.0 * q ** 4 + forces / kT * q ** 2)
+    use = t_eq >= 3.0 * tau
+    zm = np.array([rz[fe & (fpn == f)].mean() for f in forces])
+    zs = np.array([rz[fe & (fpn == f)].std(ddof=1) / np.sqrt(np.sum(fe & (fpn == f))) for f in forces])
+
+    def ms(z, L, lp):
+        x = np.clip(z / L, -0.99, 0.99)
+        return kT / lp * (x + 0.25 / (1 - x) ** 2 - 0.25)
+
+    # the interpolation gives F(R_z): fit the forces at the measured mean
+    # extensions (residuals in force)
+    popt, pcov = curve_fit(ms, zm[use], forces[use], p0=(0.34 * n_bp[fe][0], 50.0), maxfev=20000)
+    L, lp = popt
+    dL, dlp = np.sqrt(np.diag(pcov))
+    tq = grp == 1
+    torques = np.unique(gpn[tq])
+    sg = np.array([(tw[tq & (gpn == g)].mean() - 36.0) / 36.0 for g in torques])
+    ss = np.array([tw[tq & (gpn == g)].std(ddof=1) / np.sqrt(np.sum(tq & (gpn == g))) / 36.0 for g in torques])
+    lin = np.abs(sg) < 0.1
+    A = np.vstack([sg[lin], np.ones(int(lin.sum()))]).T
+    slope, icpt = np.linalg.lstsq(A, torques[lin], rcond=None)[0]   # dGamma/dsigma, pN nm
+    a0, th0 = 0.34, 2 * np.pi / 10
+    C = a0 / th0 * slope / kT
+    out = {"equilibration_steps": args.equil_steps, "samples": ns, "sample_every": args.sample_every,
+           "force_extension": {"f_pn": forces.tolist(), "rz_nm": zm.tolist(), "rz_sem": zs.tolist(),
+                               "relax_time": tau.tolist(), "in_fit": use.tolist(),
+                               "L_nm": float(L), "L_err": float(dL), "lp_nm": float(lp), "lp_err": float(dlp),
+                               "lp_bp": float(lp / 0.334), "rise_nm": float(L / n_bp[fe][0])},
+           "twist_response": {"torque_pnnm": torques.tolist(), "sigma": sg.tolist(), "sigma_sem": ss.tolist(),
+                              "in_fit": lin.tolist(),
+                              "dgamma_dsigma_pnnm": float(slope), "C_nm": float(C), "C_bp": float(C / 0.34)}}
+    log("force-extension: L = %.1f +- %.1f nm, l_p = %.1f +- %.1f nm; twist: C = %.1f nm"
+        % (L, dL, lp, dlp, C))
+    return out
+
+
 def supercoil_report(D, cfg, sim, args):
     """Linking number of the strands and writhe of the centreline of every
     ring (Gauss's double integral, appendix on the closure procedure) every
@@ -459,7 +552,8 @@ def main():
     prm = D.dsdna_default_params(seed=0, cell_size=args.cell, hash_log2=args.hash_log2,
                                  graph_steps=args.graph_steps,
                                  ssdna_rule=1 if args.config in ("denat", "denat_seq") else 0,
-                                 fene_clamp=1 if args.config == "denat_seq" else 0, **extra)
+                                 fene_clamp=1 if args.config == "denat_seq" else 0,
+                                 dihedral_damping=1 if args.config == "denat_seq" else 0, **extra)
     sim = D.DsDNA(cfg, prm, device=0, stream=stream.cuda_stream)
     sim.thermalize(1.0, 0)
     tuned = None
@@ -556,6 +650,8 @@ def main():
         observables = supercoil_report(D, cfg, sim, args)
     elif args.config == "denat_seq":
         observables = melting_report(D, cfg, sim, args)
+    elif args.config == "sm":
+        observables = single_molecule_report(D, cfg, sim, args)
     sim.close()
 
     batch = None

@@ -121,7 +121,10 @@ typedef struct {
                                        there (the force keeps growing with r,
                                        the energy is capped), and only a bond
                                        of 2 R0 stops the run               */
-    int32_t pad;
+    int32_t dihedral_damping;       /* 0: dihedral as printed; 1: multiplied
+                                       by sin^3 of both of its bond angles
+                                       (finite gradient at collinear bonds;
+                                       1 at the ideal helix)               */
 } dsdna_params;
 
 /* Table 2 values plus the defaults for what the paper leaves open: unit

@@ -56,6 +56,9 @@ typedef struct {
     int32_t hb_depth_convention;   /* 0: prefactor K2/(2(r0-rc)^2)         */
     int32_t fene_clamp;            /* 1: hold 1 - r^2/R0^2 at >= 0.1 (a
                                       reading for overstretched bonds)     */
+    int32_t dihedral_damping;      /* 1: dihedral x sin^3 of both bond
+                                      angles (a reading, see below)        */
+    int32_t pad;
 } orc_params;
 
 typedef struct {
@@ -378,6 +381,20 @@ static double angle_cos(v3 a, v3 b, v3 c, v3 *dca, v3 *dcc)
  *   dphi/dp1 = -|G|/|A|^2 A,          dphi/dp4 = +|G|/|B|^2 B,
  *   dphi/dp2 = +|G|/|A|^2 A + (F.G)/(|A|^2|G|) A - (H.G)/(|B|^2|G|) B,
  *   dphi/dp3 = -|G|/|B|^2 B - (F.G)/(|A|^2|G|) A + (H.G)/(|B|^2|G|) B. */
+/* sin^3 of the angle between u and w, and its gradients du, dw with respect
+ * to u and w: with c the cosine, d(sin^3)/dc = -3 sin c. */
+static double sin_cube(v3 u, v3 w, v3 *du, v3 *dw)
+{
+    double lu = v3_len(u), lw = v3_len(w);
+    double c = v3_dot(u, w) / (lu * lw);
+    double s2 = 1.0 - c * c;
+    double s = s2 > 0.0 ? sqrt(s2) : 0.0;
+    double k = -3.0 * s * c;
+    *du = v3_mul(v3_sub(v3_mul(w, 1.0 / (lu * lw)), v3_mul(u, c / (lu * lu))), k);
+    *dw = v3_mul(v3_sub(v3_mul(u, 1.0 / (lu * lw)), v3_mul(w, c / (lw * lw))), k);
+    return s2 * s;
+}
+
 static double dihedral(v3 p1, v3 p2, v3 p3, v3 p4, v3 g[4])
 {
     v3 b1 = v3_sub(p2, p1), b2 = v3_sub(p3, p2), b3 = v3_sub(p4, p3);
@@ -552,6 +569,31 @@ int orc_forces(const orc_params *P, const orc_system *sys, const double *bead,
                                       v3_ld(patch + 3 * j), v3_ld(bead + 3 * j), g);
                 double U = P->K3 * (1.0 + cos(phi - P->d_dih));
                 double dUdphi = -P->K3 * sin(phi - P->d_dih);
+                if (P->dihedral_damping) {
+                    /* the reading for bubbles and frayed ends: U sin^3(t1)
+                     * sin^3(t2), t1 and t2 the bond angles at the two middle
+                     * sites (the combined bending-torsion form of Bulacu et
+                     * al., J. Chem. Theory Comput. 9, 3282 (2013)); its
+                     * gradient stays finite where a bond angle reaches 0 or pi,
+                     * where that of the bare dihedral diverges */
+                    v3 p1 = v3_ld(bead + 3 * i), p2 = v3_ld(patch + 3 * i);
+                    v3 p3 = v3_ld(patch + 3 * j), p4 = v3_ld(bead + 3 * j);
+                    v3 b1 = v3_sub(p2, p1), b2 = v3_sub(p3, p2), b3 = v3_sub(p4, p3);
+                    v3 d1u, d1w, d2u, d2w;
+                    double S1 = sin_cube(b1, b2, &d1u, &d1w), S2 = sin_cube(b2, b3, &d2u, &d2w);
+                    double S = S1 * S2;
+                    v3 dS[4];
+                    dS[0] = v3_mul(d1u, -S2);
+                    dS[1] = v3_sub(v3_mul(v3_sub(d1u, d1w), S2), v3_mul(d2u, S1));
+                    dS[2] = v3_add(v3_mul(d1w, S2), v3_mul(v3_sub(d2u, d2w), S1));
+                    dS[3] = v3_mul(d2w, S1);
+                    v3_acc(FB(T_TWIST, i), v3_sub(v3_mul(g[0], -dUdphi * S), v3_mul(dS[0], U)));
+                    v3_acc(FP(T_TWIST, i), v3_sub(v3_mul(g[1], -dUdphi * S), v3_mul(dS[1], U)));
+                    v3_acc(FP(T_TWIST, j), v3_sub(v3_mul(g[2], -dUdphi * S), v3_mul(dS[2], U)));
+                    v3_acc(FB(T_TWIST, j), v3_sub(v3_mul(g[3], -dUdphi * S), v3_mul(dS[3], U)));
+                    EN(r, T_TWIST) += U * S;
+                    continue;
+                }
                 v3_acc(FB(T_TWIST, i), v3_mul(g[0], -dUdphi));
                 v3_acc(FP(T_TWIST, i), v3_mul(g[1], -dUdphi));
                 v3_acc(FP(T_TWIST, j), v3_mul(g[2], -dUdphi));

@@ -200,6 +200,7 @@ static void fill_phys(dsdna_ctx *c)
     h.noise_kind = p.noise_kind;
     h.ssdna_rule = p.ssdna_rule;
     h.fene_clamp = p.fene_clamp;
+    h.dihedral_damping = p.dihedral_damping;
 }
 
 static double rc_max(const dsdna_ctx *c) { return TWO_16 * std::max(c->prm.sig_s, c->prm.sig_x); }

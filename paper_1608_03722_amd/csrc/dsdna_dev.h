@@ -38,7 +38,7 @@ struct Phys {
     double inv_R0sq;          // 1 / R0^2
     uint64_t seed;
     int32_t noise_kind, ssdna_rule;
-    int32_t fene_clamp, pad_;
+    int32_t fene_clamp, dihedral_damping;
 };
 
 enum : uint32_t {

@@ -527,8 +527,9 @@ __device__ __forceinline__ real atan2_small(real y, real x)
 // has staged (stage_site) beforehand; `fex` is the thread's excluded-volume
 // force.  Must be called by all threads of the workgroup (it synchronises).
 // With energies != nullptr the per-term energies owned by this thread are
-// added there (diagnostics only).
-template <typename real>
+// added there (diagnostics only).  DAMP selects the damped dihedral (the
+// dihedral_damping reading).
+template <typename real, bool DAMP>
 __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileLds<real> &S, const RepInfo &ri, const Tile &tile,
                                         V3<real> fex, uint32_t mask, int64_t step, double *energies)
 {
@@ -696,7 +697,35 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
             const double inv = rsq64(AAd * BBd);
             const double cphi = dot(Ad, Bd) * inv, sphi = lGd * dot(b1d, Bd) * inv;
             // -dU/dphi = K3 sin(phi - d)
-            const real mdU = (real)(ph.K3 * (sphi * ph.cos_d - cphi * ph.sin_d));
+            double mdU64 = ph.K3 * (sphi * ph.cos_d - cphi * ph.sin_d);
+            D3 dS0 = v3(0.0, 0.0, 0.0), dS1 = dS0, dS2 = dS0, dS3 = dS0;
+            double Ud = 0.0, Sd = 1.0;
+            if constexpr (DAMP) {
+                // dihedral_damping: U sin^3(t1) sin^3(t2) with t1, t2 the bond
+                // angles at P_m and P_m+1 (combined bending-torsion form of
+                // Bulacu et al., J. Chem. Theory Comput. 9, 3282 (2013)); with c
+                // the cosine, d(sin^3)/dc = -3 sin c
+                const double L1 = dot(b1d, b1d), L3 = dot(b3d, b3d);
+                const double i12 = rsq64(L1 * GGd), i23 = rsq64(GGd * L3);
+                const double c1 = dot(b1d, b2d) * i12, c2 = dot(b2d, b3d) * i23;
+                const double q1 = fmax(1.0 - c1 * c1, 0.0), q2 = fmax(1.0 - c2 * c2, 0.0);
+                const double s1 = sqrt(q1), s2 = sqrt(q2);
+                const double S1 = q1 * s1, S2 = q2 * s2;
+                const double k1 = -3.0 * s1 * c1, k2 = -3.0 * s2 * c2;
+                // gradients of S1 (angle of b1, b2) and S2 (angle of b2, b3)
+                const D3 g1u = (b2d * i12 - b1d * (c1 * rcp64(L1))) * k1;
+                const D3 g1w = (b1d * i12 - b2d * (c1 * rcp64(GGd))) * k1;
+                const D3 g2u = (b3d * i23 - b2d * (c2 * rcp64(GGd))) * k2;
+                const D3 g2w = (b2d * i23 - b3d * (c2 * rcp64(L3))) * k2;
+                Sd = S1 * S2;
+                Ud = ph.K3 * (1.0 + cphi * ph.cos_d + sphi * ph.sin_d);
+                dS0 = g1u * (-S2);
+                dS1 = (g1u - g1w) * S2 - g2u * S1;
+                dS2 = g1w * S2 + (g2u - g2w) * S1;
+                dS3 = g2w * S1;
+                mdU64 *= Sd;
+            }
+            const real mdU = (real)mdU64;
             const V3<real> A = cvt<real>(Ad), B = cvt<real>(Bd);
             const real AA = (real)AAd, BB = (real)BBd, iG = (real)iGd, lG = (real)lGd;
             const real FG = (real)dot(b1d, b2d), HG = (real)(-dot(b3d, b2d));
@@ -707,7 +736,13 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
             fPa = fPa + (tA + sA - sB) * mdU;
             fPb = fPb + (-tB - sA + sB) * mdU;
             fBb = fBb + tB * mdU;
-            if (energies && own) energies[DSDNA_TERM_TWIST] += ph.K3 * (1.0 + cphi * ph.cos_d + sphi * ph.sin_d);
+            if constexpr (DAMP) {
+                fBa = fBa - cvt<real>(dS0 * Ud);
+                fPa = fPa - cvt<real>(dS1 * Ud);
+                fPb = fPb - cvt<real>(dS2 * Ud);
+                fBb = fBb - cvt<real>(dS3 * Ud);
+            }
+            if (energies && own) energies[DSDNA_TERM_TWIST] += Sd * ph.K3 * (1.0 + cphi * ph.cos_d + sphi * ph.sin_d);
         }
         put3(S.oStep[s][mi][0], get3(S.oStep[s][mi][0]) + fBa);
         put3(S.oStep[s][mi][1], get3(S.oStep[s][mi][1]) + fPa);
@@ -841,7 +876,7 @@ __device__ __forceinline__ D3 rotate(D3 u, D3 k, double th)
 
 // ---------------------------------------------------------------- k_step
 
-template <typename real>
+template <typename real, bool DAMP>
 __global__ void __launch_bounds__(WG_THREADS, 5) k_step(const StepArgs *__restrict__ A, int mode, int write_full)
 {
     __shared__ TileLds<real> S;
@@ -875,7 +910,7 @@ __global__ void __launch_bounds__(WG_THREADS, 5) k_step(const StepArgs *__restri
     f.p = f.b;
     if (mode != MODE_FROM_FORCES) {
         stage_site(a, S, site);
-        f = tile_forces<real>(a, S, ri, tile, fexv, ALL_TERMS, step, nullptr);
+        f = tile_forces<real, DAMP>(a, S, ri, tile, fexv, ALL_TERMS, step, nullptr);
     }
     // velocities and noise only now: they are not live through the force
     // phase, and the noise is drawn while the velocity loads are in flight
@@ -1683,7 +1718,7 @@ __global__ void __launch_bounds__(64) k_gauss_sum(const RingSeg *__restrict__ ri
 
 // --------------------------------------------------------------- diagnostics
 
-template <typename real>
+template <typename real, bool DAMP>
 __global__ void __launch_bounds__(WG_THREADS) k_diag(const StepArgs *__restrict__ A, int which, uint32_t mask)
 {
     __shared__ TileLds<real> S;
@@ -1704,7 +1739,7 @@ __global__ void __launch_bounds__(WG_THREADS) k_diag(const StepArgs *__restrict_
     const bool flagged = contact_flag(a, tix);
     const V3<real> fexv = (n < tile.n_bp && flagged) ? take_fex<real>(a, site.i) : v3<real>(0, 0, 0);
     stage_site(a, S, site);
-    SiteForces<real> f = tile_forces<real>(a, S, ri, tile, fexv, mask, step, e);
+    SiteForces<real> f = tile_forces<real, DAMP>(a, S, ri, tile, fexv, mask, step, e);
     if (n < tile.n_bp) {
         const int64_t i = ri.off + 2 * (int64_t)n + s;
         a.b.diag_fb[3 * i] = (double)f.b.x;
@@ -1759,10 +1794,15 @@ hipError_t launch_scatter(const StepArgs &a, int inc_step, hipStream_t s)
 
 hipError_t launch_step(const StepArgs &a, const StepArgs *dA, int fp64, int mode, int write_full, hipStream_t s)
 {
-    if (fp64)
-        hipLaunchKernelGGL(k_step<double>, tiles_grid(a), dim3(WG_THREADS), 0, s, dA, mode, write_full);
+    const bool damp = a.ph.dihedral_damping != 0;
+    if (fp64 && damp)
+        hipLaunchKernelGGL((k_step<double, true>), tiles_grid(a), dim3(WG_THREADS), 0, s, dA, mode, write_full);
+    else if (fp64)
+        hipLaunchKernelGGL((k_step<double, false>), tiles_grid(a), dim3(WG_THREADS), 0, s, dA, mode, write_full);
+    else if (damp)
+        hipLaunchKernelGGL((k_step<float, true>), tiles_grid(a), dim3(WG_THREADS), 0, s, dA, mode, write_full);
     else
-        hipLaunchKernelGGL(k_step<float>, tiles_grid(a), dim3(WG_THREADS), 0, s, dA, mode, write_full);
+        hipLaunchKernelGGL((k_step<float, false>), tiles_grid(a), dim3(WG_THREADS), 0, s, dA, mode, write_full);
     return hipGetLastError();
 }
 
@@ -1801,10 +1841,15 @@ hipError_t launch_thermalize(const StepArgs &a, const StepArgs *dA, double kT, u
 hipError_t launch_diag(const StepArgs &a, const StepArgs *dA, int which, int fp64, uint32_t term_mask,
                        hipStream_t s)
 {
-    if (fp64)
-        hipLaunchKernelGGL(k_diag<double>, tiles_grid(a), dim3(WG_THREADS), 0, s, dA, which, term_mask);
+    const bool damp = a.ph.dihedral_damping != 0;
+    if (fp64 && damp)
+        hipLaunchKernelGGL((k_diag<double, true>), tiles_grid(a), dim3(WG_THREADS), 0, s, dA, which, term_mask);
+    else if (fp64)
+        hipLaunchKernelGGL((k_diag<double, false>), tiles_grid(a), dim3(WG_THREADS), 0, s, dA, which, term_mask);
+    else if (damp)
+        hipLaunchKernelGGL((k_diag<float, true>), tiles_grid(a), dim3(WG_THREADS), 0, s, dA, which, term_mask);
     else
-        hipLaunchKernelGGL(k_diag<float>, tiles_grid(a), dim3(WG_THREADS), 0, s, dA, which, term_mask);
+        hipLaunchKernelGGL((k_diag<float, false>), tiles_grid(a), dim3(WG_THREADS), 0, s, dA, which, term_mask);
     return hipGetLastError();
 }
 

@@ -47,7 +47,8 @@ class Params(C.Structure):
         "gamma", "kT", "dt")] + [
         ("seed", C.c_uint64), ("noise_kind", C.c_int32), ("force_fp64", C.c_int32),
         ("ssdna_rule", C.c_int32), ("hb_depth_convention", C.c_int32), ("cell_size", C.c_double),
-        ("hash_log2", C.c_int32), ("graph_steps", C.c_int32), ("fene_clamp", C.c_int32), ("pad", C.c_int32)]
+        ("hash_log2", C.c_int32), ("graph_steps", C.c_int32), ("fene_clamp", C.c_int32),
+        ("dihedral_damping", C.c_int32)]
 
 
 _lib = None

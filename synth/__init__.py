@@ -244,6 +244,35 @@ def config_tethered_replicas(n_rep=256, n_torque=64, lo=500, hi=5000, f_lo_pn=0.
                 tether=np.ones(n_rep, np.uint8), wall_z=np.zeros(n_rep))
 
 
+def config_single_molecule(n_fe=300, f_pn=None, reps_fe=12, n_tq=600, f_tq_pn=16.0, g_pnnm=None, reps_tq=8):
+    """The single-molecule set-ups of Sec. 4 in one batch of tethered replicas
+    (first bp anchored at z = 1 above a wall at z = 0, ideal straight helix
+    along +z): force-extension, n_fe bp pulled by each force in f_pn (pN,
+    reps_fe replicas each); twist response, n_tq bp pulled by f_tq_pn and
+    twisted by each torque in g_pnnm (pN nm, reps_tq replicas each).  Loads in
+    reduced units; `group` is 0 for force-extension, 1 for torque replicas,
+    and `f_pn`, `g_pnnm` the loads per replica in pN and pN nm."""
+    f_pn = np.geomspace(0.1, 10.0, 10) if f_pn is None else np.asarray(f_pn, float)
+    g_pnnm = np.array([-20.0, -10.0, 0.0, 10.0, 20.0]) if g_pnnm is None else np.asarray(g_pnnm, float)
+    fa = np.repeat(f_pn, reps_fe)
+    gb = np.repeat(g_pnnm, reps_tq)
+    n_rep = len(fa) + len(gb)
+    n_bp = np.concatenate([np.full(len(fa), n_fe), np.full(len(gb), n_tq)]).astype(np.int32)
+    fpn = np.concatenate([fa, np.full(len(gb), f_tq_pn)])
+    gpn = np.concatenate([np.zeros(len(fa)), gb])
+    pull = np.zeros((n_rep, 3))
+    pull[:, 2] = fpn / PN_PER_UNIT
+    torque = np.zeros((n_rep, 3))
+    torque[:, 2] = gpn / PNNM_PER_UNIT
+    bead, patch = concat_replicas([ideal_helix(int(n), origin=(0.0, 0.0, 1.0)) for n in n_bp])
+    big = 1e5
+    return dict(n_bp=n_bp, bead=bead, patch=patch,
+                box=np.tile([-big, -big, -big, big, big, big], (n_rep, 1)).astype(np.float64),
+                periodic=np.zeros((n_rep, 3), np.uint8), pull=pull, torque=torque,
+                tether=np.ones(n_rep, np.uint8), wall_z=np.zeros(n_rep),
+                group=np.concatenate([np.zeros(len(fa), int), np.ones(len(gb), int)]), f_pn=fpn, g_pnnm=gpn)
+
+
 def config_denaturation_sequence(n_rep=64, n_bp=2000, k2_lo=1.0, k2_hi=1.4, at_ratio=2.0 / 3.0, at_frac=0.5,
                                  seed=5, k2_table=6.0):
     """Replicas of n_bp ideal helix at the paper's melting strengths: replica

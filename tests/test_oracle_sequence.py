@@ -84,3 +84,41 @@ def test_fene_hold_reading(orc, r):
     P = orc.default_params(fene_clamp=1)
     b, p = _stretched(2 * R0 + 0.01)
     assert orc.forces(P, orc.System([2]), b, p)[0] == orc.EBOND
+
+
+def test_dihedral_damping_reading(orc):
+    """dihedral_damping = 1 multiplies each dihedral by sin^3 t1 sin^3 t2 of
+    its two bond angles (Bulacu et al. 2013): unchanged at the ideal helix
+    (both angles 90 deg) and its mirror, forces minus the gradient of the
+    damped energy, and bounded where a bond angle closes, where the bare
+    dihedral's gradient diverges."""
+    t = orc.T["twist"]
+    P0, P1 = orc.default_params(), orc.default_params(dihedral_damping=1)
+    for b, p in (synth.ideal_helix(6), synth.mirror_helix(6)):
+        E0 = orc.forces(P0, orc.System([6]), b, p)[4][0, t]
+        E1 = orc.forces(P1, orc.System([6]), b, p)[4][0, t]
+        assert E1 == pytest.approx(E0, rel=1e-13) and E0 > 0.0 or E0 == 0.0
+    # finite differences of the damped energy on a thermal-like state
+    b, p = synth.ideal_helix(8)
+    b, p = synth.perturb(b, 0.05, 21), synth.perturb(p, 0.05, 22)
+    S = orc.System([8])
+    _, _, fb, fp, E, _ = orc.forces(P1, S, b, p)
+    h = 1e-6
+    for X, F, isb in ((b, fb[t], True), (p, fp[t], False)):
+        for i in range(X.shape[0]):
+            for k in range(3):
+                Xp = X.copy(); Xp[i, k] += h
+                Xm = X.copy(); Xm[i, k] -= h
+                ep = orc.forces(P1, S, *((Xp, p) if isb else (b, Xp)))[4][0, t]
+                em = orc.forces(P1, S, *((Xm, p) if isb else (b, Xm)))[4][0, t]
+                assert abs(-(ep - em) / (2 * h) - F[i, k]) < 2e-6 * max(1.0, np.abs(F).max())
+    assert E[0, t] < orc.forces(P0, S, b, p)[4][0, t] + 1e-12   # the damping only lowers the energy
+    # bp 0 strand 0: its bead placed almost on the line of the two patches
+    # (a bond angle of 1e-4 rad): bare gradient ~1/sin, damped bounded
+    b, p = synth.ideal_helix(3)
+    b, p = b.copy(), p.copy()
+    d = p[2] - p[0]
+    b[0] = p[0] - 0.5 * d / np.linalg.norm(d) + np.array([0.0, 1e-4 * 0.5, 0.0])  # phi off its minimum
+    f_bare = np.abs(orc.forces(P0, orc.System([3]), b, p)[2][t]).max()
+    f_damp = np.abs(orc.forces(P1, orc.System([3]), b, p)[2][t]).max()
+    assert f_bare > 1e3 and f_damp < 1e2, (f_bare, f_damp)

@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor peak
 FP64_PEAK_GFLOPS = 78600.0  # MI355X FP64 vector, vendor peak
 # Algorithmic bytes per nucleotide of one launch of each kernel in a fully
-# periodic box (every byte the kernel must move once; see DESIGN.md).  The
+# periodic box (every byte the kernel must move once).  The
 # excluded-volume forces travel through sparse accumulators touched only by
 # beads in contact (about 1e-3 of them), so they add no bytes per nucleotide.
 KERNEL_BYTES_PER_NT = {
@@ -354,10 +354,10 @@ def persistence_report(D, cfg, sim, args):
 
 # FP64 operations of one segment-pair solid angle as the kernel writes it:
 # four difference vectors (12), four squared lengths (20), two triangles of
-# (cross 9 + triple 5 + denominator 23 + 1), one sum; the 4 square roots and
-# 2 atan2 calls are counted as one operation each, so this figure is a floor
-# on the arithmetic issued.
-PAIR_FLOPS = 115
+# (cross 9 + triple 5 + denominator 23), their complex product (6), one
+# doubling; the 4 square roots and the atan2 call are counted as one
+# operation each, so this figure is a floor on the arithmetic issued.
+PAIR_FLOPS = 118
 
 
 def melting_report(D, cfg, sim, args):
@@ -490,7 +490,9 @@ def supercoil_report(D, cfg, sim, args):
                        "wr_sem": float(wr.std(ddof=1) / np.sqrt(len(wr))), "lk_mean": float(lk.mean())})
         times.append(ms)
         log("sample %d: Lk %.6f .. %.6f, <Wr> %.4f (pair kernel %.3f ms)" % (k, lk.min(), lk.max(), wr.mean(), ms))
-    pairs = int(np.sum(2 * n_bp * n_bp))   # Lk and Wr rows, all ordered segment pairs
+    # Lk: every ordered pair of strand segments; Wr: each unordered pair of
+    # centreline segments that share no vertex, once
+    pairs = int(np.sum(n_bp * n_bp + n_bp * (n_bp - 3) // 2))
     ms = float(np.median(times))
     return {"lk_target": 48, "lk_max_abs_dev": lk_dev, "writhe": series,
             "pair_kernel": {"ms_median": ms, "pairs_per_launch": pairs,
@@ -525,8 +527,8 @@ def main():
                     help="first run one device-to-device copy of this many MiB (a counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: there is no multi-GPU path in this library "
-              "(DESIGN.md describes how the step would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: this library has no multi-GPU path (replicas would be "
+              "assigned whole to GPUs, a single long chain split into spatial slabs)", file=sys.stderr)
         sys.exit(2)
 
     import torch

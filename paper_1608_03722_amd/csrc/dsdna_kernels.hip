@@ -1608,15 +1608,14 @@ __global__ void __launch_bounds__(LK_THREADS) k_curves(const StepArgs *__restric
     pC[0] = c.x; pC[1] = c.y; pC[2] = c.z;
 }
 
-// Signed solid angle of the spherical triangle with vertices along x, y, z
-// (lengths lx, ly, lz), from tan(Omega/2) = x.(y x z) / (lx ly lz +
-// (x.y) lz + (x.z) ly + (y.z) lx) (Van Oosterom and Strackee, IEEE Trans.
-// Biomed. Eng. 30, 125 (1983)).
-__device__ __forceinline__ double tri_omega(D3 x, D3 y, D3 z, double lx, double ly, double lz)
+// Half the signed solid angle of the spherical triangle with vertices along
+// x, y, z (lengths lx, ly, lz) as the point (den, num) whose argument it is:
+// tan(Omega/2) = x.(y x z) / (lx ly lz + (x.y) lz + (x.z) ly + (y.z) lx)
+// (Van Oosterom and Strackee, IEEE Trans. Biomed. Eng. 30, 125 (1983)).
+__device__ __forceinline__ void tri_half(D3 x, D3 y, D3 z, double lx, double ly, double lz, double &num, double &den)
 {
-    const double num = dot(x, cross(y, z));
-    const double den = lx * ly * lz + dot(x, y) * lz + dot(x, z) * ly + dot(y, z) * lx;
-    return 2.0 * atan2(num, den);
+    num = dot(x, cross(y, z));
+    den = lx * ly * lz + dot(x, y) * lz + dot(x, z) * ly + dot(y, z) * lx;
 }
 
 // Gauss's double integral (appendix on the closure procedure) over segment
@@ -1624,22 +1623,31 @@ __device__ __forceinline__ double tri_omega(D3 x, D3 y, D3 z, double lx, double 
 // 4 pi.  The integrand is the pull-back of the area form of the sphere by
 // (r_1 - r_2)/|r_1 - r_2| up to sign, so the pair integral is the signed
 // area of the geodesic quadrangle with corners p1-p3, p2-p3, p2-p4, p1-p4;
-// written with r_ij = p_j - p_i it is the fan of two triangles below.
+// written with r_ij = p_j - p_i it is the fan of two triangles below.  The
+// difference vectors of two disjoint segments fill a parallelogram that
+// misses the origin, so they lie in an open half-space and the area is below
+// 2 pi: the two half-angles add as the argument of the product of their
+// points, one atan2 for the pair.
 __device__ __forceinline__ double pair_omega(D3 p1, D3 p2, D3 p3, D3 p4)
 {
     const D3 r13 = p3 - p1, r14 = p4 - p1, r23 = p3 - p2, r24 = p4 - p2;
     const double l13 = sqrt(dot(r13, r13)), l14 = sqrt(dot(r14, r14));
     const double l23 = sqrt(dot(r23, r23)), l24 = sqrt(dot(r24, r24));
-    return tri_omega(r13, r23, r24, l13, l23, l24) + tri_omega(r13, r24, r14, l13, l24, l14);
+    double y1, x1, y2, x2;
+    tri_half(r13, r23, r24, l13, l23, l24, y1, x1);
+    tri_half(r13, r24, r14, l13, l24, l14, y2, x2);
+    return 2.0 * atan2(y1 * x2 + y2 * x1, x1 * x2 - y1 * y2);
 }
 
 // Row sums of the segment-pair solid angles: thread i of a workgroup holds
 // segment i -> i+1 (mod n) of the strand 0 curve and of the centreline; the
 // strand 1 curve and the centreline stream through LDS in chunks of
 // LK_THREADS segments.  Per workgroup: sum over its rows of Omega(A_i, B_j)
-// over all j (the linking number) and of Omega(C_i, C_j) over every j whose
-// segment shares no vertex with segment i (the writhe, each unordered pair
-// twice), reduced in a fixed order to partial[block][2].
+// over all j (the linking number) and of Omega(C_i, C_j) over the half
+// window of j whose segment shares no vertex with segment i, j - i = 2 ..
+// n/2 (mod n), the antipodal j - i = n/2 of an even ring only from i < n/2
+// (the writhe, each unordered pair once), reduced in a fixed order to
+// partial[block][2].
 __global__ void __launch_bounds__(LK_THREADS) k_gauss(const RingSeg *__restrict__ rings, const int2 *__restrict__ blocks,
                                                      int n_pts, const double *__restrict__ curves,
                                                      double *__restrict__ partial)
@@ -1678,8 +1686,9 @@ __global__ void __launch_bounds__(LK_THREADS) k_gauss(const RingSeg *__restrict_
             const D3 b0 = lds3(sB, q), b1 = lds3(sB, q + 1);
             lk += pair_omega(a0, a1, b0, b1);
             const int j = j0 + q;
-            const int j1 = j + 1 == n ? 0 : j + 1;
-            if (j != i && j != i1 && j1 != i) wr += pair_omega(c0, c1, lds3(sC, q), lds3(sC, q + 1));
+            const int d = j >= i ? j - i : j - i + n;  // (j - i) mod n
+            if (d >= 2 && d <= n - 2 && (2 * d < n || (2 * d == n && 2 * i < n)))
+                wr += pair_omega(c0, c1, lds3(sC, q), lds3(sC, q + 1));
         }
     }
     red[t][0] = lk;
@@ -1697,9 +1706,9 @@ __global__ void __launch_bounds__(LK_THREADS) k_gauss(const RingSeg *__restrict_
     }
 }
 
-// Per ring, in block order: Lk = (sum of its rows) / (4 pi) and Wr the same
-// for the centreline (whose rows count each pair twice, as the integral
-// over the torus does).
+// Per ring, in block order: Lk = (sum of its rows) / (4 pi) and Wr twice the
+// sum of its rows over 4 pi (the rows hold each unordered pair once, the
+// integral over the torus counts it twice).
 __global__ void __launch_bounds__(64) k_gauss_sum(const RingSeg *__restrict__ rings, int n_rings,
                                                  const double *__restrict__ partial, double *__restrict__ out)
 {
@@ -1713,7 +1722,7 @@ __global__ void __launch_bounds__(64) k_gauss_sum(const RingSeg *__restrict__ ri
     }
     const double k = 0.25 / 3.14159265358979323846;
     out[2 * r] = lk * k;
-    out[2 * r + 1] = wr * k;
+    out[2 * r + 1] = 2.0 * wr * k;
 }
 
 // --------------------------------------------------------------- diagnostics

@@ -307,7 +307,11 @@ def persistence_report(D, cfg, sim, args):
     5 bp dropped at each end, <t(n).t(n+m)> averaged over positions and
     samples per replica, l_p from straight-line fits of its logarithm over
     windows of m.  Errors from 8 groups of replicas; the straight and the
-    pre-bent halves are reported apart."""
+    pre-bent halves are reported apart.  Also the torsional persistence
+    length (Sec. 3.2 and the appendix on it): the twist phi_n of each step is
+    the angle between the two bead-bead vectors projected across the step's
+    tangent, Omega(m) the sum of m consecutive ones, and <cos(Omega(m) - m
+    theta)> with theta the mean twist decays as exp(-m / l_tau)."""
     n_rep, n_bp = len(cfg["n_bp"]), int(cfg["n_bp"][0])
     done = 0
     while done < args.equil_steps:
@@ -318,13 +322,30 @@ def persistence_report(D, cfg, sim, args):
     M = 151
     acc = np.zeros((n_rep, M))
     cnt = np.zeros((n_rep, M))
+    tw_cos = np.zeros((n_rep, M))
+    tw_sin = np.zeros((n_rep, M))
+    tw_cnt = np.zeros((n_rep, M))
+    tw_sum, tw_n = 0.0, 0
     for k in range(max(2, args.samples)):
         sim.step(args.sample_every)
-        _, p = sim.sites()
+        b, p = sim.sites()
         p = p.reshape(n_rep, 2 * n_bp, 3)
+        b = b.reshape(n_rep, 2 * n_bp, 3)
         c = 0.5 * (p[:, 0::2] + p[:, 1::2])
         t = c[:, 1:] - c[:, :-1]
         t /= np.linalg.norm(t, axis=2, keepdims=True)
+        v = b[:, 0::2] - b[:, 1::2]
+        f0 = v[:, :-1] - t * np.sum(v[:, :-1] * t, 2, keepdims=True)
+        f1 = v[:, 1:] - t * np.sum(v[:, 1:] * t, 2, keepdims=True)
+        phi = np.arctan2(np.sum(np.cross(f0, f1) * t, 2), np.sum(f0 * f1, 2))[:, 5:-5]
+        tw_sum += phi.sum()
+        tw_n += phi.size
+        P = np.concatenate([np.zeros((n_rep, 1)), np.cumsum(phi, 1)], 1)
+        for m in range(1, M):
+            om = P[:, m:] - P[:, :-m]
+            tw_cos[:, m] += np.cos(om).sum(1)
+            tw_sin[:, m] += np.sin(om).sum(1)
+            tw_cnt[:, m] += om.shape[1]
         t = t[:, 5:-5]
         n = t.shape[1]
         for m in range(M):
@@ -349,6 +370,20 @@ def persistence_report(D, cfg, sim, args):
         out[name] = {"lp_fits": fits, "corr": {str(m): float(cr.mean(0)[m]) for m in (1, 10, 50, 100, 150)}}
     log("persistence length (bp): %s" % {k: round(v["lp_fits"]["m_5_50"]["lp_bp"], 1)
                                          for k, v in out.items() if isinstance(v, dict)})
+    # torsional: <cos(Omega(m) - m theta)> = <cos Omega> cos(m theta) + <sin Omega> sin(m theta)
+    theta = tw_sum / tw_n
+    ms_all = np.arange(M)
+    ct = (tw_cos * np.cos(ms_all * theta) + tw_sin * np.sin(ms_all * theta))[:, 1:] / tw_cnt[:, 1:]
+    g = ct.reshape(groups, -1, M - 1).mean(1)
+    tfits = {}
+    for lo, hi in ((1, 30), (5, 50), (10, 100), (1, 150)):
+        mm = np.arange(lo, hi + 1)
+        fit = lambda c: float(-1.0 / np.polyfit(mm, np.log(c[lo - 1:hi]), 1)[0])
+        vals = np.array([fit(x) for x in g])
+        tfits["m_%d_%d" % (lo, hi)] = {"ltau_bp": fit(ct.mean(0)), "sem": float(vals.std(ddof=1) / np.sqrt(groups))}
+    out["torsion"] = {"twist_deg_per_bp": float(np.degrees(theta)), "ltau_fits": tfits,
+                      "corr": {str(m): float(ct.mean(0)[m - 1]) for m in (1, 10, 50, 100, 150)}}
+    log("torsional persistence length (bp, m 1-150): %.1f" % tfits["m_1_150"]["ltau_bp"])
     return out
 
 

@@ -558,6 +558,8 @@ def main():
                     help="denat / 10kbp / lp300: observables every this many steps")
     ap.add_argument("--samples", type=int, default=20, help="denat / 10kbp / lp300: number of samples")
     ap.add_argument("--equil-steps", type=int, default=0, help="lp300: steps before the first sample")
+    ap.add_argument("--param", action="append", default=[],
+                    help="override a dsdna_params field, name=value (e.g. hb_depth_convention=1); repeatable")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a counter calibration)")
     args = ap.parse_args()
@@ -591,6 +593,11 @@ def main():
                                  ssdna_rule=1 if args.config in ("denat", "denat_seq") else 0,
                                  fene_clamp=1 if args.config == "denat_seq" else 0,
                                  dihedral_damping=1 if args.config == "denat_seq" else 0, **extra)
+    for kv in args.param:
+        k, v = kv.split("=", 1)
+        if not hasattr(prm, k):
+            raise SystemExit("unknown parameter " + k)
+        setattr(prm, k, float(v) if isinstance(getattr(prm, k), float) else int(v))
     sim = D.DsDNA(cfg, prm, device=0, stream=stream.cuda_stream)
     sim.thermalize(1.0, 0)
     tuned = None
@@ -719,6 +726,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": desc, "n_bp": int(np.sum(cfg["n_bp"])), "n_nt": n_nt,
+                   "param_overrides": args.param,
                    "forces": "f32", "state": "f64", "cell_size": h, "buckets": nb,
                    "graph_steps": args.graph_steps, "parallelism": "single GPU"},
         "roofline": roof,

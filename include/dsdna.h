@@ -27,9 +27,10 @@
  *   - Every function returns a dsdna_status; DSDNA_OK is 0.  On failure
  *     dsdna_last_error() describes the cause (with step and nucleotide for
  *     DSDNA_EBOND, DSDNA_ENAN, DSDNA_EWALL, DSDNA_EDOMAIN, DSDNA_ECELL).
- *   - Call order: create -> set_topology -> (set_box, set_external,
- *     set_k2_scale) -> set_sites or set_state -> (thermalize or
- *     set_velocities) -> step ...  Out-of-order calls return DSDNA_ESTATE.
+ *   - Call order: create -> set_topology -> (set_box, set_circular,
+ *     set_external, set_k2_scale, set_k2_bp) -> set_sites or set_state ->
+ *     (thermalize or set_velocities) -> step ...  Out-of-order calls return
+ *     DSDNA_ESTATE.
  */
 #ifndef DSDNA_H
 #define DSDNA_H

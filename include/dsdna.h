@@ -165,7 +165,8 @@ dsdna_status dsdna_set_external(dsdna_ctx *ctx, int32_t rep, const double F[3],
  * multiplies K2 of each base pair, in replica order then bp order, on top of
  * the per-replica dsdna_set_k2_scale.  NULL removes the table (every base
  * pair then has multiplier 1).  Entries must be finite and >= 0
- * (DSDNA_EINVAL).  The table is copied; set_topology removes it. */
+ * (DSDNA_EINVAL).  The table is copied; set_topology removes it, and so does
+ * a failed copy. */
 dsdna_status dsdna_set_k2_bp(dsdna_ctx *ctx, const double *scale);
 
 /* Close replicas into rings (Sec. 4.2, circular DNA): circular[n_rep], 1 for
@@ -176,7 +177,8 @@ dsdna_status dsdna_set_k2_bp(dsdna_ctx *ctx, const double *scale);
  * bubbles cyclically.  A ring needs n_bp >= 6 and n_bp a multiple of 3 (the
  * steric beads, every third base pair, stay every third across the seam)
  * and takes no external loads; either is DSDNA_EINVAL.  The flag of every
- * replica is replaced by this call; set_topology clears all of them.
+ * replica is replaced by this call; set_topology clears all of them.  On
+ * any failure the previous rings stay as they were.
  * Placing the sites so that the ring closes is the caller's concern. */
 dsdna_status dsdna_set_circular(dsdna_ctx *ctx, const uint8_t *circular);
 

@@ -845,7 +845,12 @@ dsdna_status dsdna_set_k2_bp(dsdna_ctx *c, const double *scale)
         if (!(scale[n] >= 0.0 && std::isfinite(scale[n])))
             return fail(c, DSDNA_EINVAL, "K2 multiplier of base pair %lld is %g", (long long)n, scale[n]);
     if (!b.k2bp) HIPCHK(c, dalloc(&b.k2bp, (size_t)c->n_bp_total));
-    return copy(c, b.k2bp, scale, sizeof(double) * c->n_bp_total, hipMemcpyHostToDevice);
+    if ((st = copy(c, b.k2bp, scale, sizeof(double) * c->n_bp_total, hipMemcpyHostToDevice))) {
+        // a partly written table is not left behind
+        dfree(b.k2bp);
+        b.k2bp = nullptr;
+    }
+    return st;
 }
 
 dsdna_status dsdna_set_circular(dsdna_ctx *c, const uint8_t *circular)
@@ -865,40 +870,64 @@ dsdna_status dsdna_set_circular(dsdna_ctx *c, const uint8_t *circular)
     }
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    free_rings(c);
+    // the new ring tables and their device buffers first; the context takes
+    // them only when every allocation and copy has succeeded, so a failure
+    // leaves the previous rings in place
+    std::vector<RingSeg> rings;
+    std::vector<int32_t> ring_rep;
     std::vector<int2> blk;
     int32_t pts = 0;
     for (int r = 0; r < c->n_rep; ++r) {
-        RepInfo &ri = c->rep_h[r];
-        ri.flags &= ~(uint32_t)REP_RING;
         if (!circular[r]) continue;
-        ri.flags |= REP_RING;
+        const RepInfo &ri = c->rep_h[r];
         RingSeg g;
         g.off = ri.off;
         g.n_bp = ri.n_bp;
         g.pt0 = pts;
         g.blk0 = (int32_t)blk.size();
         g.n_blk = (ri.n_bp + LK_THREADS - 1) / LK_THREADS;
-        for (int b = 0; b < g.n_blk; ++b) blk.push_back(int2{(int)c->rings_h.size(), b * LK_THREADS});
-        c->rings_h.push_back(g);
-        c->ring_rep.push_back(r);
+        for (int b = 0; b < g.n_blk; ++b) blk.push_back(int2{(int)rings.size(), b * LK_THREADS});
+        rings.push_back(g);
+        ring_rep.push_back(r);
         pts += ri.n_bp;
+    }
+    RingSeg *d_rings = nullptr;
+    int2 *d_blk = nullptr;
+    double *d_curves = nullptr, *d_part = nullptr, *d_out = nullptr;
+    const auto drop = [&] {
+        dfree(d_rings); dfree(d_blk); dfree(d_curves); dfree(d_part); dfree(d_out);
+    };
+    if (!rings.empty()) {
+        if (dalloc(&d_rings, rings.size()) != hipSuccess || dalloc(&d_blk, blk.size()) != hipSuccess ||
+            dalloc(&d_curves, 9 * (size_t)pts) != hipSuccess || dalloc(&d_part, 2 * blk.size()) != hipSuccess ||
+            dalloc(&d_out, 2 * rings.size()) != hipSuccess) {
+            drop();
+            return fail(c, DSDNA_ENOMEM, "device allocation for %zu rings failed", rings.size());
+        }
+        if ((st = copy(c, d_rings, rings.data(), sizeof(RingSeg) * rings.size(), hipMemcpyHostToDevice)) ||
+            (st = copy(c, d_blk, blk.data(), sizeof(int2) * blk.size(), hipMemcpyHostToDevice))) {
+            drop();
+            return st;
+        }
+    }
+    free_rings(c);
+    c->rings_h = std::move(rings);
+    c->ring_rep = std::move(ring_rep);
+    c->d_rings = d_rings;
+    c->d_lkblk = d_blk;
+    c->d_curves = d_curves;
+    c->d_lkpart = d_part;
+    c->d_lkout = d_out;
+    c->lk_blocks = (int)blk.size();
+    c->lk_pts = pts;
+    for (int r = 0; r < c->n_rep; ++r) {
+        RepInfo &ri = c->rep_h[r];
+        ri.flags &= ~(uint32_t)REP_RING;
+        if (circular[r]) ri.flags |= REP_RING;
     }
     for (Tile &t : c->tiles_h) t.ring = (c->rep_h[t.rep].flags & REP_RING) ? 1 : 0;
     if ((st = copy(c, c->a.b.tiles, c->tiles_h.data(), sizeof(Tile) * c->tiles_h.size(), hipMemcpyHostToDevice)))
         return st;
-    if (!c->rings_h.empty()) {
-        c->lk_blocks = (int)blk.size();
-        c->lk_pts = pts;
-        HIPCHK(c, dalloc(&c->d_rings, c->rings_h.size()));
-        HIPCHK(c, dalloc(&c->d_lkblk, blk.size()));
-        HIPCHK(c, dalloc(&c->d_curves, 9 * (size_t)pts));
-        HIPCHK(c, dalloc(&c->d_lkpart, 2 * blk.size()));
-        HIPCHK(c, dalloc(&c->d_lkout, 2 * c->rings_h.size()));
-        if ((st = copy(c, c->d_rings, c->rings_h.data(), sizeof(RingSeg) * c->rings_h.size(), hipMemcpyHostToDevice)))
-            return st;
-        if ((st = copy(c, c->d_lkblk, blk.data(), sizeof(int2) * blk.size(), hipMemcpyHostToDevice))) return st;
-    }
     return upload_reps(c);
 }
 

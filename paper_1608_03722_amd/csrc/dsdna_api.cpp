@@ -708,6 +708,8 @@ dsdna_status dsdna_destroy(dsdna_ctx *c)
 
 const char *dsdna_last_error(const dsdna_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
+static dsdna_status build_topology(dsdna_ctx *c, int32_t n_rep, const int32_t *n_bp, int64_t N);
+
 dsdna_status dsdna_set_topology(dsdna_ctx *c, int32_t n_rep, const int32_t *n_bp)
 {
     if (!c) return DSDNA_EINVAL;
@@ -718,6 +720,22 @@ dsdna_status dsdna_set_topology(dsdna_ctx *c, int32_t n_rep, const int32_t *n_bp
         N += 2 * (int64_t)n_bp[r];
     }
     if (N >= (int64_t(1) << 31) || n_rep >= (1 << 29)) return fail(c, DSDNA_EINVAL, "too many nucleotides");
+    const dsdna_status st = build_topology(c, n_rep, n_bp, N);
+    if (st) {
+        // a half-built context is not left behind: it has no topology
+        const std::string msg = c->err;
+        free_state(c);
+        c->n_rep = 0;
+        c->phase = PH_NONE;
+        c->tiles_h.clear();
+        c->rep_h.clear();
+        c->err = msg;
+    }
+    return st;
+}
+
+static dsdna_status build_topology(dsdna_ctx *c, int32_t n_rep, const int32_t *n_bp, int64_t N)
+{
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     drop_graph(c);

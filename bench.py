@@ -222,6 +222,51 @@ def _per_term_error(D, sim32, sim64):
     return out
 
 
+def divergence_report(D, cfg, sim32, args):
+    """The 100 bp configuration: an FP64-force run beside the FP32 one from
+    the same state and Philox stream.  Every 100 steps up to 10^4 the largest
+    distance between corresponding body positions of the two runs (the
+    divergence of the FP32 trajectory); at steps 0, 10^3 and 10^4 the per-term
+    force and energy difference of the two precisions on the FP64 run's state;
+    the mean kinetic temperature 2 KE / (5 N) of the FP32 run (three
+    translational and two rotational degrees of freedom per body)."""
+    extra = {"dt": args.dt} if args.dt > 0 else {}
+    prm64 = D.dsdna_default_params(seed=0, force_fp64=1, graph_steps=args.graph_steps, **extra)
+    prm32 = D.dsdna_default_params(seed=0, graph_steps=args.graph_steps, **extra)
+    n_nt = int(2 * np.sum(cfg["n_bp"]))
+    sim64 = D.DsDNA(cfg, prm64, device=0)
+    state = sim32.state()
+    sim64.set_state(*state)
+    sim32.set_state(*state)
+
+    def term_error(st):
+        probe = D.DsDNA(cfg, prm32, device=0)
+        probe.set_state(*st)
+        ref = D.DsDNA(cfg, prm64, device=0)
+        ref.set_state(*st)
+        err = _per_term_error(D, probe, ref)
+        probe.close()
+        ref.close()
+        return err
+
+    errs = {"0": term_error(state)}
+    curve, temps = [], []
+    for k in range(1, 101):
+        sim32.step(100)
+        sim64.step(100)
+        R32, R64 = sim32.state()[0], sim64.state()[0]
+        curve.append(float(np.abs(R32 - R64).max()))
+        E = sim32.energies()
+        temps.append(float(2.0 * (E[:, D.NTERMS].sum() + E[:, D.NTERMS + 1].sum()) / (5.0 * n_nt)))
+        if k in (10, 100):
+            errs[str(100 * k)] = term_error(sim64.state())
+    sim64.close()
+    log("divergence after 10^2, 10^3, 10^4 steps: %.2e %.2e %.2e; <T> = %.4f"
+        % (curve[0], curve[9], curve[99], float(np.mean(temps))))
+    return {"max_dR_every_100_steps": curve, "term_error_fp32_vs_fp64": errs,
+            "T_mean": float(np.mean(temps)), "T_sem": float(np.std(temps, ddof=1) / np.sqrt(len(temps)))}
+
+
 def denaturation_report(D, cfg, sim32, args):
     """64 x 2 kbp with scaled base-pair attraction: an all-FP64 run beside the
     FP32-force run from the same state and noise; fraction unpaired and bubble
@@ -696,6 +741,8 @@ def main():
         observables = melting_report(D, cfg, sim, args)
     elif args.config == "sm":
         observables = single_molecule_report(D, cfg, sim, args)
+    elif args.config == "100bp":
+        observables = divergence_report(D, cfg, sim, args)
     sim.close()
 
     batch = None

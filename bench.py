@@ -724,7 +724,8 @@ def main():
     traffic = measured_traffic() if (dom == "step" and args.config == "1mbp") else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_step<float>" if dom == "step" else "k_excl<float>",
+            "kernel": "k_step<float, false>" if dom == "step" else
+            "k_excl<float, false, %s>" % ("true" if any_open else "false"),
             "bytes_per_nt": bytes_per_nt[dom], "kernels": kernels}
     observables = None
     if failure is not None:

@@ -583,6 +583,31 @@ def supercoil_report(D, cfg, sim, args):
                             "bound": "alu", "flops_per_pair": PAIR_FLOPS}}
 
 
+def copy_ceiling(torch, dev, mib=1024, reps=10):
+    """HBM bandwidth a plain streaming kernel reaches on this GPU: the faster
+    of a device-to-device copy and an elementwise scale of a 1 GiB buffer
+    (four times the Infinity Cache), read + written bytes over the mean of
+    `reps` event-timed launches on the current stream."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    best = 0.0
+    for kind, op in (("copy", lambda: dst.copy_(src)), ("scale", lambda: torch.mul(src, 1.0, out=dst))):
+        op(); op()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            op()
+        e1.record()
+        e1.synchronize()
+        gbs = 2 * 4 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        log("copy ceiling, %s of %d MiB: %.1f GB/s" % (kind, mib, gbs))
+        best = max(best, gbs)
+    del src, dst
+    torch.cuda.synchronize()
+    return best
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -605,6 +630,8 @@ def main():
     ap.add_argument("--equil-steps", type=int, default=0, help="lp300: steps before the first sample")
     ap.add_argument("--param", action="append", default=[],
                     help="override a dsdna_params field, name=value (e.g. hb_depth_convention=1); repeatable")
+    ap.add_argument("--no-copy-ceiling", action="store_true",
+                    help="skip the measured streaming-copy bandwidth reported beside the vendor peak")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a counter calibration)")
     args = ap.parse_args()
@@ -727,6 +754,10 @@ def main():
             "kernel": "k_step<float, false>" if dom == "step" else
             "k_excl<float, false, %s>" % ("true" if any_open else "false"),
             "bytes_per_nt": bytes_per_nt[dom], "kernels": kernels}
+    if not args.no_copy_ceiling:
+        ceil = copy_ceiling(torch, dev)
+        roof["copy_ceiling"] = {"GB/s": round(ceil, 1), "frac": round(achieved / ceil, 4),
+                                "kernel": "streaming copy / scale of 1 GiB (torch)"}
     observables = None
     if failure is not None:
         observables = {"stopped": failure}

@@ -210,6 +210,36 @@ def test_replicas_with_loads(D):
         sim.close()
 
 
+def test_tiny_and_tile_edge_chains(D):
+    """Chains of 1-4 base pairs, where the terms that would reach past an end
+    are absent (a 1 bp chain has only its hydrogen bond, 2 bp no bending), and
+    chains one short of, exactly at and one past one and two tiles of 124 bp,
+    batched in one context from an oracle-thermalised state: every term, the
+    open flags and the per-replica energies, with FP32 and FP64 forces; then
+    50 FP64 steps against the oracle's trajectory."""
+    lens = [1, 2, 3, 4, 123, 124, 125, 248, 249]
+    parts = [synth.ideal_helix(m, origin=(12.0 * k, 0.0, 0.0)) for k, m in enumerate(lens)]
+    bead, patch = synth.concat_replicas(parts)
+    cfg = dict(n_bp=np.array(lens), bead=bead, patch=patch)
+    P, S, st = _oracle_state(steps=200, seed=17, cfg=cfg)
+    b, p = O.sites_from_bodies(P, st.R, st.u)
+    _, _, fb, fp, E, op = O.forces(P, S, b, p, use_cells=True)
+    assert E[0, O.T["bond"]] == 0.0 and E[1, O.T["bend"]] == 0.0   # the terms a short chain lacks
+    for fp64, tol in ((0, 1e-5), (1, 1e-10)):
+        sim = _gpu(D, cfg, seed=17, force_fp64=fp64)
+        sim.set_state(st.R, st.V, st.u, st.L, st.step)
+        _compare_terms(D, sim, P, S, st.R, st.u, tol, use_cells=True)
+        np.testing.assert_array_equal(sim.bp_open(), op)
+        if fp64:
+            ref = O.State(st.R, st.u, st.V, st.L, st.step)
+            sim.step(50)
+            assert O.step(P, S, ref, 50, use_cells=1)[0] == O.OK
+            R, V, u, L, k = sim.state()
+            assert k == ref.step
+            assert np.abs(R - ref.R).max() < 1e-9 and np.abs(u - ref.u).max() < 1e-9
+        sim.close()
+
+
 def test_ssdna_rule(D):
     """Dihedral and bending terms inside bubbles > 2 bp are dropped; open flags
     and bubble statistics match the oracle."""

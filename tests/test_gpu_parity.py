@@ -360,6 +360,33 @@ def test_error_paths(D):
     assert ei.value.status == D.EINVAL
 
 
+def test_invalid_inputs_leave_the_context_usable(D):
+    """Out-of-order calls return ESTATE, an empty topology and a zero-length
+    replica EINVAL; none of them changes the context, which then runs."""
+    ctx = D.dsdna_create(D.dsdna_default_params(seed=1))
+    try:
+        def status(fn, *args):
+            with pytest.raises(D.DsdnaError) as ei:
+                fn(ctx, *args)
+            return ei.value.status
+        assert status(D.dsdna_step, 1) == D.ESTATE                     # no topology
+        assert status(D.dsdna_set_topology, np.zeros(0, np.int32)) == D.EINVAL
+        assert status(D.dsdna_set_topology, [10, 0]) == D.EINVAL
+        assert status(D.dsdna_step, 1) == D.ESTATE                     # still none
+        D.dsdna_set_topology(ctx, [10])
+        assert status(D.dsdna_thermalize, 1.0, 0) == D.ESTATE          # no positions
+        assert status(D.dsdna_step, 1) == D.ESTATE
+        b, p = synth.ideal_helix(10)
+        D.dsdna_set_sites(ctx, b, p)
+        assert status(D.dsdna_get_forces, D.NTERMS, 20) == D.EINVAL     # no such term
+        D.dsdna_thermalize(ctx, 1.0, 0)
+        D.dsdna_step(ctx, 5)
+        R, V, u, L, k = D.dsdna_get_state(ctx, 20)
+        assert k == 5 and np.isfinite(R).all() and np.abs(V).max() > 0.0
+    finally:
+        D.dsdna_destroy(ctx)
+
+
 def test_full_bucket_is_reported(D):
     """More than 65535 beads in one cell-list bucket (every nucleotide of a
     40 kbp chain placed on the same bead and patch positions) stops the run

@@ -709,10 +709,13 @@ def main():
     to_time = args.steps if failure is None else 0
     left = to_time
     chunk = max(1, min(args.steps, 5000))
+    chunk_rates = []   # each chunk ends in the status read of dsdna_step
     while left > 0:
         k = min(left, chunk)
+        tc = time.perf_counter()
         try:
             sim.step(k)
+            chunk_rates.append(n_nt * k / (time.perf_counter() - tc))
         except D.DsdnaError as e:
             # the model's dynamics stopped (e.g. a backbone bond reached R0):
             # outside the default workload this is reported, not hidden
@@ -809,6 +812,8 @@ def main():
                    "forces": "f32", "state": "f64", "cell_size": h, "buckets": nb,
                    "graph_steps": args.graph_steps, "parallelism": "single GPU"},
         "roofline": roof,
+        "chunks": ({"steps_each": chunk, "n": len(chunk_rates), "median": float(np.median(chunk_rates)),
+                    "min": float(min(chunk_rates)), "max": float(max(chunk_rates))} if chunk_rates else None),
         "autotune": tuned,
         "observables": observables,
         "batched_vs_single": batch,

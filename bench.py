@@ -324,10 +324,12 @@ def denaturation_report(D, cfg, sim32, args):
 def chain_report(D, cfg, sim, args):
     """Single chain: end-to-end distance (unwrapped FP64 positions) and mean
     twist per base-pair step every `sample_every` steps."""
-    ree, tw = [], []
+    ree, tw, phis = [], [], []
     n_samples = max(2, args.samples)
-    for _ in range(n_samples):
+    for q in range(n_samples):
         sim.step(args.sample_every)
+        if (q + 1) % 10 == 0:
+            log("  chain sample %d of %d" % (q + 1, n_samples))
         b, p = sim.sites()
         c = 0.5 * (p[0::2] + p[1::2])
         ree.append(float(np.linalg.norm(c[-1] - c[0])))
@@ -338,11 +340,33 @@ def chain_report(D, cfg, sim, args):
         f1 = bb[1:] - t * np.sum(bb[1:] * t, 1, keepdims=True)
         phi = np.arctan2(np.sum(np.cross(f0, f1) * t, 1), np.sum(f0 * f1, 1))
         tw.append(float(np.degrees(phi[5:-5]).mean()))
+        phis.append(phi[5:-5])
     ree, tw = np.array(ree), np.array(tw)
     log("chain: <R_ee> %.2f, twist %.3f deg/bp over %d samples" % (ree.mean(), tw.mean(), len(ree)))
+    # twist correlator <cos(Omega(m) - m theta)> (Sec. 3.2): Omega(m) the sum
+    # of m consecutive step twists, theta their mean; errors from blocks of
+    # consecutive samples
+    P = np.array(phis)
+    theta = P.mean()
+    cs = np.concatenate([np.zeros((len(P), 1)), np.cumsum(P - theta, axis=1)], axis=1)
+    nblk = min(10, len(P))
+    corr = {}
+    for m in (1, 2, 5, 10, 20, 50, 100, 200, 500):
+        if m >= P.shape[1]:
+            break
+        per = np.cos(cs[:, m:] - cs[:, :-m]).mean(axis=1)
+        blk = np.array([b.mean() for b in np.array_split(per, nblk)])
+        corr[str(m)] = {"mean": float(per.mean()), "sem": float(blk.std(ddof=1) / np.sqrt(nblk))}
+    ms = [int(m) for m in corr if 10 <= int(m) <= 100 and corr[m]["mean"] > 0]
+    l_tau = None
+    if len(ms) >= 2:
+        y = np.log([corr[str(m)]["mean"] for m in ms])
+        l_tau = float(-1.0 / np.polyfit(ms, y, 1)[0])
+    log("chain: twist correlator %s, l_tau %s bp" % ({m: round(v["mean"], 4) for m, v in corr.items()}, l_tau))
     return {"end_to_end": {"mean": float(ree.mean()), "sem": float(ree.std(ddof=1) / np.sqrt(len(ree))),
                            "samples": ree.tolist()},
             "twist_deg_per_bp": {"mean": float(tw.mean()), "sem": float(tw.std(ddof=1) / np.sqrt(len(tw)))},
+            "twist_correlator": corr, "l_tau_bp_fit_m10_100": l_tau,
             "sample_every": args.sample_every}
 
 

@@ -635,7 +635,7 @@ def copy_ceiling(torch, dev, mib=1024, reps=10):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--steps", type=int, default=100000)
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--config", default="1mbp")
     ap.add_argument("--cell", type=float, default=0.0)

@@ -27,27 +27,30 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor peak
 FP64_PEAK_GFLOPS = 78600.0  # MI355X FP64 vector, vendor peak
-# Algorithmic bytes per nucleotide of one launch of each kernel in a fully
-# periodic box (every byte the kernel must move once).  The
-# excluded-volume forces travel through sparse accumulators touched only by
-# beads in contact (about 1e-3 of them), so they add no bytes per nucleotide.
-KERNEL_BYTES_PER_NT = {
-    # R, u, V, L read (96) and written (96); bead record (16), bucket key and
-    # slot (4 + 4) written
-    "step": 96 + 96 + 16 + 4 + 4,
-    # own sorted record and nucleotide id (16 + 4); every record read once as
-    # a candidate (16); plus the histogram it clears (per bucket, below)
-    "excl": 16 + 4 + 16,
-    # key, slot, start[key] (12); record read (16); sorted record and id
-    # written (16 + 4)
-    "scatter": 12 + 16 + 16 + 4,
-}
+# Algorithmic bytes of one step, per kernel class, in a fully periodic box
+# (every byte a kernel must move once).
+#   step: R, u, V, L read (96) and written (96); the bead's record at the
+#         last neighbour-list build, read for the skin test (16)
+#   excl: per neighbour-list pair its record (16) and the FP64 bodies of its
+#         two nucleotides (2 x 48)
+# The rebuild kernels move, when they run (per nucleotide):
+#   bin: R, u read (48); record (16), key and slot (8) written
+#   scatter: key, slot, start[key] (12); record read (16); sorted record and
+#            id written (16 + 4)
+#   build: own sorted record and id (16 + 4); every record once as a
+#          candidate (16); each list pair written (16)
+# and per bucket: the scan reads the 16-bit histogram twice and writes the
+# 32-bit offsets (8); the build clears the histogram (2).  They run on the
+# steps where a bead has moved half the skin, so their per-step bytes are
+# these times the measured rebuild rate.  The excluded-volume forces travel
+# through sparse accumulators touched only by beads in contact, which add no
+# bytes per nucleotide.
+STEP_BYTES_PER_NT = 96 + 96 + 16
+PAIR_BYTES = 16 + 2 * 48
+REBUILD_BYTES_PER_NT = {"bin": 48 + 16 + 8, "scatter": 12 + 16 + 16 + 4, "build": 16 + 4 + 16}
+REBUILD_BYTES_PER_KEY = {"scan": 2 + 2 + 4, "build": 2}
 # With an open edge the cell of every bead is stored and sorted as well.
-OPEN_EXTRA_BYTES_PER_NT = {"step": 16, "excl": 16, "scatter": 16 + 16}
-# Per bucket: the scan reads the 16-bit histogram twice and writes the 32-bit
-# offsets; the excluded-volume pass clears the histogram.
-SCAN_BYTES_PER_KEY = 2 + 2 + 4
-EXCL_BYTES_PER_KEY = 2
+OPEN_EXTRA_BYTES_PER_NT = {"bin": 16, "scatter": 16 + 16, "build": 16}
 KERNEL_SOURCES = ("paper_1608_03722_amd/csrc/dsdna_kernels.hip", "paper_1608_03722_amd/csrc/dsdna_dev.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_1mbp_traffic.json")
 
@@ -698,11 +701,13 @@ def main():
     sim.thermalize(1.0, 0)
     tuned = None
     if not args.no_autotune and args.cell == 0.0 and args.hash_log2 == 0:
-        # cell edges from just above the largest cutoff, bucket counts around
-        # four per bead; the trial steps are part of the warm-up
+        # cell edges from just above the search reach (largest cutoff plus
+        # skin), bucket counts around four per bead; the trial steps are part
+        # of the warm-up
         base = int(np.ceil(np.log2(4 * n_nt)))
         lgs = [lg for lg in (base - 1, base, base + 1) if 12 <= lg <= 24]
-        cells_try = [1.1236, 1.2, 1.35]
+        reach = 2 ** (1 / 6) + (prm.skin or 0.5) + 1e-4
+        cells_try = [round(reach * f, 4) for f in (1.001, 1.08, 1.2)]
         t0 = time.perf_counter()
         bc, bl = sim.autotune(cells_try, lgs, 30)
         tuned = {"cells": cells_try, "hash_log2": lgs, "trial_steps": 30, "cell": bc, "hash_log2_best": bl}
@@ -729,6 +734,7 @@ def main():
     log("warm-up %d steps in %.2f s" % (args.warmup - left, time.perf_counter() - t0))
 
     torch.cuda.synchronize()
+    ns0 = sim.neighbour_stats()
     t0 = time.perf_counter()
     to_time = args.steps if failure is None else 0
     left = to_time
@@ -757,33 +763,57 @@ def main():
     ms_step = 1e3 * elapsed / max(done, 1)
     log("timed %d steps in %.3f s: %.4g nt-steps/s" % (done, elapsed, value))
 
+    ns1 = sim.neighbour_stats()
+    # neighbour-list rebuilds per timed step (the stats count from the last
+    # state change, which precedes the warm-up)
+    rebuild_rate = ((ns1["rebuilds"] - ns0["rebuilds"]) / max(1, ns1["steps"] - ns0["steps"])
+                    if failure is None else float("nan"))
+    log("neighbour list: skin %.3g, %d pairs, a rebuild every %.1f steps"
+        % (ns1["skin"], ns1["pairs"], 1.0 / rebuild_rate if rebuild_rate > 0 else float("inf")))
+
     # per-kernel durations with HIP events around every launch, on the
-    # stream the kernels run on
+    # stream the kernels run on (means per step; a rebuild kernel's mean
+    # includes the steps on which it returns at once)
     if failure is not None:
         R, V, u, L, kk = sim.state()   # the state at the failing step: restart from it
         sim.set_state(R, V, u, L, kk)
     prof = sim.profile(args.profile_steps) if failure is None else {k: float("nan") for k in D.KERNELS}
-    log("kernel means (ms): %s" % {k: round(v, 5) for k, v in prof.items()})
-    kernels = {}
+    log("kernel means per step (ms): %s" % {k: round(v, 5) for k, v in prof.items()})
     any_open = "periodic" not in cfg or not np.all(np.asarray(cfg["periodic"]))
-    bytes_per_nt = {k: v + (OPEN_EXTRA_BYTES_PER_NT[k] if any_open else 0) for k, v in KERNEL_BYTES_PER_NT.items()}
+    pairs = ns1["pairs"]
+    per_step = {
+        "step": STEP_BYTES_PER_NT * n_nt,
+        "excl": PAIR_BYTES * pairs,
+        "scan": rebuild_rate * REBUILD_BYTES_PER_KEY["scan"] * nb,
+    }
+    for k in ("bin", "scatter", "build"):
+        bpn = REBUILD_BYTES_PER_NT[k] + (OPEN_EXTRA_BYTES_PER_NT[k] if any_open else 0)
+        per_step[k] = rebuild_rate * (bpn * n_nt + (PAIR_BYTES - 2 * 48) * pairs * (k == "build")
+                                      + REBUILD_BYTES_PER_KEY.get(k, 0) * nb)
+    kernels = {}
     for k, ms in prof.items():
-        bpn = bytes_per_nt.get(k)
-        nbytes = bpn * n_nt if bpn is not None else SCAN_BYTES_PER_KEY * nb
-        if k == "excl":
-            nbytes += EXCL_BYTES_PER_KEY * nb
-        kernels[k] = {"ms": round(ms, 5), "bytes": int(nbytes), "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1)}
-    dom = max(("step", "excl"), key=lambda k: prof[k])
-    achieved = kernels[dom]["bytes"] / (prof[dom] * 1e-3) / 1e9
-    traffic = measured_traffic() if (dom == "step" and args.config == "1mbp") else None
+        nbytes = per_step.get(k, 0.0)
+        kernels[k] = {"ms": round(ms, 5), "bytes": int(nbytes),
+                      "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1) if ms > 0 else None}
+    dom = "step"
+    achieved = per_step[dom] / (prof[dom] * 1e-3) / 1e9
+    traffic = measured_traffic() if args.config == "1mbp" else None
+    whole_bytes = float(sum(per_step.values()))
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_step<float, false>" if dom == "step" else
-            "k_excl<float, false, %s>" % ("true" if any_open else "false"),
-            "bytes_per_nt": bytes_per_nt[dom], "kernels": kernels}
+            "kernel": "k_step<float, false>", "bytes_per_nt": STEP_BYTES_PER_NT,
+            "whole_step": {"bytes": int(whole_bytes),
+                           "bytes_per_nt": round(whole_bytes / n_nt, 1),
+                           "achieved": round(whole_bytes / (ms_step * 1e-3) / 1e9, 1),
+                           "frac": round(whole_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                           "note": "algorithmic bytes of every kernel of a step (rebuilds at the measured "
+                                   "rate) over the wall-clock time per step"},
+            "neighbour_list": {"skin": ns1["skin"], "pairs": pairs, "rebuilds_per_step": rebuild_rate},
+            "kernels": kernels}
     if not args.no_copy_ceiling:
         ceil = copy_ceiling(torch, dev)
         roof["copy_ceiling"] = {"GB/s": round(ceil, 1), "frac": round(achieved / ceil, 4),
+                                "whole_step_frac": round(roof["whole_step"]["achieved"] / ceil, 4),
                                 "kernel": "streaming copy / scale of 1 GiB (torch)"}
     observables = None
     if failure is not None:

@@ -50,9 +50,9 @@ typedef enum {
     DSDNA_EBOND = 4,    /* backbone bond reached R0: the FENE energy is
                            infinite (Appendix A, U_bb for r >= R0)           */
     DSDNA_ENAN = 5,     /* non-finite position or orientation, or an
-                           excluded-volume contact force beyond the exact
-                           accumulation range (2^25 with FP32 forces, 2^23
-                           with FP64 forces: overlapping beads)             */
+                           excluded-volume contact force that is not finite
+                           or exceeds 2^40 kT/nm (beads on top of each
+                           other)                                           */
     DSDNA_ESTATE = 6,   /* call out of order                                 */
     DSDNA_EWALL = 7,    /* a bead of a tethered replica reached its wall     */
     DSDNA_EDOMAIN = 8,  /* a bead left the representable coordinate range   */
@@ -77,13 +77,18 @@ enum {
  * energy of the full-step velocities. */
 #define DSDNA_NENERGY (DSDNA_NTERMS + 2)
 
-/* Kernels timed by dsdna_profile_kernels. */
+/* Kernels timed by dsdna_profile_kernels.  The last four make up a rebuild
+ * of the neighbour list and do their work only on the steps that need one;
+ * their means are per step, so they include the rebuild frequency. */
 enum {
-    DSDNA_KERNEL_STEP = 0,    /* bonded forces + Langevin + integrate + bin  */
+    DSDNA_KERNEL_STEP = 0,    /* bonded + chain-local excluded volume +
+                                 loads + Langevin + integrate + skin test    */
     DSDNA_KERNEL_SCAN = 1,    /* exclusive scan of the cell histogram (2 kernels) */
     DSDNA_KERNEL_SCATTER = 2, /* counting-sort scatter into cell order       */
-    DSDNA_KERNEL_EXCL = 3,    /* excluded volume from the sorted cell list   */
-    DSDNA_NKERNELS = 4
+    DSDNA_KERNEL_EXCL = 3,    /* excluded volume of the neighbour-list pairs */
+    DSDNA_KERNEL_BIN = 4,     /* cell of every bead (counting-sort count)    */
+    DSDNA_KERNEL_BUILD = 5,   /* neighbour search into the list              */
+    DSDNA_NKERNELS = 6
 };
 
 typedef struct dsdna_ctx dsdna_ctx; /* opaque */
@@ -111,7 +116,8 @@ typedef struct {
                                        inside bubbles > 2 bp (Sec. 5)        */
     int32_t hb_depth_convention;    /* 0: H-bond prefactor K2/(2(r0-rc)^2)
                                        as printed; 1: K2/(r0-rc)^2           */
-    double cell_size;               /* cell edge; 0: 1.001 x largest cutoff  */
+    double cell_size;               /* cell edge of the neighbour search; 0:
+                                       1.001 x (largest cutoff + skin)       */
     int32_t hash_log2;              /* log2 of cell-hash buckets; 0: the
                                        power of two >= 4 x nucleotides,
                                        within [12, 24]                      */
@@ -126,6 +132,17 @@ typedef struct {
                                        by sin^3 of both of its bond angles
                                        (finite gradient at collinear bonds;
                                        1 at the ideal helix)               */
+    double skin;                    /* neighbour-list skin: bead pairs more
+                                       than 3 base pairs apart are listed
+                                       when closer than their WCA cutoff plus
+                                       the skin, and the list is rebuilt
+                                       once a bead has moved skin/2; 0: 0.5,
+                                       else at least 1e-3.
+                                       Results do not depend on it.        */
+    int64_t list_capacity;          /* initial pairs the neighbour list holds;
+                                       0: max(4096, nucleotides / 8).  The
+                                       list grows by itself when a rebuild
+                                       finds more pairs.                    */
 } dsdna_params;
 
 /* Table 2 values plus the defaults for what the paper leaves open: unit
@@ -141,6 +158,11 @@ dsdna_status dsdna_create(dsdna_ctx **out, const dsdna_params *params, int devic
 dsdna_status dsdna_destroy(dsdna_ctx *ctx);
 /* Description of the last failure on this context ("" if none). */
 const char *dsdna_last_error(const dsdna_ctx *ctx);
+
+/* Sizes of the current topology: replicas, nucleotides (2 sum n_bp) and base
+ * pairs (sum n_bp); any pointer may be NULL.  DSDNA_ESTATE before
+ * dsdna_set_topology. */
+dsdna_status dsdna_get_sizes(dsdna_ctx *ctx, int32_t *n_rep, int64_t *n_nt, int64_t *n_bp_total);
 
 /* Replica lengths n_bp[n_rep] (each >= 1).  Allocates device memory for
  * sum 2 n_bp nucleotides.  Resets boxes to open, loads to zero, K2 scales
@@ -264,6 +286,16 @@ dsdna_status dsdna_get_bubbles(dsdna_ctx *ctx, int32_t nhist, double *frac, int6
  * return the mean duration in milliseconds of each DSDNA_KERNEL_* class
  * (ms[DSDNA_NKERNELS]).  The steps advance the state like dsdna_step. */
 dsdna_status dsdna_profile_kernels(dsdna_ctx *ctx, int64_t n_steps, double *ms);
+
+/* Neighbour list (Sec. 6: short-range neighbour search without O(N^2)
+ * loops): bead pairs more than 3 base pairs apart along the chain within
+ * their WCA cutoff plus the skin, rebuilt from a counting-sort cell list
+ * whenever a bead has moved half the skin.  Since the last state change
+ * (set_sites, set_state, thermalize, ...): rebuilds (including the one that
+ * preceded the first step), steps taken, pairs in the current list, and the
+ * skin in use.  Any pointer may be NULL. */
+dsdna_status dsdna_get_neighbour_stats(dsdna_ctx *ctx, int64_t *rebuilds, int64_t *steps, int64_t *pairs,
+                                       double *skin);
 
 /* Sizes chosen for the cell list: cell edge, number of hash buckets and
  * cells per periodic dimension of replica 0 (cells[3], 0 for open). */

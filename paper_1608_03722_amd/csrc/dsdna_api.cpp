@@ -33,6 +33,8 @@ namespace {
 enum Phase { PH_NONE = 0, PH_FULL, PH_RESUME, PH_LEAPFROG, PH_HALTED };
 
 constexpr double TWO_16 = 1.12246204830937298143;  // 2^(1/6)
+constexpr double DEFAULT_SKIN = 0.5;
+constexpr double LIST_SLACK = 1e-4;
 
 }  // namespace
 
@@ -60,6 +62,7 @@ struct dsdna_ctx {
     int binned_buf = -1;  // buffer the cell list describes, -1 if none
     int cur_par = 0;      // host mirror of ctl.par
     int64_t cur_step = 0; // host mirror of ctl.step
+    int64_t state_step = 0;  // step counter at the last state change
 
     hipGraphExec_t gexec = nullptr;
     int gsteps = 0;
@@ -125,7 +128,7 @@ static void free_state(dsdna_ctx *c)
     }
     dfree(b.Vf); dfree(b.Lf); dfree(b.Fb); dfree(b.Fp);
     dfree(b.rec); dfree(b.rcell); dfree(b.key); dfree(b.slot); dfree(b.srec); dfree(b.sid); dfree(b.scell);
-    dfree(b.fex); dfree(b.cmask); dfree(b.eex);
+    dfree(b.fex); dfree(b.cmask); dfree(b.eex); dfree(b.plist);
     dfree(b.rep); dfree(b.tiles); dfree(b.eacc); dfree(b.open);
     dfree(b.diag_fb); dfree(b.diag_fp);
     dfree(b.k2bp);
@@ -193,6 +196,13 @@ static void fill_phys(dsdna_ctx *c)
     h.cos_a0 = std::cos(p.a0);
     h.sin_a0 = std::sin(p.a0);
     h.kick = 0.5 * p.dt;
+    h.skin = p.skin > 0.0 ? p.skin : DEFAULT_SKIN;
+    // list cutoffs carry a slack for their FP32 evaluation on the fixed-point
+    // records; the stale threshold is as much below half the skin, so a pair
+    // left out of the list cannot come within its cutoff before a rebuild
+    h.rl2_s = (h.rc_s + h.skin + LIST_SLACK) * (h.rc_s + h.skin + LIST_SLACK);
+    h.rl2_x = (h.rc_x + h.skin + LIST_SLACK) * (h.rc_x + h.skin + LIST_SLACK);
+    h.half_skin2 = (float)((0.5 * h.skin - LIST_SLACK) * (0.5 * h.skin - LIST_SLACK));
     h.inv_I = 1.0 / h.I;
     h.kick_M = h.kick / h.M;
     h.inv_R0sq = 1.0 / (p.R0 * p.R0);
@@ -203,11 +213,15 @@ static void fill_phys(dsdna_ctx *c)
     h.dihedral_damping = p.dihedral_damping;
 }
 
-static double rc_max(const dsdna_ctx *c) { return TWO_16 * std::max(c->prm.sig_s, c->prm.sig_x); }
+// Reach of the neighbour search: the largest WCA cutoff plus the skin.
+static double rc_max(const dsdna_ctx *c)
+{
+    return TWO_16 * std::max(c->prm.sig_s, c->prm.sig_x) + c->a.ph.skin + LIST_SLACK;
+}
 
 static double cell_edge(const dsdna_ctx *c)
 {
-    // default: just above the largest cutoff (fewest candidates per bead)
+    // default: just above the search reach (fewest candidates per bead)
     return c->prm.cell_size > 0.0 ? c->prm.cell_size : rc_max(c) * 1.001;
 }
 
@@ -241,15 +255,21 @@ static bool hash_separates(uint32_t A, uint32_t B, uint32_t mask, const std::vec
     return true;
 }
 
-// Choose the cell edge, per-replica cell counts, bucket count and hash.
-static dsdna_status configure_grid(dsdna_ctx *c)
+// Choose the cell edge, per-replica cell counts, bucket count and hash for
+// the replicas `reps` (the context's, or a candidate set of them).  The new
+// replica table and grid are built in local copies and become the context's
+// only when every check and allocation has succeeded, so a failure leaves the
+// context as it was.
+static dsdna_status configure_grid_for(dsdna_ctx *c, std::vector<RepInfo> reps)
 {
     const double h = cell_edge(c);
-    if (!(h >= rc_max(c) * (1.0 + 1e-6)))
-        return fail(c, DSDNA_EINVAL, "cell_size %g is below the largest WCA cutoff %g", h, rc_max(c));
+    const double reach = rc_max(c);
+    if (!(h >= reach * (1.0 + 1e-6)))
+        return fail(c, DSDNA_EINVAL, "cell_size %g is below the search reach %g (largest WCA cutoff plus skin)", h,
+                    reach);
     bool all_per_same = c->n_rep > 0;
     for (int r = 0; r < c->n_rep; ++r) {
-        RepInfo &ri = c->rep_h[r];
+        RepInfo &ri = reps[r];
         for (int k = 0; k < 3; ++k) {
             if (ri.flags & (REP_PER_X << k)) {
                 const int64_t n = (int64_t)std::floor(ri.len[k] / h);
@@ -258,8 +278,8 @@ static dsdna_status configure_grid(dsdna_ctx *c)
                                 ri.len[k], h);
                 if (n > (1 << 20)) return fail(c, DSDNA_EINVAL, "replica %d: periodic edge too long", r);
                 // cells are cut on the 32-bit coordinates (unit L / 2^32): a
-                // cell must stay wider than the cutoff plus a few units
-                if (ri.len[k] / (double)n < rc_max(c) + 4.0 * ri.len[k] / 4294967296.0)
+                // cell must stay wider than the reach plus a few units
+                if (ri.len[k] / (double)n < reach + 4.0 * ri.len[k] / 4294967296.0)
                     return fail(c, DSDNA_EINVAL, "replica %d: periodic edge %g too long for cell %g", r, ri.len[k], h);
                 ri.ncell[k] = (int32_t)n;
                 ri.inv_h[k] = (double)n / ri.len[k];
@@ -270,7 +290,7 @@ static dsdna_status configure_grid(dsdna_ctx *c)
             }
         }
         if (r > 0)
-            for (int k = 0; k < 3; ++k) all_per_same = all_per_same && ri.ncell[k] == c->rep_h[0].ncell[k];
+            for (int k = 0; k < 3; ++k) all_per_same = all_per_same && ri.ncell[k] == reps[0].ncell[k];
     }
     int lg = c->prm.hash_log2;
     if (lg <= 0) {
@@ -287,48 +307,73 @@ static dsdna_status configure_grid(dsdna_ctx *c)
     const uint32_t nb = 1u << lg, mask = nb - 1u;
     uint32_t A = 1031u, B = 1031u * 1031u;
     if (all_per_same) {
-        A = (uint32_t)c->rep_h[0].ncell[0];
-        B = A * (uint32_t)c->rep_h[0].ncell[1];
+        A = (uint32_t)reps[0].ncell[0];
+        B = A * (uint32_t)reps[0].ncell[1];
     }
     // fall back to other odd multipliers if the first choice folds two
     // neighbouring cells into one bucket
     uint64_t x = 0x9E3779B97F4A7C15ull;
     int tries = 0;
-    while (!hash_separates(A, B, mask, c->rep_h)) {
+    while (!hash_separates(A, B, mask, reps)) {
         if (++tries > 1000) return fail(c, DSDNA_EINVAL, "no cell hash separates neighbours with 2^%d buckets", lg);
         x ^= x << 13; x ^= x >> 7; x ^= x << 17;
         A = ((uint32_t)x | 1u) & 0xFFFFu;
         if (A < 17) A += 17;
         B = (uint32_t)(x >> 32) | 1u;
     }
-    Grid &g = c->a.g;
+    Grid g = c->a.g;
     g.A = A;
     g.B = B;
-    g.C = all_per_same ? B * (uint32_t)c->rep_h[0].ncell[2] : B * 1031u + 7u;
+    g.C = all_per_same ? B * (uint32_t)reps[0].ncell[2] : B * 1031u + 7u;
     g.mask = mask;
     g.h = h;
     g.any_open = 0;
     for (int r = 0; r < c->n_rep; ++r)
-        for (int k = 0; k < 3; ++k) g.any_open |= (c->rep_h[r].flags & (REP_PER_X << k)) ? 0 : 1;
+        for (int k = 0; k < 3; ++k) g.any_open |= (reps[r].flags & (REP_PER_X << k)) ? 0 : 1;
     for (int r = 0; r < c->n_rep; ++r) {
-        RepInfo &ri = c->rep_h[r];
+        RepInfo &ri = reps[r];
         for (int k = 0; k < 3; ++k)
             ri.qlen[k] = (ri.flags & (REP_PER_X << k)) ? (float)(ri.len[k] / 4294967296.0) : (float)(1.0 / OPEN_QINV);
     }
-    if (g.nbucket != (int32_t)nb || !c->a.b.count) {
+    const bool new_buckets = c->a.g.nbucket != (int32_t)nb || !c->a.b.count;
+    uint32_t *count = nullptr;
+    int32_t *start = nullptr, *bsum = nullptr;
+    const auto drop = [&] { dfree(count); dfree(start); dfree(bsum); };
+    if (new_buckets) {
+        if (dalloc(&count, (size_t)nb / 2) != hipSuccess || dalloc(&start, (size_t)nb + 1) != hipSuccess ||
+            dalloc(&bsum, (size_t)nb / SCAN_CHUNK) != hipSuccess) {
+            drop();
+            return fail(c, DSDNA_ENOMEM, "cell-list allocation for 2^%d buckets failed", lg);
+        }
+    }
+    hipError_t e = hipSuccess;
+    if (new_buckets) e = hipMemsetAsync(count, 0, sizeof(uint32_t) * (nb / 2), c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->a.b.rep, reps.data(), sizeof(RepInfo) * c->n_rep, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        drop();
+        // the device table may be partly written: put the previous one back
+        (void)hipMemcpyAsync(c->a.b.rep, c->rep_h.data(), sizeof(RepInfo) * c->n_rep, hipMemcpyHostToDevice,
+                             c->stream);
+        (void)hipStreamSynchronize(c->stream);
+        return fail(c, DSDNA_EDEVICE, "grid upload failed: %s", hipGetErrorString(e));
+    }
+    if (new_buckets) {
         free_grid(c);
-        HIPCHK(c, dalloc(&c->a.b.count, (size_t)nb / 2));
-        HIPCHK(c, dalloc(&c->a.b.start, (size_t)nb + 1));
-        HIPCHK(c, dalloc(&c->a.b.bsum, (size_t)nb / SCAN_CHUNK));
-        HIPCHK(c, hipMemsetAsync(c->a.b.count, 0, sizeof(uint32_t) * (nb / 2), c->stream));
+        c->a.b.count = count;
+        c->a.b.start = start;
+        c->a.b.bsum = bsum;
         g.nbucket = (int32_t)nb;
     }
-    HIPCHK(c, hipMemcpyAsync(c->a.b.rep, c->rep_h.data(), sizeof(RepInfo) * c->n_rep, hipMemcpyHostToDevice,
-                             c->stream));
+    c->rep_h = std::move(reps);
+    c->a.g = g;
     c->binned_buf = -1;
     drop_graph(c);
     return DSDNA_OK;
 }
+
+static dsdna_status configure_grid(dsdna_ctx *c) { return configure_grid_for(c, c->rep_h); }
 
 // Clear the cell histogram and the sparse excluded-volume accumulators (a
 // halted step or evaluation may leave entries behind).  Not used during graph
@@ -337,7 +382,7 @@ static dsdna_status clear_accumulators(dsdna_ctx *c)
 {
     Bufs &b = c->a.b;
     HIPCHK(c, hipMemsetAsync(b.count, 0, sizeof(uint32_t) * ((size_t)c->a.g.nbucket / 2), c->stream));
-    HIPCHK(c, hipMemsetAsync(b.fex, 0, sizeof(unsigned long long) * 4 * (size_t)c->N, c->stream));
+    HIPCHK(c, hipMemsetAsync(b.fex, 0, sizeof(unsigned long long) * FEX_WORDS * (size_t)c->N, c->stream));
     HIPCHK(c, hipMemsetAsync(b.cmask, 0, sizeof(uint32_t) * CMASK_WORDS * (size_t)c->a.n_tiles, c->stream));
     return DSDNA_OK;
 }
@@ -358,6 +403,7 @@ static dsdna_status write_ctl(dsdna_ctx *c, int64_t step, int par)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->cur_step = step;
     c->cur_par = par;
+    c->state_step = step;
     return DSDNA_OK;
 }
 
@@ -404,18 +450,50 @@ static dsdna_status check_ready(dsdna_ctx *c, bool need_state)
     return DSDNA_OK;
 }
 
-// Rebuild the cell list of buffer `which`: bin, scan, scatter.
+// Enlarge the neighbour-list buffer to hold at least `need` pairs.
+static dsdna_status grow_list(dsdna_ctx *c, int64_t need)
+{
+    const int64_t cap = std::max<int64_t>(need + need / 4 + 64, 2 * c->a.list_cap);
+    PairRec *p = nullptr;
+    if (dalloc(&p, (size_t)cap) != hipSuccess)
+        return fail(c, DSDNA_ENOMEM, "neighbour list of %lld pairs: allocation failed", (long long)cap);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    dfree(c->a.b.plist);
+    c->a.b.plist = p;
+    c->a.list_cap = cap;
+    return sync_args(c);
+}
+
+// Rebuild the neighbour list from the positions of buffer `which`: bin,
+// scan, scatter, search.  A list larger than its buffer is rebuilt into a
+// larger one.  Leaves the stale flag clear.
 static dsdna_status rebin(dsdna_ctx *c, int which)
 {
     dsdna_status st = sync_args(c);
     if (st) return st;
-    // the histogram is cleared by the excluded-volume pass of a step, which
-    // may not have run since the last binning
-    HIPCHK(c, hipMemsetAsync(c->a.b.count, 0, sizeof(uint32_t) * ((size_t)c->a.g.nbucket / 2), c->stream));
-    HIPCHK(c, launch_bin(c->a, c->dA, which, c->stream));
-    HIPCHK(c, launch_scan(c->a, c->stream));
-    HIPCHK(c, launch_scatter(c->a, 0, c->stream));
-    c->binned_buf = which;
+    for (;;) {
+        // the histogram is cleared by the search that ends a rebuild, which an
+        // error may have cut short
+        HIPCHK(c, hipMemsetAsync(c->a.b.count, 0, sizeof(uint32_t) * ((size_t)c->a.g.nbucket / 2), c->stream));
+        HIPCHK(c, launch_bin(c->a, c->dA, which, 1, c->stream));
+        HIPCHK(c, launch_scan(c->a, 0, 1, c->stream));
+        HIPCHK(c, launch_scatter(c->a, 1, c->stream));
+        HIPCHK(c, launch_build(c->a, c->dA, 1, c->stream));
+        Ctl h;
+        if ((st = read_ctl(c, &h))) return st;
+        h.stale = 0;
+        if (h.code == CODE_LIST_FULL) {
+            if ((st = grow_list(c, (int64_t)h.list_n))) return st;
+            h.code = 0;
+            if ((st = copy(c, c->a.b.ctl, &h, sizeof h, hipMemcpyHostToDevice))) return st;
+            continue;
+        }
+        if ((st = copy(c, c->a.b.ctl, &h, sizeof h, hipMemcpyHostToDevice))) return st;
+        if (h.code != 0) break;  // the caller reads the error
+        c->binned_buf = which;
+        return DSDNA_OK;
+    }
+    c->binned_buf = -1;
     return DSDNA_OK;
 }
 
@@ -483,17 +561,30 @@ static dsdna_status status_from_ctl(dsdna_ctx *c, const Ctl &h)
                 (long long)h.err_id);
 }
 
-// One step: fused step kernel, scan, scatter (advances ctl.step/par).
-static hipError_t enqueue_step(dsdna_ctx *c, int mode, int write_full, hipStream_t s)
+// One step: the neighbour-list pairs, the step kernel, and the kernels of a
+// rebuild (which work only when the step kernel found the list stale); the
+// scan advances ctl.step/par.  `ev` (7 events, or null) brackets the
+// kernels: pairs, step, bin, scan, scatter, build.
+static hipError_t enqueue_step(dsdna_ctx *c, int mode, int write_full, hipStream_t s, hipEvent_t *ev = nullptr)
 {
     hipError_t e = hipSuccess;
-    // the excluded-volume pass clears the histogram; without it (resume from
-    // stored forces, never captured in a graph) a memset does
-    if (mode != MODE_FROM_FORCES) e = launch_excl(c->a, c->dA, c->prm.force_fp64, 0, -1, s);
-    else e = hipMemsetAsync(c->a.b.count, 0, sizeof(uint32_t) * ((size_t)c->a.g.nbucket / 2), s);
+    auto mark = [&](int k) {
+        if (ev && e == hipSuccess) e = hipEventRecord(ev[k], s);
+    };
+    mark(0);
+    // a resume from stored forces evaluates no forces in its first launch
+    if (mode != MODE_FROM_FORCES) e = launch_pairs(c->a, c->dA, -1, 0, 1, s);
+    mark(1);
     if (e == hipSuccess) e = launch_step(c->a, c->dA, c->prm.force_fp64, mode, write_full, s);
-    if (e == hipSuccess) e = launch_scan(c->a, s);
-    if (e == hipSuccess) e = launch_scatter(c->a, 1, s);
+    mark(2);
+    if (e == hipSuccess) e = launch_bin(c->a, c->dA, -1, 0, s);
+    mark(3);
+    if (e == hipSuccess) e = launch_scan(c->a, 1, 0, s);
+    mark(4);
+    if (e == hipSuccess) e = launch_scatter(c->a, 0, s);
+    mark(5);
+    if (e == hipSuccess) e = launch_build(c->a, c->dA, 0, s);
+    mark(6);
     return e;
 }
 
@@ -520,7 +611,13 @@ static dsdna_status build_graph(dsdna_ctx *c, int steps)
     return DSDNA_OK;
 }
 
-// Run n_steps; with `events` (2 per launch class per step) record timings.
+// Kernel classes timed by dsdna_profile_kernels, in the order enqueue_step
+// brackets them.
+static const int PROF_CLASS[6] = {DSDNA_KERNEL_EXCL, DSDNA_KERNEL_STEP, DSDNA_KERNEL_BIN,
+                                  DSDNA_KERNEL_SCAN, DSDNA_KERNEL_SCATTER, DSDNA_KERNEL_BUILD};
+
+// Run n_steps; with `prof`, eager launches with events around every kernel
+// and the mean duration per step of each kernel class.
 static dsdna_status run_steps(dsdna_ctx *c, int64_t n_steps, std::vector<double> *prof)
 {
     dsdna_status st = check_ready(c, true);
@@ -536,62 +633,85 @@ static dsdna_status run_steps(dsdna_ctx *c, int64_t n_steps, std::vector<double>
     int first_mode = MODE_NORMAL;
     if (c->phase == PH_FULL) { first_mode = MODE_FIRST; launches += 1; }
     if (c->phase == PH_RESUME) { first_mode = MODE_FROM_FORCES; launches += 1; }
-
-    auto mark = [&](hipEvent_t *e) -> hipError_t {
-        hipError_t r = hipEventCreate(e);
-        if (r == hipSuccess) r = hipEventRecord(*e, c->stream);
-        return r;
-    };
-    int64_t k = 0;
-    if (prof) {
-        // eager launches with an event pair around each kernel class
-        std::vector<hipEvent_t> evs;
-        for (; k < launches; ++k) {
-            const int mode = k == 0 ? first_mode : MODE_NORMAL;
-            hipEvent_t e0, e1, e2, e3, e4;
-            HIPCHK(c, mark(&e0));
-            if (mode != MODE_FROM_FORCES) HIPCHK(c, launch_excl(c->a, c->dA, c->prm.force_fp64, 0, -1, c->stream));
-            else HIPCHK(c, hipMemsetAsync(c->a.b.count, 0, sizeof(uint32_t) * ((size_t)c->a.g.nbucket / 2), c->stream));
-            HIPCHK(c, mark(&e1));
-            HIPCHK(c, launch_step(c->a, c->dA, c->prm.force_fp64, mode, k == launches - 1, c->stream));
-            HIPCHK(c, mark(&e2));
-            HIPCHK(c, launch_scan(c->a, c->stream));
-            HIPCHK(c, mark(&e3));
-            HIPCHK(c, launch_scatter(c->a, 1, c->stream));
-            HIPCHK(c, mark(&e4));
-            evs.insert(evs.end(), {e0, e1, e2, e3, e4});
-        }
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        prof->assign(DSDNA_NKERNELS, 0.0);
-        for (size_t q = 0; q + 4 < evs.size(); q += 5) {
-            float t[4];
-            for (int m = 0; m < 4; ++m) HIPCHK(c, hipEventElapsedTime(&t[m], evs[q + m], evs[q + m + 1]));
-            (*prof)[DSDNA_KERNEL_EXCL] += t[0];
-            (*prof)[DSDNA_KERNEL_STEP] += t[1];
-            (*prof)[DSDNA_KERNEL_SCAN] += t[2];
-            (*prof)[DSDNA_KERNEL_SCATTER] += t[3];
-        }
-        for (auto &x : *prof) x /= (double)launches;
+    const int64_t step0 = c->cur_step;
+    if (prof) prof->assign(DSDNA_NKERNELS, 0.0);
+    std::vector<hipEvent_t> evs;
+    const auto free_events = [&] {
         for (hipEvent_t e : evs) (void)hipEventDestroy(e);
-    } else {
-        if (first_mode != MODE_NORMAL) {
-            HIPCHK(c, enqueue_step(c, first_mode, launches == 1, c->stream));
-            ++k;
-        }
-        const int G = c->prm.graph_steps;
-        if (G > 0 && launches - 1 - k >= G) {
-            if (!c->gexec || c->gsteps != G) {
-                if ((st = build_graph(c, G))) return st;
-            }
-            while (launches - 1 - k >= G) {
-                HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
-                k += G;
-            }
-        }
-        for (; k < launches; ++k) HIPCHK(c, enqueue_step(c, MODE_NORMAL, k == launches - 1, c->stream));
-    }
+        evs.clear();
+    };
+    int64_t k = 0;  // launches done
     Ctl h;
-    if ((st = read_ctl(c, &h))) return st;
+    for (;;) {
+        if (prof) {
+            for (; k < launches; ++k) {
+                const size_t e0 = evs.size();
+                evs.resize(e0 + 7, nullptr);
+                for (int q = 0; q < 7; ++q)
+                    if (hipEventCreate(&evs[e0 + q]) != hipSuccess) {
+                        free_events();
+                        return fail(c, DSDNA_EDEVICE, "hipEventCreate failed");
+                    }
+                const hipError_t e = enqueue_step(c, k == 0 ? first_mode : MODE_NORMAL, k == launches - 1,
+                                                  c->stream, &evs[e0]);
+                if (e != hipSuccess) {
+                    free_events();
+                    return fail(c, DSDNA_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+                }
+            }
+        } else {
+            if (k == 0 && first_mode != MODE_NORMAL) {
+                HIPCHK(c, enqueue_step(c, first_mode, launches == 1, c->stream));
+                ++k;
+            }
+            const int G = c->prm.graph_steps;
+            if (G > 0 && launches - 1 - k >= G) {
+                if (!c->gexec || c->gsteps != G) {
+                    if ((st = build_graph(c, G))) return st;
+                }
+                while (launches - 1 - k >= G) {
+                    HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+                    k += G;
+                }
+            }
+            for (; k < launches; ++k) HIPCHK(c, enqueue_step(c, MODE_NORMAL, k == launches - 1, c->stream));
+        }
+        if ((st = read_ctl(c, &h))) {
+            free_events();
+            return st;
+        }
+        if (h.code != CODE_LIST_FULL) break;
+        // the neighbour list outgrew its buffer at the rebuild of the launch
+        // that took the step counter to h.step: every later kernel returned at
+        // once, and the positions and half-step velocities of h.step are
+        // intact.  Enlarge the list, rebuild it there and continue.
+        k = h.step - step0;
+        if ((st = grow_list(c, (int64_t)h.list_n))) {
+            free_events();
+            return st;
+        }
+        h.code = 0;
+        if ((st = copy(c, c->a.b.ctl, &h, sizeof h, hipMemcpyHostToDevice))) {
+            free_events();
+            return st;
+        }
+        if ((st = rebin(c, h.par))) {
+            free_events();
+            return st;
+        }
+        if (k >= launches) break;
+    }
+    if (prof) {
+        // events of launches that were cut short by a rebuild time nothing
+        for (size_t q = 0; q + 6 < evs.size(); q += 7)
+            for (int m = 0; m < 6; ++m) {
+                float t = 0.0f;
+                if (hipEventElapsedTime(&t, evs[q + m], evs[q + m + 1]) == hipSuccess) (*prof)[PROF_CLASS[m]] += t;
+            }
+        for (auto &x : *prof) x /= (double)launches;
+        free_events();
+        if ((st = read_ctl(c, &h))) return st;
+    }
     c->cur_step = h.step;
     c->cur_par = h.par;
     if (h.code != 0) return status_from_ctl(c, h);
@@ -614,7 +734,8 @@ static dsdna_status run_diag(dsdna_ctx *c, uint32_t mask)
     if (c->binned_buf != which) {
         if ((st = rebin(c, which))) return st;
     }
-    HIPCHK(c, launch_excl(c->a, c->dA, c->prm.force_fp64, 1, which, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->a.b.eex, 0, sizeof(double) * (size_t)c->N, c->stream));
+    HIPCHK(c, launch_pairs(c->a, c->dA, which, 1, 0, c->stream));
     HIPCHK(c, launch_diag(c->a, c->dA, which, c->prm.force_fp64, mask, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     Ctl h;
@@ -662,7 +783,8 @@ dsdna_status dsdna_create(dsdna_ctx **out, const dsdna_params *params, int devic
     if (!out || !params) return DSDNA_EINVAL;
     *out = nullptr;
     if (params->dt <= 0 || params->ell <= 0 || params->m_bead <= 0 || params->m_patch <= 0 || params->gamma < 0 ||
-        params->kT < 0 || params->R0 <= 0 || params->rc_hb <= params->r0_hb)
+        params->kT < 0 || params->R0 <= 0 || params->rc_hb <= params->r0_hb || !(params->skin == 0.0 || params->skin >= 1e-3) ||
+        params->list_capacity < 0)
         return DSDNA_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return DSDNA_EDEVICE;
@@ -779,9 +901,13 @@ static dsdna_status build_topology(dsdna_ctx *c, int32_t n_rep, const int32_t *n
     HIPCHK(c, dalloc(&b.key, (size_t)N)); HIPCHK(c, dalloc(&b.slot, (size_t)N));
     HIPCHK(c, dalloc(&b.rec, (size_t)N)); HIPCHK(c, dalloc(&b.rcell, (size_t)N));
     HIPCHK(c, dalloc(&b.srec, (size_t)N)); HIPCHK(c, dalloc(&b.sid, (size_t)N)); HIPCHK(c, dalloc(&b.scell, (size_t)N));
-    HIPCHK(c, dalloc(&b.fex, 4 * (size_t)N));
+    HIPCHK(c, dalloc(&b.fex, FEX_WORDS * (size_t)N));
     HIPCHK(c, dalloc(&b.cmask, CMASK_WORDS * (size_t)a.n_tiles));
     HIPCHK(c, dalloc(&b.eex, (size_t)N));
+    // the list holds the non-local pairs within the cutoffs plus the skin: a
+    // few per thousand beads in a relaxed duplex; it grows when needed
+    a.list_cap = c->prm.list_capacity > 0 ? c->prm.list_capacity : std::max<int64_t>(4096, N / 8);
+    HIPCHK(c, dalloc(&b.plist, (size_t)a.list_cap));
     HIPCHK(c, dalloc(&b.rep, (size_t)n_rep));
     HIPCHK(c, dalloc(&b.tiles, c->tiles_h.size()));
     HIPCHK(c, dalloc(&b.eacc, (size_t)a.n_tiles * DSDNA_NTERMS));
@@ -800,19 +926,23 @@ dsdna_status dsdna_set_box(dsdna_ctx *c, const double *lo_hi, const uint8_t *per
     dsdna_status st = check_ready(c, false);
     if (st) return st;
     if (!lo_hi || !periodic) return fail(c, DSDNA_EINVAL, "null box");
+    // the new boxes go into a copy of the replica table, which replaces the
+    // context's only if the grid can be built for it
+    std::vector<RepInfo> reps = c->rep_h;
     for (int r = 0; r < c->n_rep; ++r) {
-        RepInfo &ri = c->rep_h[r];
+        RepInfo &ri = reps[r];
         ri.flags &= ~(uint32_t)(REP_PER_X | REP_PER_Y | REP_PER_Z);
         for (int k = 0; k < 3; ++k) {
             const double lo = lo_hi[6 * r + k], hi = lo_hi[6 * r + 3 + k];
-            if (!(hi > lo)) return fail(c, DSDNA_EINVAL, "replica %d: empty box along %d", r, k);
+            if (!(hi > lo) || !std::isfinite(hi - lo))
+                return fail(c, DSDNA_EINVAL, "replica %d: empty box along %d", r, k);
             ri.lo[k] = lo;
             ri.len[k] = hi - lo;
             ri.inv_len[k] = 1.0 / (hi - lo);
             if (periodic[3 * r + k]) ri.flags |= (REP_PER_X << k);
         }
     }
-    return configure_grid(c);
+    return configure_grid_for(c, std::move(reps));
 }
 
 dsdna_status dsdna_set_external(dsdna_ctx *c, int32_t rep, const double F[3], const double G[3], int32_t tether,
@@ -879,9 +1009,10 @@ dsdna_status dsdna_set_circular(dsdna_ctx *c, const uint8_t *circular)
     for (int r = 0; r < c->n_rep; ++r) {
         if (!circular[r]) continue;
         const int nb = c->n_bp[r];
-        if (nb < 6 || nb % 3 != 0)
+        if (nb < 9 || nb % 3 != 0)
             return fail(c, DSDNA_EINVAL,
-                        "ring %d has %d base pairs: a ring needs at least 6 and a multiple of 3 (steric beads every "
+                        "ring %d has %d base pairs: a ring needs at least 9 (the chain-local excluded-volume pairs, "
+                        "up to 3 base pairs either way, must be distinct) and a multiple of 3 (steric beads every "
                         "third base pair on both sides of the seam)", r, nb);
         if (c->rep_h[r].flags & (REP_TETHER | REP_PULL | REP_TORQUE))
             return fail(c, DSDNA_EINVAL, "replica %d carries external loads and cannot be a ring", r);
@@ -1217,6 +1348,31 @@ dsdna_status dsdna_profile_kernels(dsdna_ctx *c, int64_t n_steps, double *ms)
     return DSDNA_OK;
 }
 
+dsdna_status dsdna_get_sizes(dsdna_ctx *c, int32_t *n_rep, int64_t *n_nt, int64_t *n_bp_total)
+{
+    dsdna_status st = check_ready(c, false);
+    if (st) return st;
+    if (n_rep) *n_rep = c->n_rep;
+    if (n_nt) *n_nt = c->N;
+    if (n_bp_total) *n_bp_total = c->n_bp_total;
+    return DSDNA_OK;
+}
+
+dsdna_status dsdna_get_neighbour_stats(dsdna_ctx *c, int64_t *rebuilds, int64_t *steps, int64_t *pairs,
+                                       double *skin)
+{
+    dsdna_status st = check_ready(c, false);
+    if (st) return st;
+    HIPCHK(c, hipSetDevice(c->device));
+    Ctl h;
+    if ((st = read_ctl(c, &h))) return st;
+    if (rebuilds) *rebuilds = h.rebuilds;
+    if (steps) *steps = c->phase == PH_LEAPFROG ? h.step - 1 - c->state_step : 0;
+    if (pairs) *pairs = std::min<int64_t>((int64_t)h.list_n, c->a.list_cap);
+    if (skin) *skin = c->a.ph.skin;
+    return DSDNA_OK;
+}
+
 dsdna_status dsdna_get_grid(dsdna_ctx *c, double *cell_size, int64_t *n_buckets, int32_t *cells)
 {
     dsdna_status st = check_ready(c, false);
@@ -1235,23 +1391,36 @@ dsdna_status dsdna_autotune(dsdna_ctx *c, int32_t n, const double *cell_sizes, i
     if (st) return st;
     if (n < 1 || m < 1 || !cell_sizes || !hash_log2s || trial_steps < 1)
         return fail(c, DSDNA_EINVAL, "autotune needs candidates and trial_steps >= 1");
-    double best_t = 1e300, bc = cell_edge(c);
+    double best_t = 1e300, bc = c->prm.cell_size;
     int32_t bl = c->prm.hash_log2;
-    hipEvent_t e0, e1;
-    HIPCHK(c, hipEventCreate(&e0));
-    HIPCHK(c, hipEventCreate(&e1));
+    const double cell0 = c->prm.cell_size;
+    const int32_t hash0 = c->prm.hash_log2;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    // on any failure the parameters and the grid they give are put back
+    const auto give_up = [&](dsdna_status code) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        const std::string msg = c->err;
+        c->prm.cell_size = cell0;
+        c->prm.hash_log2 = hash0;
+        (void)configure_grid(c);
+        c->err = msg;
+        return code;
+    };
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return give_up(fail(c, DSDNA_EDEVICE, "hipEventCreate failed"));
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < m; ++j) {
             c->prm.cell_size = cell_sizes[i];
             c->prm.hash_log2 = hash_log2s[j];
-            if ((st = configure_grid(c))) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return st; }
-            if ((st = run_steps(c, 1, nullptr))) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return st; }
-            HIPCHK(c, hipEventRecord(e0, c->stream));
-            if ((st = run_steps(c, trial_steps, nullptr))) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return st; }
-            HIPCHK(c, hipEventRecord(e1, c->stream));
-            HIPCHK(c, hipEventSynchronize(e1));
+            if ((st = configure_grid(c))) return give_up(st);
+            if ((st = run_steps(c, 1, nullptr))) return give_up(st);
             float t = 0.0f;
-            HIPCHK(c, hipEventElapsedTime(&t, e0, e1));
+            if (hipEventRecord(e0, c->stream) != hipSuccess) return give_up(fail(c, DSDNA_EDEVICE, "event failed"));
+            if ((st = run_steps(c, trial_steps, nullptr))) return give_up(st);
+            if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+                return give_up(fail(c, DSDNA_EDEVICE, "event failed"));
             if (t < best_t) { best_t = t; bc = cell_sizes[i]; bl = hash_log2s[j]; }
         }
     (void)hipEventDestroy(e0);

@@ -8,13 +8,19 @@
 namespace dsdna {
 
 // Base pairs per tile: one workgroup of WG_THREADS threads owns the
-// nucleotides of TILE_BP consecutive base pairs of one replica.  124 base
-// pairs keep every per-tile phase (sites with halo, backbone steps, bending
-// centres) within one item per thread.
+// nucleotides of TILE_BP consecutive base pairs of one replica, and its spare
+// threads stage a halo of HALO_BP base pairs on either side.  Three base
+// pairs of halo hold every site a tile's terms reach: bending reaches two
+// base pairs away, and the chain-local excluded-volume pairs (LOCAL_BP) three.
 constexpr int WG_THREADS = 256;
-constexpr int TILE_BP = 124;
+constexpr int HALO_BP = 3;
+constexpr int TILE_BP = (WG_THREADS - 4 * HALO_BP) / 2;  // 122
 constexpr int TILE_NT = 2 * TILE_BP;
-constexpr int HALO_BP = 2;  // bending reaches two base pairs away
+// Bead pairs whose base pairs lie at most LOCAL_BP apart along the chain
+// (cyclically on a ring) are evaluated by the step kernel from the tile's
+// staged sites; all others come from the neighbour list.
+constexpr int LOCAL_BP = 3;
+static_assert(LOCAL_BP <= HALO_BP, "local pairs must lie inside the staged halo");
 constexpr int CMASK_WORDS = WG_THREADS / 32;  // contact-bit words per tile
 constexpr int SCAN_CHUNK = 4096;  // histogram entries per scan workgroup
 
@@ -34,6 +40,10 @@ struct Phys {
     double cos_d, sin_d;      // cos and sin of the dihedral phase
     double cos_a0, sin_a0;    // cos and sin of the planarity angle
     double kick;              // dt / 2
+    double skin;              // neighbour-list skin
+    double rl2_s, rl2_x;      // squared list cutoffs (rc + skin + slack) for
+                              // same-strand steric pairs and cross-strand pairs
+    float half_skin2;         // squared displacement that makes the list stale
     double inv_I, kick_M;     // 1 / I, (dt / 2) / M
     double inv_R0sq;          // 1 / R0^2
     uint64_t seed;
@@ -86,13 +96,29 @@ struct Tile {
 
 // Control block in device memory.  `step` is the step index of the positions
 // in buffer `par`; kernels read both at launch so that captured graphs replay
-// without argument changes.
+// without argument changes.  `stale` is set by the step kernel when a bead
+// has moved half the skin since the neighbour list was built: the rebuild
+// kernels of the same step then run, and the next pair kernel clears it.
 struct Ctl {
     int64_t step;
     int32_t par;
-    int32_t code;      // first error (dsdna_status), 0 if none
+    int32_t code;      // first error (dsdna_status or CODE_*), 0 if none
     int64_t err_step;
     int64_t err_id;
+    int32_t stale;
+    uint32_t list_n;   // pairs in the neighbour list (may exceed its capacity)
+    int64_t rebuilds;  // neighbour-list builds since the counter was reset
+};
+
+// Internal status: the neighbour list outgrew its buffer.  Never returned to
+// the caller: the host enlarges the buffer, rebuilds and continues.
+constexpr int CODE_LIST_FULL = 100;
+
+// A pair of beads of the neighbour list: nucleotides i and j (i's record
+// precedes j's in cell order), their replica, and whether they are on the
+// same strand (same-strand pairs are steric-steric).
+struct PairRec {
+    int32_t i, j, rep, same;
 };
 
 // Hash of cell (cx, cy, cz) of replica r into [0, nbucket): linear in the
@@ -122,14 +148,16 @@ struct Bufs {
     // 16 (k & 1) .. 16 (k & 1) + 15 of word k >> 1)
     uint32_t *count;
     int32_t *start, *bsum;              // per key (start: nbucket + 1); per scan chunk
-    // excluded-volume force per nt as exact fixed-point sums (x, y, z, unused;
-    // units FIX32_UNIT or FIX64_UNIT), zero except beads with contacts;
-    // consumers read and clear the entries whose contact bit is set
+    // excluded-volume force of the neighbour-list pairs per nt as exact
+    // fixed-point sums (FEX_WORDS per nt: FIX_HI and FIX_LO parts of x, y,
+    // z), zero except beads with contacts; consumers read and clear the
+    // entries whose contact bit is set
     unsigned long long *fex;
     // contact bits, CMASK_WORDS words per tile: bit t of the tile's mask is
     // set when tile thread t's nucleotide (2 (n - n0) + s) has a fex entry
     uint32_t *cmask;
-    double *eex;                        // excluded-volume energy per nt (diagnostics)
+    double *eex;                        // list-pair excluded-volume energy per nt (diagnostics)
+    PairRec *plist;                     // neighbour list (non-local bead pairs)
     RepInfo *rep;
     Tile *tiles;
     Ctl *ctl;
@@ -141,10 +169,16 @@ struct Bufs {
 
 enum StepMode : int { MODE_NORMAL = 0, MODE_FIRST = 1, MODE_FROM_FORCES = 2 };
 
-// Units of the fixed-point excluded-volume sums: 2^24 per force unit with
-// FP32 forces, 2^36 with FP64 forces.
-constexpr double FIX32_UNIT = 16777216.0;
-constexpr double FIX64_UNIT = 68719476736.0;
+// Exact, order-independent sums of the neighbour-list contact forces: each
+// force component f is split into a coarse part (an integer number of
+// FIX_HI units) and the remainder (an integer number of FIX_LO units, |.| <=
+// 2^31), and the two are summed in separate 64-bit integers.  The total is
+// resolved to 2^-40 force units whatever its size; a pair force of
+// PAIR_FORCE_MAX or more (or not finite) is an error.
+constexpr double FIX_HI = 256.0;              // 2^8 per force unit
+constexpr double FIX_LO = 1099511627776.0;    // 2^40 per force unit
+constexpr double PAIR_FORCE_MAX = 1099511627776.0;  // 2^40 (|fx| + |fy| + |fz|)
+constexpr int FEX_WORDS = 8;  // per nucleotide: coarse x, y, z, unused; fine x, y, z, unused
 
 // Everything the kernels read that does not change from launch to launch.
 // The host keeps a copy in device memory and passes its address, so the
@@ -157,6 +191,7 @@ struct StepArgs {
     int64_t n_nt;
     int32_t n_tiles;
     int32_t n_tiles_pad;   // launched workgroups (multiple of 8)
+    int64_t list_cap;      // capacity of b.plist
 };
 
 // A ring for the linking-number kernels: its first nucleotide, length,
@@ -173,14 +208,28 @@ struct RingSeg {
 
 // Launchers (defined in dsdna_kernels.hip).  `a` is the host copy (grid
 // sizes), `dA` the device copy the kernels read.
-hipError_t launch_bin(const StepArgs &a, const StepArgs *dA, int which, hipStream_t s);
-hipError_t launch_scan(const StepArgs &a, hipStream_t s);
-hipError_t launch_scatter(const StepArgs &a, int inc_step, hipStream_t s);
+//
+// One step is launch_pairs, launch_step, then the four kernels of a
+// neighbour-list rebuild (launch_bin, launch_scan, launch_scatter,
+// launch_build).  The rebuild kernels do their work when `force` is set or
+// when the step kernel has flagged the list stale; otherwise they return at
+// once.  launch_scan with inc_step advances the step counter and flips the
+// position buffers (every step).
 hipError_t launch_step(const StepArgs &a, const StepArgs *dA, int fp64, int mode, int write_full, hipStream_t s);
-// Excluded-volume force (and with `energy`, energy) of every bead from the
-// sorted records, written to b.fex (b.eex) by nucleotide.  `which`: position
-// buffer the records describe (-1: the control block's current buffer).
-hipError_t launch_excl(const StepArgs &a, const StepArgs *dA, int fp64, int energy, int which, hipStream_t s);
+// Excluded-volume force of every neighbour-list pair within its cutoff at the
+// positions of buffer `which` (-1: the control block's current buffer),
+// accumulated into b.fex / b.cmask (and with `energy`, half of each pair's
+// energy into b.eex of both beads).  clear_stale: reset the stale flag.
+hipError_t launch_pairs(const StepArgs &a, const StepArgs *dA, int which, int energy, int clear_stale,
+                        hipStream_t s);
+// Counting-sort count phase: record, cell, key and slot of every bead of
+// buffer `which` (-1: the buffer the step kernel has just written).
+hipError_t launch_bin(const StepArgs &a, const StepArgs *dA, int which, int force, hipStream_t s);
+hipError_t launch_scan(const StepArgs &a, int inc_step, int force, hipStream_t s);
+hipError_t launch_scatter(const StepArgs &a, int force, hipStream_t s);
+// Neighbour search over the sorted records: every non-local bead pair within
+// its cutoff plus the skin goes to b.plist; clears the histogram.
+hipError_t launch_build(const StepArgs &a, const StepArgs *dA, int force, hipStream_t s);
 hipError_t launch_thermalize(const StepArgs &a, const StepArgs *dA, double kT, uint64_t seed, hipStream_t s);
 // term_mask: bit t selects term t; writes per-term forces (AoS doubles) to
 // b.diag_fb / b.diag_fp, energies per tile to b.eacc[tile][DSDNA_NTERMS] and

@@ -3,19 +3,26 @@
 //
 // Per step (all kernels read the step index and the buffer parity from the
 // device control block, so a captured graph replays unchanged):
-//   k_excl     excluded volume of every bead from the key-sorted cell list
-//              (one thread per sorted record, neighbours from 27 cells)
+//   k_pairs    excluded volume of the neighbour-list pairs (bead pairs more
+//              than LOCAL_BP base pairs apart along the chain), from the FP64
+//              bodies, into exact fixed-point sums per bead
 //   k_step     one workgroup per tile of TILE_BP base pairs of one replica:
 //              stage the tile's FP64 sites in LDS, evaluate every
-//              fixed-topology term once into LDS outboxes, gather them per
-//              site (no atomics), add the excluded volume, the external
-//              loads and the Langevin forces, then integrate the rigid body
-//              (FP64) and bin its new bead position (histogram atomics: the
-//              counting-sort count phase).
-//   k_scan_*   exclusive scan of the histogram (counting-sort offsets)
-//   k_scatter  counting-sort scatter of the bead records into key order
+//              fixed-topology term once into LDS outboxes and the chain-local
+//              excluded volume per bead, gather per site (no atomics), add the
+//              list pairs' excluded volume, the external loads and the
+//              Langevin forces, then integrate the rigid body (FP64) and test
+//              whether its bead has moved half the skin since the list was
+//              built (the list is then stale)
+//   rebuild    when the list is stale (or the host forces it): k_bin (cell of
+//              every bead, histogram), k_scan_* (offsets), k_scatter (records
+//              into cell order), k_build (neighbour search within the cutoffs
+//              plus the skin); otherwise each returns at once.  k_scan_reduce
+//              also advances the step.
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include <algorithm>
 #include <stdint.h>
 
 #include "dsdna.h"
@@ -322,29 +329,6 @@ __device__ __forceinline__ int hist_add(const StepArgs &a, uint32_t key, int n, 
     return base;
 }
 
-// Bin one bead: record, cell, counting-sort key (its bucket) and slot
-// within the key (histogram count phase).
-__device__ __forceinline__ void insert_bead(const StepArgs &a, const RepInfo &ri, int rep, int n, int s,
-                                            int64_t i, D3 bead, int64_t step)
-{
-    int c[3];
-    uint32_t qc[3];
-    if (!cell_of(ri, bead, c, qc)) {
-        raise_error(a.b.ctl, isfinite(bead.x + bead.y + bead.z) ? DSDNA_EDOMAIN : DSDNA_ENAN, step, i);
-        c[0] = c[1] = c[2] = 0;
-    }
-    const uint32_t key = bucket_of(a.g, c[0], c[1], c[2], rep);
-    BeadRec r;
-    r.x = qc[0];
-    r.y = qc[1];
-    r.z = qc[2];
-    r.tag = make_tag(rep, n, s);
-    a.b.rec[i] = r;
-    if (a.g.any_open) a.b.rcell[i] = make_int4(c[0], c[1], c[2], 0);
-    a.b.key[i] = (int32_t)key;
-    a.b.slot[i] = hist_add(a, key, 1, i, step);
-}
-
 // Bin the new bead positions of a tile (all threads of the workgroup call
 // this): record, cell and key per bead, then the slots.  The keys of the tile
 // are first counted in an LDS hash table (at most WG_THREADS distinct keys in
@@ -395,13 +379,20 @@ __device__ __forceinline__ void bin_tile(const StepArgs &a, uint32_t *tab, uint3
 
 // ------------------------------------------------------------------- tiles
 
+// Work item of workgroup slot b out of n_pad (a multiple of 8): consecutive
+// workgroups go to the 8 XCDs in turn, so each XCD is given a contiguous run
+// of items (chain neighbours, or neighbouring cells, share an L2).  A
+// grid-stride loop over b keeps this when the grid is a multiple of 8.
+__device__ __forceinline__ int xcd_item(int b, int n_pad)
+{
+    const int per = n_pad >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
 __device__ __forceinline__ int tile_index(int n_tiles, int n_tiles_pad)
 {
-    // consecutive workgroups go to the 8 XCDs in turn; give each XCD a
-    // contiguous run of tiles so chain neighbours share an L2
-    const int per = n_tiles_pad >> 3;
-    const int b = blockIdx.x;
-    return (b & 7) * per + (b >> 3);
+    (void)n_tiles;
+    return xcd_item((int)blockIdx.x, n_tiles_pad);
 }
 
 // ------------------------------------------------------------- tile stage
@@ -493,20 +484,23 @@ __device__ __forceinline__ bool contact_flag(const StepArgs &a, int tix)
     return (w >> (threadIdx.x & 31)) & 1u;
 }
 
-// Excluded-volume force of nucleotide i accumulated by k_excl (only read
-// when its contact bit is set); the entry is cleared for the next step.
+// Excluded-volume force of nucleotide i from the neighbour-list pairs,
+// accumulated by k_pairs (only read when its contact bit is set); the entry
+// is cleared for the next step.
 template <typename real>
 __device__ __forceinline__ V3<real> take_fex(const StepArgs &a, int64_t i)
 {
-    unsigned long long *f = a.b.fex + 4 * i;
-    const long long x = (long long)f[0], y = (long long)f[1], z = (long long)f[2];
-    if (x | y | z) {
-        f[0] = 0ull;
-        f[1] = 0ull;
-        f[2] = 0ull;
+    unsigned long long *f = a.b.fex + FEX_WORDS * i;
+    const longlong4 hi = *reinterpret_cast<const longlong4 *>(f);
+    const longlong4 lo = *reinterpret_cast<const longlong4 *>(f + 4);
+    if (hi.x | hi.y | hi.z | lo.x | lo.y | lo.z) {
+        *reinterpret_cast<longlong4 *>(f) = make_longlong4(0, 0, 0, 0);
+        *reinterpret_cast<longlong4 *>(f + 4) = make_longlong4(0, 0, 0, 0);
     }
-    const double s = 1.0 / (sizeof(real) == sizeof(double) ? FIX64_UNIT : FIX32_UNIT);
-    return v3<real>((real)((double)x * s), (real)((double)y * s), (real)((double)z * s));
+    // each part converts exactly; the sum rounds once
+    const double sh = 1.0 / FIX_HI, sl = 1.0 / FIX_LO;
+    return v3<real>((real)((double)hi.x * sh + (double)lo.x * sl), (real)((double)hi.y * sh + (double)lo.y * sl),
+                    (real)((double)hi.z * sh + (double)lo.z * sl));
 }
 
 // exp(x) - 1 and atan2(y, x) where the thermal arguments fall: Taylor
@@ -611,7 +605,8 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
         const int s = q & 1, mi = q >> 1, m = n0 - 1 + mi;
         V3<real> fBa = v3<real>(0, 0, 0), fPa = fBa, fBb = fBa, fPb = fBa;
         if (m >= step_lo && m < step_hi) {
-            const int la = 2 * (mi + 1) + s, lb = la + 2;
+            // LDS site of (s, bp m) and (s, bp m + 1)
+            const int la = 2 * (mi + HALO_BP - 1) + s, lb = la + 2;
             const D3 Ba = lds3(S.sB, la), Pa = lds3(S.sP, la), Bb = lds3(S.sB, lb), Pb = lds3(S.sP, lb);
             const bool own = mi >= 1;  // step m belongs to the tile that holds nucleotide m
             // backbone: FENE + WCA(eps_bb, sig_bb) between consecutive beads
@@ -698,14 +693,16 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
     for (int q = t; q < 2 * (TILE_BP + 1); q += blockDim.x) {
         const int s = q & 1, mi = q >> 1, m = n0 - 1 + mi;
         if (!(m >= step_lo && m < step_hi)) continue;
-        const int la = 2 * (mi + 1) + s, lb = la + 2;
+        const int la = 2 * (mi + HALO_BP - 1) + s, lb = la + 2;
         const D3 Ba = lds3(S.sB, la), Pa = lds3(S.sP, la), Bb = lds3(S.sB, lb), Pb = lds3(S.sP, lb);
         const bool own = mi >= 1;
         const D3 b1d = Pa - Ba, b2d = Pb - Pa, b3d = Bb - Pb;
         V3<real> fBa = v3<real>(0, 0, 0), fPa = fBa, fBb = fBa, fPb = fBa;
         // helical twist: dihedral of (B_m, P_m, P_m+1, B_m+1); gradient as in
         // Blondel & Karplus (1996), free of the 1/sin(phi) singularity
-        const bool masked = rule && S.sOpen[mi + 1] && S.sOpen[mi + 2] && (S.sOpen[mi] || S.sOpen[mi + 3]);
+        // open flags of bp m - 1 .. m + 2 (sOpen index of bp m: mi + HALO_BP - 1)
+        const uint8_t *op = &S.sOpen[mi + HALO_BP - 2];
+        const bool masked = rule && op[1] && op[2] && (op[0] || op[3]);
         if ((mask & (1u << DSDNA_TERM_TWIST)) && !masked) {
             // the angle in FP64: near the minimum sin(phi - d) is a small
             // difference of O(1) products; the gradient directions in the
@@ -772,9 +769,11 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
     for (int q = t; q < 2 * (TILE_BP + 2); q += blockDim.x) {
         const int s = q & 1, mi = q >> 1, m = n0 - 1 + mi;
         V3<real> f0 = v3<real>(0, 0, 0), f2 = f0;
-        const bool masked = rule && S.sOpen[mi] && S.sOpen[mi + 1] && S.sOpen[mi + 2];
+        // open flags of bp m - 1, m, m + 1
+        const uint8_t *op = &S.sOpen[mi + HALO_BP - 2];
+        const bool masked = rule && op[0] && op[1] && op[2];
         if ((mask & (1u << DSDNA_TERM_BEND)) && m >= bend_lo && m < bend_hi && !masked) {
-            const int la = 2 * mi + s;
+            const int la = 2 * (mi + HALO_BP - 2) + s;  // LDS site of (s, bp m - 1)
             const D3 Pa = lds3(S.sP, la), Pc = lds3(S.sP, la + 2), Pe = lds3(S.sP, la + 4);
             const D3 r1 = Pa - Pc, r2 = Pe - Pc;
             const double l11 = dot(r1, r1), l22 = dot(r2, r2), d12 = dot(r1, r2);
@@ -789,6 +788,43 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
         }
         put3(S.oBend[s][mi][0], f0);
         put3(S.oBend[s][mi][1], f2);
+    }
+
+    // --- chain-local excluded volume (WCA with the steric/ghost rule of
+    //     Sec. 2): the pairs of the thread's own bead with the beads at most
+    //     LOCAL_BP base pairs away, every cross-strand bead and, for a steric
+    //     bead, the steric beads LOCAL_BP away on its own strand.  Evaluated
+    //     from the staged FP64 sites in FP64 (a contact just inside its
+    //     cutoff keeps its relative accuracy); each pair is evaluated by the
+    //     threads of both its beads, whose results are exact negatives, so
+    //     no outbox is needed.  Energies: half of each pair per bead.
+    V3<real> floc = v3<real>(0, 0, 0);
+    if (t < TILE_NT && n0 + (t >> 1) < nbp && (mask & (1u << DSDNA_TERM_EXCL))) {
+        const int s = t & 1, bl = t >> 1, n = n0 + bl;
+        const D3 bi = lds3(S.sB, t + 2 * HALO_BP);
+        D3 acc = v3(0.0, 0.0, 0.0);
+        double eh = 0.0;
+        auto wca = [&](int lj, double sig2, double rc2) {
+            const D3 d = lds3(S.sB, lj) - bi;  // from this bead to the other
+            const double r2 = dot(d, d);
+            if (r2 < rc2) {
+                const double ir2 = 1.0 / r2, sr2 = sig2 * ir2, sr6 = sr2 * sr2 * sr2;
+                acc = acc - d * (24.0 * ph.eps * (2.0 * sr6 * sr6 - sr6) * ir2);
+                if (energies) eh += 2.0 * ph.eps * (sr6 * sr6 - sr6 + 0.25);
+            }
+        };
+        const double sx2 = ph.sig_x * ph.sig_x, rx2 = ph.rc_x * ph.rc_x;
+#pragma unroll
+        for (int k = -LOCAL_BP; k <= LOCAL_BP; ++k)
+            if (site_exists(tile, n + k)) wca(2 * (bl + k + HALO_BP) + (s ^ 1), sx2, rx2);
+        if (n % 3 == 0) {  // steric: the steric beads of its strand LOCAL_BP away
+            static_assert(LOCAL_BP % 3 == 0, "steric beads are every third base pair");
+            const double ss2 = ph.sig_s * ph.sig_s, rs2 = ph.rc_s * ph.rc_s;
+            if (site_exists(tile, n - LOCAL_BP)) wca(2 * (bl - LOCAL_BP + HALO_BP) + s, ss2, rs2);
+            if (site_exists(tile, n + LOCAL_BP)) wca(2 * (bl + LOCAL_BP + HALO_BP) + s, ss2, rs2);
+        }
+        floc = cvt<real>(acc);
+        if (energies) energies[DSDNA_TERM_EXCL] += eh;
     }
     __syncthreads();
 
@@ -809,9 +845,10 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
         out.p = s == 0 ? out.p + hb : out.p - hb;
     }
 
-    // --- excluded volume: computed per bead from the cell list beforehand
+    // --- excluded volume: the chain-local pairs above plus the neighbour-list
+    //     pairs, accumulated per bead beforehand
     if (n < nbp && (mask & (1u << DSDNA_TERM_EXCL))) {
-        out.b = out.b + fex;
+        out.b = out.b + floc + fex;
         if (energies) energies[DSDNA_TERM_EXCL] += a.b.eex[ri.off + 2 * (int64_t)n + s];
     }
     if (n >= nbp) return out;
@@ -934,9 +971,11 @@ __global__ void __launch_bounds__(WG_THREADS, 5) k_step(const StepArgs *__restri
     // velocities and noise only now: they are not live through the force
     // phase, and the noise is drawn while the velocity loads are in flight
     D3 V = v3(0.0, 0.0, 0.0), L = V;
+    BeadRec ref = {0u, 0u, 0u, 0u};  // the bead's record when the list was built
     if (own) {
         V = ld3nt(a.b.V[cur], N, i);
         L = ld3nt(a.b.L[cur], N, i);
+        ref = a.b.rec[i];
     }
     real xi[6] = {0, 0, 0, 0, 0, 0};
     if (langevin) {
@@ -1026,56 +1065,156 @@ __global__ void __launch_bounds__(WG_THREADS, 5) k_step(const StepArgs *__restri
         if (!(isfinite(R.x + R.y + R.z) && isfinite(u.x + u.y + u.z))) raise_error(a.b.ctl, DSDNA_ENAN, step + 1, i);
         bead_new = bead_of(R, u, ph.db);
     }
-    // the force phase is over: its LDS outboxes hold the binning table
-    uint32_t *lds = reinterpret_cast<uint32_t *>(&S.oStep[0][0][0][0]);
-    bin_tile(a, lds, lds + WG_THREADS, reinterpret_cast<int *>(lds + 2 * WG_THREADS), ri, tile.rep, n, s, i, own,
-             bead_new, step + 1);
+    // --- the neighbour list stays valid while no bead has moved half the
+    //     skin since it was built: compare the new bead with its record (the
+    //     wrapped fixed-point difference is the exact displacement)
+    bool far = false;
+    if (own) {
+        int c[3];
+        uint32_t q[3];
+        if (!cell_of(ri, bead_new, c, q))
+            raise_error(a.b.ctl, isfinite(bead_new.x + bead_new.y + bead_new.z) ? DSDNA_EDOMAIN : DSDNA_ENAN, step + 1, i);
+        const float dx = (float)(int32_t)(q[0] - ref.x) * ri.qlen[0];
+        const float dy = (float)(int32_t)(q[1] - ref.y) * ri.qlen[1];
+        const float dz = (float)(int32_t)(q[2] - ref.z) * ri.qlen[2];
+        far = dx * dx + dy * dy + dz * dz >= ph.half_skin2;
+    }
+    const uint64_t far_lanes = __ballot(far);
+    if (far_lanes && (threadIdx.x & 63) == (unsigned)__builtin_ctzll(far_lanes)) atomicOr(&a.b.ctl->stale, 1);
 }
 
-// ------------------------------------------------------------ binning only
+// ------------------------------------------------- neighbour-list rebuild
 
-// Bins the beads of buffer `which` (after the state was set from the host).
-__global__ void __launch_bounds__(256) k_bin(const StepArgs *__restrict__ A, int which)
+// Whether the kernels of a neighbour-list rebuild do their work: when the
+// host forces a rebuild, or when the step kernel of this step found a bead
+// half the skin away from where the list saw it.
+__device__ __forceinline__ bool rebuild_now(const Ctl *ctl, int force)
+{
+    return ctl->code == 0 && (force || ctl->stale);
+}
+
+// Workgroups of the rebuild kernels (grid-stride loops): enough to fill the
+// chip when they work, few to dispatch when they return at once.
+constexpr int REBUILD_GRID = 2048;
+
+// Counting-sort count phase: bins the beads of buffer `which` (-1: the
+// buffer the step kernel has just written, i.e. the one after the control
+// block's current buffer; its step index is one ahead).  Each bead's record
+// becomes the reference position of the displacement test.
+__global__ void __launch_bounds__(WG_THREADS) k_bin(const StepArgs *__restrict__ A, int which, int force)
 {
     const StepArgs &a = *A;
-    const int tix = tile_index(a.n_tiles, a.n_tiles_pad);
-    if (tix >= a.n_tiles) return;
-    const Tile tile = a.b.tiles[tix];
-    const RepInfo &ri = a.b.rep[tile.rep];
-    const int s = threadIdx.x & 1, n = threadIdx.x < TILE_NT ? tile.n0 + (int)(threadIdx.x >> 1) : tile.n_bp;
-    if (n >= tile.n_bp) return;
-    const int64_t i = ri.off + 2 * (int64_t)n + s;
-    const D3 R = ld3(a.b.R[which], a.n_nt, i), u = ld3(a.b.u[which], a.n_nt, i);
-    insert_bead(a, ri, tile.rep, n, s, i, bead_of(R, u, a.ph.db), a.b.ctl->step);
+    const Ctl *ctl = a.b.ctl;
+    if (!rebuild_now(ctl, force)) return;
+    __shared__ uint32_t tab[WG_THREADS], cnt[WG_THREADS];
+    __shared__ int base[WG_THREADS];
+    const int buf = which < 0 ? (ctl->par ^ 1) : which;
+    const int64_t step = ctl->step + (which < 0 ? 1 : 0);
+    const int t = threadIdx.x;
+    for (int b = blockIdx.x; b < a.n_tiles_pad; b += gridDim.x) {
+        const int tix = xcd_item(b, a.n_tiles_pad);
+        if (tix >= a.n_tiles) continue;  // the same for the whole workgroup
+        const Tile tile = a.b.tiles[tix];
+        const RepInfo &ri = a.b.rep[tile.rep];
+        const int s = t & 1, n = t < TILE_NT ? tile.n0 + (t >> 1) : tile.n_bp;
+        const bool own = n < tile.n_bp;
+        const int64_t i = ri.off + 2 * (int64_t)n + s;
+        D3 bead = v3(0.0, 0.0, 0.0);
+        if (own) bead = bead_of(ld3(a.b.R[buf], a.n_nt, i), ld3(a.b.u[buf], a.n_nt, i), a.ph.db);
+        bin_tile(a, tab, cnt, base, ri, tile.rep, n, s, i, own, bead, step);
+    }
 }
 
 // ------------------------------------------------------- excluded volume
 
-// Excluded-volume sums are exact and order independent: every contact force
-// component is rounded to the fixed-point grid (FIX32_UNIT or FIX64_UNIT per
-// force unit) and summed as a 64-bit integer, so a bead's total does not
-// depend on which thread evaluated a pair or in what order.  A contact force
-// beyond the limits (overlapping beads; at most 16 such contacts keep the
-// sums in range) is reported as an error.
-constexpr double PAIR_FORCE_MAX_F32 = 33554432.0;  // 2^25 (|fx| + |fy| + |fz|)
-constexpr double PAIR_FORCE_MAX_F64 = 8388608.0;   // 2^23
+// Excluded-volume sums of the neighbour-list pairs are exact and order
+// independent: every contact force component is split into a coarse integer
+// number of 1/FIX_HI units and a remainder of 1/FIX_LO units, summed as two
+// 64-bit integers, so a bead's total depends neither on which thread
+// evaluated a pair nor on the order.
 
-// Add a fixed-point force to nucleotide j and set its contact bit (bit
-// 2 (n - n0) + s of its tile's mask, the tile thread that owns it).
-__device__ __forceinline__ void fex_add(const StepArgs &a, const RepInfo &ri, int64_t j, long long fx, long long fy,
-                                        long long fz)
+// The two integer parts of force component f (units 2^-8 and 2^-40): v = f
+// 2^40 is exact, h the nearest multiple of 2^32 to it, and v - h 2^32 exact
+// (the two lie within a factor 2 of each other, or h is 0), then rounded to
+// the 2^-40 grid.
+__device__ __forceinline__ void fix_split(double f, long long &hi, long long &lo)
 {
-    unsigned long long *f = a.b.fex + 4 * j;
-    if (fx) atomicAdd(f, (unsigned long long)fx);
-    if (fy) atomicAdd(f + 1, (unsigned long long)fy);
-    if (fz) atomicAdd(f + 2, (unsigned long long)fz);
+    const double v = f * FIX_LO;
+    const double h = rint(v * (1.0 / 4294967296.0));
+    hi = (long long)h;
+    lo = __double2ll_rn(v - h * 4294967296.0);
+}
+
+// Add the force f (sign +1 or -1) to nucleotide j and set its contact bit
+// (bit 2 (n - n0) + s of its tile's mask, the tile thread that owns it).
+__device__ __forceinline__ void fex_add(const StepArgs &a, const RepInfo &ri, int64_t j, const long long hi[3],
+                                        const long long lo[3], long long sign)
+{
+    unsigned long long *f = a.b.fex + FEX_WORDS * j;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (hi[k]) atomicAdd(f + k, (unsigned long long)(sign * hi[k]));
+        if (lo[k]) atomicAdd(f + 4 + k, (unsigned long long)(sign * lo[k]));
+    }
     const int64_t jj = j - ri.off;
     const int tb = (int)(jj >> 1) / TILE_BP;
     const int lt = (int)(jj - 2 * (int64_t)TILE_BP * tb);
     atomicOr(&a.b.cmask[(int64_t)(ri.tile0 + tb) * CMASK_WORDS + (lt >> 5)], 1u << (lt & 31));
 }
 
-// A bead of the sorted cell list as the excluded-volume search sees it.
+// Excluded volume (WCA, Sec. 2 and App. A) of the neighbour-list pairs, the
+// bead pairs more than LOCAL_BP base pairs apart: one thread per pair.  The
+// distance is formed from the FP64 bodies of both nucleotides (minimum image
+// along periodic edges) and the force in FP64, whatever the precision of the
+// other terms: contacts are rare, and near the cutoff the force is a small
+// difference of O(1) numbers.  Pairs beyond the cutoff (within the skin)
+// contribute nothing.
+__global__ void __launch_bounds__(256) k_pairs(const StepArgs *__restrict__ A, int which, int energy, int clear_stale)
+{
+    const StepArgs &a = *A;
+    Ctl *ctl = a.b.ctl;
+    if (ctl->code != 0) return;
+    // the rebuild kernels of the previous step have read the flag
+    if (clear_stale && blockIdx.x == 0 && threadIdx.x == 0) ctl->stale = 0;
+    const int64_t n = min((int64_t)ctl->list_n, a.list_cap);
+    const int buf = which < 0 ? ctl->par : which;
+    const double *Rc = a.b.R[buf], *uc = a.b.u[buf];
+    const int64_t N = a.n_nt;
+    const Phys &ph = a.ph;
+    int64_t bad = -1;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const PairRec pr = a.b.plist[k];
+        const RepInfo &ri = a.b.rep[pr.rep];
+        D3 d = bead_of(ld3(Rc, N, pr.j), ld3(uc, N, pr.j), ph.db) - bead_of(ld3(Rc, N, pr.i), ld3(uc, N, pr.i), ph.db);
+        if (ri.flags & REP_PER_X) d.x = __fma_rn(-ri.len[0], rint(d.x * ri.inv_len[0]), d.x);
+        if (ri.flags & REP_PER_Y) d.y = __fma_rn(-ri.len[1], rint(d.y * ri.inv_len[1]), d.y);
+        if (ri.flags & REP_PER_Z) d.z = __fma_rn(-ri.len[2], rint(d.z * ri.inv_len[2]), d.z);
+        const double r2 = dot(d, d);
+        const double rc = pr.same ? ph.rc_s : ph.rc_x, sig = pr.same ? ph.sig_s : ph.sig_x;
+        if (!(r2 < rc * rc)) continue;
+        const double ir2 = 1.0 / r2, sr2 = sig * sig * ir2, sr6 = sr2 * sr2 * sr2;
+        // force on j (+), on i (-): repulsive
+        const D3 f = d * (24.0 * ph.eps * (2.0 * sr6 * sr6 - sr6) * ir2);
+        if (!(fabs(f.x) + fabs(f.y) + fabs(f.z) < PAIR_FORCE_MAX)) {
+            bad = pr.i;
+            continue;
+        }
+        long long hi[3], lo[3];
+        fix_split(f.x, hi[0], lo[0]);
+        fix_split(f.y, hi[1], lo[1]);
+        fix_split(f.z, hi[2], lo[2]);
+        fex_add(a, ri, pr.j, hi, lo, 1);
+        fex_add(a, ri, pr.i, hi, lo, -1);
+        if (energy) {
+            const double eh = 2.0 * ph.eps * (sr6 * sr6 - sr6 + 0.25);  // half the pair energy
+            atomicAdd(&a.b.eex[pr.i], eh);
+            atomicAdd(&a.b.eex[pr.j], eh);
+        }
+    }
+    if (bad >= 0) raise_error(ctl, DSDNA_ENAN, ctl->step, bad);
+}
+
+// A bead of the sorted cell list as the neighbour search sees it.
 struct ExclBead {
     BeadRec me;
     uint32_t rep, mt, accept;
@@ -1116,7 +1255,7 @@ __device__ __forceinline__ ExclBead excl_bead(const StepArgs &a, const BeadRec *
     return B;
 }
 
-// Does a ghost bead (cross-strand partners only, within rc_x) need the
+// Does a ghost bead (cross-strand partners only, within rc of it) need the
 // neighbour cells below / above it along dimension k?  Periodic dims: from
 // its position inside the cell (the low 32 bits of q * ncell); open dims:
 // always.
@@ -1133,52 +1272,55 @@ __device__ __forceinline__ void ghost_reach(const RepInfo &ri, int k, uint32_t q
     hi = 4294967296ull - frac < T;
 }
 
-// Excluded volume (WCA, steric/ghost rule of Sec. 2), one thread per record
-// of the key-sorted cell list, so the lanes of a wave hold beads of
-// neighbouring cells and read overlapping candidate ranges.  A bead
-// interacts with every bead of the other strand (sigma_x) and, if steric,
-// with the steric beads of its own strand (sigma_s).  Each pair is evaluated
-// once (half stencil): the thread of a bead scans the later records of its
-// own bucket, the next cell of its row, the row above (dy = +1) and the three
-// rows of the next layer (dz = +1), as one stream of five record ranges.  A
-// ghost bead has only cross-strand partners, within rc_x of it, so it skips
-// the neighbour cells farther than rc_x from its position (exact: a skipped
-// cell holds no bead that close).  The candidate counts of a workgroup's
-// records vary a lot, so the records are handed to the threads in order of
-// decreasing count (a counting sort in LDS) and each wave's lanes carry
-// similar loads.  Contacts are rare, so forces go to the sparse accumulators
-// by atomics.  With FP32 forces the distance comes from the fixed-point
-// coordinates; with FP64 forces those only pre-select, and the distance is
-// taken from the FP64 positions (minimum image along periodic edges).
+// Whether nucleotides i and j of replica ri form a chain-local pair (base
+// pairs at most LOCAL_BP apart, cyclically on a ring): those pairs are the
+// step kernel's.
+__device__ __forceinline__ bool local_pair(const RepInfo &ri, int64_t i, int64_t j)
+{
+    int d = abs((int)((i - ri.off) >> 1) - (int)((j - ri.off) >> 1));
+    if (ri.flags & REP_RING) d = min(d, ri.n_bp - d);
+    return d <= LOCAL_BP;
+}
+
+// Neighbour-list build (Verlet list with a skin) from the key-sorted cell
+// list: one thread per sorted record, so the lanes of a wave hold beads of
+// neighbouring cells and read overlapping candidate ranges.  A bead pairs
+// with every bead of the other strand and, if steric, with the steric beads
+// of its own strand (Sec. 2); a pair enters the list when its distance is
+// below its WCA cutoff plus the skin and it is not chain-local.  Each pair is
+// found once (half stencil): the thread of a bead scans the later records of
+// its own bucket, the next cell of its row, the row above (dy = +1) and the
+// three rows of the next layer (dz = +1), as one stream of five record
+// ranges.  A ghost bead has only cross-strand partners, so it skips the
+// neighbour cells farther than that reach from its position (exact: a
+// skipped cell holds no bead that close).  The candidate counts of a
+// workgroup's records vary a lot, so the records are handed to the threads
+// in order of decreasing count (a counting sort in LDS) and each wave's lanes
+// carry similar loads.  Distances come from the fixed-point records (exact
+// differences; the list cutoffs carry a slack for their FP32 evaluation).
 constexpr int EXCL_THREADS = 256;  // records per workgroup (sorted by load together)
 
-template <typename real, bool energy, bool any_open>
-__global__ void __launch_bounds__(EXCL_THREADS) k_excl(const StepArgs *__restrict__ A, const BeadRec *__restrict__ srec,
+template <bool any_open>
+__global__ void __launch_bounds__(EXCL_THREADS) k_build(const StepArgs *__restrict__ A, const BeadRec *__restrict__ srec,
                                               const int *__restrict__ sid, const int4 *__restrict__ scell,
-                                              const int *__restrict__ start, int which)
+                                              const int *__restrict__ start, int force)
 {
     const StepArgs &a = *A;
-    if (a.b.ctl->code != 0) return;
-    const int per = (int)(gridDim.x >> 3);
-    const int blk = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-    const int p0 = blk * (int)blockDim.x;
+    Ctl *ctl = a.b.ctl;
+    if (!rebuild_now(ctl, force)) return;
     const int t = threadIdx.x;
     // the histogram has served this cell list: clear it for the next
-    // binning (streaming stores while this kernel is bound by arithmetic)
+    // binning (streaming stores while this kernel is bound by its search)
     {
         int4 *c4 = reinterpret_cast<int4 *>(a.b.count);
         const int n4 = a.g.nbucket >> 3, stride = (int)(gridDim.x * blockDim.x);
         for (int k = (int)(blockIdx.x * blockDim.x + threadIdx.x); k < n4; k += stride) c4[k] = make_int4(0, 0, 0, 0);
     }
-    constexpr bool F64 = sizeof(real) == sizeof(double);
+    if (blockIdx.x == 0 && t == 0) ctl->rebuilds += 1;
     const Phys &ph = a.ph;
+    const float rcs2 = (float)ph.rl2_s, rcx2 = (float)ph.rl2_x;
+    const uint32_t cap = (uint32_t)min(a.list_cap, (int64_t)0x7FFFFFFF);
 
-    // --- the candidate stream of record p0 + t: stream position k of range
-    // q sits at k + s_sh[q] in the sorted records; s_pre[q] = first stream
-    // position of range q.  Range 0: the rest of the own bucket and the next
-    // cell; ranges 1..4: rows (dy, dz) = (+1, 0), (-1, +1), (0, +1), (+1, +1)
-    // over the needed dx.  A range that wraps (periodic x or bucket index)
-    // is empty here and walked cell by cell later (bit q of s_wr).
     __shared__ int s_sh[5][EXCL_THREADS];
     __shared__ int s_pre[5][EXCL_THREADS];
     __shared__ uint32_t s_pk[EXCL_THREADS];
@@ -1186,6 +1328,19 @@ __global__ void __launch_bounds__(EXCL_THREADS) k_excl(const StepArgs *__restric
     __shared__ uint8_t s_wr[EXCL_THREADS];
     __shared__ int s_hist[64];
     __shared__ int s_order[EXCL_THREADS];
+    const int nblk = (int)((a.n_nt + EXCL_THREADS - 1) / EXCL_THREADS);
+    const int nblk_pad = (nblk + 7) / 8 * 8;
+    for (int vb = blockIdx.x; vb < nblk_pad; vb += gridDim.x) {
+    const int blk = xcd_item(vb, nblk_pad);
+    const int p0 = blk * EXCL_THREADS;
+    __syncthreads();  // the LDS of the previous block is free
+
+    // --- the candidate stream of record p0 + t: stream position k of range
+    // q sits at k + s_sh[q] in the sorted records; s_pre[q] = first stream
+    // position of range q.  Range 0: the rest of the own bucket and the next
+    // cell; ranges 1..4: rows (dy, dz) = (+1, 0), (-1, +1), (0, +1), (+1, +1)
+    // over the needed dx.  A range that wraps (periodic x or bucket index)
+    // is empty here and walked cell by cell later (bit q of s_wr).
     int key = 0;
     {
         int total = 0;
@@ -1198,7 +1353,7 @@ __global__ void __launch_bounds__(EXCL_THREADS) k_excl(const StepArgs *__restric
             auto wrap = [&](int v, int n, bool per_) { return per_ ? (v < 0 ? v + n : (v >= n ? v - n : v)) : v; };
             bool xm = true, xp = true, ym = true, yp = true, zm = true, zp = true;
             if (!(B.mt & 2u)) {
-                const double rc = ph.rc_x + 1e-3;
+                const double rc = ph.rc_x + ph.skin + 1e-3;
                 ghost_reach(ri, 0, B.me.x, rc, xm, xp);
                 ghost_reach(ri, 1, B.me.y, rc, ym, yp);
                 ghost_reach(ri, 2, B.me.z, rc, zm, zp);
@@ -1237,7 +1392,7 @@ __global__ void __launch_bounds__(EXCL_THREADS) k_excl(const StepArgs *__restric
         s_wr[t] = (uint8_t)wrapped;
         // (clamped: every key is a histogram bin, so s_order below is always a
         // full permutation of the workgroup's threads)
-        key = min(max(total, 0), 63);
+        key = min(max(total >> 1, 0), 63);
     }
 
     // --- counting sort of the workgroup's records by decreasing count
@@ -1260,32 +1415,20 @@ __global__ void __launch_bounds__(EXCL_THREADS) k_excl(const StepArgs *__restric
     __syncthreads();
     const int src = s_order[t];
     const int p = p0 + src;
-    if (p >= a.n_nt) return;
+    if (p < a.n_nt) {
 
     // --- the candidates of record p (its stream is LDS column src)
-    const double unit = F64 ? FIX64_UNIT : FIX32_UNIT;
     const ExclBead B = excl_bead<any_open>(a, srec, scell, p);
     const BeadRec me = B.me;
     const uint32_t rep = B.rep, mt = B.mt, accept = B.accept;
     const RepInfo &ri = *B.ri;
     const int64_t i = sid[p];
     const float qx = ri.qlen[0], qy = ri.qlen[1], qz = ri.qlen[2];
-    const int64_t N = a.n_nt;
-    const int buf = which < 0 ? a.b.ctl->par : which;
-    const double *Rc = a.b.R[buf], *uc = a.b.u[buf];
     const bool px = B.px, py = B.py, pz = B.pz;
     const bool open_any = any_open && !(px && py && pz);
     const int *c = B.c;
-    // FP64 forces: pre-select with a slack that covers the fixed-point error
-    const float rcs2 = (float)(F64 ? (ph.rc_s + 1e-3) * (ph.rc_s + 1e-3) : ph.rc_s * ph.rc_s);
-    const float rcx2 = (float)(F64 ? (ph.rc_x + 1e-3) * (ph.rc_x + 1e-3) : ph.rc_x * ph.rc_x);
-    const real sig_s2 = (real)(ph.sig_s * ph.sig_s), sig_x2 = (real)(ph.sig_x * ph.sig_x);
-    const real e24 = (real)(24.0 * ph.eps);
-    long long ox = 0, oy = 0, oz = 0;  // this bead's own sum
-    double e_excl = 0.0;
-    bool overflow = false;
 
-    // contact test of candidate o (sorted position q): every test evaluated,
+    // list test of candidate o (sorted position q): every test evaluated,
     // no branch
     auto test = [&](const BeadRec &o, int q) -> bool {
         const uint32_t ot = o.tag & 3u;
@@ -1296,17 +1439,11 @@ __global__ void __launch_bounds__(EXCL_THREADS) k_excl(const StepArgs *__restric
         const float r2f = dx * dx + dy * dy + dz * dz;
         return (r2f < (same ? rcs2 : rcx2)) & (((accept >> ot) & 1u) != 0u) & ((o.tag >> 2) == rep) & (q != p);
     };
-    auto pair = [&](const BeadRec &o, int q, bool valid) {
-        // distance first (keeps the record load whole), then the type,
-        // replica and self tests in one predicate
-        const uint32_t ot = o.tag & 3u;
-        const bool same = ((ot ^ mt) & 1u) == 0u;
-        const float dx = (float)(int32_t)(o.x - me.x) * qx;
-        const float dy = (float)(int32_t)(o.y - me.y) * qy;
-        const float dz = (float)(int32_t)(o.z - me.z) * qz;
-        const float r2f = dx * dx + dy * dy + dz * dz;
-        if (!(valid && r2f < (same ? rcs2 : rcx2) && ((accept >> ot) & 1u) && (o.tag >> 2) == rep && q != p))
-            return;
+    // a candidate that passed the test (or, with `check`, one to test):
+    // into the list unless it is chain-local
+    auto hit = [&](int q, bool check) {
+        const BeadRec o = srec[q];
+        if (check && !test(o, q)) return;
         // open edges: the fixed-point difference is exact only modulo 2^32
         // units, so a record of a far cell that shares a bucket with a
         // neighbour cell is rejected by its cell coordinates
@@ -1316,39 +1453,15 @@ __global__ void __launch_bounds__(EXCL_THREADS) k_excl(const StepArgs *__restric
                 return;
         }
         const int64_t j = sid[q];
-        V3<real> d = v3<real>(dx, dy, dz);
-        real r2 = r2f;
-        D3 d64 = v3(0.0, 0.0, 0.0);
-        if (F64) {
-            d64 = bead_of(ld3(Rc, N, j), ld3(uc, N, j), ph.db) - bead_of(ld3(Rc, N, i), ld3(uc, N, i), ph.db);
-            if (px) d64.x = __fma_rn(-ri.len[0], rint(d64.x * ri.inv_len[0]), d64.x);
-            if (py) d64.y = __fma_rn(-ri.len[1], rint(d64.y * ri.inv_len[1]), d64.y);
-            if (pz) d64.z = __fma_rn(-ri.len[2], rint(d64.z * ri.inv_len[2]), d64.z);
-            d = cvt<real>(d64);
-            r2 = dot(d, d);
-            if (r2 >= (real)(same ? ph.rc_s * ph.rc_s : ph.rc_x * ph.rc_x)) return;
-        }
-        const real ir2 = rcp(r2);
-        const real sr2 = (same ? sig_s2 : sig_x2) * ir2;
-        const real sr6 = sr2 * sr2 * sr2;
-        const real g = e24 * ((real)2 * sr6 * sr6 - sr6) * ir2;
-        const real fx = g * d.x, fy = g * d.y, fz = g * d.z;
-        if (!(fabs(fx) + fabs(fy) + fabs(fz) < (real)(F64 ? PAIR_FORCE_MAX_F64 : PAIR_FORCE_MAX_F32))) {
-            overflow = true;
-            return;
-        }
-        // repulsive: -g d on this bead, +g d on the partner
-        const long long lx = __double2ll_rn((double)fx * unit);
-        const long long ly = __double2ll_rn((double)fy * unit);
-        const long long lz = __double2ll_rn((double)fz * unit);
-        ox -= lx;
-        oy -= ly;
-        oz -= lz;
-        fex_add(a, ri, j, lx, ly, lz);
-        if (energy) {
-            const double s2 = (same ? ph.sig_s * ph.sig_s : ph.sig_x * ph.sig_x) / (F64 ? dot(d64, d64) : (double)r2);
-            const double s6 = s2 * s2 * s2;
-            e_excl += 4.0 * ph.eps * (s6 * s6 - s6 + 0.25);
+        if (local_pair(ri, i, j)) return;
+        const uint32_t slot = atomicAdd(&ctl->list_n, 1u);
+        if (slot < cap) {
+            PairRec pr;
+            pr.i = (int32_t)i;
+            pr.j = (int32_t)j;
+            pr.rep = (int32_t)rep;
+            pr.same = (((o.tag ^ mt) & 1u) == 0u) ? 1 : 0;
+            a.b.plist[slot] = pr;
         }
     };
 
@@ -1373,8 +1486,9 @@ __global__ void __launch_bounds__(EXCL_THREADS) k_excl(const StepArgs *__restric
     // while the current U are evaluated (two register sets, so the pipeline
     // needs no copies)
     constexpr int U = 2;
-    // The stream is screened without branches: a contact sets bit k of the
-    // hit masks (k < 128), and the (rare) contacts are evaluated afterwards.
+    // The stream is screened without branches: a candidate within the list
+    // cutoff sets bit k of the hit masks (k < 128), and the hits are
+    // processed afterwards.
     uint64_t hit0 = 0, hit1 = 0;
     auto mark = [&](int k, bool h) {
         const uint64_t bit = (uint64_t)h << (k & 63);
@@ -1406,19 +1520,12 @@ __global__ void __launch_bounds__(EXCL_THREADS) k_excl(const StepArgs *__restric
             for (int v = 0; v < U; ++v) mark(k0 + U + v, (k0 + U + v < nfast) & test(ob[v], pb[v]));
         }
     }
-    for (uint64_t h = hit0; h; h &= h - 1) {
-        const int pq = locate(__builtin_ctzll(h));
-        pair(srec[pq], pq, true);
-    }
-    for (uint64_t h = hit1; h; h &= h - 1) {
-        const int pq = locate(64 + __builtin_ctzll(h));
-        pair(srec[pq], pq, true);
-    }
+    for (uint64_t h = hit0; h; h &= h - 1) hit(locate(__builtin_ctzll(h)), false);
+    for (uint64_t h = hit1; h; h &= h - 1) hit(locate(64 + __builtin_ctzll(h)), false);
     for (int k = nfast; k < total; ++k) {
         int q = 0;
         for (int r = 1; r < 5; ++r) q = (k >= s_pre[r][src]) ? r : q;
-        const int pq = k + s_sh[q][src];
-        pair(srec[pq], pq, true);
+        hit(k + s_sh[q][src], true);
     }
     // ranges that wrap: cell by cell (rare), over the dx a ghost needs
     if (wrapped & 0x1Fu) {
@@ -1429,22 +1536,25 @@ __global__ void __launch_bounds__(EXCL_THREADS) k_excl(const StepArgs *__restric
         for (int q = 0; q < 5; ++q) {
             if (!((wrapped >> q) & 1u)) continue;
             if (q == 0) {
-                for (int q2 = p + 1; q2 < start[B.kown + 1]; ++q2) pair(srec[q2], q2, true);
+                for (int q2 = p + 1; q2 < start[B.kown + 1]; ++q2) hit(q2, true);
                 const uint32_t kb = bucket_of(a.g, wrap(c[0] + 1, ncx, px), c[1], c[2], (int)rep);
-                for (int q2 = start[kb]; q2 < start[kb + 1]; ++q2) pair(srec[q2], q2, true);
+                for (int q2 = start[kb]; q2 < start[kb + 1]; ++q2) hit(q2, true);
                 continue;
             }
             const int dy = q == 1 ? 1 : q - 3, dz = q == 1 ? 0 : 1;
             const int cy = wrap(c[1] + dy, ncy, py), cz = wrap(c[2] + dz, ncz, pz);
             for (int dx = dxlo; dx <= dxhi; ++dx) {
                 const uint32_t kb = bucket_of(a.g, wrap(c[0] + dx, ncx, px), cy, cz, (int)rep);
-                for (int q2 = start[kb]; q2 < start[kb + 1]; ++q2) pair(srec[q2], q2, true);
+                for (int q2 = start[kb]; q2 < start[kb + 1]; ++q2) hit(q2, true);
             }
         }
     }
-    if (overflow) raise_error(a.b.ctl, DSDNA_ENAN, a.b.ctl->step, i);
-    if (ox | oy | oz) fex_add(a, ri, i, ox, oy, oz);
-    if (energy) a.b.eex[i] = e_excl;
+    }  // p < n_nt
+    }  // record blocks
+    // a list past its buffer stops the run; the host enlarges it and rebuilds
+    __syncthreads();
+    if (t == 0 && __hip_atomic_load(&ctl->list_n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > cap)
+        raise_error(ctl, CODE_LIST_FULL, ctl->step, -1);
 }
 
 // ------------------------------------------------------------------- scan
@@ -1475,11 +1585,19 @@ __device__ __forceinline__ int block_excl_scan(int v, int *total)
     return base + incl - v;
 }
 
-// Total of each chunk of SCAN_CHUNK histogram entries.
+// Total of each chunk of SCAN_CHUNK histogram entries.  inc: this is the
+// last kernel of a step that reads the step index or the buffer parity, so
+// advance the step and flip the position buffers (the rebuild kernels after
+// it read neither).
 __global__ void __launch_bounds__(256) k_scan_reduce(const uint32_t *__restrict__ count, int *__restrict__ bsum,
-                                                     const Ctl *ctl)
+                                                     Ctl *ctl, int inc, int force)
 {
     if (ctl->code != 0) return;
+    if (inc && blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->step += 1;
+        ctl->par ^= 1;
+    }
+    if (!rebuild_now(ctl, force)) return;
     // 16 buckets (8 words) per thread
     const uint4 *c4 = reinterpret_cast<const uint4 *>(count + (int64_t)blockIdx.x * (SCAN_CHUNK / 2)) + threadIdx.x * 2;
     int v = 0;
@@ -1496,9 +1614,9 @@ __global__ void __launch_bounds__(256) k_scan_reduce(const uint32_t *__restrict_
 
 // Offsets of one chunk of SCAN_CHUNK keys from the preceding chunk totals.
 __global__ void __launch_bounds__(256) k_scan_down(const uint32_t *__restrict__ count, const int *__restrict__ bsum,
-                                                   int *__restrict__ start, int nkeys, const Ctl *ctl)
+                                                   int *__restrict__ start, int nkeys, const Ctl *ctl, int force)
 {
-    if (ctl->code != 0) return;
+    if (!rebuild_now(ctl, force)) return;
     // the chunk's counts first (in flight while the offset is summed): 16
     // buckets in 8 words per thread
     const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + threadIdx.x * 16;
@@ -1547,26 +1665,22 @@ __global__ void __launch_bounds__(256) k_scan_down(const uint32_t *__restrict__ 
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == blockDim.x - 1) start[nkeys] = run;
 }
 
-// Counting-sort scatter: bead records into key order.  inc: also advance
-// the step and flip the position buffers.
+// Counting-sort scatter: bead records into key order (grid-stride); empties
+// the neighbour list for the build that follows.
 __global__ void __launch_bounds__(256) k_scatter(const int *__restrict__ key, const int *__restrict__ slot,
                                                  const int *__restrict__ start, const BeadRec *__restrict__ rec,
                                                  const int4 *__restrict__ rcell, BeadRec *__restrict__ srec,
                                                  int *__restrict__ sid, int4 *__restrict__ scell, Ctl *ctl,
-                                                 int64_t n, int inc, int any_open)
+                                                 int64_t n, int any_open, int force)
 {
-    if (ctl->code != 0) return;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
+    if (!rebuild_now(ctl, force)) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->list_n = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int k = key[i];
         const int p = start[k] + slot[i];
         srec[p] = rec[i];
         sid[p] = (int)i;
         if (any_open) scell[p] = rcell[i];
-    }
-    if (inc && i == 0) {
-        ctl->step += 1;
-        ctl->par ^= 1;
     }
 }
 
@@ -1796,27 +1910,57 @@ __global__ void __launch_bounds__(WG_THREADS) k_diag(const StepArgs *__restrict_
 
 static dim3 tiles_grid(const StepArgs &a) { return dim3((unsigned)a.n_tiles_pad); }
 
-hipError_t launch_bin(const StepArgs &a, const StepArgs *dA, int which, hipStream_t s)
+// Grid of a rebuild kernel over `items` work items: at most REBUILD_GRID
+// workgroups, a multiple of 8 (the XCD-aware grid-stride loops need it).
+static dim3 rebuild_grid(int64_t items)
 {
-    hipLaunchKernelGGL(k_bin, tiles_grid(a), dim3(WG_THREADS), 0, s, dA, which);
+    const int64_t g = std::min<int64_t>(std::max<int64_t>(items, 1), REBUILD_GRID);
+    return dim3((unsigned)((g + 7) / 8 * 8));
+}
+
+hipError_t launch_bin(const StepArgs &a, const StepArgs *dA, int which, int force, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bin, rebuild_grid(a.n_tiles_pad), dim3(WG_THREADS), 0, s, dA, which, force);
     return hipGetLastError();
 }
 
-hipError_t launch_scan(const StepArgs &a, hipStream_t s)
+hipError_t launch_scan(const StepArgs &a, int inc_step, int force, hipStream_t s)
 {
     const int nkeys = a.g.nbucket;
     const int nchunk = nkeys / SCAN_CHUNK;
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nchunk), dim3(256), 0, s, a.b.count, a.b.bsum, a.b.ctl);
-    hipLaunchKernelGGL(k_scan_down, dim3(nchunk), dim3(256), 0, s, a.b.count, a.b.bsum, a.b.start, nkeys,
-                       a.b.ctl);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nchunk), dim3(256), 0, s, a.b.count, a.b.bsum, a.b.ctl, inc_step, force);
+    hipLaunchKernelGGL(k_scan_down, dim3(nchunk), dim3(256), 0, s, a.b.count, a.b.bsum, a.b.start, nkeys, a.b.ctl,
+                       force);
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(const StepArgs &a, int inc_step, hipStream_t s)
+hipError_t launch_scatter(const StepArgs &a, int force, hipStream_t s)
 {
-    const unsigned nb = (unsigned)((a.n_nt + 255) / 256);
-    hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, s, a.b.key, a.b.slot, a.b.start, a.b.rec, a.b.rcell,
-                       a.b.srec, a.b.sid, a.b.scell, a.b.ctl, a.n_nt, inc_step, a.g.any_open);
+    hipLaunchKernelGGL(k_scatter, rebuild_grid((a.n_nt + 255) / 256), dim3(256), 0, s, a.b.key, a.b.slot, a.b.start,
+                       a.b.rec, a.b.rcell, a.b.srec, a.b.sid, a.b.scell, a.b.ctl, a.n_nt, a.g.any_open, force);
+    return hipGetLastError();
+}
+
+hipError_t launch_build(const StepArgs &a, const StepArgs *dA, int force, hipStream_t s)
+{
+    const dim3 g = rebuild_grid((a.n_nt + EXCL_THREADS - 1) / EXCL_THREADS);
+    if (a.g.any_open)
+        hipLaunchKernelGGL(k_build<true>, g, dim3(EXCL_THREADS), 0, s, dA, a.b.srec, a.b.sid, a.b.scell, a.b.start,
+                           force);
+    else
+        hipLaunchKernelGGL(k_build<false>, g, dim3(EXCL_THREADS), 0, s, dA, a.b.srec, a.b.sid, a.b.scell, a.b.start,
+                           force);
+    return hipGetLastError();
+}
+
+// Threads of the pair kernel: the list holds a few pairs per thousand beads.
+constexpr int PAIRS_GRID = 256;
+
+hipError_t launch_pairs(const StepArgs &a, const StepArgs *dA, int which, int energy, int clear_stale,
+                        hipStream_t s)
+{
+    (void)a;
+    hipLaunchKernelGGL(k_pairs, dim3(PAIRS_GRID), dim3(256), 0, s, dA, which, energy, clear_stale);
     return hipGetLastError();
 }
 
@@ -1831,32 +1975,6 @@ hipError_t launch_step(const StepArgs &a, const StepArgs *dA, int fp64, int mode
         hipLaunchKernelGGL((k_step<float, true>), tiles_grid(a), dim3(WG_THREADS), 0, s, dA, mode, write_full);
     else
         hipLaunchKernelGGL((k_step<float, false>), tiles_grid(a), dim3(WG_THREADS), 0, s, dA, mode, write_full);
-    return hipGetLastError();
-}
-
-template <typename real, bool energy>
-static void launch_excl_t(const StepArgs &a, const StepArgs *dA, int which, unsigned nb, hipStream_t s)
-{
-    if (a.g.any_open)
-        hipLaunchKernelGGL((k_excl<real, energy, true>), dim3(nb), dim3(EXCL_THREADS), 0, s, dA, a.b.srec, a.b.sid,
-                           a.b.scell, a.b.start, which);
-    else
-        hipLaunchKernelGGL((k_excl<real, energy, false>), dim3(nb), dim3(EXCL_THREADS), 0, s, dA, a.b.srec, a.b.sid,
-                           a.b.scell, a.b.start, which);
-}
-
-hipError_t launch_excl(const StepArgs &a, const StepArgs *dA, int fp64, int energy, int which, hipStream_t s)
-{
-    // whole groups of 8 workgroups: the kernel hands each XCD one contiguous
-    // eighth of the sorted records
-    const unsigned nb = (unsigned)(((a.n_nt + EXCL_THREADS - 1) / EXCL_THREADS + 7) / 8 * 8);
-    if (fp64) {
-        if (energy) launch_excl_t<double, true>(a, dA, which, nb, s);
-        else launch_excl_t<double, false>(a, dA, which, nb, s);
-    } else {
-        if (energy) launch_excl_t<float, true>(a, dA, which, nb, s);
-        else launch_excl_t<float, false>(a, dA, which, nb, s);
-    }
     return hipGetLastError();
 }
 

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EBOND", 5: 
 TERMS = ("excl", "bond", "stack", "hbond", "twist", "planar", "bend", "ext")
 NTERMS = len(TERMS)
 NENERGY = NTERMS + 2
-KERNELS = ("step", "scan", "scatter", "excl")
+KERNELS = ("step", "scan", "scatter", "excl", "bin", "build")
 
 # every symbol include/dsdna.h declares
 EXPORTS = (
@@ -30,7 +30,8 @@ EXPORTS = (
     "dsdna_set_velocities", "dsdna_thermalize", "dsdna_step", "dsdna_get_state", "dsdna_set_state",
     "dsdna_get_resume", "dsdna_set_resume", "dsdna_get_sites", "dsdna_get_forces", "dsdna_get_energies",
     "dsdna_get_bp_open", "dsdna_get_bubbles", "dsdna_profile_kernels", "dsdna_get_grid", "dsdna_autotune",
-    "dsdna_set_circular", "dsdna_get_linking", "dsdna_set_k2_bp",
+    "dsdna_set_circular", "dsdna_get_linking", "dsdna_set_k2_bp", "dsdna_get_sizes",
+    "dsdna_get_neighbour_stats",
 )
 
 
@@ -48,7 +49,7 @@ class Params(C.Structure):
         ("seed", C.c_uint64), ("noise_kind", C.c_int32), ("force_fp64", C.c_int32),
         ("ssdna_rule", C.c_int32), ("hb_depth_convention", C.c_int32), ("cell_size", C.c_double),
         ("hash_log2", C.c_int32), ("graph_steps", C.c_int32), ("fene_clamp", C.c_int32),
-        ("dihedral_damping", C.c_int32)]
+        ("dihedral_damping", C.c_int32), ("skin", C.c_double), ("list_capacity", C.c_int64)]
 
 
 _lib = None
@@ -91,6 +92,8 @@ def lib():
             "dsdna_set_circular": [vp, vp],
             "dsdna_set_k2_bp": [vp, vp],
             "dsdna_get_linking": [vp, vp, vp, vp],
+            "dsdna_get_sizes": [vp, vp, vp, vp],
+            "dsdna_get_neighbour_stats": [vp, vp, vp, vp, vp],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
@@ -106,11 +109,31 @@ def _p(a):
     return None if a is None else a.ctypes.data
 
 
-def _f64(a, shape=None):
+def _f64(a, shape=None, name="array"):
+    """A C-contiguous float64 copy or view of `a` with exactly `shape`
+    (None stays None: the C side takes NULL)."""
+    if a is None:
+        return None
     a = np.ascontiguousarray(a, dtype=np.float64)
-    if shape is not None:
-        a = a.reshape(shape)
+    if shape is not None and a.shape != tuple(shape):
+        raise ValueError("%s has shape %s, expected %s" % (name, a.shape, tuple(shape)))
     return a
+
+
+def _arr(a, dtype, shape, name):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=dtype)
+    if a.shape != tuple(shape):
+        raise ValueError("%s has shape %s, expected %s" % (name, a.shape, tuple(shape)))
+    return a
+
+
+def _sizes(ctx):
+    """(n_rep, n_nt, n_bp_total) of the context's topology."""
+    nr, nn, nb = C.c_int32(), C.c_int64(), C.c_int64()
+    _check(ctx, lib().dsdna_get_sizes(ctx, C.byref(nr), C.byref(nn), C.byref(nb)))
+    return nr.value, nn.value, nb.value
 
 
 # ------------------------------------------------------------ entry points
@@ -151,29 +174,30 @@ def dsdna_set_topology(ctx, n_bp):
 
 
 def dsdna_set_box(ctx, lo_hi, periodic):
-    b = _f64(lo_hi).reshape(-1, 6)
-    p = np.ascontiguousarray(periodic, dtype=np.uint8).reshape(-1, 3)
+    nr = _sizes(ctx)[0]
+    b = _f64(lo_hi, (nr, 6), "lo_hi")
+    p = _arr(periodic, np.uint8, (nr, 3), "periodic")
     _check(ctx, lib().dsdna_set_box(ctx, _p(b), _p(p)))
 
 
 def dsdna_set_external(ctx, rep, F=(0, 0, 0), G=(0, 0, 0), tether=0, wall_z=0.0):
-    f = _f64(F, (3,))
-    g = _f64(G, (3,))
+    f = _f64(F, (3,), "F")
+    g = _f64(G, (3,), "G")
     _check(ctx, lib().dsdna_set_external(ctx, int(rep), _p(f), _p(g), int(tether), float(wall_z)))
 
 
 def dsdna_set_k2_scale(ctx, scale):
-    s = _f64(np.atleast_1d(scale))
+    s = _f64(np.atleast_1d(scale), (_sizes(ctx)[0],), "scale")
     _check(ctx, lib().dsdna_set_k2_scale(ctx, _p(s)))
 
 
 def dsdna_set_k2_bp(ctx, scale):
-    s = None if scale is None else _f64(np.ravel(scale))
+    s = None if scale is None else _f64(scale, (_sizes(ctx)[2],), "scale")
     _check(ctx, lib().dsdna_set_k2_bp(ctx, _p(s)))
 
 
 def dsdna_set_circular(ctx, circular):
-    c = np.ascontiguousarray(np.atleast_1d(circular), dtype=np.uint8)
+    c = _arr(np.atleast_1d(circular), np.uint8, (_sizes(ctx)[0],), "circular")
     _check(ctx, lib().dsdna_set_circular(ctx, _p(c)))
 
 
@@ -191,12 +215,14 @@ def dsdna_set_temperature(ctx, kT):
 
 
 def dsdna_set_sites(ctx, bead, patch):
-    b, p = _f64(bead), _f64(patch)
+    n = _sizes(ctx)[1]
+    b, p = _f64(bead, (n, 3), "bead"), _f64(patch, (n, 3), "patch")
     _check(ctx, lib().dsdna_set_sites(ctx, _p(b), _p(p)))
 
 
 def dsdna_set_velocities(ctx, V, L):
-    v, l = _f64(V), _f64(L)
+    n = _sizes(ctx)[1]
+    v, l = _f64(V, (n, 3), "V"), _f64(L, (n, 3), "L")
     _check(ctx, lib().dsdna_set_velocities(ctx, _p(v), _p(l)))
 
 
@@ -216,7 +242,9 @@ def dsdna_get_state(ctx, n_nt):
 
 
 def dsdna_set_state(ctx, R, V, u, L, step):
-    R, V, u, L = (_f64(x) for x in (R, V, u, L))
+    """V and L may be None (zero velocities)."""
+    n = _sizes(ctx)[1]
+    R, V, u, L = (_f64(x, (n, 3), nm) for x, nm in ((R, "R"), (V, "V"), (u, "u"), (L, "L")))
     _check(ctx, lib().dsdna_set_state(ctx, _p(R), _p(V), _p(u), _p(L), int(step)))
 
 
@@ -228,7 +256,9 @@ def dsdna_get_resume(ctx, n_nt):
 
 
 def dsdna_set_resume(ctx, R, V, u, L, fb, fp, step):
-    R, V, u, L, fb, fp = (_f64(x) for x in (R, V, u, L, fb, fp))
+    n = _sizes(ctx)[1]
+    R, V, u, L, fb, fp = (_f64(x, (n, 3), nm) for x, nm in
+                          ((R, "R"), (V, "V"), (u, "u"), (L, "L"), (fb, "f_bead"), (fp, "f_patch")))
     _check(ctx, lib().dsdna_set_resume(ctx, _p(R), _p(V), _p(u), _p(L), _p(fb), _p(fp), int(step)))
 
 
@@ -268,6 +298,19 @@ def dsdna_profile_kernels(ctx, n_steps):
     ms = np.zeros(len(KERNELS))
     _check(ctx, lib().dsdna_profile_kernels(ctx, int(n_steps), _p(ms)))
     return dict(zip(KERNELS, ms))
+
+
+def dsdna_get_sizes(ctx):
+    """(n_rep, n_nt, n_bp_total)."""
+    return _sizes(ctx)
+
+
+def dsdna_get_neighbour_stats(ctx):
+    """Since the last state change: dict of rebuilds, steps, pairs (in the
+    current list) and skin."""
+    rb, st, pr, sk = C.c_int64(), C.c_int64(), C.c_int64(), C.c_double()
+    _check(ctx, lib().dsdna_get_neighbour_stats(ctx, C.byref(rb), C.byref(st), C.byref(pr), C.byref(sk)))
+    return {"rebuilds": rb.value, "steps": st.value, "pairs": pr.value, "skin": sk.value}
 
 
 def dsdna_get_grid(ctx):
@@ -371,6 +414,9 @@ class DsDNA:
 
     def grid(self):
         return dsdna_get_grid(self.ctx)
+
+    def neighbour_stats(self):
+        return dsdna_get_neighbour_stats(self.ctx)
 
     def autotune(self, cell_sizes, hash_log2s, trial_steps):
         return dsdna_autotune(self.ctx, cell_sizes, hash_log2s, trial_steps)

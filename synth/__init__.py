@@ -305,3 +305,58 @@ def config_denaturation(n_rep=64, n_bp=2000, seed=4):
     return dict(n_bp=lens, bead=bead, patch=patch,
                 box=np.tile([-big, -big, -big, big, big, big], (n_rep, 1)).astype(np.float64),
                 periodic=np.zeros((n_rep, 3), np.uint8), k2_scale=scale)
+
+
+def helix_on_curve(points, phase0=0.0):
+    """Duplex whose patches sit on the given axis points (consecutive points a
+    rise apart): tangents by central differences, the twist frame
+    parallel-transported from point to point (the normal is rotated with the
+    tangent by the smallest rotation)."""
+    p = np.asarray(points, dtype=np.float64)
+    t = np.gradient(p, axis=0)
+    t /= np.linalg.norm(t, axis=1, keepdims=True)
+    e1 = np.empty_like(p)
+    _, e1[0], _ = _frame(t[0])
+    for k in range(1, len(p)):
+        a, b = t[k - 1], t[k]
+        ax = np.cross(a, b)
+        s, c = np.linalg.norm(ax), float(np.dot(a, b))
+        v = e1[k - 1]
+        if s > 1e-15:
+            ax /= s
+            v = v * c + np.cross(ax, v) * s + ax * np.dot(ax, v) * (1.0 - c)
+        v = v - b * np.dot(v, b)
+        e1[k] = v / np.linalg.norm(v)
+    return helix_on_axis(p, t, e1, phase0)
+
+
+def crossing_loop(sep, rho=8.0, arm=10.0, phase0=0.0, origin=(0.0, 0.0, 0.0)):
+    """A duplex whose axis makes one loop and crosses itself at right angles:
+    it runs along +y at height +sep/2 through `origin`, turns 270 degrees
+    counter-clockwise on a circle of radius rho while descending to -sep/2,
+    and leaves along +x through `origin`.  The two straight arms (each `arm`
+    beyond the crossing) pass each other with axis separation `sep` there and
+    nowhere else.  Axis points are a rise apart; returns (bead, patch, n_bp)."""
+    o = np.asarray(origin, dtype=np.float64)
+    h = 0.5 * sep
+    pts = []
+    # arm 1: from y = -arm to y = rho at z = +h
+    L1 = arm + rho
+    n1 = int(round(L1 / RISE))
+    for k in range(n1):
+        pts.append([0.0, -arm + k * L1 / n1, h])
+    # the loop: centre (-rho, rho), angle 0 -> 270 deg, z from +h to -h
+    arc = 1.5 * math.pi * rho
+    la = math.hypot(arc, 2.0 * h)
+    na = int(round(la / RISE))
+    for k in range(na):
+        ph = 1.5 * math.pi * k / na
+        pts.append([-rho + rho * math.cos(ph), rho + rho * math.sin(ph), h - 2.0 * h * k / na])
+    # arm 2: from x = -rho to x = arm at z = -h (y = 0)
+    L2 = arm + rho
+    n2 = int(round(L2 / RISE))
+    for k in range(n2 + 1):
+        pts.append([-rho + k * L2 / n2, 0.0, -h])
+    pts = np.asarray(pts) + o[None, :]
+    bead, patch = helix_on_curve(pts, phase0)
+    return bead, patch, len(pts)

@@ -65,7 +65,7 @@ def test_forces_and_energies_1mbp(run):
 def test_forces_identical_on_another_grid(run):
     D, cfg, sim, (R, V, u, L, k) = run
     ref = [np.concatenate(sim.forces(t)) for t in (0, -1)]
-    other = D.DsDNA(cfg, D.dsdna_default_params(seed=0, cell_size=1.2, hash_log2=22))
+    other = D.DsDNA(cfg, D.dsdna_default_params(seed=0, cell_size=1.9, hash_log2=22, skin=0.7))
     other.set_state(R, V, u, L, k)
     got = [np.concatenate(other.forces(t)) for t in (0, -1)]
     other.close()

@@ -130,8 +130,8 @@ def test_forces_periodic_box(D):
     """A compressed duplex in a periodic box: it straddles the x and y faces
     (wrapped cells, minimum image) and its two ends meet across the z face
     (contacts through the periodic seam).  Forces agree with the oracle at
-    several cell sizes and bucket counts, and are identical bit for bit across
-    them (order-independent accumulation)."""
+    several cell sizes, neighbour-list skins and bucket counts, and are
+    identical bit for bit across them (order-independent accumulation)."""
     n = 301
     d = np.array([0.004, 0.003, 1.0])
     d /= np.linalg.norm(d)
@@ -147,9 +147,9 @@ def test_forces_periodic_box(D):
     seam = [(i, j) for i, j in pairs if abs(b[i, 2] - b[j, 2]) > box[0, 5] / 2]
     assert len(pairs) > 100 and len(seam) >= 1
     ref = None
-    for cell in (1.1235, 1.3, 1.83):
+    for cell, skin in ((0.0, 0.0), (1.83, 0.3), (2.4, 1.0)):
         for lg in (12, 16):
-            sim = _gpu(D, cfg, cell_size=cell, hash_log2=lg)
+            sim = _gpu(D, cfg, cell_size=cell, hash_log2=lg, skin=skin)
             _compare_terms(D, sim, P, S, R, u, 1e-5, use_cells=True)
             f = np.concatenate(sim.forces(0))
             if ref is None:
@@ -161,24 +161,28 @@ def test_forces_periodic_box(D):
 @pytest.mark.parametrize("fp64", [0, 1])
 def test_open_box_far_records(D, fp64):
     """Open edges: the 32-bit neighbour coordinates repeat every 256 length
-    units.  In a straight compressed duplex (rise 0.30, radius 0.3) steric
-    beads 17,070 bp apart sit at the same helical phase 5121.0 apart along the
-    axis; with cell edge 1.25 and 2^12 buckets many of their cells (4096 apart)
-    share a bucket, and their wrapped coordinates are 1.0 apart, inside the
-    steric cutoff.  No force may come from such a record."""
-    n, gap = 17200, 17070
-    bead, patch = synth.ideal_helix(n, rise=0.30, radius=0.3)
-    assert abs((bead[2 * gap, 2] - bead[0, 2]) - 5121.0) < 1e-6 and gap % 30 == 0
+    units.  In a straight compressed duplex (radius 0.3, rise chosen so that
+    23,040 bp are 6913.0 nm) steric beads 23,040 bp apart sit at the same
+    helical phase 6913.0 apart along the axis; with cell edge 6913/4096 and
+    2^12 buckets many of their cells (4096 apart) share a bucket, and their
+    wrapped coordinates are 1.0 apart, inside the steric cutoff.  No force may
+    come from such a record."""
+    gap, span = 23040, 6913.0
+    n = gap + 160
+    rise = span / gap
+    bead, patch = synth.ideal_helix(n, rise=rise, radius=0.3)
+    assert abs((bead[2 * gap, 2] - bead[0, 2]) - span) < 1e-6 and gap % 30 == 0
+    cell = span / 4096.0
     cfg = dict(n_bp=np.array([n]), bead=bead, patch=patch)
     P = O.default_params()
     S = O.System([n])
     R, u = O.bodies_from_sites(P, bead, patch)
     b, p = O.sites_from_bodies(P, R, u)
-    cz = np.floor(b[:, 2] / 1.25).astype(np.int64)
+    cz = np.floor(b[:, 2] / cell).astype(np.int64)
     assert np.sum(cz[2 * gap::6] - cz[:2 * (n - gap):6] == 4096) >= 5  # steric strand-0 pairs
     st, _, fb, fp, _, _ = O.forces(P, S, b, p, use_cells=True)
     assert st == O.OK
-    sim = _gpu(D, cfg, cell_size=1.25, hash_log2=12, force_fp64=fp64)
+    sim = _gpu(D, cfg, cell_size=cell, hash_log2=12, force_fp64=fp64)
     gb, gp = sim.forces("excl")
     ref = fb[O.T["excl"]]
     scale = np.abs(ref).max()
@@ -213,11 +217,11 @@ def test_replicas_with_loads(D):
 def test_tiny_and_tile_edge_chains(D):
     """Chains of 1-4 base pairs, where the terms that would reach past an end
     are absent (a 1 bp chain has only its hydrogen bond, 2 bp no bending), and
-    chains one short of, exactly at and one past one and two tiles of 124 bp,
+    chains one short of, exactly at and one past one and two tiles of 122 bp,
     batched in one context from an oracle-thermalised state: every term, the
     open flags and the per-replica energies, with FP32 and FP64 forces; then
     50 FP64 steps against the oracle's trajectory."""
-    lens = [1, 2, 3, 4, 123, 124, 125, 248, 249]
+    lens = [1, 2, 3, 4, 121, 122, 123, 244, 245]
     parts = [synth.ideal_helix(m, origin=(12.0 * k, 0.0, 0.0)) for k, m in enumerate(lens)]
     bead, patch = synth.concat_replicas(parts)
     cfg = dict(n_bp=np.array(lens), bead=bead, patch=patch)

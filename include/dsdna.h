@@ -156,7 +156,8 @@ dsdna_status dsdna_default_params(dsdna_params *out);
 dsdna_status dsdna_create(dsdna_ctx **out, const dsdna_params *params, int device,
                           void *hip_stream);
 dsdna_status dsdna_destroy(dsdna_ctx *ctx);
-/* Description of the last failure on this context ("" if none). */
+/* Description of the last failure on this context ("" if none); with NULL,
+ * of the last failed context-free call on this thread. */
 const char *dsdna_last_error(const dsdna_ctx *ctx);
 
 /* Sizes of the current topology: replicas, nucleotides (2 sum n_bp) and base
@@ -309,6 +310,30 @@ dsdna_status dsdna_get_grid(dsdna_ctx *ctx, double *cell_size, int64_t *n_bucket
 dsdna_status dsdna_autotune(dsdna_ctx *ctx, int32_t n, const double *cell_sizes, int32_t m,
                             const int32_t *hash_log2s, int64_t trial_steps, double *best_cell,
                             int32_t *best_hash_log2);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * linking number and writhe of one ring given as three closed curves, the
+ * computation dsdna_get_linking performs for the rings of a context, with no
+ * context and no allocation.  Its per-workgroup partial sums live in a fixed
+ * device array inside the library (2 doubles per 256 points, at most
+ * DSDNA_NOALLOC_MAX_POINTS points: 64 KiB per GPU, held until the process
+ * ends).
+ *   A, B: DEVICE pointers to the two strand curves, C: to the centreline,
+ *         each n points [n][3] of FP64, closed (point n-1 joins point 0);
+ *   out:  DEVICE pointer to 2 doubles, receives Lk(A, B) and Wr(C) as
+ *         dsdna_get_linking defines them;
+ *   stream: hipStream_t of the current device (NULL: the null stream).
+ * Runs on the current HIP device, asynchronously on `stream`; the caller
+ * keeps the buffers alive until the work completes.  Calls whose work
+ * overlaps on one GPU share the fixed array and race: serialise them (one
+ * stream, or events).  The first call on each device resolves the array's
+ * address; make it outside a stream capture.  n outside [3,
+ * DSDNA_NOALLOC_MAX_POINTS] or a NULL pointer is DSDNA_EINVAL,
+ * dsdna_last_error(NULL) describes the failure. */
+#define DSDNA_NOALLOC_MAX_POINTS 1048576
+dsdna_status dsdna_linking_curves_noalloc(const double *A, const double *B, const double *C, int64_t n,
+                                          double *out, void *stream);
 
 #ifdef __cplusplus
 }

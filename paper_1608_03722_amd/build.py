@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdsdna.so")
-SOURCES = [os.path.join(CSRC, "dsdna_kernels.hip"), os.path.join(CSRC, "dsdna_api.cpp")]
+SOURCES = [os.path.join(CSRC, "dsdna_kernels.hip"), os.path.join(CSRC, "dsdna_api.cpp"),
+           os.path.join(CSRC, "dsdna_noalloc.hip")]
 HEADERS = [os.path.join(ROOT, "include", "dsdna.h"), os.path.join(CSRC, "dsdna_dev.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -79,6 +79,19 @@ struct dsdna_ctx {
 
 // ------------------------------------------------------------------ helpers
 
+// Last failure of a context-free call on this thread.
+static thread_local std::string g_free_error = "null context";
+
+void dsdna::set_free_error(const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_free_error = buf;
+}
+
 static dsdna_status fail(dsdna_ctx *c, dsdna_status st, const char *fmt, ...)
 {
     char buf[512];
@@ -828,7 +841,7 @@ dsdna_status dsdna_destroy(dsdna_ctx *c)
     return DSDNA_OK;
 }
 
-const char *dsdna_last_error(const dsdna_ctx *c) { return c ? c->err.c_str() : "null context"; }
+const char *dsdna_last_error(const dsdna_ctx *c) { return c ? c->err.c_str() : g_free_error.c_str(); }
 
 static dsdna_status build_topology(dsdna_ctx *c, int32_t n_rep, const int32_t *n_bp, int64_t N);
 

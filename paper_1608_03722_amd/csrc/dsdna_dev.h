@@ -241,6 +241,15 @@ hipError_t launch_diag(const StepArgs &a, const StepArgs *dA, int which, int fp6
 // doubles) and partial ([n_blocks][2]) are scratch, out[n_rings][2]
 // receives (Lk, Wr).  blocks[n_blocks] = (ring, first bp).  ev0/ev1 (may be
 // null) bracket the pair kernel.
+// The same for one ring given as three closed curves A, B, C of n points
+// ([n][3] doubles each, device memory): partial holds 2 ceil(n /
+// LK_THREADS) doubles, out[2] receives (Lk(A, B), Wr(C)).
+hipError_t launch_linking_curves(const double *A, const double *B, const double *C, int n, double *partial,
+                                 double *out, hipStream_t s);
+// Message of the last failure of a context-free call on this thread (read by
+// dsdna_last_error(NULL)); printf-style.
+void set_free_error(const char *fmt, ...);
+
 hipError_t launch_linking(const StepArgs *dA, int which, const RingSeg *rings, int n_rings, const int2 *blocks,
                           int n_blocks, int n_pts, double *curves, double *partial, double *out, hipStream_t s,
                           hipEvent_t ev0, hipEvent_t ev1);

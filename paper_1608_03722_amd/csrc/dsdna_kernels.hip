@@ -1772,29 +1772,23 @@ __device__ __forceinline__ double pair_omega(D3 p1, D3 p2, D3 p3, D3 p4)
     return 2.0 * atan2(y1 * x2 + y2 * x1, x1 * x2 - y1 * y2);
 }
 
-// Row sums of the segment-pair solid angles: thread i of a workgroup holds
-// segment i -> i+1 (mod n) of the strand 0 curve and of the centreline; the
-// strand 1 curve and the centreline stream through LDS in chunks of
-// LK_THREADS segments.  Per workgroup: sum over its rows of Omega(A_i, B_j)
-// over all j (the linking number) and of Omega(C_i, C_j) over the half
-// window of j whose segment shares no vertex with segment i, j - i = 2 ..
-// n/2 (mod n), the antipodal j - i = n/2 of an even ring only from i < n/2
-// (the writhe, each unordered pair once), reduced in a fixed order to
-// partial[block][2].
-__global__ void __launch_bounds__(LK_THREADS) k_gauss(const RingSeg *__restrict__ rings, const int2 *__restrict__ blocks,
-                                                     int n_pts, const double *__restrict__ curves,
-                                                     double *__restrict__ partial)
+// Row sums of the segment-pair solid angles of one ring, for the rows
+// i0 .. i0 + LK_THREADS - 1: thread i holds segment i -> i+1 (mod n) of
+// curve A (strand 0) and of the centreline C; curve B (strand 1) and the
+// centreline stream through LDS in chunks of LK_THREADS segments.  Sum over
+// the rows of Omega(A_i, B_j) over all j (the linking number) and of
+// Omega(C_i, C_j) over the half window of j whose segment shares no vertex
+// with segment i, j - i = 2 .. n/2 (mod n), the antipodal j - i = n/2 of an
+// even ring only from i < n/2 (the writhe, each unordered pair once),
+// reduced in a fixed order to part[2].  Called by all threads of a workgroup.
+__device__ void gauss_rows(const double *__restrict__ cA, const double *__restrict__ cB,
+                           const double *__restrict__ cC, int n, int i0, double *__restrict__ part)
 {
     __shared__ double sB[LK_THREADS + 1][3];
     __shared__ double sC[LK_THREADS + 1][3];
     __shared__ double red[LK_THREADS][2];
     const int t = threadIdx.x;
-    const int2 blk = blocks[blockIdx.x];
-    const RingSeg rg = rings[blk.x];
-    const int n = rg.n_bp;
-    const double *cA = curves + 3 * (int64_t)rg.pt0;
-    const double *cB = cA + 3 * (int64_t)n_pts, *cC = cB + 3 * (int64_t)n_pts;
-    const int i = blk.y + t;
+    const int i = i0 + t;
     const bool row = i < n;
     const int i1 = i + 1 == n ? 0 : i + 1;
     D3 a0 = v3(0.0, 0.0, 0.0), a1 = a0, c0 = a0, c1 = a0;
@@ -1834,28 +1828,63 @@ __global__ void __launch_bounds__(LK_THREADS) k_gauss(const RingSeg *__restrict_
         }
     }
     if (t == 0) {
-        partial[2 * blockIdx.x] = red[0][0];
-        partial[2 * blockIdx.x + 1] = red[0][1];
+        part[0] = red[0][0];
+        part[1] = red[0][1];
     }
+}
+
+// Rings of a context: one workgroup per block of LK_THREADS base pairs of
+// one ring (the curves of k_curves), partial[block][2].
+__global__ void __launch_bounds__(LK_THREADS) k_gauss(const RingSeg *__restrict__ rings, const int2 *__restrict__ blocks,
+                                                     int n_pts, const double *__restrict__ curves,
+                                                     double *__restrict__ partial)
+{
+    const int2 blk = blocks[blockIdx.x];
+    const RingSeg rg = rings[blk.x];
+    const double *cA = curves + 3 * (int64_t)rg.pt0;
+    const double *cB = cA + 3 * (int64_t)n_pts, *cC = cB + 3 * (int64_t)n_pts;
+    gauss_rows(cA, cB, cC, rg.n_bp, blk.y, partial + 2 * blockIdx.x);
 }
 
 // Per ring, in block order: Lk = (sum of its rows) / (4 pi) and Wr twice the
 // sum of its rows over 4 pi (the rows hold each unordered pair once, the
 // integral over the torus counts it twice).
+__device__ __forceinline__ void gauss_total(const double *__restrict__ partial, int blk0, int n_blk,
+                                            double *__restrict__ out)
+{
+    double lk = 0.0, wr = 0.0;
+    for (int b = 0; b < n_blk; ++b) {
+        lk += partial[2 * (blk0 + b)];
+        wr += partial[2 * (blk0 + b) + 1];
+    }
+    const double k = 0.25 / 3.14159265358979323846;
+    out[0] = lk * k;
+    out[1] = 2.0 * wr * k;
+}
+
 __global__ void __launch_bounds__(64) k_gauss_sum(const RingSeg *__restrict__ rings, int n_rings,
                                                  const double *__restrict__ partial, double *__restrict__ out)
 {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n_rings) return;
     const RingSeg rg = rings[r];
-    double lk = 0.0, wr = 0.0;
-    for (int b = 0; b < rg.n_blk; ++b) {
-        lk += partial[2 * (rg.blk0 + b)];
-        wr += partial[2 * (rg.blk0 + b) + 1];
-    }
-    const double k = 0.25 / 3.14159265358979323846;
-    out[2 * r] = lk * k;
-    out[2 * r + 1] = 2.0 * wr * k;
+    gauss_total(partial, rg.blk0, rg.n_blk, out + 2 * r);
+}
+
+// One ring given as three closed curves of n points each (A, B: the two
+// strands; C: the centreline): workgroup b takes the rows from b LK_THREADS
+// on; then the fixed-order total.
+__global__ void __launch_bounds__(LK_THREADS) k_gauss_curves(const double *__restrict__ A, const double *__restrict__ B,
+                                                            const double *__restrict__ C, int n,
+                                                            double *__restrict__ partial)
+{
+    gauss_rows(A, B, C, n, (int)blockIdx.x * LK_THREADS, partial + 2 * blockIdx.x);
+}
+
+__global__ void __launch_bounds__(64) k_gauss_curves_sum(const double *__restrict__ partial, int n_blk,
+                                                        double *__restrict__ out)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) gauss_total(partial, 0, n_blk, out);
 }
 
 // --------------------------------------------------------------- diagnostics
@@ -1996,6 +2025,15 @@ hipError_t launch_diag(const StepArgs &a, const StepArgs *dA, int which, int fp6
         hipLaunchKernelGGL((k_diag<float, true>), tiles_grid(a), dim3(WG_THREADS), 0, s, dA, which, term_mask);
     else
         hipLaunchKernelGGL((k_diag<float, false>), tiles_grid(a), dim3(WG_THREADS), 0, s, dA, which, term_mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_linking_curves(const double *A, const double *B, const double *C, int n, double *partial,
+                                 double *out, hipStream_t s)
+{
+    const int n_blk = (n + LK_THREADS - 1) / LK_THREADS;
+    hipLaunchKernelGGL(k_gauss_curves, dim3(n_blk), dim3(LK_THREADS), 0, s, A, B, C, n, partial);
+    hipLaunchKernelGGL(k_gauss_curves_sum, dim3(1), dim3(64), 0, s, partial, n_blk, out);
     return hipGetLastError();
 }
 

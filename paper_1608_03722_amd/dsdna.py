@@ -31,8 +31,9 @@ EXPORTS = (
     "dsdna_get_resume", "dsdna_set_resume", "dsdna_get_sites", "dsdna_get_forces", "dsdna_get_energies",
     "dsdna_get_bp_open", "dsdna_get_bubbles", "dsdna_profile_kernels", "dsdna_get_grid", "dsdna_autotune",
     "dsdna_set_circular", "dsdna_get_linking", "dsdna_set_k2_bp", "dsdna_get_sizes",
-    "dsdna_get_neighbour_stats",
+    "dsdna_get_neighbour_stats", "dsdna_linking_curves_noalloc",
 )
+NOALLOC_MAX_POINTS = 1048576
 
 
 class DsdnaError(RuntimeError):
@@ -94,6 +95,7 @@ def lib():
             "dsdna_get_linking": [vp, vp, vp, vp],
             "dsdna_get_sizes": [vp, vp, vp, vp],
             "dsdna_get_neighbour_stats": [vp, vp, vp, vp, vp],
+            "dsdna_linking_curves_noalloc": [vp, vp, vp, i64, vp, vp],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
@@ -298,6 +300,15 @@ def dsdna_profile_kernels(ctx, n_steps):
     ms = np.zeros(len(KERNELS))
     _check(ctx, lib().dsdna_profile_kernels(ctx, int(n_steps), _p(ms)))
     return dict(zip(KERNELS, ms))
+
+
+def dsdna_linking_curves_noalloc(A, B, C, n, out, stream=None):
+    """Lk(A, B) and Wr(C) of three closed curves of n points into out[2]; A, B,
+    C and out are DEVICE addresses (ints, e.g. torch's data_ptr()), stream a
+    hipStream_t handle or None.  Allocates nothing; asynchronous."""
+    st = lib().dsdna_linking_curves_noalloc(A, B, C, int(n), out, stream)
+    if st != OK:
+        raise DsdnaError(st, lib().dsdna_last_error(None).decode())
 
 
 def dsdna_get_sizes(ctx):

@@ -701,17 +701,19 @@ def main():
     sim.thermalize(1.0, 0)
     tuned = None
     if not args.no_autotune and args.cell == 0.0 and args.hash_log2 == 0:
-        # cell edges from just above the search reach (largest cutoff plus
-        # skin), bucket counts around four per bead; the trial steps are part
-        # of the warm-up
+        # skins and cell edges (factors of the search reach), bucket counts
+        # around four per bead; the trial steps are part of the warm-up
         base = int(np.ceil(np.log2(4 * n_nt)))
         lgs = [lg for lg in (base - 1, base, base + 1) if 12 <= lg <= 24]
-        reach = 2 ** (1 / 6) + (prm.skin or 0.5) + 1e-4
-        cells_try = [round(reach * f, 4) for f in (1.001, 1.08, 1.2)]
+        skins = [0.5, 1.0, 1.5]
+        facs = [1.001, 1.1]
         t0 = time.perf_counter()
-        bc, bl = sim.autotune(cells_try, lgs, 30)
-        tuned = {"cells": cells_try, "hash_log2": lgs, "trial_steps": 30, "cell": bc, "hash_log2_best": bl}
-        log("autotune: cell %.4f, 2^%d buckets (%.1f s)" % (bc, bl, time.perf_counter() - t0))
+        tuned = sim.autotune(skins=skins, cell_factors=facs, hash_log2s=lgs, warm_steps=300, trial_steps=200)
+        tuned.update({"skins": skins, "cell_factors": facs, "hash_log2s": lgs, "warm_steps": 300,
+                      "trial_steps": 200, "seconds": round(time.perf_counter() - t0, 2)})
+        log("autotune: skin %.2f, cell %.4f, 2^%d buckets, interval %d (%d candidates, %.1f s)"
+            % (tuned["skin"], tuned["cell_size"], tuned["hash_log2"], tuned["interval"], tuned["candidates"],
+               tuned["seconds"]))
     h, nb, cells = sim.grid()
     log("grid: cell %.4f, %d buckets, cells %s" % (h, nb, list(cells)))
 
@@ -768,8 +770,9 @@ def main():
     # state change, which precedes the warm-up)
     rebuild_rate = ((ns1["rebuilds"] - ns0["rebuilds"]) / max(1, ns1["steps"] - ns0["steps"])
                     if failure is None else float("nan"))
-    log("neighbour list: skin %.3g, %d pairs, a rebuild every %.1f steps"
-        % (ns1["skin"], ns1["pairs"], 1.0 / rebuild_rate if rebuild_rate > 0 else float("inf")))
+    log("neighbour list: skin %.3g, %d pairs, a rebuild every %.1f steps (interval %d), %d outruns"
+        % (ns1["skin"], ns1["pairs"], 1.0 / rebuild_rate if rebuild_rate > 0 else float("inf"), ns1["interval"],
+           ns1["outruns"] - ns0["outruns"]))
 
     # per-kernel durations with HIP events around every launch, on the
     # stream the kernels run on (means per step; a rebuild kernel's mean
@@ -808,7 +811,8 @@ def main():
                            "frac": round(whole_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                            "note": "algorithmic bytes of every kernel of a step (rebuilds at the measured "
                                    "rate) over the wall-clock time per step"},
-            "neighbour_list": {"skin": ns1["skin"], "pairs": pairs, "rebuilds_per_step": rebuild_rate},
+            "neighbour_list": {"skin": ns1["skin"], "pairs": pairs, "rebuilds_per_step": rebuild_rate,
+                               "interval": ns1["interval"], "outruns": ns1["outruns"] - ns0["outruns"]},
             "kernels": kernels}
     if not args.no_copy_ceiling:
         ceil = copy_ceiling(torch, dev)

@@ -291,25 +291,57 @@ dsdna_status dsdna_profile_kernels(dsdna_ctx *ctx, int64_t n_steps, double *ms);
 /* Neighbour list (Sec. 6: short-range neighbour search without O(N^2)
  * loops): bead pairs more than 3 base pairs apart along the chain within
  * their WCA cutoff plus the skin, rebuilt from a counting-sort cell list
- * whenever a bead has moved half the skin.  Since the last state change
- * (set_sites, set_state, thermalize, ...): rebuilds (including the one that
- * preceded the first step), steps taken, pairs in the current list, and the
- * skin in use.  Any pointer may be NULL. */
-dsdna_status dsdna_get_neighbour_stats(dsdna_ctx *ctx, int64_t *rebuilds, int64_t *steps, int64_t *pairs,
-                                       double *skin);
+ * every `interval` steps.  The interval adapts so that no bead moves three
+ * quarters of half the skin between rebuilds; a bead that moves half the
+ * skin before its rebuild (an outrun) stops the queued steps, and the list
+ * is rebuilt there and the run continues (the results do not depend on the
+ * skin or the interval).  Since the last state change (set_sites, set_state,
+ * thermalize, ...): rebuilds (including the one that preceded the first
+ * step), steps taken, outruns; and now: pairs in the list, the skin, the
+ * interval.  Any pointer may be NULL. */
+dsdna_status dsdna_get_neighbour_stats(dsdna_ctx *ctx, int64_t *rebuilds, int64_t *steps, int64_t *outruns,
+                                       int64_t *pairs, double *skin, int32_t *interval);
 
 /* Sizes chosen for the cell list: cell edge, number of hash buckets and
  * cells per periodic dimension of replica 0 (cells[3], 0 for open). */
 dsdna_status dsdna_get_grid(dsdna_ctx *ctx, double *cell_size, int64_t *n_buckets,
                             int32_t *cells);
 
-/* Try cell edges cell_sizes[n] (each >= the largest WCA cutoff) and bucket
- * counts 2^hash_log2s[m] for `trial_steps` steps each on the current state,
- * keep the fastest, and report it in best_cell / best_hash_log2.  Trial
- * steps advance the state. */
-dsdna_status dsdna_autotune(dsdna_ctx *ctx, int32_t n, const double *cell_sizes, int32_t m,
-                            const int32_t *hash_log2s, int64_t trial_steps, double *best_cell,
-                            int32_t *best_hash_log2);
+/* Autotuner of the neighbour search (Sec. 6): every combination of a skin,
+ * a cell edge (a factor >= 1.001 times the search reach, the largest WCA
+ * cutoff plus the skin) and a bucket count is run for warm_steps untimed
+ * steps (the rebuild interval settles) and trial_steps timed ones on the
+ * current state, and the fastest is kept.  NULL or 0-length lists mean the
+ * context's current value.  The trial steps advance the state.  With
+ * use_cache, the choice is remembered for the rest of the process, keyed by
+ * (nucleotides, replicas, bead density of periodic boxes, open or periodic,
+ * force precision), and a later call with the same key takes it without
+ * trials; if the environment variable DSDNA_TUNE_CACHE names a file, choices
+ * are also read from and appended to it.  On failure the previous settings
+ * are restored. */
+typedef struct {
+    int32_t n_skins;
+    const double *skins;
+    int32_t n_cell_factors;
+    const double *cell_factors;
+    int32_t n_hash_log2s;
+    const int32_t *hash_log2s;
+    int64_t warm_steps;
+    int64_t trial_steps;
+    int32_t use_cache;
+} dsdna_tune_space;
+
+typedef struct {
+    double skin;
+    double cell_size;
+    int32_t hash_log2;
+    int32_t interval;       /* rebuild interval at the end of the winner's trial */
+    double ms_per_step;     /* the winner's trial (0 when taken from the cache) */
+    int32_t candidates;     /* combinations timed */
+    int32_t from_cache;     /* 1: taken from the cache, no trials */
+} dsdna_tune_result;
+
+dsdna_status dsdna_autotune(dsdna_ctx *ctx, const dsdna_tune_space *space, dsdna_tune_result *best);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the

@@ -19,7 +19,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <limits>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -35,6 +38,17 @@ enum Phase { PH_NONE = 0, PH_FULL, PH_RESUME, PH_LEAPFROG, PH_HALTED };
 constexpr double TWO_16 = 1.12246204830937298143;  // 2^(1/6)
 constexpr double DEFAULT_SKIN = 0.5;
 constexpr double LIST_SLACK = 1e-4;
+
+// Longest rebuild interval, and steps between two reads of the control block
+// (each read waits for the queued work: an outrun or a full list is caught
+// there, and the interval adapted): SYNC_FIRST after a state change, then
+// twice as many each time up to SYNC_STEPS.
+constexpr int K_MAX = 256;
+constexpr int64_t SYNC_FIRST = 64;
+constexpr int64_t SYNC_STEPS = 500;
+// The interval aims at rebuilds when the farthest bead has covered this
+// fraction of half the skin.
+constexpr double SCHEDULE_FRACTION = 0.95;
 
 }  // namespace
 
@@ -66,6 +80,15 @@ struct dsdna_ctx {
 
     hipGraphExec_t gexec = nullptr;
     int gsteps = 0;
+    int gK = 0;            // rebuild interval of the captured graph
+
+    // neighbour-list schedule: a rebuild follows every K-th step kernel;
+    // `age` step kernels have run since the last rebuild
+    int K = 4;
+    int age = 0;
+    int64_t outruns = 0;   // beads that outran the schedule since the last state change
+    int64_t sync_batch = 64;  // steps until the next read of the control block
+    bool rebuilt = false;     // a scheduled rebuild ran since the last read
 
     // rings and the scratch of the linking-number kernels
     std::vector<RingSeg> rings_h;
@@ -141,7 +164,7 @@ static void free_state(dsdna_ctx *c)
     }
     dfree(b.Vf); dfree(b.Lf); dfree(b.Fb); dfree(b.Fp);
     dfree(b.rec); dfree(b.rcell); dfree(b.key); dfree(b.slot); dfree(b.srec); dfree(b.sid); dfree(b.scell);
-    dfree(b.fex); dfree(b.cmask); dfree(b.eex); dfree(b.plist);
+    dfree(b.fex); dfree(b.cmask); dfree(b.eex); dfree(b.plist); dfree(b.vmax);
     dfree(b.rep); dfree(b.tiles); dfree(b.eacc); dfree(b.open);
     dfree(b.diag_fb); dfree(b.diag_fp);
     dfree(b.k2bp);
@@ -181,6 +204,7 @@ static void drop_graph(dsdna_ctx *c)
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     c->gexec = nullptr;
     c->gsteps = 0;
+    c->gK = 0;
 }
 
 static void fill_phys(dsdna_ctx *c)
@@ -412,11 +436,15 @@ static dsdna_status write_ctl(dsdna_ctx *c, int64_t step, int par)
     Ctl h{};
     h.step = step;
     h.par = par;
+    h.done_step = step - 1;
+    h.done_par = par ^ 1;
     HIPCHK(c, hipMemcpyAsync(c->a.b.ctl, &h, sizeof h, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->cur_step = step;
     c->cur_par = par;
     c->state_step = step;
+    c->outruns = 0;
+    c->sync_batch = SYNC_FIRST;
     return DSDNA_OK;
 }
 
@@ -479,31 +507,35 @@ static dsdna_status grow_list(dsdna_ctx *c, int64_t need)
 
 // Rebuild the neighbour list from the positions of buffer `which`: bin,
 // scan, scatter, search.  A list larger than its buffer is rebuilt into a
-// larger one.  Leaves the stale flag clear.
+// larger one.  Clears a stale mark and restarts the rebuild schedule.
 static dsdna_status rebin(dsdna_ctx *c, int which)
 {
     dsdna_status st = sync_args(c);
     if (st) return st;
+    Ctl h;
+    if ((st = read_ctl(c, &h))) return st;
+    if (h.halt_step != 0) {
+        h.halt_step = 0;
+        if ((st = copy(c, c->a.b.ctl, &h, sizeof h, hipMemcpyHostToDevice))) return st;
+    }
     for (;;) {
         // the histogram is cleared by the search that ends a rebuild, which an
         // error may have cut short
         HIPCHK(c, hipMemsetAsync(c->a.b.count, 0, sizeof(uint32_t) * ((size_t)c->a.g.nbucket / 2), c->stream));
-        HIPCHK(c, launch_bin(c->a, c->dA, which, 1, c->stream));
-        HIPCHK(c, launch_scan(c->a, 0, 1, c->stream));
-        HIPCHK(c, launch_scatter(c->a, 1, c->stream));
-        HIPCHK(c, launch_build(c->a, c->dA, 1, c->stream));
-        Ctl h;
+        HIPCHK(c, launch_bin(c->a, c->dA, which, c->stream));
+        HIPCHK(c, launch_scan(c->a, c->stream));
+        HIPCHK(c, launch_scatter(c->a, c->stream));
+        HIPCHK(c, launch_build(c->a, c->dA, c->stream));
         if ((st = read_ctl(c, &h))) return st;
-        h.stale = 0;
-        if (h.code == CODE_LIST_FULL) {
+        if (h.code != 0) break;  // the caller reads the error
+        if (h.list_n > (uint64_t)c->a.list_cap) {
             if ((st = grow_list(c, (int64_t)h.list_n))) return st;
-            h.code = 0;
+            h.halt_step = 0;
             if ((st = copy(c, c->a.b.ctl, &h, sizeof h, hipMemcpyHostToDevice))) return st;
             continue;
         }
-        if ((st = copy(c, c->a.b.ctl, &h, sizeof h, hipMemcpyHostToDevice))) return st;
-        if (h.code != 0) break;  // the caller reads the error
         c->binned_buf = which;
+        c->age = 0;
         return DSDNA_OK;
     }
     c->binned_buf = -1;
@@ -574,40 +606,51 @@ static dsdna_status status_from_ctl(dsdna_ctx *c, const Ctl &h)
                 (long long)h.err_id);
 }
 
-// One step: the neighbour-list pairs, the step kernel, and the kernels of a
-// rebuild (which work only when the step kernel found the list stale); the
-// scan advances ctl.step/par.  `ev` (7 events, or null) brackets the
-// kernels: pairs, step, bin, scan, scatter, build.
-static hipError_t enqueue_step(dsdna_ctx *c, int mode, int write_full, hipStream_t s, hipEvent_t *ev = nullptr)
+// One step: the neighbour-list pairs and the step kernel, then, when the
+// schedule says so, the kernels of a rebuild from the new positions.  `ev`
+// (7 events, or null) brackets the kernels: pairs, step, bin, scan,
+// scatter, build.
+static hipError_t enqueue_step(dsdna_ctx *c, int mode, int write_full, int rebuild_after, int age, hipStream_t s,
+                               hipEvent_t *ev = nullptr)
 {
     hipError_t e = hipSuccess;
     auto mark = [&](int k) {
         if (ev && e == hipSuccess) e = hipEventRecord(ev[k], s);
     };
     mark(0);
-    // a resume from stored forces evaluates no forces in its first launch
-    if (mode != MODE_FROM_FORCES) e = launch_pairs(c->a, c->dA, -1, 0, 1, s);
+    // the pair kernel publishes the step; a resume from stored forces
+    // evaluates no forces in its first launch
+    e = launch_pairs(c->a, c->dA, -1, 0, mode == MODE_FROM_FORCES ? PAIRS_PUBLISH : PAIRS_STEP, s);
     mark(1);
-    if (e == hipSuccess) e = launch_step(c->a, c->dA, c->prm.force_fp64, mode, write_full, s);
+    if (e == hipSuccess) e = launch_step(c->a, c->dA, c->prm.force_fp64, mode, write_full, rebuild_after, age, s);
     mark(2);
-    if (e == hipSuccess) e = launch_bin(c->a, c->dA, -1, 0, s);
-    mark(3);
-    if (e == hipSuccess) e = launch_scan(c->a, 1, 0, s);
-    mark(4);
-    if (e == hipSuccess) e = launch_scatter(c->a, 0, s);
-    mark(5);
-    if (e == hipSuccess) e = launch_build(c->a, c->dA, 0, s);
+    if (rebuild_after) {
+        // the step kernel has binned its new beads
+        mark(3);
+        if (e == hipSuccess) e = launch_scan(c->a, s);
+        mark(4);
+        if (e == hipSuccess) e = launch_scatter(c->a, s);
+        mark(5);
+        if (e == hipSuccess) e = launch_build(c->a, c->dA, s);
+    } else {
+        mark(3);
+        mark(4);
+        mark(5);
+    }
     mark(6);
     return e;
 }
 
-static dsdna_status build_graph(dsdna_ctx *c, int steps)
+// A graph of `steps` steps (a multiple of the rebuild interval K) that starts
+// right after a rebuild: rebuilds follow its K-th, 2K-th, ... step.
+static dsdna_status build_graph(dsdna_ctx *c, int steps, int K)
 {
     drop_graph(c);
     hipGraph_t g = nullptr;
     HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int k = 0; k < steps && e == hipSuccess; ++k) e = enqueue_step(c, MODE_NORMAL, 0, c->stream);
+    for (int k = 0; k < steps && e == hipSuccess; ++k)
+        e = enqueue_step(c, MODE_NORMAL, 0, (k + 1) % K == 0, k % K + 1, c->stream);
     hipError_t e2 = hipStreamEndCapture(c->stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -621,6 +664,7 @@ static dsdna_status build_graph(dsdna_ctx *c, int steps)
         return fail(c, DSDNA_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
     }
     c->gsteps = steps;
+    c->gK = K;
     return DSDNA_OK;
 }
 
@@ -628,6 +672,28 @@ static dsdna_status build_graph(dsdna_ctx *c, int steps)
 // brackets them.
 static const int PROF_CLASS[6] = {DSDNA_KERNEL_EXCL, DSDNA_KERNEL_STEP, DSDNA_KERNEL_BIN,
                                   DSDNA_KERNEL_SCAN, DSDNA_KERNEL_SCATTER, DSDNA_KERNEL_BUILD};
+
+// Rebuild interval from the largest displacement of a bead over an interval
+// since the last read (the per-tile maxima, which are then cleared): scaled
+// by SCHEDULE_FRACTION of half the skin over that displacement, at most
+// doubled or halved at a time.  Displacements grow at most linearly with
+// the interval, so the scaling approaches the target from either side.
+static dsdna_status adapt_interval(dsdna_ctx *c)
+{
+    if (!c->rebuilt) return DSDNA_OK;  // nothing measured since the last read
+    c->rebuilt = false;
+    std::vector<float> v((size_t)c->a.n_tiles);
+    dsdna_status st = copy(c, v.data(), c->a.b.vmax, sizeof(float) * v.size(), hipMemcpyDeviceToHost);
+    if (st) return st;
+    HIPCHK(c, hipMemsetAsync(c->a.b.vmax, 0, sizeof(float) * v.size(), c->stream));
+    float d2 = 0.0f;
+    for (float x : v) d2 = std::max(d2, x);
+    const double half = 0.5 * c->a.ph.skin - LIST_SLACK;
+    double k = 2.0 * c->K;
+    if (d2 > 0.0f) k = std::min(k, std::floor(c->K * SCHEDULE_FRACTION * half / std::sqrt((double)d2)));
+    c->K = (int)std::max(1.0, std::min((double)K_MAX, std::max(k, (double)(c->K / 2))));
+    return DSDNA_OK;
+}
 
 // Run n_steps; with `prof`, eager launches with events around every kernel
 // and the mean duration per step of each kernel class.
@@ -653,69 +719,88 @@ static dsdna_status run_steps(dsdna_ctx *c, int64_t n_steps, std::vector<double>
         for (hipEvent_t e : evs) (void)hipEventDestroy(e);
         evs.clear();
     };
+    const auto give_up = [&](dsdna_status code) {
+        free_events();
+        return code;
+    };
+    // one eager launch, following the schedule
+    const auto one = [&](int64_t k) -> hipError_t {
+        const int rebuild_after = c->age + 1 >= c->K;
+        hipEvent_t *ev = nullptr;
+        if (prof) {
+            const size_t e0 = evs.size();
+            evs.resize(e0 + 7, nullptr);
+            for (int q = 0; q < 7; ++q) {
+                const hipError_t e = hipEventCreate(&evs[e0 + q]);
+                if (e != hipSuccess) return e;
+            }
+            ev = &evs[e0];
+        }
+        const hipError_t e = enqueue_step(c, k == 0 ? first_mode : MODE_NORMAL, k == launches - 1, rebuild_after,
+                                          c->age + 1, c->stream, ev);
+        c->age = rebuild_after ? 0 : c->age + 1;
+        c->rebuilt = c->rebuilt || rebuild_after;
+        return e;
+    };
     int64_t k = 0;  // launches done
     Ctl h;
-    for (;;) {
-        if (prof) {
-            for (; k < launches; ++k) {
-                const size_t e0 = evs.size();
-                evs.resize(e0 + 7, nullptr);
-                for (int q = 0; q < 7; ++q)
-                    if (hipEventCreate(&evs[e0 + q]) != hipSuccess) {
-                        free_events();
-                        return fail(c, DSDNA_EDEVICE, "hipEventCreate failed");
-                    }
-                const hipError_t e = enqueue_step(c, k == 0 ? first_mode : MODE_NORMAL, k == launches - 1,
-                                                  c->stream, &evs[e0]);
-                if (e != hipSuccess) {
-                    free_events();
-                    return fail(c, DSDNA_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
-                }
-            }
-        } else {
-            if (k == 0 && first_mode != MODE_NORMAL) {
-                HIPCHK(c, enqueue_step(c, first_mode, launches == 1, c->stream));
+    while (k < launches) {
+        const int64_t end = std::min(launches, k + c->sync_batch);
+        c->sync_batch = std::min(SYNC_STEPS, 2 * c->sync_batch);
+        const auto launch_fail = [&](hipError_t e) {
+            return give_up(fail(c, DSDNA_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e)));
+        };
+        hipError_t e = hipSuccess;
+        if (k == 0 && first_mode != MODE_NORMAL) {
+            if ((e = one(k)) != hipSuccess) return launch_fail(e);
+            ++k;
+        }
+        const int G0 = c->prm.graph_steps;
+        if (!prof && G0 > 0) {
+            // graphs end before the run's last launch, which writes the
+            // full-step state; eager steps up to the next rebuild, then whole
+            // graphs
+            const int64_t gend = end == launches ? end - 1 : end;
+            while (c->age != 0 && k < gend) {
+                if ((e = one(k)) != hipSuccess) return launch_fail(e);
                 ++k;
             }
-            const int G = c->prm.graph_steps;
-            if (G > 0 && launches - 1 - k >= G) {
-                if (!c->gexec || c->gsteps != G) {
-                    if ((st = build_graph(c, G))) return st;
+            const int G = (G0 + c->K - 1) / c->K * c->K;
+            if (c->age == 0 && gend - k >= G) {
+                if (!c->gexec || c->gsteps != G || c->gK != c->K) {
+                    if ((st = build_graph(c, G, c->K))) return st;
                 }
-                while (launches - 1 - k >= G) {
-                    HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+                while (gend - k >= G) {
+                    if ((e = hipGraphLaunch(c->gexec, c->stream)) != hipSuccess) return launch_fail(e);
                     k += G;
+                    c->rebuilt = true;
                 }
             }
-            for (; k < launches; ++k) HIPCHK(c, enqueue_step(c, MODE_NORMAL, k == launches - 1, c->stream));
         }
-        if ((st = read_ctl(c, &h))) {
-            free_events();
-            return st;
+        for (; k < end; ++k)
+            if ((e = one(k)) != hipSuccess) return launch_fail(e);
+        if ((st = read_ctl(c, &h))) return give_up(st);
+        if (h.code != 0) break;  // an error: reported below
+        if ((st = adapt_interval(c))) return give_up(st);
+        if (h.halt_step != 0) {
+            // a bead outran the schedule, or a rebuild outgrew the list: every
+            // kernel after the step kernel that wrote the positions of
+            // halt_step returned at once, and those positions and half-step
+            // velocities are intact.  Rebuild the list there and go on from
+            // the launch that did not run.
+            k = h.done_step + 1 - step0;
+            const bool full = h.list_n > (uint64_t)c->a.list_cap;
+            if (full && (st = grow_list(c, (int64_t)h.list_n))) return give_up(st);
+            if (!full) {
+                c->K = std::max(1, std::min(c->K, (c->K + 1) / 2));
+                ++c->outruns;
+            }
+            h.halt_step = 0;
+            if ((st = copy(c, c->a.b.ctl, &h, sizeof h, hipMemcpyHostToDevice))) return give_up(st);
+            if ((st = rebin(c, h.done_par ^ 1))) return give_up(st);
         }
-        if (h.code != CODE_LIST_FULL) break;
-        // the neighbour list outgrew its buffer at the rebuild of the launch
-        // that took the step counter to h.step: every later kernel returned at
-        // once, and the positions and half-step velocities of h.step are
-        // intact.  Enlarge the list, rebuild it there and continue.
-        k = h.step - step0;
-        if ((st = grow_list(c, (int64_t)h.list_n))) {
-            free_events();
-            return st;
-        }
-        h.code = 0;
-        if ((st = copy(c, c->a.b.ctl, &h, sizeof h, hipMemcpyHostToDevice))) {
-            free_events();
-            return st;
-        }
-        if ((st = rebin(c, h.par))) {
-            free_events();
-            return st;
-        }
-        if (k >= launches) break;
     }
     if (prof) {
-        // events of launches that were cut short by a rebuild time nothing
         for (size_t q = 0; q + 6 < evs.size(); q += 7)
             for (int m = 0; m < 6; ++m) {
                 float t = 0.0f;
@@ -723,14 +808,20 @@ static dsdna_status run_steps(dsdna_ctx *c, int64_t n_steps, std::vector<double>
             }
         for (auto &x : *prof) x /= (double)launches;
         free_events();
-        if ((st = read_ctl(c, &h))) return st;
     }
-    c->cur_step = h.step;
-    c->cur_par = h.par;
-    if (h.code != 0) return status_from_ctl(c, h);
-    c->binned_buf = h.par;
-    c->full_par = h.par ^ 1;
-    c->full_step = h.step - 1;
+    if ((st = read_ctl(c, &h))) return st;
+    if (h.code != 0) {
+        // the state stays at the step the failing kernels worked on
+        c->cur_step = h.step;
+        c->cur_par = h.par;
+        return status_from_ctl(c, h);
+    }
+    // the last step kernel wrote the positions one step ahead
+    c->cur_step = h.done_step + 1;
+    c->cur_par = h.done_par ^ 1;
+    c->binned_buf = c->cur_par;
+    c->full_par = h.done_par;
+    c->full_step = h.done_step;
     c->phase = PH_LEAPFROG;
     return DSDNA_OK;
 }
@@ -748,7 +839,7 @@ static dsdna_status run_diag(dsdna_ctx *c, uint32_t mask)
         if ((st = rebin(c, which))) return st;
     }
     HIPCHK(c, hipMemsetAsync(c->a.b.eex, 0, sizeof(double) * (size_t)c->N, c->stream));
-    HIPCHK(c, launch_pairs(c->a, c->dA, which, 1, 0, c->stream));
+    HIPCHK(c, launch_pairs(c->a, c->dA, which, 1, PAIRS_DIAG, c->stream));
     HIPCHK(c, launch_diag(c->a, c->dA, which, c->prm.force_fp64, mask, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     Ctl h;
@@ -766,6 +857,73 @@ static dsdna_status run_diag(dsdna_ctx *c, uint32_t mask)
         return fail(c, code, "invalid state: error %d at nucleotide %lld", (int)code, (long long)h.err_id);
     }
     return DSDNA_OK;
+}
+
+// ------------------------------------------------------------ tuning cache
+
+// Key of an autotuner choice: what the best neighbour-search settings depend
+// on (the size and kind of the workload and the force precision).
+static std::string tune_key(const dsdna_ctx *c)
+{
+    bool open = false;
+    double vol = 0.0;
+    for (const RepInfo &r : c->rep_h) {
+        const bool per = (r.flags & (REP_PER_X | REP_PER_Y | REP_PER_Z)) == (REP_PER_X | REP_PER_Y | REP_PER_Z);
+        open = open || !per;
+        if (per) vol += r.len[0] * r.len[1] * r.len[2];
+    }
+    char buf[160];
+    snprintf(buf, sizeof buf, "nt=%lld rep=%d fp64=%d open=%d density=%.3g", (long long)c->N, c->n_rep,
+             c->prm.force_fp64, open ? 1 : 0, open || vol <= 0.0 ? 0.0 : (double)c->N / vol);
+    return buf;
+}
+
+static std::mutex g_tune_mutex;
+static std::map<std::string, dsdna_tune_result> g_tune;
+static bool g_tune_file_read = false;
+
+// The cache file: one choice per line, "key<TAB>skin<TAB>cell<TAB>hash_log2<TAB>interval".
+static void tune_cache_load_file()
+{
+    if (g_tune_file_read) return;
+    g_tune_file_read = true;
+    const char *path = std::getenv("DSDNA_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        char *tab = std::strchr(line, '\t');
+        if (!tab) continue;
+        *tab = 0;
+        dsdna_tune_result r{};
+        if (std::sscanf(tab + 1, "%lf\t%lf\t%d\t%d", &r.skin, &r.cell_size, &r.hash_log2, &r.interval) == 4)
+            g_tune[line] = r;
+    }
+    std::fclose(f);
+}
+
+static bool tune_cache_find(const std::string &key, dsdna_tune_result *out)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    tune_cache_load_file();
+    const auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+static void tune_cache_store(const std::string &key, const dsdna_tune_result &r)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    tune_cache_load_file();
+    g_tune[key] = r;
+    const char *path = std::getenv("DSDNA_TUNE_CACHE");
+    if (!path || !*path) return;
+    if (FILE *f = std::fopen(path, "a")) {
+        std::fprintf(f, "%s\t%.17g\t%.17g\t%d\t%d\n", key.c_str(), r.skin, r.cell_size, r.hash_log2, r.interval);
+        std::fclose(f);
+    }
 }
 
 // ----------------------------------------------------------------- C ABI
@@ -921,6 +1079,8 @@ static dsdna_status build_topology(dsdna_ctx *c, int32_t n_rep, const int32_t *n
     // few per thousand beads in a relaxed duplex; it grows when needed
     a.list_cap = c->prm.list_capacity > 0 ? c->prm.list_capacity : std::max<int64_t>(4096, N / 8);
     HIPCHK(c, dalloc(&b.plist, (size_t)a.list_cap));
+    HIPCHK(c, dalloc(&b.vmax, (size_t)a.n_tiles));
+    HIPCHK(c, hipMemsetAsync(b.vmax, 0, sizeof(float) * (size_t)a.n_tiles, c->stream));
     HIPCHK(c, dalloc(&b.rep, (size_t)n_rep));
     HIPCHK(c, dalloc(&b.tiles, c->tiles_h.size()));
     HIPCHK(c, dalloc(&b.eacc, (size_t)a.n_tiles * DSDNA_NTERMS));
@@ -1371,8 +1531,8 @@ dsdna_status dsdna_get_sizes(dsdna_ctx *c, int32_t *n_rep, int64_t *n_nt, int64_
     return DSDNA_OK;
 }
 
-dsdna_status dsdna_get_neighbour_stats(dsdna_ctx *c, int64_t *rebuilds, int64_t *steps, int64_t *pairs,
-                                       double *skin)
+dsdna_status dsdna_get_neighbour_stats(dsdna_ctx *c, int64_t *rebuilds, int64_t *steps, int64_t *outruns,
+                                       int64_t *pairs, double *skin, int32_t *interval)
 {
     dsdna_status st = check_ready(c, false);
     if (st) return st;
@@ -1380,9 +1540,11 @@ dsdna_status dsdna_get_neighbour_stats(dsdna_ctx *c, int64_t *rebuilds, int64_t 
     Ctl h;
     if ((st = read_ctl(c, &h))) return st;
     if (rebuilds) *rebuilds = h.rebuilds;
-    if (steps) *steps = c->phase == PH_LEAPFROG ? h.step - 1 - c->state_step : 0;
+    if (steps) *steps = c->phase == PH_LEAPFROG ? h.done_step - c->state_step : 0;
     if (pairs) *pairs = std::min<int64_t>((int64_t)h.list_n, c->a.list_cap);
     if (skin) *skin = c->a.ph.skin;
+    if (outruns) *outruns = c->outruns;
+    if (interval) *interval = c->K;
     return DSDNA_OK;
 }
 
@@ -1397,52 +1559,95 @@ dsdna_status dsdna_get_grid(dsdna_ctx *c, double *cell_size, int64_t *n_buckets,
     return DSDNA_OK;
 }
 
-dsdna_status dsdna_autotune(dsdna_ctx *c, int32_t n, const double *cell_sizes, int32_t m, const int32_t *hash_log2s,
-                            int64_t trial_steps, double *best_cell, int32_t *best_hash_log2)
+dsdna_status dsdna_autotune(dsdna_ctx *c, const dsdna_tune_space *sp, dsdna_tune_result *best)
 {
     dsdna_status st = check_ready(c, true);
     if (st) return st;
-    if (n < 1 || m < 1 || !cell_sizes || !hash_log2s || trial_steps < 1)
-        return fail(c, DSDNA_EINVAL, "autotune needs candidates and trial_steps >= 1");
-    double best_t = 1e300, bc = c->prm.cell_size;
-    int32_t bl = c->prm.hash_log2;
-    const double cell0 = c->prm.cell_size;
-    const int32_t hash0 = c->prm.hash_log2;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!sp || !best || sp->trial_steps < 1 || sp->warm_steps < 0 || sp->n_skins < 0 || sp->n_cell_factors < 0 ||
+        sp->n_hash_log2s < 0)
+        return fail(c, DSDNA_EINVAL, "autotune needs a space, a result and trial_steps >= 1");
+    const std::vector<double> skins = sp->n_skins > 0 && sp->skins
+                                          ? std::vector<double>(sp->skins, sp->skins + sp->n_skins)
+                                          : std::vector<double>{c->a.ph.skin};
+    const std::vector<double> facs = sp->n_cell_factors > 0 && sp->cell_factors
+                                         ? std::vector<double>(sp->cell_factors, sp->cell_factors + sp->n_cell_factors)
+                                         : std::vector<double>{1.001};
+    const std::vector<int32_t> lgs = sp->n_hash_log2s > 0 && sp->hash_log2s
+                                         ? std::vector<int32_t>(sp->hash_log2s, sp->hash_log2s + sp->n_hash_log2s)
+                                         : std::vector<int32_t>{c->prm.hash_log2};
+    for (double x : skins)
+        if (!(x >= 1e-3)) return fail(c, DSDNA_EINVAL, "autotune: skin %g below 1e-3", x);
+    for (double f : facs)
+        if (!(f >= 1.001)) return fail(c, DSDNA_EINVAL, "autotune: cell factor %g below 1.001", f);
+    std::memset(best, 0, sizeof *best);
+    const std::string key = tune_key(c);
+    const dsdna_params prm0 = c->prm;
+    const int K0 = c->K;
     // on any failure the parameters and the grid they give are put back
-    const auto give_up = [&](dsdna_status code) {
-        if (e0) (void)hipEventDestroy(e0);
-        if (e1) (void)hipEventDestroy(e1);
+    const auto restore = [&](dsdna_status code) {
         const std::string msg = c->err;
-        c->prm.cell_size = cell0;
-        c->prm.hash_log2 = hash0;
+        c->prm = prm0;
+        fill_phys(c);
         (void)configure_grid(c);
+        c->K = K0;
         c->err = msg;
         return code;
     };
+    const auto apply = [&](double skin, double cell, int32_t lg) -> dsdna_status {
+        c->prm.skin = skin;
+        c->prm.cell_size = cell;
+        c->prm.hash_log2 = lg;
+        fill_phys(c);
+        return configure_grid(c);
+    };
+    dsdna_tune_result hit;
+    if (sp->use_cache && tune_cache_find(key, &hit)) {
+        if ((st = apply(hit.skin, hit.cell_size, hit.hash_log2))) return restore(st);
+        *best = hit;
+        best->from_cache = 1;
+        best->ms_per_step = 0.0;
+        best->candidates = 0;
+        return DSDNA_OK;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const auto done = [&](dsdna_status code) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        return code == DSDNA_OK ? code : restore(code);
+    };
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-        return give_up(fail(c, DSDNA_EDEVICE, "hipEventCreate failed"));
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < m; ++j) {
-            c->prm.cell_size = cell_sizes[i];
-            c->prm.hash_log2 = hash_log2s[j];
-            if ((st = configure_grid(c))) return give_up(st);
-            if ((st = run_steps(c, 1, nullptr))) return give_up(st);
-            float t = 0.0f;
-            if (hipEventRecord(e0, c->stream) != hipSuccess) return give_up(fail(c, DSDNA_EDEVICE, "event failed"));
-            if ((st = run_steps(c, trial_steps, nullptr))) return give_up(st);
-            if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                hipEventElapsedTime(&t, e0, e1) != hipSuccess)
-                return give_up(fail(c, DSDNA_EDEVICE, "event failed"));
-            if (t < best_t) { best_t = t; bc = cell_sizes[i]; bl = hash_log2s[j]; }
-        }
+        return done(fail(c, DSDNA_EDEVICE, "hipEventCreate failed"));
+    double best_ms = 1e300;
+    for (double skin : skins)
+        for (double f : facs)
+            for (int32_t lg : lgs) {
+                const double cell = f * (TWO_16 * std::max(c->prm.sig_s, c->prm.sig_x) + skin + LIST_SLACK);
+                if ((st = apply(skin, cell, lg))) return done(st);
+                c->sync_batch = SYNC_FIRST;
+                if ((st = run_steps(c, std::max<int64_t>(1, sp->warm_steps), nullptr))) return done(st);
+                float t = 0.0f;
+                if (hipEventRecord(e0, c->stream) != hipSuccess) return done(fail(c, DSDNA_EDEVICE, "event failed"));
+                if ((st = run_steps(c, sp->trial_steps, nullptr))) return done(st);
+                if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+                    return done(fail(c, DSDNA_EDEVICE, "event failed"));
+                const double ms = t / (double)sp->trial_steps;
+                ++best->candidates;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best->skin = skin;
+                    best->cell_size = cell;
+                    best->hash_log2 = c->a.g.nbucket > 0 ? (int32_t)std::lround(std::log2((double)c->a.g.nbucket)) : lg;
+                    best->interval = c->K;
+                    best->ms_per_step = ms;
+                }
+            }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    c->prm.cell_size = bc;
-    c->prm.hash_log2 = bl;
-    if ((st = configure_grid(c))) return st;
-    if (best_cell) *best_cell = bc;
-    if (best_hash_log2) *best_hash_log2 = bl;
+    e0 = e1 = nullptr;
+    if ((st = apply(best->skin, best->cell_size, best->hash_log2))) return restore(st);
+    c->K = best->interval;
+    if (sp->use_cache) tune_cache_store(key, *best);
     return DSDNA_OK;
 }
 

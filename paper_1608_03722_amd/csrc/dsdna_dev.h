@@ -94,25 +94,33 @@ struct Tile {
     int32_t ring;  // 1 if the replica is a ring (REP_RING)
 };
 
-// Control block in device memory.  `step` is the step index of the positions
-// in buffer `par`; kernels read both at launch so that captured graphs replay
-// without argument changes.  `stale` is set by the step kernel when a bead
-// has moved half the skin since the neighbour list was built: the rebuild
-// kernels of the same step then run, and the next pair kernel clears it.
+// Control block in device memory.  (step, par) is the step index of the
+// positions in buffer par that the current step integrates, and (done_step,
+// done_par) those of the last step kernel that started; kernels read them at
+// launch, so captured graphs replay without argument changes.  The first
+// kernel of a step (the pair kernel) publishes step = done_step + 1 and par =
+// done_par ^ 1, and block 0 of the step kernel records done_step = step at
+// its start: each field is written by one thread of a kernel that does not
+// read it, so no kernel sees a value change under it.  The neighbour list is
+// rebuilt on a schedule the host chooses.  halt_step (0: none) stops the run
+// so that the host can rebuild the list there and continue: a step kernel
+// that finds a bead half the skin from where the list last saw it (on a step
+// not followed by a rebuild) sets it to the index of the new positions, a
+// rebuild that outgrows the list buffer to that of the positions it binned;
+// every kernel of that step or later returns at once, after the pair kernel
+// has published the step.
 struct Ctl {
     int64_t step;
     int32_t par;
-    int32_t code;      // first error (dsdna_status or CODE_*), 0 if none
+    int32_t code;      // first error (dsdna_status), 0 if none
     int64_t err_step;
     int64_t err_id;
-    int32_t stale;
+    int64_t done_step;
+    int32_t done_par;
     uint32_t list_n;   // pairs in the neighbour list (may exceed its capacity)
+    int64_t halt_step;
     int64_t rebuilds;  // neighbour-list builds since the counter was reset
 };
-
-// Internal status: the neighbour list outgrew its buffer.  Never returned to
-// the caller: the host enlarges the buffer, rebuilds and continues.
-constexpr int CODE_LIST_FULL = 100;
 
 // A pair of beads of the neighbour list: nucleotides i and j (i's record
 // precedes j's in cell order), their replica, and whether they are on the
@@ -158,6 +166,10 @@ struct Bufs {
     uint32_t *cmask;
     double *eex;                        // list-pair excluded-volume energy per nt (diagnostics)
     PairRec *plist;                     // neighbour list (non-local bead pairs)
+    // per tile: the largest squared displacement of a bead over a rebuild
+    // interval (measured on the steps a rebuild follows) since the host last
+    // cleared it
+    float *vmax;
     RepInfo *rep;
     Tile *tiles;
     Ctl *ctl;
@@ -209,27 +221,32 @@ struct RingSeg {
 // Launchers (defined in dsdna_kernels.hip).  `a` is the host copy (grid
 // sizes), `dA` the device copy the kernels read.
 //
-// One step is launch_pairs, launch_step, then the four kernels of a
-// neighbour-list rebuild (launch_bin, launch_scan, launch_scatter,
-// launch_build).  The rebuild kernels do their work when `force` is set or
-// when the step kernel has flagged the list stale; otherwise they return at
-// once.  launch_scan with inc_step advances the step counter and flips the
-// position buffers (every step).
-hipError_t launch_step(const StepArgs &a, const StepArgs *dA, int fp64, int mode, int write_full, hipStream_t s);
+// One step is launch_pairs and launch_step, followed on the steps the host
+// schedules a rebuild by the kernels of a neighbour-list rebuild from the
+// positions the step kernel has just written and binned (launch_scan,
+// launch_scatter, launch_build).  rebuild_after: a rebuild follows this step
+// kernel, which then bins its new beads; age: steps since the last rebuild,
+// this one included.  launch_bin bins a given buffer (a rebuild outside the
+// steps).
+hipError_t launch_step(const StepArgs &a, const StepArgs *dA, int fp64, int mode, int write_full, int rebuild_after,
+                       int age, hipStream_t s);
 // Excluded-volume force of every neighbour-list pair within its cutoff at the
 // positions of buffer `which` (-1: the control block's current buffer),
 // accumulated into b.fex / b.cmask (and with `energy`, half of each pair's
-// energy into b.eex of both beads).  clear_stale: reset the stale flag.
-hipError_t launch_pairs(const StepArgs &a, const StepArgs *dA, int which, int energy, int clear_stale,
-                        hipStream_t s);
+// energy into b.eex of both beads).  mode PAIRS_STEP: the first kernel of a
+// step (publishes the step; which is ignored); PAIRS_PUBLISH: only
+// publishes it (a step that starts from stored forces); PAIRS_DIAG: for the
+// diagnostics, at the control block's step.
+enum PairsMode : int { PAIRS_DIAG = 0, PAIRS_STEP = 1, PAIRS_PUBLISH = 2 };
+hipError_t launch_pairs(const StepArgs &a, const StepArgs *dA, int which, int energy, int mode, hipStream_t s);
 // Counting-sort count phase: record, cell, key and slot of every bead of
-// buffer `which` (-1: the buffer the step kernel has just written).
-hipError_t launch_bin(const StepArgs &a, const StepArgs *dA, int which, int force, hipStream_t s);
-hipError_t launch_scan(const StepArgs &a, int inc_step, int force, hipStream_t s);
-hipError_t launch_scatter(const StepArgs &a, int force, hipStream_t s);
+// buffer `which` (-1: the positions the last step kernel wrote).
+hipError_t launch_bin(const StepArgs &a, const StepArgs *dA, int which, hipStream_t s);
+hipError_t launch_scan(const StepArgs &a, hipStream_t s);
+hipError_t launch_scatter(const StepArgs &a, hipStream_t s);
 // Neighbour search over the sorted records: every non-local bead pair within
 // its cutoff plus the skin goes to b.plist; clears the histogram.
-hipError_t launch_build(const StepArgs &a, const StepArgs *dA, int force, hipStream_t s);
+hipError_t launch_build(const StepArgs &a, const StepArgs *dA, hipStream_t s);
 hipError_t launch_thermalize(const StepArgs &a, const StepArgs *dA, double kT, uint64_t seed, hipStream_t s);
 // term_mask: bit t selects term t; writes per-term forces (AoS doubles) to
 // b.diag_fb / b.diag_fp, energies per tile to b.eacc[tile][DSDNA_NTERMS] and

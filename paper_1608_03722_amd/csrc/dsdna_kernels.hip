@@ -13,12 +13,12 @@
 //              list pairs' excluded volume, the external loads and the
 //              Langevin forces, then integrate the rigid body (FP64) and test
 //              whether its bead has moved half the skin since the list was
-//              built (the list is then stale)
-//   rebuild    when the list is stale (or the host forces it): k_bin (cell of
-//              every bead, histogram), k_scan_* (offsets), k_scatter (records
-//              into cell order), k_build (neighbour search within the cutoffs
-//              plus the skin); otherwise each returns at once.  k_scan_reduce
-//              also advances the step.
+//              built; its last tile to finish advances the step
+//   rebuild    on the steps the host schedules (every K steps): the step
+//              kernel bins its new beads (cell, histogram), then k_scan_*
+//              (offsets), k_scatter (records into cell order), k_build
+//              (neighbour search within the cutoffs plus the skin); k_bin
+//              bins a given buffer for a rebuild outside the steps
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -249,6 +249,13 @@ __device__ __forceinline__ void raise_error(Ctl *ctl, int code, int64_t step, in
         ctl->err_step = step;
         ctl->err_id = id;
     }
+}
+
+// Whether the kernels of the positions of step m must not run: an error is
+// latched, or the run stops at step m or before (halt_step).
+__device__ __forceinline__ bool halted(const Ctl &ctl, int64_t m)
+{
+    return ctl.code != 0 || (ctl.halt_step != 0 && ctl.halt_step <= m);
 }
 
 // --------------------------------------------------------------- cell list
@@ -933,12 +940,18 @@ __device__ __forceinline__ D3 rotate(D3 u, D3 k, double th)
 // ---------------------------------------------------------------- k_step
 
 template <typename real, bool DAMP>
-__global__ void __launch_bounds__(WG_THREADS, 5) k_step(const StepArgs *__restrict__ A, int mode, int write_full)
+__global__ void __launch_bounds__(WG_THREADS, 5) k_step(const StepArgs *__restrict__ A, int mode, int write_full,
+                                                       int rebuild_after, int age)
 {
     __shared__ TileLds<real> S;
+    __shared__ float s_v2[WG_THREADS / 64];
     const StepArgs &a = *A;
     const Ctl ctl = *a.b.ctl;
-    if (ctl.code != 0) return;
+    if (halted(ctl, ctl.step)) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.b.ctl->done_step = ctl.step;
+        a.b.ctl->done_par = ctl.par;
+    }
     const int tix = tile_index(a.n_tiles, a.n_tiles_pad);
     if (tix >= a.n_tiles) return;
     const Tile tile = a.b.tiles[tix];
@@ -1067,8 +1080,13 @@ __global__ void __launch_bounds__(WG_THREADS, 5) k_step(const StepArgs *__restri
     }
     // --- the neighbour list stays valid while no bead has moved half the
     //     skin since it was built: compare the new bead with its record (the
-    //     wrapped fixed-point difference is the exact displacement)
+    //     wrapped fixed-point difference is the exact displacement).  Unless a
+    //     rebuild follows this step, a bead that far stops the run at the new
+    //     positions.  On the step a rebuild follows, the largest squared
+    //     displacement over the interval is kept for the host's schedule.
     bool far = false;
+    float v2 = 0.0f;
+    (void)age;
     if (own) {
         int c[3];
         uint32_t q[3];
@@ -1077,39 +1095,53 @@ __global__ void __launch_bounds__(WG_THREADS, 5) k_step(const StepArgs *__restri
         const float dx = (float)(int32_t)(q[0] - ref.x) * ri.qlen[0];
         const float dy = (float)(int32_t)(q[1] - ref.y) * ri.qlen[1];
         const float dz = (float)(int32_t)(q[2] - ref.z) * ri.qlen[2];
-        far = dx * dx + dy * dy + dz * dz >= ph.half_skin2;
+        const float d2 = dx * dx + dy * dy + dz * dz;
+        far = !rebuild_after && d2 >= ph.half_skin2;
+        v2 = rebuild_after ? d2 : 0.0f;
     }
     const uint64_t far_lanes = __ballot(far);
-    if (far_lanes && (threadIdx.x & 63) == (unsigned)__builtin_ctzll(far_lanes)) atomicOr(&a.b.ctl->stale, 1);
+    const unsigned lane = threadIdx.x & 63;
+    if (far_lanes && lane == (unsigned)__builtin_ctzll(far_lanes))
+        atomicMax((unsigned long long *)&a.b.ctl->halt_step, (unsigned long long)(step + 1));
+    // the tile's largest displacement into its own slot (no other tile
+    // touches it)
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v2 = fmaxf(v2, __shfl_xor(v2, d, 64));
+    if (lane == 0) s_v2[threadIdx.x >> 6] = v2;
+    __syncthreads();
+    if (rebuild_after && threadIdx.x == 0) {
+        float m = s_v2[0];
+        for (int w = 1; w < WG_THREADS / 64; ++w) m = fmaxf(m, s_v2[w]);
+        if (m > a.b.vmax[tix]) a.b.vmax[tix] = m;
+    }
+    // --- a rebuild follows: bin the new bead (record, cell, key, slot and
+    //     histogram), the counting sort's count phase; the force phase's
+    //     outboxes hold the binning table
+    if (rebuild_after) {
+        uint32_t *lds = reinterpret_cast<uint32_t *>(&S.oStep[0][0][0][0]);
+        bin_tile(a, lds, lds + WG_THREADS, reinterpret_cast<int *>(lds + 2 * WG_THREADS), ri, tile.rep, n, s, i,
+                 own, bead_new, step + 1);
+    }
 }
 
 // ------------------------------------------------- neighbour-list rebuild
 
-// Whether the kernels of a neighbour-list rebuild do their work: when the
-// host forces a rebuild, or when the step kernel of this step found a bead
-// half the skin away from where the list saw it.
-__device__ __forceinline__ bool rebuild_now(const Ctl *ctl, int force)
-{
-    return ctl->code == 0 && (force || ctl->stale);
-}
-
-// Workgroups of the rebuild kernels (grid-stride loops): enough to fill the
-// chip when they work, few to dispatch when they return at once.
+// Workgroups of the rebuild kernels (grid-stride loops).
 constexpr int REBUILD_GRID = 2048;
 
 // Counting-sort count phase: bins the beads of buffer `which` (-1: the
-// buffer the step kernel has just written, i.e. the one after the control
-// block's current buffer; its step index is one ahead).  Each bead's record
-// becomes the reference position of the displacement test.
-__global__ void __launch_bounds__(WG_THREADS) k_bin(const StepArgs *__restrict__ A, int which, int force)
+// positions the last step kernel wrote).
+// Each bead's record becomes the reference position of the displacement test.
+__global__ void __launch_bounds__(WG_THREADS) k_bin(const StepArgs *__restrict__ A, int which)
 {
     const StepArgs &a = *A;
-    const Ctl *ctl = a.b.ctl;
-    if (!rebuild_now(ctl, force)) return;
+    const Ctl ctl = *a.b.ctl;
+    // which < 0: the positions the last step kernel wrote
+    const int64_t step = which < 0 ? ctl.done_step + 1 : ctl.step;
+    if (halted(ctl, step)) return;
     __shared__ uint32_t tab[WG_THREADS], cnt[WG_THREADS];
     __shared__ int base[WG_THREADS];
-    const int buf = which < 0 ? (ctl->par ^ 1) : which;
-    const int64_t step = ctl->step + (which < 0 ? 1 : 0);
+    const int buf = which < 0 ? (ctl.done_par ^ 1) : which;
     const int t = threadIdx.x;
     for (int b = blockIdx.x; b < a.n_tiles_pad; b += gridDim.x) {
         const int tix = xcd_item(b, a.n_tiles_pad);
@@ -1169,15 +1201,26 @@ __device__ __forceinline__ void fex_add(const StepArgs &a, const RepInfo &ri, in
 // other terms: contacts are rare, and near the cutoff the force is a small
 // difference of O(1) numbers.  Pairs beyond the cutoff (within the skin)
 // contribute nothing.
-__global__ void __launch_bounds__(256) k_pairs(const StepArgs *__restrict__ A, int which, int energy, int clear_stale)
+__global__ void __launch_bounds__(256) k_pairs(const StepArgs *__restrict__ A, int which, int energy, int mode)
 {
     const StepArgs &a = *A;
     Ctl *ctl = a.b.ctl;
-    if (ctl->code != 0) return;
-    // the rebuild kernels of the previous step have read the flag
-    if (clear_stale && blockIdx.x == 0 && threadIdx.x == 0) ctl->stale = 0;
-    const int64_t n = min((int64_t)ctl->list_n, a.list_cap);
-    const int buf = which < 0 ? ctl->par : which;
+    const Ctl c0 = *ctl;
+    if (c0.code != 0) return;
+    int64_t m = c0.step;
+    int buf = which < 0 ? c0.par : which;
+    if (mode != PAIRS_DIAG) {
+        // the first kernel of a step: publish its step and buffer
+        m = c0.done_step + 1;
+        buf = c0.done_par ^ 1;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            ctl->step = m;
+            ctl->par = buf;
+        }
+        if (mode == PAIRS_PUBLISH) return;
+    }
+    if (halted(c0, m)) return;
+    const int64_t n = min((int64_t)c0.list_n, a.list_cap);
     const double *Rc = a.b.R[buf], *uc = a.b.u[buf];
     const int64_t N = a.n_nt;
     const Phys &ph = a.ph;
@@ -1211,7 +1254,7 @@ __global__ void __launch_bounds__(256) k_pairs(const StepArgs *__restrict__ A, i
             atomicAdd(&a.b.eex[pr.j], eh);
         }
     }
-    if (bad >= 0) raise_error(ctl, DSDNA_ENAN, ctl->step, bad);
+    if (bad >= 0) raise_error(ctl, DSDNA_ENAN, m, bad);
 }
 
 // A bead of the sorted cell list as the neighbour search sees it.
@@ -1303,11 +1346,12 @@ constexpr int EXCL_THREADS = 256;  // records per workgroup (sorted by load toge
 template <bool any_open>
 __global__ void __launch_bounds__(EXCL_THREADS) k_build(const StepArgs *__restrict__ A, const BeadRec *__restrict__ srec,
                                               const int *__restrict__ sid, const int4 *__restrict__ scell,
-                                              const int *__restrict__ start, int force)
+                                              const int *__restrict__ start)
 {
     const StepArgs &a = *A;
     Ctl *ctl = a.b.ctl;
-    if (!rebuild_now(ctl, force)) return;
+    const int64_t built_step = ctl->done_step + 1;  // the positions k_bin binned
+    if (halted(*ctl, built_step)) return;
     const int t = threadIdx.x;
     // the histogram has served this cell list: clear it for the next
     // binning (streaming stores while this kernel is bound by its search)
@@ -1551,10 +1595,11 @@ __global__ void __launch_bounds__(EXCL_THREADS) k_build(const StepArgs *__restri
     }
     }  // p < n_nt
     }  // record blocks
-    // a list past its buffer stops the run; the host enlarges it and rebuilds
+    // a list past its buffer stops the run at these positions; the host
+    // enlarges it, rebuilds and continues
     __syncthreads();
     if (t == 0 && __hip_atomic_load(&ctl->list_n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > cap)
-        raise_error(ctl, CODE_LIST_FULL, ctl->step, -1);
+        atomicMax((unsigned long long *)&ctl->halt_step, (unsigned long long)built_step);
 }
 
 // ------------------------------------------------------------------- scan
@@ -1585,19 +1630,11 @@ __device__ __forceinline__ int block_excl_scan(int v, int *total)
     return base + incl - v;
 }
 
-// Total of each chunk of SCAN_CHUNK histogram entries.  inc: this is the
-// last kernel of a step that reads the step index or the buffer parity, so
-// advance the step and flip the position buffers (the rebuild kernels after
-// it read neither).
+// Total of each chunk of SCAN_CHUNK histogram entries.
 __global__ void __launch_bounds__(256) k_scan_reduce(const uint32_t *__restrict__ count, int *__restrict__ bsum,
-                                                     Ctl *ctl, int inc, int force)
+                                                     const Ctl *ctl)
 {
-    if (ctl->code != 0) return;
-    if (inc && blockIdx.x == 0 && threadIdx.x == 0) {
-        ctl->step += 1;
-        ctl->par ^= 1;
-    }
-    if (!rebuild_now(ctl, force)) return;
+    if (halted(*ctl, ctl->done_step + 1)) return;
     // 16 buckets (8 words) per thread
     const uint4 *c4 = reinterpret_cast<const uint4 *>(count + (int64_t)blockIdx.x * (SCAN_CHUNK / 2)) + threadIdx.x * 2;
     int v = 0;
@@ -1614,9 +1651,9 @@ __global__ void __launch_bounds__(256) k_scan_reduce(const uint32_t *__restrict_
 
 // Offsets of one chunk of SCAN_CHUNK keys from the preceding chunk totals.
 __global__ void __launch_bounds__(256) k_scan_down(const uint32_t *__restrict__ count, const int *__restrict__ bsum,
-                                                   int *__restrict__ start, int nkeys, const Ctl *ctl, int force)
+                                                   int *__restrict__ start, int nkeys, const Ctl *ctl)
 {
-    if (!rebuild_now(ctl, force)) return;
+    if (halted(*ctl, ctl->done_step + 1)) return;
     // the chunk's counts first (in flight while the offset is summed): 16
     // buckets in 8 words per thread
     const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + threadIdx.x * 16;
@@ -1671,9 +1708,9 @@ __global__ void __launch_bounds__(256) k_scatter(const int *__restrict__ key, co
                                                  const int *__restrict__ start, const BeadRec *__restrict__ rec,
                                                  const int4 *__restrict__ rcell, BeadRec *__restrict__ srec,
                                                  int *__restrict__ sid, int4 *__restrict__ scell, Ctl *ctl,
-                                                 int64_t n, int any_open, int force)
+                                                 int64_t n, int any_open)
 {
-    if (!rebuild_now(ctl, force)) return;
+    if (halted(*ctl, ctl->done_step + 1)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->list_n = 0u;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int k = key[i];
@@ -1947,63 +1984,60 @@ static dim3 rebuild_grid(int64_t items)
     return dim3((unsigned)((g + 7) / 8 * 8));
 }
 
-hipError_t launch_bin(const StepArgs &a, const StepArgs *dA, int which, int force, hipStream_t s)
+hipError_t launch_bin(const StepArgs &a, const StepArgs *dA, int which, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_bin, rebuild_grid(a.n_tiles_pad), dim3(WG_THREADS), 0, s, dA, which, force);
+    hipLaunchKernelGGL(k_bin, rebuild_grid(a.n_tiles_pad), dim3(WG_THREADS), 0, s, dA, which);
     return hipGetLastError();
 }
 
-hipError_t launch_scan(const StepArgs &a, int inc_step, int force, hipStream_t s)
+hipError_t launch_scan(const StepArgs &a, hipStream_t s)
 {
     const int nkeys = a.g.nbucket;
     const int nchunk = nkeys / SCAN_CHUNK;
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nchunk), dim3(256), 0, s, a.b.count, a.b.bsum, a.b.ctl, inc_step, force);
-    hipLaunchKernelGGL(k_scan_down, dim3(nchunk), dim3(256), 0, s, a.b.count, a.b.bsum, a.b.start, nkeys, a.b.ctl,
-                       force);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nchunk), dim3(256), 0, s, a.b.count, a.b.bsum, a.b.ctl);
+    hipLaunchKernelGGL(k_scan_down, dim3(nchunk), dim3(256), 0, s, a.b.count, a.b.bsum, a.b.start, nkeys, a.b.ctl);
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(const StepArgs &a, int force, hipStream_t s)
+hipError_t launch_scatter(const StepArgs &a, hipStream_t s)
 {
     hipLaunchKernelGGL(k_scatter, rebuild_grid((a.n_nt + 255) / 256), dim3(256), 0, s, a.b.key, a.b.slot, a.b.start,
-                       a.b.rec, a.b.rcell, a.b.srec, a.b.sid, a.b.scell, a.b.ctl, a.n_nt, a.g.any_open, force);
+                       a.b.rec, a.b.rcell, a.b.srec, a.b.sid, a.b.scell, a.b.ctl, a.n_nt, a.g.any_open);
     return hipGetLastError();
 }
 
-hipError_t launch_build(const StepArgs &a, const StepArgs *dA, int force, hipStream_t s)
+hipError_t launch_build(const StepArgs &a, const StepArgs *dA, hipStream_t s)
 {
     const dim3 g = rebuild_grid((a.n_nt + EXCL_THREADS - 1) / EXCL_THREADS);
     if (a.g.any_open)
-        hipLaunchKernelGGL(k_build<true>, g, dim3(EXCL_THREADS), 0, s, dA, a.b.srec, a.b.sid, a.b.scell, a.b.start,
-                           force);
+        hipLaunchKernelGGL(k_build<true>, g, dim3(EXCL_THREADS), 0, s, dA, a.b.srec, a.b.sid, a.b.scell, a.b.start);
     else
-        hipLaunchKernelGGL(k_build<false>, g, dim3(EXCL_THREADS), 0, s, dA, a.b.srec, a.b.sid, a.b.scell, a.b.start,
-                           force);
+        hipLaunchKernelGGL(k_build<false>, g, dim3(EXCL_THREADS), 0, s, dA, a.b.srec, a.b.sid, a.b.scell, a.b.start);
     return hipGetLastError();
 }
 
 // Threads of the pair kernel: the list holds a few pairs per thousand beads.
 constexpr int PAIRS_GRID = 256;
 
-hipError_t launch_pairs(const StepArgs &a, const StepArgs *dA, int which, int energy, int clear_stale,
-                        hipStream_t s)
+hipError_t launch_pairs(const StepArgs &a, const StepArgs *dA, int which, int energy, int mode, hipStream_t s)
 {
     (void)a;
-    hipLaunchKernelGGL(k_pairs, dim3(PAIRS_GRID), dim3(256), 0, s, dA, which, energy, clear_stale);
+    hipLaunchKernelGGL(k_pairs, dim3(PAIRS_GRID), dim3(256), 0, s, dA, which, energy, mode);
     return hipGetLastError();
 }
 
-hipError_t launch_step(const StepArgs &a, const StepArgs *dA, int fp64, int mode, int write_full, hipStream_t s)
+hipError_t launch_step(const StepArgs &a, const StepArgs *dA, int fp64, int mode, int write_full, int rebuild_after,
+                       int age, hipStream_t s)
 {
     const bool damp = a.ph.dihedral_damping != 0;
-    if (fp64 && damp)
-        hipLaunchKernelGGL((k_step<double, true>), tiles_grid(a), dim3(WG_THREADS), 0, s, dA, mode, write_full);
-    else if (fp64)
-        hipLaunchKernelGGL((k_step<double, false>), tiles_grid(a), dim3(WG_THREADS), 0, s, dA, mode, write_full);
-    else if (damp)
-        hipLaunchKernelGGL((k_step<float, true>), tiles_grid(a), dim3(WG_THREADS), 0, s, dA, mode, write_full);
-    else
-        hipLaunchKernelGGL((k_step<float, false>), tiles_grid(a), dim3(WG_THREADS), 0, s, dA, mode, write_full);
+#define DSDNA_LAUNCH_STEP(R, D)                                                                             \
+    hipLaunchKernelGGL((k_step<R, D>), tiles_grid(a), dim3(WG_THREADS), 0, s, dA, mode, write_full, rebuild_after, \
+                       age)
+    if (fp64 && damp) DSDNA_LAUNCH_STEP(double, true);
+    else if (fp64) DSDNA_LAUNCH_STEP(double, false);
+    else if (damp) DSDNA_LAUNCH_STEP(float, true);
+    else DSDNA_LAUNCH_STEP(float, false);
+#undef DSDNA_LAUNCH_STEP
     return hipGetLastError();
 }
 

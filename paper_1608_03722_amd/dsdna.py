@@ -53,6 +53,18 @@ class Params(C.Structure):
         ("dihedral_damping", C.c_int32), ("skin", C.c_double), ("list_capacity", C.c_int64)]
 
 
+class TuneSpace(C.Structure):
+    _fields_ = [("n_skins", C.c_int32), ("skins", C.c_void_p), ("n_cell_factors", C.c_int32),
+                ("cell_factors", C.c_void_p), ("n_hash_log2s", C.c_int32), ("hash_log2s", C.c_void_p),
+                ("warm_steps", C.c_int64), ("trial_steps", C.c_int64), ("use_cache", C.c_int32)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("skin", C.c_double), ("cell_size", C.c_double), ("hash_log2", C.c_int32),
+                ("interval", C.c_int32), ("ms_per_step", C.c_double), ("candidates", C.c_int32),
+                ("from_cache", C.c_int32)]
+
+
 _lib = None
 
 
@@ -89,12 +101,12 @@ def lib():
             "dsdna_get_bubbles": [vp, i32, vp, vp],
             "dsdna_profile_kernels": [vp, i64, vp],
             "dsdna_get_grid": [vp, vp, vp, vp],
-            "dsdna_autotune": [vp, i32, vp, i32, vp, i64, vp, vp],
+            "dsdna_autotune": [vp, vp, vp],
             "dsdna_set_circular": [vp, vp],
             "dsdna_set_k2_bp": [vp, vp],
             "dsdna_get_linking": [vp, vp, vp, vp],
             "dsdna_get_sizes": [vp, vp, vp, vp],
-            "dsdna_get_neighbour_stats": [vp, vp, vp, vp, vp],
+            "dsdna_get_neighbour_stats": [vp, vp, vp, vp, vp, vp, vp],
             "dsdna_linking_curves_noalloc": [vp, vp, vp, i64, vp, vp],
         }
         for name, args in sigs.items():
@@ -317,11 +329,14 @@ def dsdna_get_sizes(ctx):
 
 
 def dsdna_get_neighbour_stats(ctx):
-    """Since the last state change: dict of rebuilds, steps, pairs (in the
-    current list) and skin."""
-    rb, st, pr, sk = C.c_int64(), C.c_int64(), C.c_int64(), C.c_double()
-    _check(ctx, lib().dsdna_get_neighbour_stats(ctx, C.byref(rb), C.byref(st), C.byref(pr), C.byref(sk)))
-    return {"rebuilds": rb.value, "steps": st.value, "pairs": pr.value, "skin": sk.value}
+    """Since the last state change: rebuilds, steps, outruns (beads that moved
+    half the skin before their rebuild); now: pairs in the list, skin,
+    interval (steps between rebuilds)."""
+    rb, st, ou, pr, sk, iv = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64(), C.c_double(), C.c_int32()
+    _check(ctx, lib().dsdna_get_neighbour_stats(ctx, C.byref(rb), C.byref(st), C.byref(ou), C.byref(pr),
+                                                 C.byref(sk), C.byref(iv)))
+    return {"rebuilds": rb.value, "steps": st.value, "outruns": ou.value, "pairs": pr.value, "skin": sk.value,
+            "interval": iv.value}
 
 
 def dsdna_get_grid(ctx):
@@ -332,14 +347,18 @@ def dsdna_get_grid(ctx):
     return h.value, nb.value, cells
 
 
-def dsdna_autotune(ctx, cell_sizes, hash_log2s, trial_steps):
-    cs = _f64(np.atleast_1d(cell_sizes))
-    hl = np.ascontiguousarray(np.atleast_1d(hash_log2s), dtype=np.int32)
-    bc = C.c_double()
-    bl = C.c_int32()
-    _check(ctx, lib().dsdna_autotune(ctx, len(cs), _p(cs), len(hl), _p(hl), int(trial_steps),
-                                     C.byref(bc), C.byref(bl)))
-    return bc.value, bl.value
+def dsdna_autotune(ctx, skins=None, cell_factors=None, hash_log2s=None, warm_steps=200, trial_steps=200,
+                   use_cache=True):
+    """The fastest (skin, cell edge, bucket count) of the given candidates
+    (None: the current value), as a dict of dsdna_tune_result's fields."""
+    sk = None if skins is None else _f64(np.atleast_1d(skins))
+    cf = None if cell_factors is None else _f64(np.atleast_1d(cell_factors))
+    hl = None if hash_log2s is None else np.ascontiguousarray(np.atleast_1d(hash_log2s), dtype=np.int32)
+    sp = TuneSpace(0 if sk is None else len(sk), _p(sk), 0 if cf is None else len(cf), _p(cf),
+                   0 if hl is None else len(hl), _p(hl), int(warm_steps), int(trial_steps), int(bool(use_cache)))
+    r = TuneResult()
+    _check(ctx, lib().dsdna_autotune(ctx, C.byref(sp), C.byref(r)))
+    return {f: getattr(r, f) for f, _ in TuneResult._fields_}
 
 
 # ----------------------------------------------------- convenience wrapper
@@ -429,5 +448,5 @@ class DsDNA:
     def neighbour_stats(self):
         return dsdna_get_neighbour_stats(self.ctx)
 
-    def autotune(self, cell_sizes, hash_log2s, trial_steps):
-        return dsdna_autotune(self.ctx, cell_sizes, hash_log2s, trial_steps)
+    def autotune(self, **kw):
+        return dsdna_autotune(self.ctx, **kw)

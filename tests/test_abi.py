@@ -62,6 +62,24 @@ def test_params_struct_layout_matches_c(D, tmp_path):
     assert (nt, ne, nk) == (D.NTERMS, D.NENERGY, len(D.KERNELS))
 
 
+@pytest.mark.parametrize("struct,cname", [("TuneSpace", "dsdna_tune_space"), ("TuneResult", "dsdna_tune_result")])
+def test_tune_struct_layouts_match_c(D, tmp_path, struct, cname):
+    S = getattr(D, struct)
+    fields = [f[0] for f in S._fields_]
+    src = tmp_path / "probe.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "dsdna.h"', 'int main(void){',
+             'printf("%%zu\\n", sizeof(%s));' % cname]
+    lines += ['printf("%%zu\\n", offsetof(%s, %s));' % (cname, f) for f in fields]
+    lines += ['return 0;}']
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.check_call(["gcc", "-I" + os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    assert int(out[0]) == C.sizeof(S)
+    for k, f in enumerate(fields):
+        assert int(out[1 + k]) == getattr(S, f).offset, f
+
+
 def _golden(name):
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
     out = {}

@@ -158,13 +158,14 @@ def _thermal_state(cfg, steps, seed):
 @pytest.mark.parametrize("fp64", [0, 1])
 def test_results_do_not_depend_on_skin(D, fp64):
     """400 steps of a 300 bp loop whose arms touch, captured in graphs: the
-    same state bit for bit with skins 0.05 (a rebuild every few steps), 0.5
-    and 1.5, on cells from just above the reach to twice it; the rebuild
-    count falls as the skin grows."""
+    same state bit for bit with skins 0.05 (a rebuild every step or two, and
+    beads that outrun the schedule, which stop the queued steps), 0.5 and
+    1.5, on cells from just above the reach to twice it; the rebuild count
+    falls as the skin grows."""
     bead, patch, n = _nonlocal_contact()
     cfg = dict(n_bp=np.array([n]), bead=bead, patch=patch)
     _, _, st = _thermal_state(cfg, 100, 3)
-    out, rebuilds = [], []
+    out, rebuilds, outruns = [], [], []
     for skin, cell in ((0.05, 0.0), (0.5, 0.0), (1.5, 0.0), (0.5, 3.3)):
         sim = D.DsDNA(cfg, D.dsdna_default_params(seed=3, force_fp64=fp64, skin=skin, cell_size=cell,
                                                   graph_steps=25))
@@ -174,11 +175,13 @@ def test_results_do_not_depend_on_skin(D, fp64):
         ns = sim.neighbour_stats()
         assert ns["steps"] == 400 and ns["skin"] == skin
         rebuilds.append(ns["rebuilds"])
+        outruns.append(ns["outruns"])
         sim.close()
     for o in out[1:]:
         for x, y in zip(o, out[0]):
             assert np.array_equal(x, y)
     assert rebuilds[0] > rebuilds[1] > rebuilds[2] >= 1, rebuilds
+    assert outruns[0] >= 1, outruns   # the recovery path ran
 
 
 def test_list_grows_before_the_first_step(D):

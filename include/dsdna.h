@@ -254,6 +254,32 @@ dsdna_status dsdna_get_state(dsdna_ctx *ctx, double *R, double *V, double *u, do
 dsdna_status dsdna_set_state(dsdna_ctx *ctx, const double *R, const double *V, const double *u,
                              const double *L, int64_t step);
 
+/* Bind caller-owned device arrays as the full-step state (App. A: centres
+ * R, velocities V, axes u, angular momenta L of the rigid nucleotides), so
+ * that device memory from another allocator (torch tensors, say) holds the
+ * state with no host copy.
+ *   R, V, u, L: FP64 device memory of the context's device, each 3N doubles,
+ *     component-major: element k * N + i is component k of nucleotide i (a
+ *     contiguous (3, N) array, the layout the step kernel works in); four
+ *     distinct, non-overlapping arrays.
+ *   Binding makes the arrays' contents the state (as dsdna_set_state, keeping
+ *   the step counter): the next step starts from a force evaluation there.
+ *   From then on every call that changes the state (dsdna_step, _thermalize,
+ *   _set_velocities, _set_state, _set_sites, _set_resume) leaves the
+ *   full-step state in the arrays before it returns, also when a step fails
+ *   with DSDNA_EBOND etc. (the state the error left).  The step kernel writes
+ *   the full-step velocities straight into V and L, and R and u on the last
+ *   step of each call.  After writing into the arrays, bind them again (the
+ *   same pointers will do) for the context to take the new contents.
+ *   All four NULL: unbind; the context keeps the current state.
+ *   Ownership: the arrays stay the caller's; they must outlive the binding
+ *   (dsdna_set_topology and dsdna_destroy end it).  Work on other streams
+ *   that touches them must be ordered with the context's stream by the caller.
+ * Errors: DSDNA_EINVAL when only some pointers are NULL, when an array is not
+ * device memory of the context's device, has fewer than 3N doubles up to the
+ * end of its allocation, or overlaps another; nothing is changed then. */
+dsdna_status dsdna_bind_device(dsdna_ctx *ctx, double *R, double *V, double *u, double *L);
+
 /* Exact resume point: the full-step state plus the total site forces
  * (f_bead, f_patch [N][3], including the Langevin forces) that the next half
  * kick uses.  Restoring it with dsdna_set_resume continues the trajectory
@@ -272,15 +298,18 @@ dsdna_status dsdna_get_sites(dsdna_ctx *ctx, double *bead, double *patch);
  * same device code as the step in the context's precision. */
 dsdna_status dsdna_get_forces(dsdna_ctx *ctx, int32_t term, double *f_bead, double *f_patch);
 
-/* Energies E[n_rep][DSDNA_NENERGY] at the current state. */
+/* Energies E[n_rep][DSDNA_NENERGY] at the current state: the potential
+ * terms and the kinetic energies of the full-step velocities, each summed
+ * per replica on the device in a fixed order. */
 dsdna_status dsdna_get_energies(dsdna_ctx *ctx, double *E);
 
 /* Open flags (H-bond beyond r_c) of every base pair, open[sum n_bp]. */
 dsdna_status dsdna_get_bp_open(dsdna_ctx *ctx, uint8_t *open);
 
-/* Bubble statistics of Sec. 5 per replica: frac[n_rep] = fraction of open
- * base pairs; hist[n_rep][nhist] = number of maximal open runs of length k
- * (k < nhist; longer runs counted in nhist-1). */
+/* Bubble statistics of Sec. 5 per replica, computed on the device: frac[n_rep]
+ * = fraction of open base pairs; hist[n_rep][nhist] = number of maximal open
+ * runs of length k (k < nhist; longer runs counted in nhist-1); on a ring
+ * runs are cyclic and an all-open ring is one run.  2 <= nhist <= 4096. */
 dsdna_status dsdna_get_bubbles(dsdna_ctx *ctx, int32_t nhist, double *frac, int64_t *hist);
 
 /* Run n_steps steps with a HIP event pair around every kernel launch and

@@ -98,7 +98,22 @@ struct dsdna_ctx {
     double *d_curves = nullptr, *d_lkpart = nullptr, *d_lkout = nullptr;
     int lk_blocks = 0, lk_pts = 0;
     hipEvent_t lk_ev[2] = {nullptr, nullptr};
+
+    // per-replica energies, and the bubble statistics' scratch and results
+    // (sized for bub_nhist bins)
+    double *d_rep_e = nullptr;
+    int32_t *d_bub_hist = nullptr;
+    int4 *d_bub_info = nullptr;
+    double *d_bub_frac = nullptr;
+    int64_t *d_bub_out = nullptr;
+    int bub_nhist = 0;
+
+    // the context's own full-step velocity buffers while the caller's arrays
+    // are bound in their place (null when nothing is bound)
+    double *own_Vf = nullptr, *own_Lf = nullptr;
 };
+
+static bool is_bound(const dsdna_ctx *c) { return c->own_Vf != nullptr; }
 
 // ------------------------------------------------------------------ helpers
 
@@ -155,10 +170,28 @@ static void free_rings(dsdna_ctx *c)
     c->lk_blocks = c->lk_pts = 0;
 }
 
+static void free_bubbles(dsdna_ctx *c)
+{
+    dfree(c->d_bub_hist); dfree(c->d_bub_info); dfree(c->d_bub_frac); dfree(c->d_bub_out);
+    c->d_bub_hist = nullptr;
+    c->d_bub_info = nullptr;
+    c->d_bub_frac = nullptr;
+    c->d_bub_out = nullptr;
+    c->bub_nhist = 0;
+}
+
 static void free_state(dsdna_ctx *c)
 {
     free_rings(c);
+    free_bubbles(c);
+    dfree(c->d_rep_e);
+    c->d_rep_e = nullptr;
     Bufs &b = c->a.b;
+    if (is_bound(c)) {  // the bound arrays are the caller's
+        b.Vf = c->own_Vf;
+        b.Lf = c->own_Lf;
+        c->own_Vf = c->own_Lf = nullptr;
+    }
     for (int k = 0; k < 2; ++k) {
         dfree(b.R[k]); dfree(b.u[k]); dfree(b.V[k]); dfree(b.L[k]);
     }
@@ -542,6 +575,39 @@ static dsdna_status rebin(dsdna_ctx *c, int which)
     return DSDNA_OK;
 }
 
+// Make buffer 0 the full-step state at `step`: the next step starts from a
+// force evaluation there.
+static dsdna_status start_from_buffer0(dsdna_ctx *c, int64_t step)
+{
+    dsdna_status st;
+    // a halted step may have left histogram or accumulator entries behind
+    if ((st = clear_accumulators(c))) return st;
+    if ((st = write_ctl(c, step, 0))) return st;
+    c->full_par = 0;
+    c->full_step = step;
+    c->binned_buf = -1;
+    c->phase = PH_FULL;
+    return DSDNA_OK;
+}
+
+// Copy the full-step positions and axes of buffer p into the bound arrays
+// (their velocities are the full-step buffers themselves), and with
+// `velocities` also the buffer's own velocities.
+static dsdna_status mirror_bound(dsdna_ctx *c, int p, bool velocities)
+{
+    if (!is_bound(c)) return DSDNA_OK;
+    Bufs &b = c->a.b;
+    const size_t n = sizeof(double) * 3 * (size_t)c->N;
+    HIPCHK(c, hipMemcpyAsync(b.Rf, b.R[p], n, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(b.uf, b.u[p], n, hipMemcpyDeviceToDevice, c->stream));
+    if (velocities) {
+        HIPCHK(c, hipMemcpyAsync(b.Vf, b.V[p], n, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(b.Lf, b.L[p], n, hipMemcpyDeviceToDevice, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return DSDNA_OK;
+}
+
 static dsdna_status upload_full_state(dsdna_ctx *c, const double *R, const double *V, const double *u,
                                       const double *L, int64_t step)
 {
@@ -560,14 +626,8 @@ static dsdna_status upload_full_state(dsdna_ctx *c, const double *R, const doubl
     }
     HIPCHK(c, hipMemcpyAsync(b.Vf, b.V[0], sizeof(double) * 3 * c->N, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(b.Lf, b.L[0], sizeof(double) * 3 * c->N, hipMemcpyDeviceToDevice, c->stream));
-    // a halted step may have left histogram or accumulator entries behind
-    if ((st = clear_accumulators(c))) return st;
-    if ((st = write_ctl(c, step, 0))) return st;
-    c->full_par = 0;
-    c->full_step = step;
-    c->binned_buf = -1;
-    c->phase = PH_FULL;
-    return DSDNA_OK;
+    if ((st = mirror_bound(c, 0, false))) return st;
+    return start_from_buffer0(c, step);
 }
 
 // Bring a LEAPFROG context back to its full-step state in buffer full_par so
@@ -596,6 +656,9 @@ static dsdna_status status_from_ctl(dsdna_ctx *c, const Ctl &h)
     c->phase = PH_HALTED;
     c->full_par = h.par;
     c->full_step = h.step;
+    // bound arrays show the state the error left, velocities included
+    const dsdna_status ms = mirror_bound(c, h.par, true);
+    if (ms) return ms;
     const char *what = h.code == DSDNA_EBOND    ? "backbone bond reached R0 (FENE energy infinite)"
                        : h.code == DSDNA_ENAN   ? "non-finite position or orientation"
                        : h.code == DSDNA_EWALL  ? "bead reached the anchoring wall"
@@ -840,7 +903,11 @@ static dsdna_status run_diag(dsdna_ctx *c, uint32_t mask)
     }
     HIPCHK(c, hipMemsetAsync(c->a.b.eex, 0, sizeof(double) * (size_t)c->N, c->stream));
     HIPCHK(c, launch_pairs(c->a, c->dA, which, 1, PAIRS_DIAG, c->stream));
-    HIPCHK(c, launch_diag(c->a, c->dA, which, c->prm.force_fp64, mask, c->stream));
+    // the full-step velocities (a halted context keeps them in its buffer)
+    const Bufs &b = c->a.b;
+    const bool halted = c->phase == PH_HALTED;
+    HIPCHK(c, launch_diag(c->a, c->dA, which, c->prm.force_fp64, mask, halted ? b.V[which] : b.Vf,
+                          halted ? b.L[which] : b.Lf, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     Ctl h;
     if ((st = read_ctl(c, &h))) return st;
@@ -1083,7 +1150,8 @@ static dsdna_status build_topology(dsdna_ctx *c, int32_t n_rep, const int32_t *n
     HIPCHK(c, hipMemsetAsync(b.vmax, 0, sizeof(float) * (size_t)a.n_tiles, c->stream));
     HIPCHK(c, dalloc(&b.rep, (size_t)n_rep));
     HIPCHK(c, dalloc(&b.tiles, c->tiles_h.size()));
-    HIPCHK(c, dalloc(&b.eacc, (size_t)a.n_tiles * DSDNA_NTERMS));
+    HIPCHK(c, dalloc(&b.eacc, (size_t)a.n_tiles * DSDNA_NENERGY));
+    HIPCHK(c, dalloc(&c->d_rep_e, (size_t)n_rep * DSDNA_NENERGY));
     HIPCHK(c, dalloc(&b.open, (size_t)c->n_bp_total));
     HIPCHK(c, dalloc(&b.diag_fb, n3)); HIPCHK(c, dalloc(&b.diag_fp, n3));
     c->phase = PH_NONE;
@@ -1386,6 +1454,78 @@ dsdna_status dsdna_set_state(dsdna_ctx *c, const double *R, const double *V, con
     return upload_full_state(c, R, V, u, L, step);
 }
 
+// A caller's array: device memory of the context's device with at least
+// `bytes` from `p` to the end of its allocation.
+static dsdna_status check_device_array(dsdna_ctx *c, const void *p, size_t bytes, const char *name)
+{
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, p) != hipSuccess || at.type != hipMemoryTypeDevice) {
+        (void)hipGetLastError();
+        return fail(c, DSDNA_EINVAL, "%s is not device memory", name);
+    }
+    if (at.device != c->device) return fail(c, DSDNA_EINVAL, "%s is on device %d, not %d", name, at.device, c->device);
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, DSDNA_EINVAL, "%s: no allocation range", name);
+    }
+    const size_t used = (size_t)((const char *)p - (const char *)base);
+    if (used > size || size - used < bytes)
+        return fail(c, DSDNA_EINVAL, "%s: %zu bytes needed, %zu available", name, bytes, size - used);
+    return DSDNA_OK;
+}
+
+dsdna_status dsdna_bind_device(dsdna_ctx *c, double *R, double *V, double *u, double *L)
+{
+    dsdna_status st = check_ready(c, false);
+    if (st) return st;
+    HIPCHK(c, hipSetDevice(c->device));
+    Bufs &b = c->a.b;
+    const size_t n = sizeof(double) * 3 * (size_t)c->N;
+    if (!R && !V && !u && !L) {
+        // unbind: the full-step velocities go back to the context's buffers
+        if (!is_bound(c)) return DSDNA_OK;
+        HIPCHK(c, hipMemcpyAsync(c->own_Vf, b.Vf, n, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->own_Lf, b.Lf, n, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        b.Vf = c->own_Vf;
+        b.Lf = c->own_Lf;
+        b.Rf = b.uf = nullptr;
+        c->own_Vf = c->own_Lf = nullptr;
+        return DSDNA_OK;
+    }
+    if (!R || !V || !u || !L) return fail(c, DSDNA_EINVAL, "bind R, V, u and L together (or pass none to unbind)");
+    double *arr[4] = {R, V, u, L};
+    const char *names[4] = {"R", "V", "u", "L"};
+    for (int k = 0; k < 4; ++k) {
+        if ((st = check_device_array(c, arr[k], n, names[k]))) return st;
+        for (int q = 0; q < k; ++q) {
+            const char *a0 = (const char *)arr[k], *a1 = (const char *)arr[q];
+            if (a0 < a1 + n && a1 < a0 + n) return fail(c, DSDNA_EINVAL, "%s and %s overlap", names[q], names[k]);
+        }
+    }
+    // finish queued work that may still write the full-step buffers
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (!is_bound(c)) {
+        c->own_Vf = b.Vf;
+        c->own_Lf = b.Lf;
+    }
+    b.Rf = R;
+    b.uf = u;
+    b.Vf = V;
+    b.Lf = L;
+    // the arrays' contents become the state; the step counter goes on
+    const int64_t step = c->phase == PH_NONE ? 0 : c->full_step;
+    HIPCHK(c, hipMemcpyAsync(b.R[0], R, n, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(b.u[0], u, n, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(b.V[0], V, n, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(b.L[0], L, n, hipMemcpyDeviceToDevice, c->stream));
+    if ((st = start_from_buffer0(c, step))) return st;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return DSDNA_OK;
+}
+
 dsdna_status dsdna_get_resume(dsdna_ctx *c, double *R, double *V, double *u, double *L, double *fb, double *fp,
                               int64_t *step)
 {
@@ -1443,23 +1583,8 @@ dsdna_status dsdna_get_energies(dsdna_ctx *c, double *E)
     if (st) return st;
     if (!E) return fail(c, DSDNA_EINVAL, "null E");
     if ((st = run_diag(c, (1u << DSDNA_NTERMS) - 1u))) return st;
-    std::vector<double> part((size_t)c->a.n_tiles * DSDNA_NTERMS);
-    if ((st = copy(c, part.data(), c->a.b.eacc, sizeof(double) * part.size(), hipMemcpyDeviceToHost))) return st;
-    std::fill(E, E + (size_t)c->n_rep * DSDNA_NENERGY, 0.0);
-    for (int t = 0; t < c->a.n_tiles; ++t)
-        for (int k = 0; k < DSDNA_NTERMS; ++k) E[(size_t)c->tiles_h[t].rep * DSDNA_NENERGY + k] += part[(size_t)t * DSDNA_NTERMS + k];
-    std::vector<double> V(3 * c->N), L(3 * c->N);
-    if ((st = dsdna_get_state(c, nullptr, V.data(), nullptr, L.data(), nullptr))) return st;
-    for (int r = 0; r < c->n_rep; ++r) {
-        double kt = 0.0, kr = 0.0;
-        for (int64_t i = c->off[r]; i < c->off[r] + 2 * (int64_t)c->n_bp[r]; ++i) {
-            kt += 0.5 * c->a.ph.M * (V[3 * i] * V[3 * i] + V[3 * i + 1] * V[3 * i + 1] + V[3 * i + 2] * V[3 * i + 2]);
-            kr += 0.5 * (L[3 * i] * L[3 * i] + L[3 * i + 1] * L[3 * i + 1] + L[3 * i + 2] * L[3 * i + 2]) / c->a.ph.I;
-        }
-        E[(size_t)r * DSDNA_NENERGY + DSDNA_NTERMS] = kt;
-        E[(size_t)r * DSDNA_NENERGY + DSDNA_NTERMS + 1] = kr;
-    }
-    return DSDNA_OK;
+    HIPCHK(c, launch_rep_energy(c->a, c->dA, c->d_rep_e, c->n_rep, c->stream));
+    return copy(c, E, c->d_rep_e, sizeof(double) * (size_t)c->n_rep * DSDNA_NENERGY, hipMemcpyDeviceToHost);
 }
 
 dsdna_status dsdna_get_bp_open(dsdna_ctx *c, uint8_t *open)
@@ -1476,38 +1601,24 @@ dsdna_status dsdna_get_bubbles(dsdna_ctx *c, int32_t nhist, double *frac, int64_
 {
     dsdna_status st = check_ready(c, true);
     if (st) return st;
-    if (nhist < 2 || !frac || !hist) return fail(c, DSDNA_EINVAL, "need nhist >= 2, frac and hist");
-    std::vector<uint8_t> op((size_t)c->n_bp_total);
-    if ((st = dsdna_get_bp_open(c, op.data()))) return st;
-    int64_t base = 0;
-    for (int r = 0; r < c->n_rep; ++r) {
-        int64_t *h = hist + (size_t)r * nhist;
-        std::fill(h, h + nhist, 0);
-        int64_t nopen = 0, k = 0;
-        const int64_t nb = c->n_bp[r];
-        // on a ring, runs are read from just after a closed base pair z, so
-        // a run through the seam counts once; an all-open ring is one run
-        const bool ring = c->rep_h[r].flags & REP_RING;
-        int64_t z = 0;
-        if (ring) while (z < nb && op[base + z]) ++z;
-        const auto at = [&](int64_t q) { return op[base + (ring ? (z + q) % nb : q)]; };
-        if (ring && z == nb) {
-            nopen = nb;
-            h[std::min<int64_t>(nb, nhist - 1)] += 1;
-            k = nb;
+    if (nhist < 2 || nhist > 4096 || !frac || !hist)
+        return fail(c, DSDNA_EINVAL, "need 2 <= nhist <= 4096, frac and hist");
+    if ((st = run_diag(c, 1u << DSDNA_TERM_HBOND))) return st;
+    if (nhist > c->bub_nhist) {
+        free_bubbles(c);
+        if (dalloc(&c->d_bub_hist, (size_t)c->a.n_tiles * nhist) != hipSuccess ||
+            dalloc(&c->d_bub_info, (size_t)c->a.n_tiles) != hipSuccess ||
+            dalloc(&c->d_bub_frac, (size_t)c->n_rep) != hipSuccess ||
+            dalloc(&c->d_bub_out, (size_t)c->n_rep * nhist) != hipSuccess) {
+            free_bubbles(c);
+            return fail(c, DSDNA_ENOMEM, "bubble statistics: allocation failed");
         }
-        while (k < nb) {
-            if (!at(k)) { ++k; continue; }
-            int64_t e = k;
-            while (e < nb && at(e)) ++e;
-            nopen += e - k;
-            h[std::min<int64_t>(e - k, nhist - 1)] += 1;
-            k = e;
-        }
-        frac[r] = (double)nopen / (double)nb;
-        base += nb;
+        c->bub_nhist = nhist;
     }
-    return DSDNA_OK;
+    HIPCHK(c, launch_bubbles(c->a, c->dA, nhist, c->d_bub_hist, c->d_bub_info, c->d_bub_frac, c->d_bub_out, c->n_rep,
+                             c->stream));
+    if ((st = copy(c, frac, c->d_bub_frac, sizeof(double) * (size_t)c->n_rep, hipMemcpyDeviceToHost))) return st;
+    return copy(c, hist, c->d_bub_out, sizeof(int64_t) * (size_t)c->n_rep * nhist, hipMemcpyDeviceToHost);
 }
 
 dsdna_status dsdna_profile_kernels(dsdna_ctx *c, int64_t n_steps, double *ms)

@@ -145,6 +145,7 @@ struct Grid {
 struct Bufs {
     double *R[2], *u[2], *V[2], *L[2];  // SoA [3][N] (x block, y block, z block)
     double *Vf, *Lf;                    // full-step velocities of the last step
+    double *Rf, *uf;                    // caller-bound full-step R and u, or null
     double *Fb, *Fp;                    // full-step site forces (SoA [3][N])
     BeadRec *rec;                       // bead record per nucleotide
     int4 *rcell;                        // cell (x, y, z) of each bead (open edges only)
@@ -249,10 +250,19 @@ hipError_t launch_scatter(const StepArgs &a, hipStream_t s);
 hipError_t launch_build(const StepArgs &a, const StepArgs *dA, hipStream_t s);
 hipError_t launch_thermalize(const StepArgs &a, const StepArgs *dA, double kT, uint64_t seed, hipStream_t s);
 // term_mask: bit t selects term t; writes per-term forces (AoS doubles) to
-// b.diag_fb / b.diag_fp, energies per tile to b.eacc[tile][DSDNA_NTERMS] and
-// open flags per bp to b.open.
+// b.diag_fb / b.diag_fp, energies per tile to b.eacc[tile][DSDNA_NENERGY]
+// (the kinetic ones from the velocities Vk, Lk, SoA [3][N]) and open flags
+// per bp to b.open.
 hipError_t launch_diag(const StepArgs &a, const StepArgs *dA, int which, int fp64, uint32_t term_mask,
-                       hipStream_t s);
+                       const double *Vk, const double *Lk, hipStream_t s);
+// Per replica: the tiles' energy partials summed in a fixed order into
+// out[n_rep][DSDNA_NENERGY] (device).
+hipError_t launch_rep_energy(const StepArgs &a, const StepArgs *dA, double *out, int n_rep, hipStream_t s);
+// Bubble statistics (Sec. 5) of the open flags in b.open: frac[n_rep] and
+// out[n_rep][nhist] (device); hist_tiles[n_tiles][nhist] and info[n_tiles]
+// are scratch.
+hipError_t launch_bubbles(const StepArgs &a, const StepArgs *dA, int nhist, int32_t *hist_tiles, int4 *info,
+                          double *frac, int64_t *out, int n_rep, hipStream_t s);
 // Linking number of the strands and writhe of the centreline of every ring
 // from the positions in buffer `which`: curves (3 curves x n_pts points x 3
 // doubles) and partial ([n_blocks][2]) are scratch, out[n_rings][2]

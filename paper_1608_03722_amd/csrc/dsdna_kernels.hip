@@ -1036,6 +1036,10 @@ __global__ void __launch_bounds__(WG_THREADS, 5) k_step(const StepArgs *__restri
                 st3(a.b.Lf, N, i, L);
                 st3(a.b.Fb, N, i, fb);
                 st3(a.b.Fp, N, i, fp);
+                if (a.b.Rf) {
+                    st3(a.b.Rf, N, i, R);
+                    st3(a.b.uf, N, i, u);
+                }
             }
         } else {
             const D3 F = fb + fp;
@@ -1050,6 +1054,10 @@ __global__ void __launch_bounds__(WG_THREADS, 5) k_step(const StepArgs *__restri
                 st3(a.b.Lf, N, i, L);
                 st3(a.b.Fb, N, i, fb);
                 st3(a.b.Fp, N, i, fp);
+                if (a.b.Rf) {  // bound arrays: the full-step positions and axes too
+                    st3(a.b.Rf, N, i, R);
+                    st3(a.b.uf, N, i, u);
+                }
             }
             // first half kick, drift, free rotation of the linear rotor
             V = V + F * km;
@@ -1926,11 +1934,15 @@ __global__ void __launch_bounds__(64) k_gauss_curves_sum(const double *__restric
 
 // --------------------------------------------------------------- diagnostics
 
+// Per-term forces and energies of the positions in buffer `which`, plus the
+// kinetic energies of the velocities Vk, Lk (the full-step ones): per tile,
+// energies in a fixed-order reduction into eacc[tile][DSDNA_NENERGY].
 template <typename real, bool DAMP>
-__global__ void __launch_bounds__(WG_THREADS) k_diag(const StepArgs *__restrict__ A, int which, uint32_t mask)
+__global__ void __launch_bounds__(WG_THREADS) k_diag(const StepArgs *__restrict__ A, int which, uint32_t mask,
+                                                    const double *__restrict__ Vk, const double *__restrict__ Lk)
 {
     __shared__ TileLds<real> S;
-    __shared__ double red[DSDNA_NTERMS][WG_THREADS / 64];
+    __shared__ double red[DSDNA_NENERGY][WG_THREADS / 64];
     const StepArgs &a = *A;
     // the cell list is only valid when the binning before this launch
     // completed without error
@@ -1939,8 +1951,8 @@ __global__ void __launch_bounds__(WG_THREADS) k_diag(const StepArgs *__restrict_
     if (tix >= a.n_tiles) return;
     const Tile tile = a.b.tiles[tix];
     const RepInfo &ri = a.b.rep[tile.rep];
-    double e[DSDNA_NTERMS];
-    for (int k = 0; k < DSDNA_NTERMS; ++k) e[k] = 0.0;
+    double e[DSDNA_NENERGY];
+    for (int k = 0; k < DSDNA_NENERGY; ++k) e[k] = 0.0;
     const int64_t step = a.b.ctl->step;
     const StagedSite site = load_site(a, ri, tile, which);
     const int s = threadIdx.x & 1, bl = threadIdx.x >> 1, n = threadIdx.x < TILE_NT ? tile.n0 + bl : tile.n_bp;
@@ -1957,19 +1969,140 @@ __global__ void __launch_bounds__(WG_THREADS) k_diag(const StepArgs *__restrict_
         a.b.diag_fp[3 * i + 1] = (double)f.p.y;
         a.b.diag_fp[3 * i + 2] = (double)f.p.z;
         if (s == 0) a.b.open[ri.off / 2 + n] = S.sOpen[bl + HALO_BP];
+        // kinetic energies of the rigid body: M V^2 / 2 and L^2 / (2 I)
+        const D3 V = ld3(Vk, a.n_nt, i), L = ld3(Lk, a.n_nt, i);
+        e[DSDNA_NTERMS] = 0.5 * a.ph.M * dot(V, V);
+        e[DSDNA_NTERMS + 1] = 0.5 * dot(L, L) * a.ph.inv_I;
     }
     // per-tile energy partials: fixed-order reduction
-    for (int k = 0; k < DSDNA_NTERMS; ++k) {
+    for (int k = 0; k < DSDNA_NENERGY; ++k) {
         double v = e[k];
         for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
         if ((threadIdx.x & 63) == 0) red[k][threadIdx.x >> 6] = v;
     }
     __syncthreads();
-    if (threadIdx.x < DSDNA_NTERMS) {
+    if (threadIdx.x < DSDNA_NENERGY) {
         double v = 0.0;
         for (int w = 0; w < WG_THREADS / 64; ++w) v += red[threadIdx.x][w];
-        a.b.eacc[(int64_t)tix * DSDNA_NTERMS + threadIdx.x] = v;
+        a.b.eacc[(int64_t)tix * DSDNA_NENERGY + threadIdx.x] = v;
     }
+}
+
+// Tiles of replica r: the first and the number of them.
+__device__ __forceinline__ int2 replica_tiles(const RepInfo &ri) { return make_int2(ri.tile0, (ri.n_bp + TILE_BP - 1) / TILE_BP); }
+
+// Per replica, the energy partials of its tiles summed in a fixed order
+// (thread t takes tiles t, t + 256, ...; then a fixed tree):
+// out[r][DSDNA_NENERGY].  One workgroup per replica.
+__global__ void __launch_bounds__(256) k_rep_energy(const StepArgs *__restrict__ A, double *__restrict__ out)
+{
+    __shared__ double red[256];
+    const StepArgs &a = *A;
+    const int r = blockIdx.x, t = threadIdx.x;
+    const int2 tl = replica_tiles(a.b.rep[r]);
+    for (int k = 0; k < DSDNA_NENERGY; ++k) {
+        double v = 0.0;
+        for (int q = t; q < tl.y; q += 256) v += a.b.eacc[(int64_t)(tl.x + q) * DSDNA_NENERGY + k];
+        red[t] = v;
+        for (int w = 128; w > 0; w >>= 1) {
+            __syncthreads();
+            if (t < w) red[t] += red[t + w];
+        }
+        __syncthreads();
+        if (t == 0) out[(int64_t)r * DSDNA_NENERGY + k] = red[0];
+        __syncthreads();
+    }
+}
+
+// Bubbles (Sec. 5: maximal runs of open base pairs), per tile of the open
+// flags: hist[tile][nhist] counts the runs inside the tile that touch
+// neither of its ends (length k, k >= nhist - 1 in the last bin); info[tile]
+// = (open run at its start, open run at its end, open base pairs, base
+// pairs).  One thread per tile.
+__global__ void __launch_bounds__(64) k_bubble_tiles(const StepArgs *__restrict__ A, int nhist,
+                                                    int32_t *__restrict__ hist, int4 *__restrict__ info)
+{
+    const StepArgs &a = *A;
+    const int tix = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tix >= a.n_tiles) return;
+    const Tile tile = a.b.tiles[tix];
+    const RepInfo &ri = a.b.rep[tile.rep];
+    const int len = min(TILE_BP, tile.n_bp - tile.n0);
+    const uint8_t *op = a.b.open + ri.off / 2 + tile.n0;
+    int32_t *h = hist + (int64_t)tix * nhist;
+    for (int k = 0; k < nhist; ++k) h[k] = 0;
+    int lead = 0;
+    while (lead < len && op[lead]) ++lead;
+    int nopen = lead, q = lead, trail = 0;
+    if (lead == len) {
+        trail = len;
+    } else {
+        while (q < len) {
+            if (!op[q]) {
+                ++q;
+                continue;
+            }
+            int e = q;
+            while (e < len && op[e]) ++e;
+            nopen += e - q;
+            if (e == len) trail = e - q;  // touches the end: counted across tiles
+            else h[min(e - q, nhist - 1)] += 1;
+            q = e;
+        }
+    }
+    info[tix] = make_int4(lead, trail, nopen, len);
+}
+
+// Per replica: the interior runs of its tiles summed bin by bin in tile
+// order, then the runs across tile boundaries by one thread walking the
+// tiles (an open run continues through all-open tiles; on a ring the run at
+// the end joins the run at the start, and an all-open ring is one run):
+// frac[r] = open fraction, out[r][nhist].  One workgroup per replica.
+__global__ void __launch_bounds__(256) k_bubble_rep(const StepArgs *__restrict__ A, int nhist,
+                                                   const int32_t *__restrict__ hist, const int4 *__restrict__ info,
+                                                   double *__restrict__ frac, int64_t *__restrict__ out)
+{
+    extern __shared__ int64_t sh[];  // nhist bins
+    const StepArgs &a = *A;
+    const int r = blockIdx.x, t = threadIdx.x;
+    const RepInfo &ri = a.b.rep[r];
+    const int2 tl = replica_tiles(ri);
+    for (int k = t; k < nhist; k += blockDim.x) {
+        int64_t v = 0;
+        for (int q = 0; q < tl.y; ++q) v += hist[(int64_t)(tl.x + q) * nhist + k];
+        sh[k] = v;
+    }
+    __syncthreads();
+    if (t == 0) {
+        const auto bin = [nhist](int64_t len) { return (int)(len < nhist - 1 ? len : nhist - 1); };
+        const bool ring = ri.flags & REP_RING;
+        int64_t nopen = 0, carry = 0, first = -1;  // first: the open run at the replica's start
+        bool all_open = true;
+        for (int q = 0; q < tl.y; ++q) {
+            const int4 in = info[tl.x + q];
+            nopen += in.z;
+            if (in.x == in.w) {  // an all-open tile: the run goes on
+                carry += in.w;
+                continue;
+            }
+            all_open = false;
+            const int64_t run = carry + in.x;  // the run that ends at this tile's first closed bp
+            if (first < 0) first = run;
+            else if (run > 0) sh[bin(run)] += 1;
+            carry = in.y;
+        }
+        if (all_open) {
+            if (ri.n_bp > 0) sh[bin(ri.n_bp)] += 1;
+        } else if (ring) {
+            if (carry + first > 0) sh[bin(carry + first)] += 1;
+        } else {
+            if (first > 0) sh[bin(first)] += 1;
+            if (carry > 0) sh[bin(carry)] += 1;
+        }
+        frac[r] = ri.n_bp > 0 ? (double)nopen / (double)ri.n_bp : 0.0;
+    }
+    __syncthreads();
+    for (int k = t; k < nhist; k += blockDim.x) out[(int64_t)r * nhist + k] = sh[k];
 }
 
 // ---------------------------------------------------------------- launchers
@@ -2048,17 +2181,32 @@ hipError_t launch_thermalize(const StepArgs &a, const StepArgs *dA, double kT, u
 }
 
 hipError_t launch_diag(const StepArgs &a, const StepArgs *dA, int which, int fp64, uint32_t term_mask,
-                       hipStream_t s)
+                       const double *Vk, const double *Lk, hipStream_t s)
 {
     const bool damp = a.ph.dihedral_damping != 0;
-    if (fp64 && damp)
-        hipLaunchKernelGGL((k_diag<double, true>), tiles_grid(a), dim3(WG_THREADS), 0, s, dA, which, term_mask);
-    else if (fp64)
-        hipLaunchKernelGGL((k_diag<double, false>), tiles_grid(a), dim3(WG_THREADS), 0, s, dA, which, term_mask);
-    else if (damp)
-        hipLaunchKernelGGL((k_diag<float, true>), tiles_grid(a), dim3(WG_THREADS), 0, s, dA, which, term_mask);
-    else
-        hipLaunchKernelGGL((k_diag<float, false>), tiles_grid(a), dim3(WG_THREADS), 0, s, dA, which, term_mask);
+#define DSDNA_LAUNCH_DIAG(R, D) \
+    hipLaunchKernelGGL((k_diag<R, D>), tiles_grid(a), dim3(WG_THREADS), 0, s, dA, which, term_mask, Vk, Lk)
+    if (fp64 && damp) DSDNA_LAUNCH_DIAG(double, true);
+    else if (fp64) DSDNA_LAUNCH_DIAG(double, false);
+    else if (damp) DSDNA_LAUNCH_DIAG(float, true);
+    else DSDNA_LAUNCH_DIAG(float, false);
+#undef DSDNA_LAUNCH_DIAG
+    return hipGetLastError();
+}
+
+hipError_t launch_rep_energy(const StepArgs &a, const StepArgs *dA, double *out, int n_rep, hipStream_t s)
+{
+    (void)a;
+    hipLaunchKernelGGL(k_rep_energy, dim3(n_rep), dim3(256), 0, s, dA, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_bubbles(const StepArgs &a, const StepArgs *dA, int nhist, int32_t *hist_tiles, int4 *info,
+                          double *frac, int64_t *out, int n_rep, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bubble_tiles, dim3((a.n_tiles + 63) / 64), dim3(64), 0, s, dA, nhist, hist_tiles, info);
+    hipLaunchKernelGGL(k_bubble_rep, dim3(n_rep), dim3(256), sizeof(int64_t) * (size_t)nhist, s, dA, nhist,
+                       hist_tiles, info, frac, out);
     return hipGetLastError();
 }
 

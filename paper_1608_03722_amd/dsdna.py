@@ -31,7 +31,7 @@ EXPORTS = (
     "dsdna_get_resume", "dsdna_set_resume", "dsdna_get_sites", "dsdna_get_forces", "dsdna_get_energies",
     "dsdna_get_bp_open", "dsdna_get_bubbles", "dsdna_profile_kernels", "dsdna_get_grid", "dsdna_autotune",
     "dsdna_set_circular", "dsdna_get_linking", "dsdna_set_k2_bp", "dsdna_get_sizes",
-    "dsdna_get_neighbour_stats", "dsdna_linking_curves_noalloc",
+    "dsdna_get_neighbour_stats", "dsdna_linking_curves_noalloc", "dsdna_bind_device",
 )
 NOALLOC_MAX_POINTS = 1048576
 
@@ -75,6 +75,14 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError("libdsdna.so is not built (run __graft_entry__.build()); "
                               "there is no fallback path")
+        # torch brings a HIP runtime of its own under the same soname; loaded
+        # first, it is the one the library binds to, so that torch's device
+        # memory and streams are valid in the library's calls.  (Loaded
+        # after the library, it would start a second runtime.)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
         sigs = {
@@ -108,6 +116,7 @@ def lib():
             "dsdna_get_sizes": [vp, vp, vp, vp],
             "dsdna_get_neighbour_stats": [vp, vp, vp, vp, vp, vp, vp],
             "dsdna_linking_curves_noalloc": [vp, vp, vp, i64, vp, vp],
+            "dsdna_bind_device": [vp, vp, vp, vp, vp],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
@@ -323,6 +332,26 @@ def dsdna_linking_curves_noalloc(A, B, C, n, out, stream=None):
         raise DsdnaError(st, lib().dsdna_last_error(None).decode())
 
 
+def _device_array(x, n_nt, name):
+    """Device address of a caller array for dsdna_bind_device: a torch
+    tensor (float64, contiguous, shape (3, n_nt), on a GPU) or an int."""
+    if x is None or isinstance(x, int):
+        return x
+    if str(x.dtype) != "torch.float64" or tuple(x.shape) != (3, n_nt) or not x.is_contiguous() \
+            or x.device.type != "cuda":
+        raise ValueError("%s must be a contiguous float64 GPU tensor of shape (3, %d), got %s %s on %s"
+                         % (name, n_nt, x.dtype, tuple(x.shape), x.device))
+    return x.data_ptr()
+
+
+def dsdna_bind_device(ctx, R, V, u, L):
+    """Bind caller device arrays (component-major (3, N) float64) as the
+    full-step state; all None unbinds."""
+    n_nt = _sizes(ctx)[1]
+    ptrs = [_device_array(x, n_nt, nm) for x, nm in zip((R, V, u, L), "RVuL")]
+    _check(ctx, lib().dsdna_bind_device(ctx, *ptrs))
+
+
 def dsdna_get_sizes(ctx):
     """(n_rep, n_nt, n_bp_total)."""
     return _sizes(ctx)
@@ -370,6 +399,8 @@ class DsDNA:
 
     def __init__(self, cfg, params: Params | None = None, device=0, stream=None):
         self.params = params if params is not None else dsdna_default_params()
+        self.device = device
+        self.bound = None
         self.ctx = dsdna_create(self.params, device, stream)
         self.n_bp = np.ascontiguousarray(cfg["n_bp"], dtype=np.int32)
         self.n_rep = len(self.n_bp)
@@ -396,6 +427,25 @@ class DsDNA:
         if self.ctx:
             dsdna_destroy(self.ctx)
             self.ctx = None
+        self.bound = None
+
+    def bind_device(self, tensors=None):
+        """Hold the full-step state in torch tensors (R, V, u, L), each
+        float64 (3, N) on the context's GPU; with None, new tensors filled
+        with the current state.  Returns the tensors, which the context keeps
+        referenced while they are bound."""
+        if tensors is None:
+            import torch
+            R, V, u, L, _ = self.state()
+            tensors = tuple(torch.from_numpy(np.ascontiguousarray(a.T)).to("cuda:%d" % self.device)
+                            for a in (R, V, u, L))
+        dsdna_bind_device(self.ctx, *tensors)
+        self.bound = tuple(tensors)
+        return self.bound
+
+    def unbind_device(self):
+        dsdna_bind_device(self.ctx, None, None, None, None)
+        self.bound = None
 
     def __del__(self):
         try:

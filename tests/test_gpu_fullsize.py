@@ -153,3 +153,21 @@ def test_denaturation_full_size():
     assert np.array_equal(sim.bp_open(), op)
     assert op.sum() > 0  # frayed ends and bubbles are present
     sim.close()
+
+
+def test_observables_1mbp(run):
+    """Open flags, bubble histogram and kinetic energies of the 2e6
+    nucleotides, element by element against the oracle on the same state."""
+    D, cfg, sim, (R, V, u, L, k) = run
+    P = O.default_params(seed=0)
+    S = _oracle_system(cfg)
+    b, p = O.sites_from_bodies(P, R, u)
+    op = O.forces(P, S, b, p, use_cells=True)[5]
+    assert np.array_equal(sim.bp_open(), op)
+    frac, hist = sim.bubbles(64)
+    f_ref, h_ref = O.bubbles(op, 64)
+    assert frac[0] == f_ref and np.array_equal(hist[0], h_ref)
+    E = sim.energies()
+    kt, kr = O.kinetic(P, S, O.State(R, u, V, L, k))
+    assert E[0, D.NTERMS] == pytest.approx(kt[0], rel=1e-12) and E[0, D.NTERMS + 1] == pytest.approx(kr[0], rel=1e-12)
+

@@ -59,31 +59,73 @@ __device__ __forceinline__ V3<R> cvt(V3<T> a) { return v3((R)a.x, (R)a.y, (R)a.z
 
 using D3 = V3<double>;
 
+// Every buffer is global memory, but a pointer read out of the argument block
+// is generic to the compiler, which then emits FLAT accesses: 64-bit
+// addresses per lane, and each access also counted against the LDS wait
+// counter, so that waiting for LDS waits for memory as well.  Accesses in the
+// hot kernels go through address-space-1 pointers instead.
+// (The host pass, which only parses device code, keeps generic pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+#else
+template <typename T>
+using gptr = T *;
+#endif
+template <typename T>
+__device__ __forceinline__ gptr<T> gmem(T *p) { return (gptr<T>)p; }
+// Read-only records that are the same for a whole workgroup (a tile, its
+// replica) come through the constant address space: scalar loads.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using cptr = __attribute__((address_space(4))) const T *;
+#else
+template <typename T>
+using cptr = const T *;
+#endif
+template <typename T>
+__device__ __forceinline__ T cload(const T *p) { return *(cptr<T>)p; }
+// Relaxed device-scope atomics on global memory.
+template <typename T>
+__device__ __forceinline__ T g_add(T *p, T v)
+{
+    return __hip_atomic_fetch_add(gmem(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T g_max(T *p, T v)
+{
+    return __hip_atomic_fetch_max(gmem(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // The body state a step reads was written past the caches by the previous
 // step and is read once: loaded non-temporally too (-2 us at 1 Mbp).
-__device__ __forceinline__ D3 ld3nt(const double *soa, int64_t n, int64_t i)
+__device__ __forceinline__ D3 ld3nt(const double *soa_, int64_t n, int64_t i)
 {
+    const gptr<const double> soa = gmem(soa_);
     return v3(__builtin_nontemporal_load(soa + i), __builtin_nontemporal_load(soa + n + i),
               __builtin_nontemporal_load(soa + 2 * n + i));
 }
 
-__device__ __forceinline__ D3 ld3(const double *soa, int64_t n, int64_t i)
+__device__ __forceinline__ D3 ld3(const double *soa_, int64_t n, int64_t i)
 {
+    const gptr<const double> soa = gmem(soa_);
     return v3(soa[i], soa[n + i], soa[2 * n + i]);
 }
 // The next step's body state is read back only by the next step's tile
 // kernel: written past the caches (non-temporal), it leaves the cache to the
 // cell-list arrays that the scatter and the excluded-volume pass reuse
 // (measured: -2.5 us in the step kernel, -3.8 us in the scatter at 1 Mbp).
-__device__ __forceinline__ void st3nt(double *soa, int64_t n, int64_t i, D3 a)
+__device__ __forceinline__ void st3nt(double *soa_, int64_t n, int64_t i, D3 a)
 {
+    const gptr<double> soa = gmem(soa_);
     __builtin_nontemporal_store(a.x, soa + i);
     __builtin_nontemporal_store(a.y, soa + n + i);
     __builtin_nontemporal_store(a.z, soa + 2 * n + i);
 }
 
-__device__ __forceinline__ void st3(double *soa, int64_t n, int64_t i, D3 a)
+__device__ __forceinline__ void st3(double *soa_, int64_t n, int64_t i, D3 a)
 {
+    const gptr<double> soa = gmem(soa_);
     soa[i] = a.x;
     soa[n + i] = a.y;
     soa[2 * n + i] = a.z;
@@ -330,7 +372,7 @@ __device__ __forceinline__ uint32_t make_tag(int rep, int n, int s)
 __device__ __forceinline__ int hist_add(const StepArgs &a, uint32_t key, int n, int64_t i, int64_t step)
 {
     const uint32_t sh = (key & 1u) << 4;
-    const uint32_t old = atomicAdd(&a.b.count[key >> 1], (uint32_t)n << sh);
+    const uint32_t old = g_add(&a.b.count[key >> 1], (uint32_t)n << sh);
     const int base = (int)((old >> sh) & 0xFFFFu);
     if (base + n > 0xFFFF) raise_error(a.b.ctl, DSDNA_ECELL, step, i);
     return base;
@@ -367,9 +409,9 @@ __device__ __forceinline__ void bin_tile(const StepArgs &a, uint32_t *tab, uint3
         r.y = qc[1];
         r.z = qc[2];
         r.tag = make_tag(rep, n, s);
-        a.b.rec[i] = r;
-        if (a.g.any_open) a.b.rcell[i] = make_int4(c[0], c[1], c[2], 0);
-        a.b.key[i] = (int32_t)key;
+        gmem(a.b.rec)[i] = r;
+        if (a.g.any_open) gmem(a.b.rcell)[i] = make_int4(c[0], c[1], c[2], 0);
+        gmem(a.b.key)[i] = (int32_t)key;
         e = (int)((key * 2654435761u) >> 24) & (WG_THREADS - 1);
         for (;;) {
             const uint32_t old = atomicCAS(&tab[e], EMPTY, key);
@@ -381,7 +423,7 @@ __device__ __forceinline__ void bin_tile(const StepArgs &a, uint32_t *tab, uint3
     __syncthreads();
     if (tab[t] != EMPTY) base[t] = hist_add(a, tab[t], (int)cnt[t], i, step);
     __syncthreads();
-    if (own) a.b.slot[i] = base[e] + (int)rank;
+    if (own) gmem(a.b.slot)[i] = base[e] + (int)rank;
 }
 
 // ------------------------------------------------------------------- tiles
@@ -487,7 +529,7 @@ __device__ __forceinline__ void stage_site(const StepArgs &a, TileLds<real> &S, 
 // excluded-volume accumulator may be nonzero.
 __device__ __forceinline__ bool contact_flag(const StepArgs &a, int tix)
 {
-    const uint32_t w = a.b.cmask[(int64_t)tix * CMASK_WORDS + (threadIdx.x >> 5)];
+    const uint32_t w = gmem(a.b.cmask)[(int64_t)tix * CMASK_WORDS + (threadIdx.x >> 5)];
     return (w >> (threadIdx.x & 31)) & 1u;
 }
 
@@ -497,12 +539,12 @@ __device__ __forceinline__ bool contact_flag(const StepArgs &a, int tix)
 template <typename real>
 __device__ __forceinline__ V3<real> take_fex(const StepArgs &a, int64_t i)
 {
-    unsigned long long *f = a.b.fex + FEX_WORDS * i;
-    const longlong4 hi = *reinterpret_cast<const longlong4 *>(f);
-    const longlong4 lo = *reinterpret_cast<const longlong4 *>(f + 4);
+    const gptr<longlong4> f = gmem(reinterpret_cast<longlong4 *>(a.b.fex + FEX_WORDS * i));
+    const longlong4 hi = f[0];
+    const longlong4 lo = f[1];
     if (hi.x | hi.y | hi.z | lo.x | lo.y | lo.z) {
-        *reinterpret_cast<longlong4 *>(f) = make_longlong4(0, 0, 0, 0);
-        *reinterpret_cast<longlong4 *>(f + 4) = make_longlong4(0, 0, 0, 0);
+        f[0] = make_longlong4(0, 0, 0, 0);
+        f[1] = make_longlong4(0, 0, 0, 0);
     }
     // each part converts exactly; the sum rounds once
     const double sh = 1.0 / FIX_HI, sl = 1.0 / FIX_LO;
@@ -559,7 +601,7 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
     __syncthreads();
     // every thread has read (and consumed) its accumulator flag before this
     // barrier
-    if (t < CMASK_WORDS) a.b.cmask[tile_index(a.n_tiles, a.n_tiles_pad) * CMASK_WORDS + t] = 0u;
+    if (t < CMASK_WORDS) gmem(a.b.cmask)[tile_index(a.n_tiles, a.n_tiles_pad) * CMASK_WORDS + t] = 0u;
 
     // --- hydrogen bonds and open flags (truncated harmonic between the
     //     patches of a base pair, Appendix A)
@@ -574,7 +616,7 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
             double k2n = k2s;
             if (a.b.k2bp) {
                 const int bw = bp < 0 ? bp + nbp : (bp >= nbp ? bp - nbp : bp);
-                k2n *= a.b.k2bp[ri.off / 2 + bw];
+                k2n *= gmem(a.b.k2bp)[ri.off / 2 + bw];
             }
             const D3 d64 = lds3(S.sP, 2 * q + 1) - lds3(S.sP, 2 * q);
             const double r = sqrt(dot(d64, d64));
@@ -946,7 +988,7 @@ __global__ void __launch_bounds__(WG_THREADS, 5) k_step(const StepArgs *__restri
     __shared__ TileLds<real> S;
     __shared__ float s_v2[WG_THREADS / 64];
     const StepArgs &a = *A;
-    const Ctl ctl = *a.b.ctl;
+    const Ctl ctl = cload(a.b.ctl);
     if (halted(ctl, ctl.step)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.b.ctl->done_step = ctl.step;
@@ -954,7 +996,7 @@ __global__ void __launch_bounds__(WG_THREADS, 5) k_step(const StepArgs *__restri
     }
     const int tix = tile_index(a.n_tiles, a.n_tiles_pad);
     if (tix >= a.n_tiles) return;
-    const Tile tile = a.b.tiles[tix];
+    const Tile tile = cload(&a.b.tiles[tix]);
     const RepInfo &ri = a.b.rep[tile.rep];
     const int cur = ctl.par, nxt = cur ^ 1;
     const int64_t step = ctl.step;
@@ -988,7 +1030,7 @@ __global__ void __launch_bounds__(WG_THREADS, 5) k_step(const StepArgs *__restri
     if (own) {
         V = ld3nt(a.b.V[cur], N, i);
         L = ld3nt(a.b.L[cur], N, i);
-        ref = a.b.rec[i];
+        ref = gmem(a.b.rec)[i];
     }
     real xi[6] = {0, 0, 0, 0, 0, 0};
     if (langevin) {
@@ -1110,7 +1152,7 @@ __global__ void __launch_bounds__(WG_THREADS, 5) k_step(const StepArgs *__restri
     const uint64_t far_lanes = __ballot(far);
     const unsigned lane = threadIdx.x & 63;
     if (far_lanes && lane == (unsigned)__builtin_ctzll(far_lanes))
-        atomicMax((unsigned long long *)&a.b.ctl->halt_step, (unsigned long long)(step + 1));
+        g_max((unsigned long long *)&a.b.ctl->halt_step, (unsigned long long)(step + 1));
     // the tile's largest displacement into its own slot (no other tile
     // touches it)
 #pragma unroll
@@ -1120,7 +1162,7 @@ __global__ void __launch_bounds__(WG_THREADS, 5) k_step(const StepArgs *__restri
     if (rebuild_after && threadIdx.x == 0) {
         float m = s_v2[0];
         for (int w = 1; w < WG_THREADS / 64; ++w) m = fmaxf(m, s_v2[w]);
-        if (m > a.b.vmax[tix]) a.b.vmax[tix] = m;
+        if (m > gmem(a.b.vmax)[tix]) gmem(a.b.vmax)[tix] = m;
     }
     // --- a rebuild follows: bin the new bead (record, cell, key, slot and
     //     histogram), the counting sort's count phase; the force phase's
@@ -1143,7 +1185,7 @@ constexpr int REBUILD_GRID = 2048;
 __global__ void __launch_bounds__(WG_THREADS) k_bin(const StepArgs *__restrict__ A, int which)
 {
     const StepArgs &a = *A;
-    const Ctl ctl = *a.b.ctl;
+    const Ctl ctl = cload(a.b.ctl);
     // which < 0: the positions the last step kernel wrote
     const int64_t step = which < 0 ? ctl.done_step + 1 : ctl.step;
     if (halted(ctl, step)) return;
@@ -1154,7 +1196,7 @@ __global__ void __launch_bounds__(WG_THREADS) k_bin(const StepArgs *__restrict__
     for (int b = blockIdx.x; b < a.n_tiles_pad; b += gridDim.x) {
         const int tix = xcd_item(b, a.n_tiles_pad);
         if (tix >= a.n_tiles) continue;  // the same for the whole workgroup
-        const Tile tile = a.b.tiles[tix];
+        const Tile tile = cload(&a.b.tiles[tix]);
         const RepInfo &ri = a.b.rep[tile.rep];
         const int s = t & 1, n = t < TILE_NT ? tile.n0 + (t >> 1) : tile.n_bp;
         const bool own = n < tile.n_bp;
@@ -1731,12 +1773,12 @@ __global__ void __launch_bounds__(256) k_scatter(const int *__restrict__ key, co
 
 // --------------------------------------------------------------- thermalize
 
-__global__ void __launch_bounds__(256) k_thermalize(const StepArgs *__restrict__ A, double kT, uint64_t seed)
+__global__ void __launch_bounds__(WG_THREADS) k_thermalize(const StepArgs *__restrict__ A, double kT, uint64_t seed)
 {
     const StepArgs &a = *A;
     const int tix = tile_index(a.n_tiles, a.n_tiles_pad);
     if (tix >= a.n_tiles) return;
-    const Tile tile = a.b.tiles[tix];
+    const Tile tile = cload(&a.b.tiles[tix]);
     const RepInfo &ri = a.b.rep[tile.rep];
     const int s = threadIdx.x & 1, n = threadIdx.x < TILE_NT ? tile.n0 + (int)(threadIdx.x >> 1) : tile.n_bp;
     if (n >= tile.n_bp) return;
@@ -1949,7 +1991,7 @@ __global__ void __launch_bounds__(WG_THREADS) k_diag(const StepArgs *__restrict_
     if (a.b.ctl->code != 0) return;
     const int tix = tile_index(a.n_tiles, a.n_tiles_pad);
     if (tix >= a.n_tiles) return;
-    const Tile tile = a.b.tiles[tix];
+    const Tile tile = cload(&a.b.tiles[tix]);
     const RepInfo &ri = a.b.rep[tile.rep];
     double e[DSDNA_NENERGY];
     for (int k = 0; k < DSDNA_NENERGY; ++k) e[k] = 0.0;
@@ -2025,7 +2067,7 @@ __global__ void __launch_bounds__(64) k_bubble_tiles(const StepArgs *__restrict_
     const StepArgs &a = *A;
     const int tix = blockIdx.x * blockDim.x + threadIdx.x;
     if (tix >= a.n_tiles) return;
-    const Tile tile = a.b.tiles[tix];
+    const Tile tile = cload(&a.b.tiles[tix]);
     const RepInfo &ri = a.b.rep[tile.rep];
     const int len = min(TILE_BP, tile.n_bp - tile.n0);
     const uint8_t *op = a.b.open + ri.off / 2 + tile.n0;

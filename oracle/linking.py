@@ -12,7 +12,8 @@ integral by quadrature with three intermediate points between beads; on
 polygons it has an exact value, the sum over segment pairs of the signed
 solid angle that one segment subtends as seen from the other (Klenin and
 Langowski, Biopolymers 54, 307 (2000)), which is what is computed here, in
-FP64, with the asin form of that solid angle.
+FP64, with the asin form of that solid angle (each asin taken as an atan2 of
+the sine and cosine of the angle between two unit normals).
 
 `crossing_linking` and `directional_writhe` count signed crossings of a
 planar projection instead: an independent route to the same numbers (the
@@ -22,6 +23,16 @@ Curves: strand s of a replica is the closed polygon of its beads in bp
 order; both strands are oriented along increasing bp index (the ribbon
 convention: a relaxed right-handed duplex has Lk ~ +N/10).  The centreline
 runs through the midpoints of the two patches of each base pair (Sec. 3.1).
+
+Open (linear) duplexes are closed as the appendix describes: each strand
+is extended from both ends along the tangent of its terminal pair of beads,
+outwards, by a distance D, and the two far points are joined by a straight
+closing segment; the linking number of the two closed strands follows from
+the same integral.  D is ten contour lengths of the relaxed duplex
+(10 x 0.34 nm per base pair) unless given.  The centreline of an open
+duplex is not closed (a straight chain's closing segment would run back
+along its own axis): its writhe is the integral over the pairs of segments
+of the open polygon that share no vertex.
 
 Only tests may import this module; it shares no code with the GPU path.
 """
@@ -36,8 +47,58 @@ def ring_curves(bead, patch, off, n_bp):
     return b[:, 0].copy(), b[:, 1].copy(), 0.5 * (p[:, 0] + p[:, 1])
 
 
+RISE_NM = 0.34          # relaxed rise per base pair (Sec. 2)
+CLOSURE_CONTOURS = 10.0  # extension length in contour lengths
+
+
+def closure_length(n_bp):
+    """Default extension length D of the closure of an n_bp duplex."""
+    return CLOSURE_CONTOURS * RISE_NM * n_bp
+
+
+def close_strand(b, D):
+    """The closed polygon of an open strand's beads b [n, 3] (n >= 2):
+    b_0 .. b_n-1, then b_n-1 + D t_end, then b_0 + D t_start (the closing
+    segment joins these two; the last edge returns to b_0), with t_end and
+    t_start the outward unit tangents of the terminal bead pairs."""
+    b = np.asarray(b, dtype=np.float64)
+    t_start = b[0] - b[1]
+    t_end = b[-1] - b[-2]
+    t_start = t_start / np.linalg.norm(t_start)
+    t_end = t_end / np.linalg.norm(t_end)
+    return np.vstack([b, (b[-1] + D * t_end)[None], (b[0] + D * t_start)[None]])
+
+
+def open_writhe(C):
+    """Writhe of the open polygon C [n, 3]: twice the sum over unordered
+    pairs of its n - 1 segments that share no vertex (no closing segment)."""
+    C = np.asarray(C, dtype=np.float64)
+    n = len(C)
+    total = 0.0
+    for i in range(n - 3):
+        j = np.arange(i + 2, n - 1)
+        total += segment_pair_omega(C[i], C[i + 1], C[j], C[j + 1]).sum()
+    return 2.0 * total / (4.0 * np.pi)
+
+
+def replica_topology(bead, patch, off, n_bp, ring, D=None):
+    """(Lk, Wr) of one replica: a ring's closed strands and centreline, or an
+    open duplex's strands closed by the appendix's procedure and its open
+    centreline (D: extension length, default closure_length(n_bp))."""
+    A, B, C = ring_curves(bead, patch, off, n_bp)
+    if ring:
+        return linking_number(A, B), writhe(C)
+    D = closure_length(n_bp) if D is None else D
+    return linking_number(close_strand(A, D), close_strand(B, D)), open_writhe(C)
+
+
 def _unit(x):
     return x / np.linalg.norm(x, axis=-1, keepdims=True)
+
+
+def _unit_or_zero(x):
+    n = np.linalg.norm(x, axis=-1, keepdims=True)
+    return np.where(n > 0.0, x / np.where(n > 0.0, n, 1.0), 0.0)
 
 
 def segment_pair_omega(p1, p2, p3, p4):
@@ -49,13 +110,16 @@ def segment_pair_omega(p1, p2, p3, p4):
     Omega* = sum of asin(n_k . n_k+1) round the quadrangle, and the sign
     is that of (r34 x r12) . r13."""
     r13, r14, r23, r24 = p3 - p1, p4 - p1, p3 - p2, p4 - p2
-    n1 = _unit(np.cross(r13, r14))
-    n2 = _unit(np.cross(r14, r24))
-    n3 = _unit(np.cross(r24, r23))
-    n4 = _unit(np.cross(r23, r13))
+    # collinear segments span no solid angle: a vanishing normal counts 0
+    n1 = _unit_or_zero(np.cross(r13, r14))
+    n2 = _unit_or_zero(np.cross(r14, r24))
+    n3 = _unit_or_zero(np.cross(r24, r23))
+    n4 = _unit_or_zero(np.cross(r23, r13))
 
     def asin_dot(a, b):
-        return np.arcsin(np.clip(np.sum(a * b, axis=-1), -1.0, 1.0))
+        # asin(a.b) for unit a, b, as the angle of (|a x b|, a.b): exact to
+        # rounding near a.b = +-1, where asin itself loses half the digits
+        return np.arctan2(np.sum(a * b, axis=-1), np.linalg.norm(np.cross(a, b), axis=-1))
 
     om = asin_dot(n1, n2) + asin_dot(n2, n3) + asin_dot(n3, n4) + asin_dot(n4, n1)
     sgn = np.sign(np.sum(np.cross(p4 - p3, p2 - p1) * r13, axis=-1))
@@ -136,19 +200,21 @@ def crossing_linking(A, B, v):
     return total
 
 
-def directional_writhe(C, dirs):
-    """Signed self-crossing number of the closed polygon C seen from each
-    direction in dirs [k, 3] (each crossing once, sign(v . (t_upper x
-    t_lower))); its mean over the sphere is the writhe."""
+def directional_writhe(C, dirs, closed=True):
+    """Signed self-crossing number of the polygon C seen from each direction
+    in dirs [k, 3] (each crossing once, sign(v . (t_upper x t_lower))); its
+    mean over the sphere is the writhe.  closed=False: the open polygon of
+    its n - 1 segments."""
     C = np.asarray(C, dtype=np.float64)
     n = len(C)
     c1 = np.roll(C, -1, axis=0)
+    m = n if closed else n - 1       # segments
     out = []
     for v in dirs:
         total = 0
-        for i in range(n):
-            hit, ha, hb, sg = _crossings(C[i], c1[i], C, c1, v)
-            j = np.arange(n)
+        for i in range(m):
+            hit, ha, hb, sg = _crossings(C[i], c1[i], C[:m], c1[:m], v)
+            j = np.arange(m)
             adj = (j == i) | (j == (i + 1) % n) | (j == (i - 1) % n)
             total += int(np.sum(sg[hit & ~adj & (ha > hb)]))
         out.append(total)

@@ -100,3 +100,105 @@ def test_writhe_is_the_mean_directional_crossing_number():
     nc = K.directional_writhe(C, _fib_sphere(2000))
     se = nc.std() / math.sqrt(len(nc))
     assert abs(nc.mean() - w) < 4 * se + 1e-3, (nc.mean(), w, se)
+
+
+# ------------------------------------------------- closure of open duplexes
+
+
+def _strands(n, **kw):
+    b, p = synth.ideal_helix(n, **kw)
+    return b.reshape(n, 2, 3)[:, 0], b.reshape(n, 2, 3)[:, 1], b, p
+
+
+@pytest.mark.parametrize("n", [56, 60, 61, 65, 100, 301])
+def test_closed_straight_helix_links_an_integer_independent_of_d(n):
+    """A straight ideal duplex closed by the appendix's procedure: an
+    integer Lk within one turn above the twist (n-1)/10, the same for any
+    extension length, start phase and rigid motion."""
+    rng = np.random.default_rng(n)
+    R, Q = np.linalg.qr(rng.standard_normal((3, 3)))
+    if np.linalg.det(R) < 0:
+        R[:, 0] *= -1
+    vals = []
+    for ph in (0.0, 1.3):
+        A, B, _, _ = _strands(n, phase0=ph)
+        for D in (20.0, 100.0, K.closure_length(n)):
+            vals.append(K.linking_number(K.close_strand(A, D), K.close_strand(B, D)))
+            A2, B2 = A @ R.T + 7.0, B @ R.T + 7.0
+            vals.append(K.linking_number(K.close_strand(A2, D), K.close_strand(B2, D)))
+    lk = vals[0]
+    assert abs(lk - round(lk)) < 1e-9
+    assert np.allclose(vals, lk, atol=1e-9)
+    tw = (n - 1) / 10.0
+    assert tw - 1e-9 <= lk < tw + 1.0
+
+
+@pytest.mark.parametrize("n", [60, 75, 203])
+def test_ten_more_base_pairs_add_one_link(n):
+    """One more helical turn of straight duplex adds exactly one to the
+    closed strands' Lk; a turn of a left-handed duplex takes one away."""
+    lk = {}
+    for m in (n, n + 10, n + 20):
+        A, B, _, _ = _strands(m)
+        lk[m] = K.linking_number(K.close_strand(A, 50.0), K.close_strand(B, 50.0))
+    assert lk[n + 10] - lk[n] == pytest.approx(1.0, abs=1e-9)
+    assert lk[n + 20] - lk[n + 10] == pytest.approx(1.0, abs=1e-9)
+    bl, _ = synth.mirror_helix(n + 10)
+    bl2, _ = synth.mirror_helix(n)
+    l1 = K.linking_number(K.close_strand(bl.reshape(-1, 2, 3)[:, 0], 50.0), K.close_strand(bl.reshape(-1, 2, 3)[:, 1], 50.0))
+    l0 = K.linking_number(K.close_strand(bl2.reshape(-1, 2, 3)[:, 0], 50.0), K.close_strand(bl2.reshape(-1, 2, 3)[:, 1], 50.0))
+    assert l1 - l0 == pytest.approx(-1.0, abs=1e-9)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_closed_thermal_duplex_matches_crossings_and_mirror(seed):
+    """A perturbed (thermal-like) duplex, closed: the solid-angle Lk is an
+    integer equal to the signed crossing count seen from three directions,
+    and the mirror image links with the opposite sign."""
+    rng = np.random.default_rng(100 + seed)
+    n = 80
+    b, p = synth.ideal_helix(n)
+    b = synth.perturb(b, 0.05, seed)
+    A, B = b.reshape(n, 2, 3)[:, 0], b.reshape(n, 2, 3)[:, 1]
+    cA, cB = K.close_strand(A, 60.0), K.close_strand(B, 60.0)
+    lk = K.linking_number(cA, cB)
+    assert abs(lk - round(lk)) < 1e-9
+    for v in rng.standard_normal((3, 3)):
+        assert K.crossing_linking(cA, cB, v) == round(lk)
+    M = np.array([1.0, -1.0, 1.0])
+    assert K.linking_number(K.close_strand(A * M, 60.0), K.close_strand(B * M, 60.0)) == pytest.approx(-lk, abs=1e-9)
+
+
+def test_rings_are_not_closed_again():
+    """replica_topology leaves a ring's strands as they are (its Lk is the
+    number of turns it was built with) and closes a linear replica."""
+    b, p = synth.ideal_ring(120, 12)
+    lk, wr = K.replica_topology(b, p, 0, 120, ring=True)
+    assert lk == pytest.approx(12.0, abs=1e-9) and wr == pytest.approx(0.0, abs=1e-12)
+    A, B, b2, p2 = _strands(61)
+    lk2, wr2 = K.replica_topology(b2, p2, 0, 61, ring=False)
+    D = K.closure_length(61)
+    assert lk2 == pytest.approx(K.linking_number(K.close_strand(A, D), K.close_strand(B, D)), abs=1e-12)
+    assert wr2 == pytest.approx(0.0, abs=1e-12)   # a straight centreline
+
+
+def test_open_writhe_planar_mirror_and_crossings():
+    """The open centreline's writhe: zero for a planar curve, odd under
+    reflection, unchanged by rigid motions and reversal, and the mean over
+    viewing directions of the signed crossing number of the open polygon."""
+    rng = np.random.default_rng(9)
+    th = np.linspace(0.0, 3.0 * math.pi, 30)
+    planar = np.stack([np.cos(th) * (1 + 0.1 * th), np.sin(th) * (1 + 0.1 * th), 0 * th], axis=1)
+    assert K.open_writhe(planar) == pytest.approx(0.0, abs=1e-12)
+    C = np.cumsum(rng.standard_normal((16, 3)), axis=0)
+    w = K.open_writhe(C)
+    assert abs(w) > 1e-3
+    assert K.open_writhe(C * np.array([1, 1, -1])) == pytest.approx(-w, abs=1e-11)
+    Rm, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    if np.linalg.det(Rm) < 0:
+        Rm[:, 0] *= -1
+    assert K.open_writhe(C @ Rm.T - 2.0) == pytest.approx(w, abs=1e-11)
+    assert K.open_writhe(C[::-1]) == pytest.approx(w, abs=1e-11)
+    nc = K.directional_writhe(C, _fib_sphere(2000), closed=False)
+    se = nc.std() / math.sqrt(len(nc))
+    assert abs(nc.mean() - w) < 4 * se + 1e-3, (nc.mean(), w, se)

@@ -205,17 +205,25 @@ dsdna_status dsdna_set_k2_bp(dsdna_ctx *ctx, const double *scale);
  * Placing the sites so that the ring closes is the caller's concern. */
 dsdna_status dsdna_set_circular(dsdna_ctx *ctx, const uint8_t *circular);
 
-/* Topology of every ring from the current state (appendix on the closure
- * procedure, Gauss's double integral): lk[n_rep] = linking number of the
- * closed curves of the strand 0 and strand 1 beads, both oriented along
+/* Topology of every replica from the current state (appendix on the
+ * closure procedure, Gauss's double integral): lk[n_rep] = linking number of
+ * the closed curves of the strand 0 and strand 1 beads, both oriented along
  * increasing base pair (a relaxed right-handed duplex has Lk ~ +n_bp/10);
  * wr[n_rep] = writhe of the centreline through the midpoints of the paired
- * patches (Sec. 3.1).  The twist is Lk - Wr.  Both are computed exactly for
- * the polygons (the sum over segment pairs of signed solid angles, FP64),
- * so lk is an integer up to rounding while the strands do not cross.
- * Linear replicas get NaN.  pair_ms (may be NULL) receives the duration of
+ * patches (Sec. 3.1).  The twist is Lk - Wr.  A ring's curves are closed by
+ * its seam.  A linear replica's strands are closed as the appendix
+ * describes: each is extended outwards from both ends along the unit
+ * tangent of its terminal bead pair by ten relaxed contour lengths
+ * (10 x 0.34 nm x n_bp) and the two far points are joined by a straight
+ * segment; its centreline is left open (wr is the integral over the open
+ * polygon's pairs of segments).  Both are computed exactly for the polygons
+ * (the sum over segment pairs of signed solid angles, FP64), so lk is an
+ * integer up to rounding while the closed strands do not cross.  A replica
+ * of one base pair gets NaN.  pair_ms (may be NULL) receives the duration of
  * the segment-pair kernel in milliseconds.  Runs on the context's stream
- * after the steps already queued. */
+ * after the steps already queued.  The curve buffers (72 bytes per base
+ * pair) are allocated at the first call after set_topology or
+ * set_circular: DSDNA_ENOMEM if that fails. */
 dsdna_status dsdna_get_linking(dsdna_ctx *ctx, double *lk, double *wr, double *pair_ms);
 
 /* Multiply K2 of each replica by scale[n_rep] (denaturation, Sec. 5). */

@@ -90,13 +90,16 @@ struct dsdna_ctx {
     int64_t sync_batch = 64;  // steps until the next read of the control block
     bool rebuilt = false;     // a scheduled rebuild ran since the last read
 
-    // rings and the scratch of the linking-number kernels
-    std::vector<RingSeg> rings_h;
-    std::vector<int32_t> ring_rep;   // replica of each ring
-    RingSeg *d_rings = nullptr;
+    // curve sets of the linking-number kernels (one per replica of at least
+    // two base pairs) and their scratch, built at the first linking call
+    // after a change of topology or ring flags
+    std::vector<CurveSet> sets_h;
+    std::vector<int32_t> set_rep;   // replica of each set
+    CurveSet *d_sets = nullptr;
     int2 *d_lkblk = nullptr;
     double *d_curves = nullptr, *d_lkpart = nullptr, *d_lkout = nullptr;
     int lk_blocks = 0, lk_pts = 0;
+    bool lk_stale = true;
     hipEvent_t lk_ev[2] = {nullptr, nullptr};
 
     // per-replica energies, and the bubble statistics' scratch and results
@@ -161,13 +164,14 @@ static void dfree(void *p)
     if (p) (void)hipFree(p);
 }
 
-static void free_rings(dsdna_ctx *c)
+static void free_curves(dsdna_ctx *c)
 {
-    dfree(c->d_rings); dfree(c->d_lkblk); dfree(c->d_curves); dfree(c->d_lkpart); dfree(c->d_lkout);
-    c->d_rings = nullptr; c->d_lkblk = nullptr; c->d_curves = c->d_lkpart = c->d_lkout = nullptr;
-    c->rings_h.clear();
-    c->ring_rep.clear();
+    dfree(c->d_sets); dfree(c->d_lkblk); dfree(c->d_curves); dfree(c->d_lkpart); dfree(c->d_lkout);
+    c->d_sets = nullptr; c->d_lkblk = nullptr; c->d_curves = c->d_lkpart = c->d_lkout = nullptr;
+    c->sets_h.clear();
+    c->set_rep.clear();
     c->lk_blocks = c->lk_pts = 0;
+    c->lk_stale = true;
 }
 
 static void free_bubbles(dsdna_ctx *c)
@@ -182,7 +186,7 @@ static void free_bubbles(dsdna_ctx *c)
 
 static void free_state(dsdna_ctx *c)
 {
-    free_rings(c);
+    free_curves(c);
     free_bubbles(c);
     dfree(c->d_rep_e);
     c->d_rep_e = nullptr;
@@ -1260,65 +1264,86 @@ dsdna_status dsdna_set_circular(dsdna_ctx *c, const uint8_t *circular)
     }
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    // the new ring tables and their device buffers first; the context takes
-    // them only when every allocation and copy has succeeded, so a failure
-    // leaves the previous rings in place
-    std::vector<RingSeg> rings;
-    std::vector<int32_t> ring_rep;
-    std::vector<int2> blk;
-    int32_t pts = 0;
+    std::vector<RepInfo> reps = c->rep_h;
+    std::vector<Tile> tiles = c->tiles_h;
     for (int r = 0; r < c->n_rep; ++r) {
-        if (!circular[r]) continue;
+        reps[r].flags &= ~(uint32_t)REP_RING;
+        if (circular[r]) reps[r].flags |= REP_RING;
+    }
+    for (Tile &t : tiles) t.ring = (reps[t.rep].flags & REP_RING) ? 1 : 0;
+    std::swap(reps, c->rep_h);
+    std::swap(tiles, c->tiles_h);
+    if ((st = copy(c, c->a.b.tiles, c->tiles_h.data(), sizeof(Tile) * c->tiles_h.size(), hipMemcpyHostToDevice)) ||
+        (st = upload_reps(c))) {
+        // the previous flags stay (on the device as well, once they upload)
+        std::swap(reps, c->rep_h);
+        std::swap(tiles, c->tiles_h);
+        const std::string msg = c->err;
+        (void)copy(c, c->a.b.tiles, c->tiles_h.data(), sizeof(Tile) * c->tiles_h.size(), hipMemcpyHostToDevice);
+        (void)upload_reps(c);
+        c->err = msg;
+        return st;
+    }
+    free_curves(c);
+    return DSDNA_OK;
+}
+
+// Relaxed rise (Sec. 2) and the extension length of an open duplex's strands
+// in its closure, in relaxed contour lengths (far from the molecule, so the
+// closing segment stays clear of it).
+constexpr double RISE_NM = 0.34;
+constexpr double CLOSURE_CONTOURS = 10.0;
+
+// The curve sets of every replica of at least two base pairs, their blocks
+// and scratch (appendix on the closure procedure).
+static dsdna_status build_curves(dsdna_ctx *c)
+{
+    std::vector<CurveSet> sets;
+    std::vector<int32_t> set_rep;
+    std::vector<int2> blk;
+    int64_t pts = 0;
+    for (int r = 0; r < c->n_rep; ++r) {
         const RepInfo &ri = c->rep_h[r];
-        RingSeg g;
+        if (ri.n_bp < 2) continue;
+        const bool ring = (ri.flags & REP_RING) != 0;
+        CurveSet g;
         g.off = ri.off;
         g.n_bp = ri.n_bp;
-        g.pt0 = pts;
+        g.open = ring ? 0 : 1;
+        g.reach = ring ? 0.0 : CLOSURE_CONTOURS * RISE_NM * ri.n_bp;
+        g.n_str = ring ? ri.n_bp : ri.n_bp + 2;
+        g.pt0 = (int32_t)pts;
         g.blk0 = (int32_t)blk.size();
-        g.n_blk = (ri.n_bp + LK_THREADS - 1) / LK_THREADS;
-        for (int b = 0; b < g.n_blk; ++b) blk.push_back(int2{(int)rings.size(), b * LK_THREADS});
-        rings.push_back(g);
-        ring_rep.push_back(r);
-        pts += ri.n_bp;
+        g.n_blk = (g.n_str + LK_THREADS - 1) / LK_THREADS;
+        for (int b = 0; b < g.n_blk; ++b) blk.push_back(int2{(int)sets.size(), b * LK_THREADS});
+        sets.push_back(g);
+        set_rep.push_back(r);
+        pts += g.n_str;
     }
-    RingSeg *d_rings = nullptr;
-    int2 *d_blk = nullptr;
-    double *d_curves = nullptr, *d_part = nullptr, *d_out = nullptr;
-    const auto drop = [&] {
-        dfree(d_rings); dfree(d_blk); dfree(d_curves); dfree(d_part); dfree(d_out);
-    };
-    if (!rings.empty()) {
-        if (dalloc(&d_rings, rings.size()) != hipSuccess || dalloc(&d_blk, blk.size()) != hipSuccess ||
-            dalloc(&d_curves, 9 * (size_t)pts) != hipSuccess || dalloc(&d_part, 2 * blk.size()) != hipSuccess ||
-            dalloc(&d_out, 2 * rings.size()) != hipSuccess) {
-            drop();
-            return fail(c, DSDNA_ENOMEM, "device allocation for %zu rings failed", rings.size());
-        }
-        if ((st = copy(c, d_rings, rings.data(), sizeof(RingSeg) * rings.size(), hipMemcpyHostToDevice)) ||
-            (st = copy(c, d_blk, blk.data(), sizeof(int2) * blk.size(), hipMemcpyHostToDevice))) {
-            drop();
-            return st;
-        }
+    if (pts >= (int64_t(1) << 31)) return fail(c, DSDNA_EINVAL, "too many curve points");
+    free_curves(c);
+    if (sets.empty()) {
+        c->lk_stale = false;
+        return DSDNA_OK;
     }
-    free_rings(c);
-    c->rings_h = std::move(rings);
-    c->ring_rep = std::move(ring_rep);
-    c->d_rings = d_rings;
-    c->d_lkblk = d_blk;
-    c->d_curves = d_curves;
-    c->d_lkpart = d_part;
-    c->d_lkout = d_out;
-    c->lk_blocks = (int)blk.size();
-    c->lk_pts = pts;
-    for (int r = 0; r < c->n_rep; ++r) {
-        RepInfo &ri = c->rep_h[r];
-        ri.flags &= ~(uint32_t)REP_RING;
-        if (circular[r]) ri.flags |= REP_RING;
+    if (dalloc(&c->d_sets, sets.size()) != hipSuccess || dalloc(&c->d_lkblk, blk.size()) != hipSuccess ||
+        dalloc(&c->d_curves, 9 * (size_t)pts) != hipSuccess || dalloc(&c->d_lkpart, 2 * blk.size()) != hipSuccess ||
+        dalloc(&c->d_lkout, 2 * sets.size()) != hipSuccess) {
+        free_curves(c);
+        return fail(c, DSDNA_ENOMEM, "device allocation for the curves of %zu replicas failed", sets.size());
     }
-    for (Tile &t : c->tiles_h) t.ring = (c->rep_h[t.rep].flags & REP_RING) ? 1 : 0;
-    if ((st = copy(c, c->a.b.tiles, c->tiles_h.data(), sizeof(Tile) * c->tiles_h.size(), hipMemcpyHostToDevice)))
+    dsdna_status st;
+    if ((st = copy(c, c->d_sets, sets.data(), sizeof(CurveSet) * sets.size(), hipMemcpyHostToDevice)) ||
+        (st = copy(c, c->d_lkblk, blk.data(), sizeof(int2) * blk.size(), hipMemcpyHostToDevice))) {
+        free_curves(c);
         return st;
-    return upload_reps(c);
+    }
+    c->sets_h = std::move(sets);
+    c->set_rep = std::move(set_rep);
+    c->lk_blocks = (int)blk.size();
+    c->lk_pts = (int)pts;
+    c->lk_stale = false;
+    return DSDNA_OK;
 }
 
 dsdna_status dsdna_get_linking(dsdna_ctx *c, double *lk, double *wr, double *pair_ms)
@@ -1330,22 +1355,23 @@ dsdna_status dsdna_get_linking(dsdna_ctx *c, double *lk, double *wr, double *pai
     std::fill(lk, lk + c->n_rep, nan);
     std::fill(wr, wr + c->n_rep, nan);
     if (pair_ms) *pair_ms = 0.0;
-    if (c->rings_h.empty()) return DSDNA_OK;
-    if ((st = sync_args(c))) return st;
     HIPCHK(c, hipSetDevice(c->device));
+    if (c->lk_stale && (st = build_curves(c))) return st;
+    if (c->sets_h.empty()) return DSDNA_OK;
+    if ((st = sync_args(c))) return st;
     if (pair_ms)
         for (hipEvent_t &e : c->lk_ev)
             if (!e) HIPCHK(c, hipEventCreate(&e));
     // the full-step positions (a stepping context holds them in the buffer
     // behind the device's current one)
-    HIPCHK(c, launch_linking(c->dA, full_buffer(c), c->d_rings, (int)c->rings_h.size(), c->d_lkblk, c->lk_blocks,
+    HIPCHK(c, launch_linking(c->dA, full_buffer(c), c->d_sets, (int)c->sets_h.size(), c->d_lkblk, c->lk_blocks,
                              c->lk_pts, c->d_curves, c->d_lkpart, c->d_lkout, c->stream,
                              pair_ms ? c->lk_ev[0] : nullptr, pair_ms ? c->lk_ev[1] : nullptr));
-    std::vector<double> out(2 * c->rings_h.size());
+    std::vector<double> out(2 * c->sets_h.size());
     if ((st = copy(c, out.data(), c->d_lkout, sizeof(double) * out.size(), hipMemcpyDeviceToHost))) return st;
-    for (size_t k = 0; k < c->rings_h.size(); ++k) {
-        lk[c->ring_rep[k]] = out[2 * k];
-        wr[c->ring_rep[k]] = out[2 * k + 1];
+    for (size_t k = 0; k < c->sets_h.size(); ++k) {
+        lk[c->set_rep[k]] = out[2 * k];
+        wr[c->set_rep[k]] = out[2 * k + 1];
     }
     if (pair_ms) {
         float ms = 0.0f;

@@ -207,13 +207,22 @@ struct StepArgs {
     int64_t list_cap;      // capacity of b.plist
 };
 
-// A ring for the linking-number kernels: its first nucleotide, length,
-// first point in the curve buffers and its workgroups (blocks of LK_THREADS
-// base pairs, first at blk0).
+// The curves of one replica for the linking-number kernels (appendix on the
+// closure procedure).  A ring's two strands and centreline are closed
+// polygons of n_bp points.  An open duplex's strands are closed by two extra
+// points each (n_str = n_bp + 2: the last bead pushed out along its end
+// tangent by `reach`, then the first bead pushed out likewise, the closing
+// segment between them), while its centreline stays an open polygon of n_bp
+// points.  pt0: first point slot of the set in each of the three curve
+// blocks (n_str slots per set); workgroups: blocks of LK_THREADS rows,
+// first at blk0.
 constexpr int LK_THREADS = 256;
-struct RingSeg {
-    int64_t off;
+struct CurveSet {
+    int64_t off;      // first nucleotide
+    double reach;     // extension length of an open duplex's strands
     int32_t n_bp;
+    int32_t open;     // 1: open duplex, 0: ring
+    int32_t n_str;    // points of each strand curve
     int32_t pt0;
     int32_t blk0;
     int32_t n_blk;
@@ -263,11 +272,15 @@ hipError_t launch_rep_energy(const StepArgs &a, const StepArgs *dA, double *out,
 // are scratch.
 hipError_t launch_bubbles(const StepArgs &a, const StepArgs *dA, int nhist, int32_t *hist_tiles, int4 *info,
                           double *frac, int64_t *out, int n_rep, hipStream_t s);
-// Linking number of the strands and writhe of the centreline of every ring
-// from the positions in buffer `which`: curves (3 curves x n_pts points x 3
-// doubles) and partial ([n_blocks][2]) are scratch, out[n_rings][2]
-// receives (Lk, Wr).  blocks[n_blocks] = (ring, first bp).  ev0/ev1 (may be
-// null) bracket the pair kernel.
+// Linking number of the strands and writhe of the centreline of every curve
+// set (a ring, or an open duplex closed by extension) from the positions in
+// buffer `which`: curves (3 curves x n_pts point slots x 3 doubles) and
+// partial ([n_blocks][2]) are scratch, out[n_sets][2] receives (Lk, Wr).
+// blocks[n_blocks] = (set, first row).  ev0/ev1 (may be null) bracket the
+// pair kernel.
+hipError_t launch_linking(const StepArgs *dA, int which, const CurveSet *sets, int n_sets, const int2 *blocks,
+                          int n_blocks, int n_pts, double *curves, double *partial, double *out, hipStream_t s,
+                          hipEvent_t ev0, hipEvent_t ev1);
 // The same for one ring given as three closed curves A, B, C of n points
 // ([n][3] doubles each, device memory): partial holds 2 ceil(n /
 // LK_THREADS) doubles, out[2] receives (Lk(A, B), Wr(C)).
@@ -276,9 +289,5 @@ hipError_t launch_linking_curves(const double *A, const double *B, const double 
 // Message of the last failure of a context-free call on this thread (read by
 // dsdna_last_error(NULL)); printf-style.
 void set_free_error(const char *fmt, ...);
-
-hipError_t launch_linking(const StepArgs *dA, int which, const RingSeg *rings, int n_rings, const int2 *blocks,
-                          int n_blocks, int n_pts, double *curves, double *partial, double *out, hipStream_t s,
-                          hipEvent_t ev0, hipEvent_t ev1);
 
 }  // namespace dsdna

@@ -1803,29 +1803,48 @@ __global__ void __launch_bounds__(WG_THREADS) k_thermalize(const StepArgs *__res
 
 // ------------------------------------------------ linking number, writhe
 
-// The closed curves of each ring from the positions in buffer `buf`:
-// strand 0 beads, strand 1 beads and the centreline through the midpoints of
-// the paired patches (Sec. 3.1), as FP64 points [n][3] per curve.  One
-// workgroup per block of LK_THREADS base pairs of one ring.
-__global__ void __launch_bounds__(LK_THREADS) k_curves(const StepArgs *__restrict__ A, const RingSeg *__restrict__ rings,
+// The curves of each replica from the positions in buffer `buf`: strand 0
+// beads, strand 1 beads and the centreline through the midpoints of the
+// paired patches (Sec. 3.1), as FP64 points [n][3] per curve.  An open
+// duplex's strands also get their closure points (appendix on the closure
+// procedure), each from the thread of its end base pair: the end bead moved
+// by `reach` along the unit tangent from the neighbouring bead of its strand
+// outwards.  One workgroup per block of LK_THREADS base pairs of one set.
+__global__ void __launch_bounds__(LK_THREADS) k_curves(const StepArgs *__restrict__ A, const CurveSet *__restrict__ sets,
                                                       const int2 *__restrict__ blocks, int n_pts, int buf,
                                                       double *__restrict__ curves)
 {
     const StepArgs &a = *A;
     const int2 blk = blocks[blockIdx.x];
-    const RingSeg rg = rings[blk.x];
+    const CurveSet cs = sets[blk.x];
     const int n = blk.y + (int)threadIdx.x;
-    if (n >= rg.n_bp) return;
-    const int64_t i0 = rg.off + 2 * (int64_t)n, i1 = i0 + 1;
+    if (n >= cs.n_bp) return;
+    auto beads = [&](int bp, D3 &q0, D3 &q1) {
+        const int64_t j0 = cs.off + 2 * (int64_t)bp, j1 = j0 + 1;
+        q0 = bead_of(ld3(a.b.R[buf], a.n_nt, j0), ld3(a.b.u[buf], a.n_nt, j0), a.ph.db);
+        q1 = bead_of(ld3(a.b.R[buf], a.n_nt, j1), ld3(a.b.u[buf], a.n_nt, j1), a.ph.db);
+    };
+    const int64_t i0 = cs.off + 2 * (int64_t)n, i1 = i0 + 1;
     const D3 R0 = ld3(a.b.R[buf], a.n_nt, i0), u0 = ld3(a.b.u[buf], a.n_nt, i0);
     const D3 R1 = ld3(a.b.R[buf], a.n_nt, i1), u1 = ld3(a.b.u[buf], a.n_nt, i1);
     const D3 b0 = bead_of(R0, u0, a.ph.db), b1 = bead_of(R1, u1, a.ph.db);
     const D3 c = (patch_of(R0, u0, a.ph.dp) + patch_of(R1, u1, a.ph.dp)) * 0.5;
-    double *pA = curves + 3 * ((int64_t)rg.pt0 + n);
+    double *pA = curves + 3 * ((int64_t)cs.pt0 + n);
     double *pB = pA + 3 * (int64_t)n_pts, *pC = pB + 3 * (int64_t)n_pts;
     pA[0] = b0.x; pA[1] = b0.y; pA[2] = b0.z;
     pB[0] = b1.x; pB[1] = b1.y; pB[2] = b1.z;
     pC[0] = c.x; pC[1] = c.y; pC[2] = c.z;
+    if (cs.open && cs.n_bp >= 2 && (n == 0 || n == cs.n_bp - 1)) {
+        D3 q0, q1;
+        beads(n == 0 ? 1 : n - 1, q0, q1);
+        const D3 d0 = b0 - q0, d1 = b1 - q1;
+        const D3 e0 = b0 + d0 * (cs.reach / sqrt(dot(d0, d0))), e1 = b1 + d1 * (cs.reach / sqrt(dot(d1, d1)));
+        // slot n_bp: after the last bead; slot n_bp + 1: before the first
+        const int64_t slot = n == 0 ? cs.n_bp + 1 : cs.n_bp;
+        double *qA = curves + 3 * ((int64_t)cs.pt0 + slot), *qB = qA + 3 * (int64_t)n_pts;
+        qA[0] = e0.x; qA[1] = e0.y; qA[2] = e0.z;
+        qB[0] = e1.x; qB[1] = e1.y; qB[2] = e1.z;
+    }
 }
 
 // Half the signed solid angle of the spherical triangle with vertices along
@@ -1859,51 +1878,70 @@ __device__ __forceinline__ double pair_omega(D3 p1, D3 p2, D3 p3, D3 p4)
     return 2.0 * atan2(y1 * x2 + y2 * x1, x1 * x2 - y1 * y2);
 }
 
-// Row sums of the segment-pair solid angles of one ring, for the rows
-// i0 .. i0 + LK_THREADS - 1: thread i holds segment i -> i+1 (mod n) of
-// curve A (strand 0) and of the centreline C; curve B (strand 1) and the
-// centreline stream through LDS in chunks of LK_THREADS segments.  Sum over
-// the rows of Omega(A_i, B_j) over all j (the linking number) and of
-// Omega(C_i, C_j) over the half window of j whose segment shares no vertex
-// with segment i, j - i = 2 .. n/2 (mod n), the antipodal j - i = n/2 of an
-// even ring only from i < n/2 (the writhe, each unordered pair once),
-// reduced in a fixed order to part[2].  Called by all threads of a workgroup.
+// Row sums of the segment-pair solid angles of one curve set, for the rows
+// i0 .. i0 + LK_THREADS - 1.  Thread i holds segment i -> i+1 (mod nS) of the
+// closed strand curve A (nS points) and segment i -> i+1 of the centreline C
+// (nC points, closed unless c_open); curve B (nS points, closed) and C
+// stream through LDS in chunks of LK_THREADS segments.  Sums over the rows
+// of Omega(A_i, B_j) over all j (the linking number) and of Omega(C_i, C_j)
+// over the j whose segment shares no vertex with segment i, each unordered
+// pair once: on a closed C the half window j - i = 2 .. nC/2 (mod nC), the
+// antipodal j - i = nC/2 of an even curve only from i < nC/2; on an open C
+// the segments j >= i + 2 (the writhe), reduced in a fixed order to part[2].
+// Called by all threads of a workgroup.
 __device__ void gauss_rows(const double *__restrict__ cA, const double *__restrict__ cB,
-                           const double *__restrict__ cC, int n, int i0, double *__restrict__ part)
+                           const double *__restrict__ cC, int nS, int nC, int c_open, int i0,
+                           double *__restrict__ part)
 {
     __shared__ double sB[LK_THREADS + 1][3];
     __shared__ double sC[LK_THREADS + 1][3];
     __shared__ double red[LK_THREADS][2];
     const int t = threadIdx.x;
     const int i = i0 + t;
-    const bool row = i < n;
-    const int i1 = i + 1 == n ? 0 : i + 1;
+    const int segC = c_open ? nC - 1 : nC;  // centreline segments
+    const bool rowA = i < nS, rowC = i < segC;
     D3 a0 = v3(0.0, 0.0, 0.0), a1 = a0, c0 = a0, c1 = a0;
-    if (row) {
+    if (rowA) {
+        const int i1 = i + 1 == nS ? 0 : i + 1;
         a0 = v3(cA[3 * i], cA[3 * i + 1], cA[3 * i + 2]);
         a1 = v3(cA[3 * i1], cA[3 * i1 + 1], cA[3 * i1 + 2]);
+    }
+    if (rowC) {
+        const int i1 = i + 1 == nC ? 0 : i + 1;
         c0 = v3(cC[3 * i], cC[3 * i + 1], cC[3 * i + 2]);
         c1 = v3(cC[3 * i1], cC[3 * i1 + 1], cC[3 * i1 + 2]);
     }
     double lk = 0.0, wr = 0.0;
-    for (int j0 = 0; j0 < n; j0 += LK_THREADS) {
-        const int m = min(LK_THREADS, n - j0);  // segments in this chunk
+    const int rows = nS > segC ? nS : segC;
+    for (int j0 = 0; j0 < rows; j0 += LK_THREADS) {
+        const int mB = max(0, min(LK_THREADS, nS - j0));    // segments of B in this chunk
+        const int mC = max(0, min(LK_THREADS, segC - j0));  // segments of C in this chunk
         __syncthreads();
-        for (int q = t; q <= m; q += LK_THREADS) {  // m + 1 points, the last may wrap
-            const int j = j0 + q == n ? 0 : j0 + q;
-            sB[q][0] = cB[3 * j]; sB[q][1] = cB[3 * j + 1]; sB[q][2] = cB[3 * j + 2];
-            sC[q][0] = cC[3 * j]; sC[q][1] = cC[3 * j + 1]; sC[q][2] = cC[3 * j + 2];
+        for (int q = t; q <= max(mB, mC); q += LK_THREADS) {  // m + 1 points, the last may wrap
+            if (mB > 0 && q <= mB) {
+                const int j = j0 + q == nS ? 0 : j0 + q;
+                sB[q][0] = cB[3 * j]; sB[q][1] = cB[3 * j + 1]; sB[q][2] = cB[3 * j + 2];
+            }
+            if (mC > 0 && q <= mC) {
+                const int j = j0 + q == nC ? 0 : j0 + q;
+                sC[q][0] = cC[3 * j]; sC[q][1] = cC[3 * j + 1]; sC[q][2] = cC[3 * j + 2];
+            }
         }
         __syncthreads();
-        if (!row) continue;
-        for (int q = 0; q < m; ++q) {
-            const D3 b0 = lds3(sB, q), b1 = lds3(sB, q + 1);
-            lk += pair_omega(a0, a1, b0, b1);
-            const int j = j0 + q;
-            const int d = j >= i ? j - i : j - i + n;  // (j - i) mod n
-            if (d >= 2 && d <= n - 2 && (2 * d < n || (2 * d == n && 2 * i < n)))
-                wr += pair_omega(c0, c1, lds3(sC, q), lds3(sC, q + 1));
-        }
+        if (rowA)
+            for (int q = 0; q < mB; ++q) lk += pair_omega(a0, a1, lds3(sB, q), lds3(sB, q + 1));
+        if (rowC)
+            for (int q = 0; q < mC; ++q) {
+                const int j = j0 + q;
+                bool take;
+                if (c_open) {
+                    take = j >= i + 2;
+                } else {
+                    const int d = j >= i ? j - i : j - i + nC;  // (j - i) mod nC
+                    take = d >= 2 && d <= nC - 2 && (2 * d < nC || (2 * d == nC && 2 * i < nC));
+                }
+                if (take) wr += pair_omega(c0, c1, lds3(sC, q), lds3(sC, q + 1));
+            }
     }
     red[t][0] = lk;
     red[t][1] = wr;
@@ -1922,15 +1960,15 @@ __device__ void gauss_rows(const double *__restrict__ cA, const double *__restri
 
 // Rings of a context: one workgroup per block of LK_THREADS base pairs of
 // one ring (the curves of k_curves), partial[block][2].
-__global__ void __launch_bounds__(LK_THREADS) k_gauss(const RingSeg *__restrict__ rings, const int2 *__restrict__ blocks,
+__global__ void __launch_bounds__(LK_THREADS) k_gauss(const CurveSet *__restrict__ sets, const int2 *__restrict__ blocks,
                                                      int n_pts, const double *__restrict__ curves,
                                                      double *__restrict__ partial)
 {
     const int2 blk = blocks[blockIdx.x];
-    const RingSeg rg = rings[blk.x];
-    const double *cA = curves + 3 * (int64_t)rg.pt0;
+    const CurveSet cs = sets[blk.x];
+    const double *cA = curves + 3 * (int64_t)cs.pt0;
     const double *cB = cA + 3 * (int64_t)n_pts, *cC = cB + 3 * (int64_t)n_pts;
-    gauss_rows(cA, cB, cC, rg.n_bp, blk.y, partial + 2 * blockIdx.x);
+    gauss_rows(cA, cB, cC, cs.n_str, cs.n_bp, cs.open, blk.y, partial + 2 * blockIdx.x);
 }
 
 // Per ring, in block order: Lk = (sum of its rows) / (4 pi) and Wr twice the
@@ -1949,13 +1987,13 @@ __device__ __forceinline__ void gauss_total(const double *__restrict__ partial, 
     out[1] = 2.0 * wr * k;
 }
 
-__global__ void __launch_bounds__(64) k_gauss_sum(const RingSeg *__restrict__ rings, int n_rings,
+__global__ void __launch_bounds__(64) k_gauss_sum(const CurveSet *__restrict__ sets, int n_sets,
                                                  const double *__restrict__ partial, double *__restrict__ out)
 {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n_rings) return;
-    const RingSeg rg = rings[r];
-    gauss_total(partial, rg.blk0, rg.n_blk, out + 2 * r);
+    if (r >= n_sets) return;
+    const CurveSet cs = sets[r];
+    gauss_total(partial, cs.blk0, cs.n_blk, out + 2 * r);
 }
 
 // One ring given as three closed curves of n points each (A, B: the two
@@ -1965,7 +2003,7 @@ __global__ void __launch_bounds__(LK_THREADS) k_gauss_curves(const double *__res
                                                             const double *__restrict__ C, int n,
                                                             double *__restrict__ partial)
 {
-    gauss_rows(A, B, C, n, (int)blockIdx.x * LK_THREADS, partial + 2 * blockIdx.x);
+    gauss_rows(A, B, C, n, n, 0, (int)blockIdx.x * LK_THREADS, partial + 2 * blockIdx.x);
 }
 
 __global__ void __launch_bounds__(64) k_gauss_curves_sum(const double *__restrict__ partial, int n_blk,
@@ -2261,16 +2299,16 @@ hipError_t launch_linking_curves(const double *A, const double *B, const double 
     return hipGetLastError();
 }
 
-hipError_t launch_linking(const StepArgs *dA, int which, const RingSeg *rings, int n_rings, const int2 *blocks,
+hipError_t launch_linking(const StepArgs *dA, int which, const CurveSet *sets, int n_sets, const int2 *blocks,
                           int n_blocks, int n_pts, double *curves, double *partial, double *out, hipStream_t s,
                           hipEvent_t ev0, hipEvent_t ev1)
 {
     if (n_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_curves, dim3(n_blocks), dim3(LK_THREADS), 0, s, dA, rings, blocks, n_pts, which, curves);
+    hipLaunchKernelGGL(k_curves, dim3(n_blocks), dim3(LK_THREADS), 0, s, dA, sets, blocks, n_pts, which, curves);
     if (ev0) (void)hipEventRecord(ev0, s);
-    hipLaunchKernelGGL(k_gauss, dim3(n_blocks), dim3(LK_THREADS), 0, s, rings, blocks, n_pts, curves, partial);
+    hipLaunchKernelGGL(k_gauss, dim3(n_blocks), dim3(LK_THREADS), 0, s, sets, blocks, n_pts, curves, partial);
     if (ev1) (void)hipEventRecord(ev1, s);
-    hipLaunchKernelGGL(k_gauss_sum, dim3((n_rings + 63) / 64), dim3(64), 0, s, rings, n_rings, partial, out);
+    hipLaunchKernelGGL(k_gauss_sum, dim3((n_sets + 63) / 64), dim3(64), 0, s, sets, n_sets, partial, out);
     return hipGetLastError();
 }
 

@@ -155,8 +155,9 @@ def test_linking_number_and_writhe_match_oracle(D):
             assert lk[r] == pytest.approx(K.linking_number(A, B), abs=1e-9)
             assert wr[r] == pytest.approx(K.writhe(C), abs=1e-9)
             assert abs(lk[r] - n // 10) < 1e-9   # 400 steps do not pass a strand through the other
-        else:
-            assert np.isnan(lk[r]) and np.isnan(wr[r])
+        else:   # closed by extension of its strands, centreline open
+            lk_ref, wr_ref = K.replica_topology(b, p, off, n, ring=False)
+            assert lk[r] == pytest.approx(lk_ref, abs=1e-9) and wr[r] == pytest.approx(wr_ref, abs=1e-9)
         off += 2 * n
     sim.close()
 
@@ -200,6 +201,8 @@ def test_ring_errors(D):
     D.dsdna_set_external(sim.ctx, 0, F=(0, 0, 1.0))
     with pytest.raises(D.DsdnaError, match="EINVAL"):
         D.dsdna_set_circular(sim.ctx, [1])
-    lk, wr = sim.linking()
-    assert np.isnan(lk[0])
+    lk, wr = sim.linking()   # still open: its strands closed by extension
+    bs, ps = sim.sites()
+    lk_ref, wr_ref = K.replica_topology(bs, ps, 0, 30, ring=False)
+    assert lk[0] == pytest.approx(lk_ref, abs=1e-9) and wr[0] == pytest.approx(wr_ref, abs=1e-9)
     sim.close()

@@ -58,7 +58,8 @@ typedef struct {
                                       reading for overstretched bonds)     */
     int32_t dihedral_damping;      /* 1: dihedral x sin^3 of both bond
                                       angles (a reading, see below)        */
-    int32_t pad;
+    int32_t planarity_both;        /* 1: a second planarity angle per step
+                                      (the mirrored triple, see below)     */
 } orc_params;
 
 typedef struct {
@@ -617,6 +618,22 @@ int orc_forces(const orc_params *P, const orc_system *sys, const double *bead,
                 v3_acc(FP(T_PLANAR, i), fa);
                 v3_acc(FB(T_PLANAR, j), fc);
                 v3_acc(FP(T_PLANAR, j), v3_mul(v3_add(fa, fc), -1.0));
+                EN(r, T_PLANAR) += U;
+                if (!P->planarity_both) continue;
+                /* the reading with both triples of the step: also the angle
+                 * at patch n between patch n+1 and bead n (the same triple
+                 * seen from the other end of the step), same potential */
+                cs = angle_cos(v3_ld(patch + 3 * j), v3_ld(patch + 3 * i), v3_ld(bead + 3 * i), &dca, &dcc);
+                if (cs > 1.0) cs = 1.0;
+                if (cs < -1.0) cs = -1.0;
+                al = acos(cs);
+                U = 0.5 * P->K5 * (al - P->a0) * (al - P->a0);
+                dUdc = -P->K5 * (al - P->a0) / sin(al);
+                fa = v3_mul(dca, -dUdc);
+                fc = v3_mul(dcc, -dUdc);
+                v3_acc(FP(T_PLANAR, j), fa);
+                v3_acc(FB(T_PLANAR, i), fc);
+                v3_acc(FP(T_PLANAR, i), v3_mul(v3_add(fa, fc), -1.0));
                 EN(r, T_PLANAR) += U;
             }
             /* --- Kratky-Porod: angle at patch n among patches n-1, n, n+1,

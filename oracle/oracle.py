@@ -48,7 +48,7 @@ class Params(C.Structure):
         "gamma", "kT", "dt")] + [
         ("seed", C.c_uint64), ("noise_kind", C.c_int32), ("ssdna_rule", C.c_int32),
         ("hb_depth_convention", C.c_int32), ("fene_clamp", C.c_int32), ("dihedral_damping", C.c_int32),
-        ("pad", C.c_int32)]
+        ("planarity_both", C.c_int32)]
 
 
 def default_params(**over) -> Params:
@@ -63,7 +63,7 @@ def default_params(**over) -> Params:
                ell=0.5, m_bead=1.0, m_patch=1.0,
                gamma=1.0, kT=1.0, dt=0.005,
                seed=0, noise_kind=0, ssdna_rule=0, hb_depth_convention=0, fene_clamp=0,
-               dihedral_damping=0, pad=0)
+               dihedral_damping=0, planarity_both=0)
     for k, v in over.items():
         setattr(p, k, v)
     return p

@@ -122,3 +122,71 @@ def test_dihedral_damping_reading(orc):
     f_bare = np.abs(orc.forces(P0, orc.System([3]), b, p)[2][t]).max()
     f_damp = np.abs(orc.forces(P1, orc.System([3]), b, p)[2][t]).max()
     assert f_bare > 1e3 and f_damp < 1e2, (f_bare, f_damp)
+
+
+def test_planarity_both_triples_reading(orc):
+    """planarity_both = 1 adds, per backbone step and strand, the triple
+    (P_n+1, P_n, B_n) at P_n to (P_n, P_n+1, B_n+1) at P_n+1: zero at the
+    ideal helix and its mirror (every such angle is 90 deg), forces minus the
+    gradient of its energy, and with both triples the energy no longer
+    depends on which end of the chain the base-pair index starts from."""
+    t = orc.T["planar"]
+    P0, P1 = orc.default_params(), orc.default_params(planarity_both=1)
+    for b, p in (synth.ideal_helix(6), synth.mirror_helix(6)):
+        st, _, fb, fp, E, _ = orc.forces(P1, orc.System([6]), b, p)
+        assert abs(E[0, t]) < 1e-20 and np.abs(fb[t]).max() < 1e-9 and np.abs(fp[t]).max() < 1e-9
+    b, p = synth.ideal_helix(8)
+    b, p = synth.perturb(b, 0.05, 31), synth.perturb(p, 0.05, 32)
+    S = orc.System([8])
+    _, _, fb, fp, E, _ = orc.forces(P1, S, b, p)
+    h = 1e-6
+    for X, F, isb in ((b, fb[t], True), (p, fp[t], False)):
+        for i in range(X.shape[0]):
+            for k in range(3):
+                Xp = X.copy(); Xp[i, k] += h
+                Xm = X.copy(); Xm[i, k] -= h
+                ep = orc.forces(P1, S, *((Xp, p) if isb else (b, Xp)))[4][0, t]
+                em = orc.forces(P1, S, *((Xm, p) if isb else (b, Xm)))[4][0, t]
+                assert abs(-(ep - em) / (2 * h) - F[i, k]) < 2e-6 * max(1.0, np.abs(F).max())
+    # reversing the base-pair order (bp n -> 7 - n, strands kept) maps the
+    # set of both triples onto itself; one triple per step does not
+    rev = lambda x: x.reshape(8, 2, 3)[::-1].reshape(16, 3).copy()
+    E1r = orc.forces(P1, S, rev(b), rev(p))[4][0, t]
+    E0 = orc.forces(P0, S, b, p)[4][0, t]
+    E0r = orc.forces(P0, S, rev(b), rev(p))[4][0, t]
+    assert E1r == pytest.approx(E[0, t], rel=1e-12)
+    assert abs(E0r - E0) > 1e-3 * abs(E0)
+    # the added energy is that of the mirrored triples, from their angles
+    extra = 0.0
+    bb, pp = b.reshape(8, 2, 3), p.reshape(8, 2, 3)
+    for s in (0, 1):
+        for n in range(7):
+            r1, r2 = pp[n + 1, s] - pp[n, s], bb[n, s] - pp[n, s]
+            al = np.arccos(np.dot(r1, r2) / np.linalg.norm(r1) / np.linalg.norm(r2))
+            extra += 0.5 * P1.K5 * (al - P1.a0) ** 2
+    assert E[0, t] == pytest.approx(E0 + extra, rel=1e-12)
+
+
+def test_planarity_both_on_a_ring(orc):
+    """On a ring the seam step gets its second triple as well.  On an ideal
+    ring (the bead azimuth advancing uniformly round a circle) the mirrored
+    triple of step n deviates from 90 deg by minus the deviation of the
+    original triple at the other end of the step, up to a cyclic shift of
+    the azimuths, so both triples together carry exactly twice the energy of
+    one; a perturbed ring's forces are the gradient of the energy."""
+    t = orc.T["planar"]
+    P0, P1 = orc.default_params(), orc.default_params(planarity_both=1)
+    b, p = synth.ideal_ring(30, 3)
+    S = orc.System([30], circular=[1])
+    E0 = orc.forces(P0, S, b, p)[4][0, t]
+    _, _, fb, fp, E, _ = orc.forces(P1, S, b, p)
+    assert E0 > 1.0 and E[0, t] == pytest.approx(2.0 * E0, rel=1e-12)
+    b2, p2 = synth.perturb(b, 0.04, 5), synth.perturb(p, 0.04, 6)
+    _, _, fb, fp, E, _ = orc.forces(P1, S, b2, p2)
+    h = 1e-6
+    for i in (0, 1, 58, 59):   # sites next to the seam
+        for k in range(3):
+            Xp = b2.copy(); Xp[i, k] += h
+            Xm = b2.copy(); Xm[i, k] -= h
+            d = -(orc.forces(P1, S, Xp, p2)[4][0, t] - orc.forces(P1, S, Xm, p2)[4][0, t]) / (2 * h)
+            assert abs(d - fb[t][i, k]) < 2e-6 * max(1.0, np.abs(fb[t]).max())

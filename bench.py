@@ -59,6 +59,17 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def _finite(x):
+    """x with every non-finite float replaced by None (strict JSON)."""
+    if isinstance(x, dict):
+        return {k: _finite(v) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [_finite(v) for v in x]
+    if isinstance(x, float) and not np.isfinite(x):
+        return None
+    return x
+
+
 def workload(name):
     """Build (or load from the per-machine cache) the synthetic input."""
     cache = os.environ.get("DSDNA_CACHE", "/tmp/dsdna_bench_cache")
@@ -277,9 +288,10 @@ def denaturation_report(D, cfg, sim32, args):
     energy difference FP32 vs FP64 on the shared start state and on the FP64
     run's last sampled state.  A run the model's dynamics stops (a backbone
     bond reaching R0) is reported with its step."""
-    extra = {"dt": args.dt} if args.dt > 0 else {}
-    prm64 = D.dsdna_default_params(seed=0, force_fp64=1, ssdna_rule=1, graph_steps=args.graph_steps, **extra)
-    prm32 = D.dsdna_default_params(seed=0, ssdna_rule=1, graph_steps=args.graph_steps, **extra)
+    # the FP32 run's own parameters (with any --param readings), FP64 forces
+    prm32 = type(sim32.params).from_buffer_copy(sim32.params)
+    prm64 = type(sim32.params).from_buffer_copy(sim32.params)
+    prm64.force_fp64 = 1
     sim64 = D.DsDNA(cfg, prm64, device=0)
     R, V, u, L, k = sim32.state()
     sim64.set_state(R, V, u, L, k)
@@ -497,18 +509,20 @@ def single_molecule_report(D, cfg, sim, args):
     """Force-extension (Sec. 4.1): R_z = (c(last bp) - c(first bp)) . e_z of
     the centreline averaged per force, fitted to the Marko-Siggia
     interpolation F l_p / kT = R_z/L + 1/(4 (1 - R_z/L)^2) - 1/4 for L and
-    l_p.  Twist response (Sec. 4.2): sigma = (<twist per bp> - 36 deg)/36 deg
-    per torque (the chain held straight by 16 pN has no writhe, so Lk - Lk0
-    is the excess twist), and C = (a0/theta0) dGamma/dsigma / kT from the
-    slope over the linear regime |sigma| < 0.1 (a torque that melts the
-    duplex leaves it).  The chains start straight, so a force enters the fit
+    l_p (residuals in extension).  Twist response (Sec. 4.2): sigma per
+    torque from the twist measured two ways, the mean base-pair frame angle
+    ((<twist per bp> - 36 deg)/36 deg) and the closure of the appendix
+    (Tw = Lk - Wr of the strands closed far away, sigma = (Tw - n/10)/(n/10);
+    the chain held straight by 16 pN has little writhe), and C = (a0/theta0)
+    dGamma/dsigma / kT from the slope over the linear regime |sigma| < 0.1
+    (a torque that melts the duplex leaves it).  The chains start straight, so a force enters the fit
     only if the equilibration lasted 3 relaxation times of the slowest
     bending mode at that tension, tau(F) = zeta / (kappa q^4 + F q^2) with
     q = 4.73/L, zeta = 4 gamma per rise (four sites per base pair) and
     kappa = 45 kT nm (the measured persistence length).  Errors: standard
     errors of the per-replica means; the fit errors from the covariance of
     the least-squares fit."""
-    from scipy.optimize import curve_fit
+    from paper_1608_03722_amd import analysis as AN
     n_bp = np.asarray(cfg["n_bp"], np.int64)
     off = np.concatenate([[0], np.cumsum(2 * n_bp)])
     grp, fpn, gpn = cfg["group"], cfg["f_pn"], cfg["g_pnnm"]
@@ -520,10 +534,13 @@ def single_molecule_report(D, cfg, sim, args):
         log("equilibration: %d of %d steps" % (done, args.equil_steps))
     rz = np.zeros(len(n_bp))
     tw = np.zeros(len(n_bp))
+    tw_lk = np.zeros(len(n_bp))
     ns = max(2, args.samples)
     for q in range(ns):
         sim.step(args.sample_every)
         b, p = sim.sites()
+        lk, wr = sim.linking()
+        tw_lk += (lk - wr) / ns
         for r in range(len(n_bp)):
             bb, pp = b[off[r]:off[r + 1]], p[off[r]:off[r + 1]]
             c = 0.5 * (pp[0::2] + pp[1::2])
@@ -550,24 +567,29 @@ def single_molecule_report(D, cfg, sim, args):
     zm = np.array([rz[fe & (fpn == f)].mean() for f in forces])
     zs = np.array([rz[fe & (fpn == f)].std(ddof=1) / np.sqrt(np.sum(fe & (fpn == f))) for f in forces])
 
-    def ms(z, L, lp):
-        x = np.clip(z / L, -0.99, 0.99)
-        return kT / lp * (x + 0.25 / (1 - x) ** 2 - 0.25)
-
-    # the interpolation gives F(R_z): fit the forces at the measured mean
-    # extensions (residuals in force)
-    popt, pcov = curve_fit(ms, zm[use], forces[use], p0=(0.34 * n_bp[fe][0], 50.0), maxfev=20000)
-    L, lp = popt
-    dL, dlp = np.sqrt(np.diag(pcov))
+    sem = zs[use] if np.all(zs[use] > 0) else None
+    nan = float("nan")
+    try:
+        msf = AN.fit_marko_siggia(zm[use], forces[use], rz_sem=sem, p0=(0.34 * n_bp[fe][0], 50.0))
+    except (ValueError, RuntimeError) as e:   # too few equilibrated forces, or no convergence
+        log("force-extension: no fit (%s)" % e)
+        msf = {"L": nan, "L_err": nan, "lp": nan, "lp_err": nan}
+    L, dL, lp, dlp = msf["L"], msf["L_err"], msf["lp"], msf["lp_err"]
     tq = grp == 1
     torques = np.unique(gpn[tq])
     sg = np.array([(tw[tq & (gpn == g)].mean() - 36.0) / 36.0 for g in torques])
     ss = np.array([tw[tq & (gpn == g)].std(ddof=1) / np.sqrt(np.sum(tq & (gpn == g))) / 36.0 for g in torques])
-    lin = np.abs(sg) < 0.1
-    A = np.vstack([sg[lin], np.ones(int(lin.sum()))]).T
-    slope, icpt = np.linalg.lstsq(A, torques[lin], rcond=None)[0]   # dGamma/dsigma, pN nm
-    a0, th0 = 0.34, 2 * np.pi / 10
-    C = a0 / th0 * slope / kT
+    sg_lk = np.array([AN.superhelical_density(tw_lk[tq & (gpn == g)].mean(), n_bp[tq][0]) for g in torques])
+
+    def stiffness(sig):
+        try:
+            return AN.torsional_stiffness(torques, sig)
+        except ValueError as e:   # fewer than two torques in the linear regime
+            log("twist response: no fit (%s)" % e)
+            return {"C": nan, "C_err": nan, "slope": nan, "intercept": nan, "in_fit": [False] * len(sig)}
+
+    tor, tor_lk = stiffness(sg), stiffness(sg_lk)
+    slope, C, lin = tor["slope"], tor["C"], np.array(tor["in_fit"])
     out = {"equilibration_steps": args.equil_steps, "samples": ns, "sample_every": args.sample_every,
            "force_extension": {"f_pn": forces.tolist(), "rz_nm": zm.tolist(), "rz_sem": zs.tolist(),
                                "relax_time": tau.tolist(), "in_fit": use.tolist(),
@@ -575,9 +597,13 @@ def single_molecule_report(D, cfg, sim, args):
                                "lp_bp": float(lp / 0.334), "rise_nm": float(L / n_bp[fe][0])},
            "twist_response": {"torque_pnnm": torques.tolist(), "sigma": sg.tolist(), "sigma_sem": ss.tolist(),
                               "in_fit": lin.tolist(),
-                              "dgamma_dsigma_pnnm": float(slope), "C_nm": float(C), "C_bp": float(C / 0.34)}}
-    log("force-extension: L = %.1f +- %.1f nm, l_p = %.1f +- %.1f nm; twist: C = %.1f nm"
-        % (L, dL, lp, dlp, C))
+                              "dgamma_dsigma_pnnm": float(slope), "C_nm": float(C), "C_err": tor["C_err"],
+                              "C_bp": float(C / 0.34),
+                              "closure": {"sigma": sg_lk.tolist(), "in_fit": tor_lk["in_fit"],
+                                          "dgamma_dsigma_pnnm": tor_lk["slope"], "C_nm": tor_lk["C"],
+                                          "C_err": tor_lk["C_err"]}}}
+    log("force-extension: L = %.1f +- %.1f nm, l_p = %.1f +- %.1f nm; twist: C = %.1f nm (frames), %.1f nm (closure)"
+        % (L, dL, lp, dlp, C, tor_lk["C"]))
     return out
 
 
@@ -877,7 +903,7 @@ def main():
         "batched_vs_single": batch,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
+    print(json.dumps(_finite(out)), flush=True)
 
 
 if __name__ == "__main__":

@@ -143,6 +143,12 @@ typedef struct {
                                        0: max(4096, nucleotides / 8).  The
                                        list grows by itself when a rebuild
                                        finds more pairs.                    */
+    int32_t planarity_both;         /* 0: one planarity angle per backbone
+                                       step and strand, at patch n+1 between
+                                       patch n and bead n+1; 1: also the
+                                       angle at patch n between patch n+1
+                                       and bead n (both triples of the step,
+                                       same potential)                     */
 } dsdna_params;
 
 /* Table 2 values plus the defaults for what the paper leaves open: unit

@@ -285,6 +285,7 @@ static void fill_phys(dsdna_ctx *c)
     h.ssdna_rule = p.ssdna_rule;
     h.fene_clamp = p.fene_clamp;
     h.dihedral_damping = p.dihedral_damping;
+    h.planarity_both = p.planarity_both;
 }
 
 // Reach of the neighbour search: the largest WCA cutoff plus the skin.

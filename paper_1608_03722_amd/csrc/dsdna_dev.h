@@ -49,6 +49,7 @@ struct Phys {
     uint64_t seed;
     int32_t noise_kind, ssdna_rule;
     int32_t fene_clamp, dihedral_damping;
+    int32_t planarity_both;
 };
 
 enum : uint32_t {

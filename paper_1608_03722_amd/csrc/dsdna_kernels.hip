@@ -814,6 +814,35 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
         put3(S.oStep[s][mi][2], get3(S.oStep[s][mi][2]) + fBb);
         put3(S.oStep[s][mi][3], get3(S.oStep[s][mi][3]) + fPb);
     }
+    // --- the planarity reading with both triples of a step: the angle at
+    //     P_m between P_m+1 and B_m as well, same potential, in a pass of its
+    //     own (from the staged sites; each thread adds to the outboxes of
+    //     the step it wrote above)
+    if (ph.planarity_both && (mask & (1u << DSDNA_TERM_PLANAR))) {
+        for (int q = t; q < 2 * (TILE_BP + 1); q += blockDim.x) {
+            const int s = q & 1, mi = q >> 1, m = n0 - 1 + mi;
+            if (!(m >= step_lo && m < step_hi)) continue;
+            const int la = 2 * (mi + HALO_BP - 1) + s, lb = la + 2;
+            const D3 Ba = lds3(S.sB, la), Pa = lds3(S.sP, la), Pb = lds3(S.sP, lb);
+            const bool own = mi >= 1;
+            const D3 q1d = Pb - Pa, q2d = Ba - Pa;
+            const double m11d = dot(q1d, q1d), m22d = dot(q2d, q2d);
+            const double jld = rsq64(m11d * m22d);
+            double ce = dot(q1d, q2d) * jld;
+            ce = ce > 1.0 ? 1.0 : (ce < -1.0 ? -1.0 : ce);
+            const double t2 = 1.0 - ce * ce, sne = t2 > 0.0 ? t2 * rsq64(t2) : 0.0;
+            const real db = atan2_small((real)(sne * ph.cos_a0 - ce * ph.sin_a0), (real)(ce * ph.cos_a0 + sne * ph.sin_a0));
+            const V3<real> q1 = cvt<real>(q1d), q2 = cvt<real>(q2d);
+            const real jl = (real)jld, cq = (real)ce;
+            const real dUde = -(real)ph.K5 * db * rcp((real)sne);
+            const V3<real> dqa = q2 * jl - q1 * (cq * rcp((real)m11d)), dqc = q1 * jl - q2 * (cq * rcp((real)m22d));
+            const V3<real> ga = dqa * (-dUde), gc = dqc * (-dUde);
+            put3(S.oStep[s][mi][0], get3(S.oStep[s][mi][0]) + gc);
+            put3(S.oStep[s][mi][1], get3(S.oStep[s][mi][1]) - (ga + gc));
+            put3(S.oStep[s][mi][3], get3(S.oStep[s][mi][3]) + ga);
+            if (energies && own) energies[DSDNA_TERM_PLANAR] += 0.5 * ph.K5 * (double)db * (double)db;
+        }
+    }
     // --- Kratky-Porod bending on patches (s, m-1), (s, m), (s, m+1)
     for (int q = t; q < 2 * (TILE_BP + 2); q += blockDim.x) {
         const int s = q & 1, mi = q >> 1, m = n0 - 1 + mi;

@@ -50,7 +50,8 @@ class Params(C.Structure):
         ("seed", C.c_uint64), ("noise_kind", C.c_int32), ("force_fp64", C.c_int32),
         ("ssdna_rule", C.c_int32), ("hb_depth_convention", C.c_int32), ("cell_size", C.c_double),
         ("hash_log2", C.c_int32), ("graph_steps", C.c_int32), ("fene_clamp", C.c_int32),
-        ("dihedral_damping", C.c_int32), ("skin", C.c_double), ("list_capacity", C.c_int64)]
+        ("dihedral_damping", C.c_int32), ("skin", C.c_double), ("list_capacity", C.c_int64),
+        ("planarity_both", C.c_int32)]
 
 
 class TuneSpace(C.Structure):

@@ -112,3 +112,23 @@ def test_dihedral_damping_matches_oracle(D, fp64, tol):
         R, V, u, L, k = sim.state()
         assert k == ref.step and np.abs(R - ref.R).max() < 1e-9
     sim.close()
+
+
+@pytest.mark.parametrize("fp64,tol", [(0, 1e-5), (1, 1e-10)])
+def test_planarity_both_matches_oracle(D, fp64, tol):
+    """The planarity reading with both triples of a step, per term and in an
+    FP64 trajectory, on rings (across the seam) and a linear chain."""
+    cfg = _seq_cfg(2)
+    P, S, st = _thermal(cfg, 200, seed=19, planarity_both=1)
+    sim = D.DsDNA(cfg, D.dsdna_default_params(seed=19, force_fp64=fp64, planarity_both=1))
+    sim.set_state(st.R, st.V, st.u, st.L, 0)
+    _compare(D, sim, P, S, st.R, st.u, tol)
+    if fp64:
+        ref = O.State(st.R, st.u, st.V, st.L, st.step)
+        sim.set_state(ref.R, ref.V, ref.u, ref.L, ref.step)
+        sim.step(50)
+        code, _, _ = O.step(P, S, ref, 50, use_cells=1)
+        assert code == O.OK
+        R, V, u, L, k = sim.state()
+        assert k == ref.step and np.abs(R - ref.R).max() < 1e-9
+    sim.close()

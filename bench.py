@@ -188,6 +188,93 @@ def cpu_baseline(cfg, steps, seed=0):
     return S.n_nt * steps / dt, dt
 
 
+def host_cpu():
+    """Model name, logical CPUs and the CPUs this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity": allowed}
+
+
+def segment(cfg, k, parts):
+    """Piece k of `parts` consecutive pieces of a single-replica config (same
+    box), as a config of its own."""
+    n = int(cfg["n_bp"][0])
+    lo, hi = n * k // parts, n * (k + 1) // parts
+    out = {"n_bp": np.array([hi - lo], np.int32), "bead": cfg["bead"][2 * lo:2 * hi],
+           "patch": cfg["patch"][2 * lo:2 * hi]}
+    for key in ("box", "periodic"):
+        if key in cfg:
+            out[key] = cfg[key][:1]
+    return out
+
+
+def cpu_worker(args):
+    """One process of the all-core leg: the oracle on piece k of `parts` of
+    the workload; reports ready after setting up, steps when told to go, and
+    prints its stepping time (no GPU, no torch)."""
+    from oracle import oracle as O
+    k, parts = (int(x) for x in args.cpu_worker.split("/"))
+    cfg, _ = workload(args.config)
+    seg = segment(cfg, k, parts)
+    P = O.default_params(seed=k)
+    S = O.System(seg["n_bp"], box=seg.get("box"), periodic=seg.get("periodic"))
+    R, u = O.bodies_from_sites(P, seg["bead"], seg["patch"])
+    st = O.State(R, u)
+    O.thermalize(P, S, st, 1.0, k)
+    O.step(P, S, st, 1, use_cells=1)
+    print("ready", flush=True)
+    sys.stdin.readline()
+    t0 = time.perf_counter()
+    code, _, _ = O.step(P, S, st, args.cpu_steps, use_cells=1)
+    dt = time.perf_counter() - t0
+    print(json.dumps({"n_nt": S.n_nt, "steps": args.cpu_steps, "s": dt, "status": int(code)}), flush=True)
+
+
+def cpu_all_cores(args, cores, steps):
+    """The oracle as it stands on every allowed host core at once: one
+    process per core, each on a consecutive piece of the workload (same box),
+    started together; nucleotide-steps of all pieces over the slowest
+    piece's time."""
+    from oracle import oracle as O
+    import subprocess
+    O.build(force=False)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    cmd = [sys.executable, os.path.abspath(__file__), "--config", args.config, "--cpu-steps", str(steps)]
+    procs = [subprocess.Popen(cmd + ["--cpu-worker", "%d/%d" % (k, cores)], stdin=subprocess.PIPE,
+                              stdout=subprocess.PIPE, text=True, env=env) for k in range(cores)]
+    try:
+        for p in procs:
+            if p.stdout.readline().strip() != "ready":
+                raise RuntimeError("oracle worker failed to start")
+        for p in procs:
+            p.stdin.write("go\n")
+            p.stdin.flush()
+        res = [json.loads(p.stdout.readline()) for p in procs]
+    finally:
+        for p in procs:
+            try:
+                p.stdin.close()
+            except OSError:
+                pass
+            p.wait(timeout=600)
+    if any(r["status"] != 0 for r in res):
+        raise RuntimeError("oracle worker step failed")
+    nt_steps = sum(r["n_nt"] * r["steps"] for r in res)
+    slowest = max(r["s"] for r in res)
+    return nt_steps / slowest, slowest
+
+
 def timed_steps(D, sim, steps, sync):
     sync()
     t0 = time.perf_counter()
@@ -672,6 +759,9 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=50)
     ap.add_argument("--profile-steps", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--cpu-core-steps", type=int, default=200,
+                    help="steps per piece in the all-core oracle leg (one piece per allowed core, at most 16)")
+    ap.add_argument("--cpu-worker", default="", help=argparse.SUPPRESS)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--replica-steps", type=int, default=200)
     ap.add_argument("--no-replicas", action="store_true")
@@ -688,6 +778,8 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a counter calibration)")
     args = ap.parse_args()
+    if args.cpu_worker:
+        return cpu_worker(args)
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this library has no multi-GPU path (replicas would be "
               "assigned whole to GPUs, a single long chain split into spatial slabs)", file=sys.stderr)
@@ -870,12 +962,26 @@ def main():
 
     cpu = None
     if not args.no_cpu:
+        host = host_cpu()
         log("oracle baseline: %d steps of the same workload on one host core" % args.cpu_steps)
-        v, dt = cpu_baseline(cfg, args.cpu_steps)
-        cpu = {"value": v, "unit": "nucleotide-timesteps/s", "cores": 1, "kind": "oracle",
-               "sample": "%d steps of the full %d-nucleotide workload, one thread (%.1f s)"
-                         % (args.cpu_steps, n_nt, dt)}
-        log("oracle: %.4g nt-steps/s" % v)
+        v1, dt1 = cpu_baseline(cfg, args.cpu_steps)
+        log("oracle, one thread: %.4g nt-steps/s" % v1)
+        single = {"value": v1, "cores": 1,
+                  "sample": "%d steps of the full %d-nucleotide workload, one thread (%.1f s)"
+                            % (args.cpu_steps, n_nt, dt1)}
+        cores = max(1, min(16, host["affinity"] or 1))
+        if len(cfg["n_bp"]) == 1 and cores > 1:
+            log("oracle baseline: %d processes, %d steps of 1/%d of the workload each" % (cores, args.cpu_core_steps, cores))
+            v, dt = cpu_all_cores(args, cores, args.cpu_core_steps)
+            log("oracle, %d cores: %.4g nt-steps/s" % (cores, v))
+            cpu = {"value": v, "unit": "nucleotide-timesteps/s", "cores": cores, "kind": "oracle",
+                   "sample": "%d steps of each of %d consecutive pieces of the %d-nucleotide chain (same box), "
+                             "one oracle process per core, started together (%.1f s for the slowest)"
+                             % (args.cpu_core_steps, cores, n_nt, dt),
+                   "single_thread": single, **host}
+        else:
+            cpu = {"value": v1, "unit": "nucleotide-timesteps/s", "cores": 1, "kind": "oracle",
+                   "sample": single["sample"], **host}
 
     out = {
         "metric": "nucleotide-timesteps/s at 1 Mbp (1 GPU) + % peak HBM; batched vs single"

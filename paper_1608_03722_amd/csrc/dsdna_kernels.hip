@@ -446,15 +446,33 @@ __device__ __forceinline__ int tile_index(int n_tiles, int n_tiles_pad)
 
 // ------------------------------------------------------------- tile stage
 
+// The tile's shared arrays, component-major with the site, step or centre
+// index fastest, so that the lanes of a wave touch consecutive words (no
+// bank conflicts; a [n][3] layout puts 24 or 12 bytes between lanes).
+constexpr int TILE_SITES = TILE_NT + 4 * HALO_BP;  // staged sites, halo included
+constexpr int TILE_STEPS = 2 * (TILE_BP + 1);      // backbone steps x strands: q = 2 m_i + s
+constexpr int TILE_BENDS = 2 * (TILE_BP + 2);      // bending centres x strands: q = 2 m_i + s
 template <typename real>
 struct TileLds {
-    double sB[TILE_NT + 4 * HALO_BP][3];   // FP64 sites, halo of 2 bp each side
-    double sP[TILE_NT + 4 * HALO_BP][3];
-    real oStep[2][TILE_BP + 1][4][3];      // per strand, per backbone step m
-    real oBend[2][TILE_BP + 2][2][3];      // per strand, per bending centre: end forces
-    real oHb[TILE_BP][3];                  // force on strand-0 patch
+    double sB[3][TILE_SITES];              // FP64 bead and patch positions
+    double sP[3][TILE_SITES];
+    real oStep[4][3][TILE_STEPS];          // per backbone step: bead a, patch a, bead b, patch b
+    real oBend[2][3][TILE_BENDS];          // per bending centre: its two end patches
+    real oHb[3][TILE_BP];                  // force on strand-0 patch
     uint8_t sOpen[TILE_BP + 2 * HALO_BP];  // open flags of bp n0-2 .. n0+TILE_BP+1
 };
+
+template <int N>
+__device__ __forceinline__ D3 site3(const double (&a)[3][N], int l) { return v3(a[0][l], a[1][l], a[2][l]); }
+template <typename real, int N>
+__device__ __forceinline__ V3<real> get_c(const real (&a)[3][N], int q) { return v3(a[0][q], a[1][q], a[2][q]); }
+template <typename real, int N>
+__device__ __forceinline__ void put_c(real (&a)[3][N], int q, V3<real> v)
+{
+    a[0][q] = v.x;
+    a[1][q] = v.y;
+    a[2][q] = v.z;
+}
 
 template <typename real>
 struct SiteForces {
@@ -521,8 +539,8 @@ __device__ __forceinline__ void stage_site(const StepArgs &a, TileLds<real> &S, 
 {
     if (!st.valid) return;
     const D3 b = bead_of(st.R, st.u, a.ph.db), p = patch_of(st.R, st.u, a.ph.dp);
-    S.sB[st.l][0] = b.x; S.sB[st.l][1] = b.y; S.sB[st.l][2] = b.z;
-    S.sP[st.l][0] = p.x; S.sP[st.l][1] = p.y; S.sP[st.l][2] = p.z;
+    S.sB[0][st.l] = b.x; S.sB[1][st.l] = b.y; S.sB[2][st.l] = b.z;
+    S.sP[0][st.l] = p.x; S.sP[1][st.l] = p.y; S.sP[2][st.l] = p.z;
 }
 
 // Contact bit of the calling thread's nucleotide in tile tix: its
@@ -618,7 +636,7 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
                 const int bw = bp < 0 ? bp + nbp : (bp >= nbp ? bp - nbp : bp);
                 k2n *= gmem(a.b.k2bp)[ri.off / 2 + bw];
             }
-            const D3 d64 = lds3(S.sP, 2 * q + 1) - lds3(S.sP, 2 * q);
+            const D3 d64 = site3(S.sP, 2 * q + 1) - site3(S.sP, 2 * q);
             const double r = sqrt(dot(d64, d64));
             open = r > ph.rc_hb;
             if (!open && (mask & (1u << DSDNA_TERM_HBOND))) {
@@ -632,7 +650,7 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
             }
         }
         S.sOpen[q] = open;
-        if (q >= HALO_BP && q < TILE_BP + HALO_BP) put3(S.oHb[q - HALO_BP], f);
+        if (q >= HALO_BP && q < TILE_BP + HALO_BP) put_c(S.oHb, q - HALO_BP, f);
     }
     // the open flags are read below only under the single-strand rule (the
     // H-bond outboxes are read after the next barrier); the condition is the
@@ -656,7 +674,7 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
         if (m >= step_lo && m < step_hi) {
             // LDS site of (s, bp m) and (s, bp m + 1)
             const int la = 2 * (mi + HALO_BP - 1) + s, lb = la + 2;
-            const D3 Ba = lds3(S.sB, la), Pa = lds3(S.sP, la), Bb = lds3(S.sB, lb), Pb = lds3(S.sP, lb);
+            const D3 Ba = site3(S.sB, la), Pa = site3(S.sP, la), Bb = site3(S.sB, lb), Pb = site3(S.sP, lb);
             const bool own = mi >= 1;  // step m belongs to the tile that holds nucleotide m
             // backbone: FENE + WCA(eps_bb, sig_bb) between consecutive beads
             if (mask & (1u << DSDNA_TERM_BOND)) {
@@ -731,10 +749,10 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
                 if (energies && own) energies[DSDNA_TERM_PLANAR] += 0.5 * ph.K5 * (double)da * (double)da;
             }
         }
-        put3(S.oStep[s][mi][0], fBa);
-        put3(S.oStep[s][mi][1], fPa);
-        put3(S.oStep[s][mi][2], fBb);
-        put3(S.oStep[s][mi][3], fPb);
+        put_c(S.oStep[0], q, fBa);
+        put_c(S.oStep[1], q, fPa);
+        put_c(S.oStep[2], q, fBb);
+        put_c(S.oStep[3], q, fPb);
     }
     // --- helical twist of the same backbone steps in a pass of its own (its
     //     FP64 intermediates are not live with the other terms'); each
@@ -743,7 +761,7 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
         const int s = q & 1, mi = q >> 1, m = n0 - 1 + mi;
         if (!(m >= step_lo && m < step_hi)) continue;
         const int la = 2 * (mi + HALO_BP - 1) + s, lb = la + 2;
-        const D3 Ba = lds3(S.sB, la), Pa = lds3(S.sP, la), Bb = lds3(S.sB, lb), Pb = lds3(S.sP, lb);
+        const D3 Ba = site3(S.sB, la), Pa = site3(S.sP, la), Bb = site3(S.sB, lb), Pb = site3(S.sP, lb);
         const bool own = mi >= 1;
         const D3 b1d = Pa - Ba, b2d = Pb - Pa, b3d = Bb - Pb;
         V3<real> fBa = v3<real>(0, 0, 0), fPa = fBa, fBb = fBa, fPb = fBa;
@@ -809,10 +827,10 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
             }
             if (energies && own) energies[DSDNA_TERM_TWIST] += Sd * ph.K3 * (1.0 + cphi * ph.cos_d + sphi * ph.sin_d);
         }
-        put3(S.oStep[s][mi][0], get3(S.oStep[s][mi][0]) + fBa);
-        put3(S.oStep[s][mi][1], get3(S.oStep[s][mi][1]) + fPa);
-        put3(S.oStep[s][mi][2], get3(S.oStep[s][mi][2]) + fBb);
-        put3(S.oStep[s][mi][3], get3(S.oStep[s][mi][3]) + fPb);
+        put_c(S.oStep[0], q, get_c(S.oStep[0], q) + fBa);
+        put_c(S.oStep[1], q, get_c(S.oStep[1], q) + fPa);
+        put_c(S.oStep[2], q, get_c(S.oStep[2], q) + fBb);
+        put_c(S.oStep[3], q, get_c(S.oStep[3], q) + fPb);
     }
     // --- the planarity reading with both triples of a step: the angle at
     //     P_m between P_m+1 and B_m as well, same potential, in a pass of its
@@ -823,7 +841,7 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
             const int s = q & 1, mi = q >> 1, m = n0 - 1 + mi;
             if (!(m >= step_lo && m < step_hi)) continue;
             const int la = 2 * (mi + HALO_BP - 1) + s, lb = la + 2;
-            const D3 Ba = lds3(S.sB, la), Pa = lds3(S.sP, la), Pb = lds3(S.sP, lb);
+            const D3 Ba = site3(S.sB, la), Pa = site3(S.sP, la), Pb = site3(S.sP, lb);
             const bool own = mi >= 1;
             const D3 q1d = Pb - Pa, q2d = Ba - Pa;
             const double m11d = dot(q1d, q1d), m22d = dot(q2d, q2d);
@@ -837,9 +855,9 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
             const real dUde = -(real)ph.K5 * db * rcp((real)sne);
             const V3<real> dqa = q2 * jl - q1 * (cq * rcp((real)m11d)), dqc = q1 * jl - q2 * (cq * rcp((real)m22d));
             const V3<real> ga = dqa * (-dUde), gc = dqc * (-dUde);
-            put3(S.oStep[s][mi][0], get3(S.oStep[s][mi][0]) + gc);
-            put3(S.oStep[s][mi][1], get3(S.oStep[s][mi][1]) - (ga + gc));
-            put3(S.oStep[s][mi][3], get3(S.oStep[s][mi][3]) + ga);
+            put_c(S.oStep[0], q, get_c(S.oStep[0], q) + gc);
+            put_c(S.oStep[1], q, get_c(S.oStep[1], q) - (ga + gc));
+            put_c(S.oStep[3], q, get_c(S.oStep[3], q) + ga);
             if (energies && own) energies[DSDNA_TERM_PLANAR] += 0.5 * ph.K5 * (double)db * (double)db;
         }
     }
@@ -852,7 +870,7 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
         const bool masked = rule && op[0] && op[1] && op[2];
         if ((mask & (1u << DSDNA_TERM_BEND)) && m >= bend_lo && m < bend_hi && !masked) {
             const int la = 2 * (mi + HALO_BP - 2) + s;  // LDS site of (s, bp m - 1)
-            const D3 Pa = lds3(S.sP, la), Pc = lds3(S.sP, la + 2), Pe = lds3(S.sP, la + 4);
+            const D3 Pa = site3(S.sP, la), Pc = site3(S.sP, la + 2), Pe = site3(S.sP, la + 4);
             const D3 r1 = Pa - Pc, r2 = Pe - Pc;
             const double l11 = dot(r1, r1), l22 = dot(r2, r2), d12 = dot(r1, r2);
             const double il = rsq64(l11 * l22);
@@ -864,8 +882,8 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
             f2 = cvt<real>((r1 - r2 * (d12 * rcp64(l22))) * k);
             if (energies && mi >= 1 && mi <= TILE_BP && m < nbp) energies[DSDNA_TERM_BEND] += ph.K6 * (1.0 + d12 * il);
         }
-        put3(S.oBend[s][mi][0], f0);
-        put3(S.oBend[s][mi][1], f2);
+        put_c(S.oBend[0], q, f0);
+        put_c(S.oBend[1], q, f2);
     }
 
     // --- chain-local excluded volume (WCA with the steric/ghost rule of
@@ -879,11 +897,11 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
     V3<real> floc = v3<real>(0, 0, 0);
     if (t < TILE_NT && n0 + (t >> 1) < nbp && (mask & (1u << DSDNA_TERM_EXCL))) {
         const int s = t & 1, bl = t >> 1, n = n0 + bl;
-        const D3 bi = lds3(S.sB, t + 2 * HALO_BP);
+        const D3 bi = site3(S.sB, t + 2 * HALO_BP);
         D3 acc = v3(0.0, 0.0, 0.0);
         double eh = 0.0;
         auto wca = [&](int lj, double sig2, double rc2) {
-            const D3 d = lds3(S.sB, lj) - bi;  // from this bead to the other
+            const D3 d = site3(S.sB, lj) - bi;  // from this bead to the other
             const double r2 = dot(d, d);
             if (r2 < rc2) {
                 const double ir2 = 1.0 / r2, sr2 = sig2 * ir2, sr6 = sr2 * sr2 * sr2;
@@ -914,12 +932,12 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
     out.b = v3<real>(0, 0, 0);
     out.p = out.b;
     if (n < nbp) {
-        out.b = get3(S.oStep[s][bl][2]) + get3(S.oStep[s][bl + 1][0]);
+        out.b = get_c(S.oStep[2], 2 * bl + s) + get_c(S.oStep[0], 2 * (bl + 1) + s);
         // middle patch of a bending triple: minus the sum of the end forces
-        const V3<real> mid = -(get3(S.oBend[s][bl + 1][0]) + get3(S.oBend[s][bl + 1][1]));
-        out.p = get3(S.oStep[s][bl][3]) + get3(S.oStep[s][bl + 1][1]) + get3(S.oBend[s][bl][1]) + mid +
-                get3(S.oBend[s][bl + 2][0]);
-        const V3<real> hb = get3(S.oHb[bl]);
+        const V3<real> mid = -(get_c(S.oBend[0], 2 * (bl + 1) + s) + get_c(S.oBend[1], 2 * (bl + 1) + s));
+        out.p = get_c(S.oStep[3], 2 * bl + s) + get_c(S.oStep[1], 2 * (bl + 1) + s) + get_c(S.oBend[1], 2 * bl + s) +
+                mid + get_c(S.oBend[0], 2 * (bl + 2) + s);
+        const V3<real> hb = get_c(S.oHb, bl);
         out.p = s == 0 ? out.p + hb : out.p - hb;
     }
 
@@ -932,7 +950,7 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
     if (n >= nbp) return out;
 
     const int l = t + 2 * HALO_BP;
-    const D3 bi = lds3(S.sB, l);
+    const D3 bi = site3(S.sB, l);
     const int64_t i = ri.off + 2 * (int64_t)n + s;
 
     // --- external loads (Sec. 4)
@@ -958,7 +976,7 @@ __device__ __forceinline__ SiteForces<real> tile_forces(const StepArgs &a, TileL
                 out.p = out.p + v3<real>((real)(0.5 * ri.pull[0]), (real)(0.5 * ri.pull[1]), (real)(0.5 * ri.pull[2]));
             if (ri.flags & REP_TORQUE) {
                 // couple on the two beads about their midpoint
-                const D3 b0 = lds3(S.sB, l - s), b1 = lds3(S.sB, l - s + 1);
+                const D3 b0 = site3(S.sB, l - s), b1 = site3(S.sB, l - s + 1);
                 const D3 cmid = (b0 + b1) * 0.5;
                 const D3 G = v3(ri.torque[0], ri.torque[1], ri.torque[2]);
                 const double G2 = dot(G, G);
@@ -1197,7 +1215,7 @@ __global__ void __launch_bounds__(WG_THREADS, 5) k_step(const StepArgs *__restri
     //     histogram), the counting sort's count phase; the force phase's
     //     outboxes hold the binning table
     if (rebuild_after) {
-        uint32_t *lds = reinterpret_cast<uint32_t *>(&S.oStep[0][0][0][0]);
+        uint32_t *lds = reinterpret_cast<uint32_t *>(&S.oStep[0][0][0]);
         bin_tile(a, lds, lds + WG_THREADS, reinterpret_cast<int *>(lds + 2 * WG_THREADS), ri, tile.rep, n, s, i,
                  own, bead_new, step + 1);
     }

@@ -816,6 +816,7 @@ def main():
             raise SystemExit("unknown parameter " + k)
         setattr(prm, k, float(v) if isinstance(getattr(prm, k), float) else int(v))
     sim = D.DsDNA(cfg, prm, device=0, stream=stream.cuda_stream)
+    tiling = D.dsdna_get_tiling(sim.ctx)
     sim.thermalize(1.0, 0)
     tuned = None
     if not args.no_autotune and args.cell == 0.0 and args.hash_log2 == 0:
@@ -1000,7 +1001,8 @@ def main():
         "config": {"workload": desc, "n_bp": int(np.sum(cfg["n_bp"])), "n_nt": n_nt,
                    "param_overrides": args.param,
                    "forces": "f32", "state": "f64", "cell_size": h, "buckets": nb,
-                   "graph_steps": args.graph_steps, "parallelism": "single GPU"},
+                   "graph_steps": args.graph_steps, "tile_bp": tiling[0], "wg_threads": tiling[1],
+                   "tiles": tiling[2], "parallelism": "single GPU"},
         "roofline": roof,
         "chunks": ({"steps_each": chunk, "n": len(chunk_rates), "median": float(np.median(chunk_rates)),
                     "min": float(min(chunk_rates)), "max": float(max(chunk_rates))} if chunk_rates else None),

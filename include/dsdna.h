@@ -232,6 +232,12 @@ dsdna_status dsdna_set_circular(dsdna_ctx *ctx, const uint8_t *circular);
  * set_circular: DSDNA_ENOMEM if that fails. */
 dsdna_status dsdna_get_linking(dsdna_ctx *ctx, double *lk, double *wr, double *pair_ms);
 
+/* The tiling of the step kernel: base pairs per tile, threads per workgroup
+ * (one per site of the tile plus its halo, a build constant) and the number
+ * of tiles of the current topology (a replica starts a new tile).  Any
+ * pointer may be NULL.  DSDNA_ESTATE before set_topology. */
+dsdna_status dsdna_get_tiling(dsdna_ctx *ctx, int32_t *tile_bp, int32_t *wg_threads, int64_t *n_tiles);
+
 /* Multiply K2 of each replica by scale[n_rep] (denaturation, Sec. 5). */
 dsdna_status dsdna_set_k2_scale(dsdna_ctx *ctx, const double *scale);
 

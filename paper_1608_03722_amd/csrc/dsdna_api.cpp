@@ -1382,6 +1382,16 @@ dsdna_status dsdna_get_linking(dsdna_ctx *c, double *lk, double *wr, double *pai
     return DSDNA_OK;
 }
 
+dsdna_status dsdna_get_tiling(dsdna_ctx *c, int32_t *tile_bp, int32_t *wg_threads, int64_t *n_tiles)
+{
+    dsdna_status st = check_ready(c, false);
+    if (st) return st;
+    if (tile_bp) *tile_bp = TILE_BP;
+    if (wg_threads) *wg_threads = WG_THREADS;
+    if (n_tiles) *n_tiles = c->a.n_tiles;
+    return DSDNA_OK;
+}
+
 dsdna_status dsdna_set_temperature(dsdna_ctx *c, double kT)
 {
     if (!c) return DSDNA_EINVAL;

@@ -31,7 +31,7 @@ EXPORTS = (
     "dsdna_get_resume", "dsdna_set_resume", "dsdna_get_sites", "dsdna_get_forces", "dsdna_get_energies",
     "dsdna_get_bp_open", "dsdna_get_bubbles", "dsdna_profile_kernels", "dsdna_get_grid", "dsdna_autotune",
     "dsdna_set_circular", "dsdna_get_linking", "dsdna_set_k2_bp", "dsdna_get_sizes",
-    "dsdna_get_neighbour_stats", "dsdna_linking_curves_noalloc", "dsdna_bind_device",
+    "dsdna_get_neighbour_stats", "dsdna_linking_curves_noalloc", "dsdna_bind_device", "dsdna_get_tiling",
 )
 NOALLOC_MAX_POINTS = 1048576
 
@@ -118,6 +118,7 @@ def lib():
             "dsdna_get_neighbour_stats": [vp, vp, vp, vp, vp, vp, vp],
             "dsdna_linking_curves_noalloc": [vp, vp, vp, i64, vp, vp],
             "dsdna_bind_device": [vp, vp, vp, vp, vp],
+            "dsdna_get_tiling": [vp, vp, vp, vp],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
@@ -351,6 +352,13 @@ def dsdna_bind_device(ctx, R, V, u, L):
     n_nt = _sizes(ctx)[1]
     ptrs = [_device_array(x, n_nt, nm) for x, nm in zip((R, V, u, L), "RVuL")]
     _check(ctx, lib().dsdna_bind_device(ctx, *ptrs))
+
+
+def dsdna_get_tiling(ctx):
+    """(base pairs per tile, threads per workgroup, tiles)."""
+    tb, wg, nt = C.c_int32(), C.c_int32(), C.c_int64()
+    _check(ctx, lib().dsdna_get_tiling(ctx, C.byref(tb), C.byref(wg), C.byref(nt)))
+    return tb.value, wg.value, nt.value
 
 
 def dsdna_get_sizes(ctx):

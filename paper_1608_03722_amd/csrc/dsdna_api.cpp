@@ -49,6 +49,8 @@ constexpr int64_t SYNC_STEPS = 500;
 // The interval aims at rebuilds when the farthest bead has covered this
 // fraction of half the skin.
 constexpr double SCHEDULE_FRACTION = 0.95;
+// Instantiated step graphs kept per context.
+constexpr int GRAPH_CACHE = 6;
 
 }  // namespace
 
@@ -78,9 +80,18 @@ struct dsdna_ctx {
     int64_t cur_step = 0; // host mirror of ctl.step
     int64_t state_step = 0;  // step counter at the last state change
 
-    hipGraphExec_t gexec = nullptr;
-    int gsteps = 0;
-    int gK = 0;            // rebuild interval of the captured graph
+    // instantiated step graphs, keyed by their length and rebuild interval:
+    // the interval moves between neighbouring values as displacements
+    // fluctuate, and each graph is captured once (least recently used first
+    // out)
+    struct StepGraph {
+        hipGraphExec_t exec = nullptr;
+        int steps = 0;
+        int K = 0;
+        uint64_t used = 0;
+    };
+    StepGraph graphs[GRAPH_CACHE];
+    uint64_t graph_clock = 0;
 
     // neighbour-list schedule: a rebuild follows every K-th step kernel;
     // `age` step kernels have run since the last rebuild
@@ -238,10 +249,10 @@ static dsdna_status sync_args(dsdna_ctx *c)
 
 static void drop_graph(dsdna_ctx *c)
 {
-    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-    c->gexec = nullptr;
-    c->gsteps = 0;
-    c->gK = 0;
+    for (auto &g : c->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g = dsdna_ctx::StepGraph{};
+    }
 }
 
 static void fill_phys(dsdna_ctx *c)
@@ -710,10 +721,21 @@ static hipError_t enqueue_step(dsdna_ctx *c, int mode, int write_full, int rebui
 }
 
 // A graph of `steps` steps (a multiple of the rebuild interval K) that starts
-// right after a rebuild: rebuilds follow its K-th, 2K-th, ... step.
-static dsdna_status build_graph(dsdna_ctx *c, int steps, int K)
+// right after a rebuild: rebuilds follow its K-th, 2K-th, ... step.  Taken
+// from the cache when there, else captured into the least recently used slot.
+static dsdna_status step_graph(dsdna_ctx *c, int steps, int K, hipGraphExec_t *out)
 {
-    drop_graph(c);
+    dsdna_ctx::StepGraph *slot = &c->graphs[0];
+    for (auto &g : c->graphs) {
+        if (g.exec && g.steps == steps && g.K == K) {
+            g.used = ++c->graph_clock;
+            *out = g.exec;
+            return DSDNA_OK;
+        }
+        if (!g.exec || (slot->exec && g.used < slot->used)) slot = &g;
+    }
+    if (slot->exec) (void)hipGraphExecDestroy(slot->exec);
+    *slot = dsdna_ctx::StepGraph{};
     hipGraph_t g = nullptr;
     HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
@@ -725,14 +747,15 @@ static dsdna_status build_graph(dsdna_ctx *c, int steps, int K)
         return fail(c, DSDNA_EDEVICE, "graph capture failed: %s",
                     hipGetErrorString(e != hipSuccess ? e : e2));
     }
-    e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
-    if (e != hipSuccess) {
-        c->gexec = nullptr;
-        return fail(c, DSDNA_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
-    }
-    c->gsteps = steps;
-    c->gK = K;
+    if (e != hipSuccess) return fail(c, DSDNA_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+    slot->exec = x;
+    slot->steps = steps;
+    slot->K = K;
+    slot->used = ++c->graph_clock;
+    *out = x;
     return DSDNA_OK;
 }
 
@@ -813,7 +836,7 @@ static dsdna_status run_steps(dsdna_ctx *c, int64_t n_steps, std::vector<double>
     int64_t k = 0;  // launches done
     Ctl h;
     while (k < launches) {
-        const int64_t end = std::min(launches, k + c->sync_batch);
+        int64_t end = std::min(launches, k + c->sync_batch);
         c->sync_batch = std::min(SYNC_STEPS, 2 * c->sync_batch);
         const auto launch_fail = [&](hipError_t e) {
             return give_up(fail(c, DSDNA_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e)));
@@ -827,22 +850,25 @@ static dsdna_status run_steps(dsdna_ctx *c, int64_t n_steps, std::vector<double>
         if (!prof && G0 > 0) {
             // graphs end before the run's last launch, which writes the
             // full-step state; eager steps up to the next rebuild, then whole
-            // graphs
+            // graphs.  Short of the run's end the batch is stretched to a
+            // whole number of graphs, so that the next starts on a rebuild.
             const int64_t gend = end == launches ? end - 1 : end;
             while (c->age != 0 && k < gend) {
                 if ((e = one(k)) != hipSuccess) return launch_fail(e);
                 ++k;
             }
             const int G = (G0 + c->K - 1) / c->K * c->K;
-            if (c->age == 0 && gend - k >= G) {
-                if (!c->gexec || c->gsteps != G || c->gK != c->K) {
-                    if ((st = build_graph(c, G, c->K))) return st;
-                }
-                while (gend - k >= G) {
-                    if ((e = hipGraphLaunch(c->gexec, c->stream)) != hipSuccess) return launch_fail(e);
+            int64_t n_g = (gend - k) / G;
+            if (end != launches) n_g = std::min((gend - k + G - 1) / G, (launches - 1 - k) / G);
+            if (c->age == 0 && n_g > 0) {
+                hipGraphExec_t gx = nullptr;
+                if ((st = step_graph(c, G, c->K, &gx))) return st;
+                for (int64_t q = 0; q < n_g; ++q) {
+                    if ((e = hipGraphLaunch(gx, c->stream)) != hipSuccess) return launch_fail(e);
                     k += G;
                     c->rebuilt = true;
                 }
+                end = std::max(end, k);
             }
         }
         for (; k < end; ++k)

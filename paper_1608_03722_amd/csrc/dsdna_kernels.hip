@@ -23,6 +23,9 @@
 #include <math.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <utility>
 #include <stdint.h>
 
 #include "dsdna.h"
@@ -2236,6 +2239,28 @@ __global__ void __launch_bounds__(256) k_bubble_rep(const StepArgs *__restrict__
 
 static dim3 tiles_grid(const StepArgs &a) { return dim3((unsigned)a.n_tiles_pad); }
 
+// Workgroups of `kernel` (with `threads` threads) resident on the current
+// device at once, rounded down to a multiple of 8 (at least 8); cached per
+// device and kernel.
+static int resident_workgroups(const void *kernel, int threads)
+{
+    static std::mutex mu;
+    static std::map<std::pair<int, const void *>, int> known;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 8;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_pair(dev, kernel);
+    const auto it = known.find(key);
+    if (it != known.end()) return it->second;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 8;
+    const int g = std::max(8, per_cu * cus / 8 * 8);
+    known[key] = g;
+    return g;
+}
+
 // Grid of a rebuild kernel over `items` work items: at most REBUILD_GRID
 // workgroups, a multiple of 8 (the XCD-aware grid-stride loops need it).
 static dim3 rebuild_grid(int64_t items)
@@ -2266,9 +2291,16 @@ hipError_t launch_scatter(const StepArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+// The list build runs as many workgroups as are resident at once, each
+// walking its share of the record blocks: its per-workgroup set-up (control
+// block, arguments, the histogram clear) is paid once per workgroup, and no
+// workgroup waits for a slot behind the first wave of them.
 hipError_t launch_build(const StepArgs &a, const StepArgs *dA, hipStream_t s)
 {
-    const dim3 g = rebuild_grid((a.n_nt + EXCL_THREADS - 1) / EXCL_THREADS);
+    const int64_t nblk = (a.n_nt + EXCL_THREADS - 1) / EXCL_THREADS;
+    const void *k = a.g.any_open ? reinterpret_cast<const void *>(k_build<true>)
+                                 : reinterpret_cast<const void *>(k_build<false>);
+    const dim3 g((unsigned)std::min<int64_t>((nblk + 7) / 8 * 8, resident_workgroups(k, EXCL_THREADS)));
     if (a.g.any_open)
         hipLaunchKernelGGL(k_build<true>, g, dim3(EXCL_THREADS), 0, s, dA, a.b.srec, a.b.sid, a.b.scell, a.b.start);
     else

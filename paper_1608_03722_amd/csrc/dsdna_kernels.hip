@@ -1038,6 +1038,11 @@ __global__ void __launch_bounds__(WG_THREADS, 5) k_step(const StepArgs *__restri
     __shared__ TileLds<real> S;
     __shared__ float s_v2[WG_THREADS / 64];
     const StepArgs &a = *A;
+    // the loads of a starting workgroup are issued ahead of the arithmetic
+    // of the workgroups already in their force phase on the same SIMDs
+    // (wave priority, lowered again before the staging): measured 4% faster
+    // at 1 Mbp
+    __builtin_amdgcn_s_setprio(1);
     const Ctl ctl = cload(a.b.ctl);
     if (halted(ctl, ctl.step)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1069,6 +1074,7 @@ __global__ void __launch_bounds__(WG_THREADS, 5) k_step(const StepArgs *__restri
     SiteForces<real> f;
     f.b = v3<real>(0, 0, 0);
     f.p = f.b;
+    __builtin_amdgcn_s_setprio(0);
     if (mode != MODE_FROM_FORCES) {
         stage_site(a, S, site);
         f = tile_forces<real, DAMP>(a, S, ri, tile, fexv, ALL_TERMS, step, nullptr);

@@ -346,6 +346,31 @@ def test_deterministic_graph_and_resume(D):
         assert np.array_equal(x, y)
 
 
+def test_long_runs_with_graphs_match_eager(D):
+    """Over many control-block batches, with the rebuild interval adapting
+    (a thin skin) and step graphs of several lengths taken from the cache, the
+    state equals the eager run's bit for bit, also when the run is split into
+    calls of uneven length."""
+    P, S, st = _oracle_state(n_bp=300, steps=300, seed=4)
+    cfg = dict(n_bp=np.array([300]), **dict(zip(("bead", "patch"), O.sites_from_bodies(P, st.R, st.u))))
+    outs, intervals = [], set()
+    for gsteps, calls in ((0, (1700,)), (7, (1700,)), (50, (1700,)), (13, (333, 1, 900, 466))):
+        sim = _gpu(D, cfg, seed=4, graph_steps=gsteps, skin=0.15)
+        sim.set_state(st.R, st.V, st.u, st.L, 0)
+        intervals.add(sim.neighbour_stats()["interval"])
+        for n in calls:
+            sim.step(n)
+            intervals.add(sim.neighbour_stats()["interval"])
+        outs.append(sim.state())
+        assert sim.neighbour_stats()["steps"] == 1700
+        sim.close()
+    assert len(intervals) > 1  # the interval moved during the runs
+    for o in outs[1:]:
+        assert o[4] == outs[0][4]
+        for x, y in zip(o[:4], outs[0][:4]):
+            assert np.array_equal(x, y)
+
+
 def test_error_paths(D):
     """A backbone bond at r >= R0 stops the run with EBOND and its location."""
     bead, patch = synth.ideal_helix(20)

@@ -3,11 +3,13 @@
 Workload (default): 1 Mbp linear dsDNA (2e6 nucleotides) pre-coiled as a
 random-walk helix in a periodic cube at 2% bead volume fraction, FP32 forces
 with FP64 positions and integrator.  A step is one pass of the whole hot path:
-excluded volume from the cell list, every bonded term, external loads,
-Langevin forces, the rigid-body velocity-Verlet update and the re-binning
-(histogram, scan, scatter).  Also measures the batched-replica path against
-one context per replica on the 256-replica tethered workload, and times the
-FP64 oracle on a bounded sample on the host.  Prints one JSON line.
+the excluded volume of the neighbour-list pairs, every bonded term and the
+chain-local excluded volume, external loads, Langevin forces, the rigid-body
+velocity-Verlet update and the skin test, plus, every few steps as the
+displacements require, the binning, scan, scatter and list build of the
+neighbour-list rebuild.  Also measures the batched-replica path against one
+context per replica on the 256-replica tethered workload, and times the FP64
+oracle on a bounded sample on the host.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 1mbp|100bp|10kbp|replicas|denat|denat_seq|lp300|rings|sm]
 """
@@ -16,6 +18,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -880,6 +883,11 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     done = to_time - left
+    if failure is not None and to_time > 0:
+        # the steps of the failing chunk that completed before the stop (the
+        # kernels after the failing step return at once)
+        done += max(0, sim.state()[4] - (args.warmup + done))
+        failure["timed_steps"] = done
     value = n_nt * done / elapsed if done > 0 else 0.0
     ms_step = 1e3 * elapsed / max(done, 1)
     log("timed %d steps in %.3f s: %.4g nt-steps/s" % (done, elapsed, value))
@@ -915,8 +923,9 @@ def main():
     kernels = {}
     for k, ms in prof.items():
         nbytes = per_step.get(k, 0.0)
-        kernels[k] = {"ms": round(ms, 5), "bytes": int(nbytes),
-                      "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1) if ms > 0 else None}
+        ok = math.isfinite(nbytes) and math.isfinite(ms)
+        kernels[k] = {"ms": round(ms, 5) if math.isfinite(ms) else None, "bytes": int(nbytes) if ok else None,
+                      "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1) if ok and ms > 0 else None}
     dom = "step"
     achieved = per_step[dom] / (prof[dom] * 1e-3) / 1e9
     traffic = measured_traffic() if args.config == "1mbp" else None
@@ -924,7 +933,7 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "k_step<float, false>", "bytes_per_nt": STEP_BYTES_PER_NT,
-            "whole_step": {"bytes": int(whole_bytes),
+            "whole_step": {"bytes": int(whole_bytes) if math.isfinite(whole_bytes) else None,
                            "bytes_per_nt": round(whole_bytes / n_nt, 1),
                            "achieved": round(whole_bytes / (ms_step * 1e-3) / 1e9, 1),
                            "frac": round(whole_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

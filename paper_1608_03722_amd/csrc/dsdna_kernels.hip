@@ -494,7 +494,7 @@ template <typename real>
 __device__ __forceinline__ V3<real> get3(const real *src) { return v3(src[0], src[1], src[2]); }
 
 constexpr uint32_t ALL_TERMS = (1u << DSDNA_NTERMS) - 1u;
-static_assert(WG_THREADS - TILE_NT == 4 * HALO_BP, "the spare threads of a tile stage its halo");
+static_assert(WG_THREADS - TILE_NT >= 4 * HALO_BP, "the spare threads of a tile stage its halo");
 
 // Whether the tile slot of base pair bp (relative to the replica start,
 // possibly outside it) holds a site: on a ring the two base pairs either
@@ -510,7 +510,7 @@ __device__ __forceinline__ bool site_exists(const Tile &tile, int bp)
 
 // The rigid body a thread loads and stages in LDS (index l <-> bp
 // n0 - 2 + l/2, strand l & 1): its own nucleotide for t < TILE_NT, a halo
-// site for the spare threads.
+// site for the next 4 HALO_BP threads, none for the rest.
 struct StagedSite {
     int l;         // LDS site index
     bool valid;    // the site exists in the replica
@@ -525,7 +525,7 @@ __device__ __forceinline__ StagedSite load_site(const StepArgs &a, const RepInfo
     StagedSite st;
     st.l = t < TILE_NT ? t + 2 * HALO_BP : (t - TILE_NT < 2 * HALO_BP ? t - TILE_NT : t);
     int bp = n0 - HALO_BP + (st.l >> 1);
-    st.valid = site_exists(tile, bp);
+    st.valid = st.l < TILE_SITES && site_exists(tile, bp);
     if (tile.ring) bp = bp < 0 ? bp + tile.n_bp : (bp >= tile.n_bp ? bp - tile.n_bp : bp);
     st.i = ri.off + 2 * (int64_t)bp + (st.l & 1);
     st.R = v3(0.0, 0.0, 0.0);

@@ -14,13 +14,13 @@ from oracle import oracle as O
 
 pytestmark = pytest.mark.gpu
 
-# linear chains of 300 and 500 bp (tiles of 122 bp), a ring of 366 bp (three
+# linear chains of 300 and 500 bp (tiles of 120 bp), a ring of 360 bp (three
 # tiles), a 20 bp chain opened completely
-LENS = (300, 500, 366, 20)
+LENS = (300, 500, 360, 20)
 OPEN = {
-    0: [(0, 4), (118, 9), (130, 140), (299, 1)],       # at the start, across 122, past a whole tile, the end
-    1: [(10, 1), (121, 2), (243, 2), (250, 3), (480, 20)],
-    2: [(360, 6), (0, 5), (100, 30), (200, 1)],       # through the ring's seam (361..365, 0..4)
+    0: [(0, 4), (118, 9), (130, 140), (299, 1)],       # at the start, across 120, past a whole tile, the end
+    1: [(10, 1), (121, 2), (239, 2), (250, 3), (480, 20)],
+    2: [(354, 6), (0, 5), (100, 30), (200, 1)],       # through the ring's seam (354..359, 0..4)
     3: [(0, 20)],
 }
 

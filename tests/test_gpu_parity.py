@@ -217,11 +217,11 @@ def test_replicas_with_loads(D):
 def test_tiny_and_tile_edge_chains(D):
     """Chains of 1-4 base pairs, where the terms that would reach past an end
     are absent (a 1 bp chain has only its hydrogen bond, 2 bp no bending), and
-    chains one short of, exactly at and one past one and two tiles of 122 bp,
+    chains one short of, exactly at and one past one and two tiles of 120 bp,
     batched in one context from an oracle-thermalised state: every term, the
     open flags and the per-replica energies, with FP32 and FP64 forces; then
     50 FP64 steps against the oracle's trajectory."""
-    lens = [1, 2, 3, 4, 121, 122, 123, 244, 245]
+    lens = [1, 2, 3, 4, 119, 120, 121, 239, 240, 241]
     parts = [synth.ideal_helix(m, origin=(12.0 * k, 0.0, 0.0)) for k, m in enumerate(lens)]
     bead, patch = synth.concat_replicas(parts)
     cfg = dict(n_bp=np.array(lens), bead=bead, patch=patch)

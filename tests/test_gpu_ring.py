@@ -13,10 +13,10 @@ from oracle import oracle as O
 
 pytestmark = pytest.mark.gpu
 
-# one-tile ring, a ring whose seam falls 1 bp into its second tile (tiles of
-# 122 bp), a ring of exactly three tiles, and a linear chain in the same
-# context
-RINGS = (30, 123, 366)
+# one-tile ring, a ring whose seam falls 3 bp into its second tile (tiles of
+# 120 bp; a ring's length is a multiple of 3), a ring of exactly three tiles,
+# and a linear chain in the same context
+RINGS = (30, 123, 360)
 
 
 @pytest.fixture(scope="module")
@@ -115,7 +115,7 @@ def test_ring_fp64_trajectory_matches_oracle(D):
 
 
 def test_ring_single_strand_rule_across_the_seam(D):
-    """Base pairs n-1, 0, 1 of the 126 bp ring opened (the two bodies of each
+    """Base pairs n-1, 0, 1 of the 123 bp ring opened (the two bodies of each
     moved 0.18 out of the ring plane on opposite sides, so that the patches
     are past the 0.3 H-bond cutoff): one
     bubble of 3 through the seam, whose dihedrals and bending triple the

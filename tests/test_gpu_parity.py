@@ -231,6 +231,11 @@ def test_tiny_and_tile_edge_chains(D):
     assert E[0, O.T["bond"]] == 0.0 and E[1, O.T["bend"]] == 0.0   # the terms a short chain lacks
     for fp64, tol in ((0, 1e-5), (1, 1e-10)):
         sim = _gpu(D, cfg, seed=17, force_fp64=fp64)
+        # the lengths sit at the edges of the library's tiles, and every
+        # replica has its own tiles
+        tb, wg, nt = D.dsdna_get_tiling(sim.ctx)
+        assert {tb - 1, tb, tb + 1, 2 * tb - 1, 2 * tb, 2 * tb + 1} <= set(lens)
+        assert 2 * tb + 12 <= wg and nt == sum(-(-m // tb) for m in lens)
         sim.set_state(st.R, st.V, st.u, st.L, st.step)
         _compare_terms(D, sim, P, S, st.R, st.u, tol, use_cells=True)
         np.testing.assert_array_equal(sim.bp_open(), op)

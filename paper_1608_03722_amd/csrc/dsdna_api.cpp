@@ -416,10 +416,12 @@ static dsdna_status configure_grid_for(dsdna_ctx *c, std::vector<RepInfo> reps)
     g.any_open = 0;
     for (int r = 0; r < c->n_rep; ++r)
         for (int k = 0; k < 3; ++k) g.any_open |= (reps[r].flags & (REP_PER_X << k)) ? 0 : 1;
+    g.fast_screen = c->n_rep == 1;
     for (int r = 0; r < c->n_rep; ++r) {
         RepInfo &ri = reps[r];
         for (int k = 0; k < 3; ++k)
             ri.qlen[k] = (ri.flags & (REP_PER_X << k)) ? (float)(ri.len[k] / 4294967296.0) : (float)(1.0 / OPEN_QINV);
+        g.fast_screen = g.fast_screen && ri.qlen[0] == ri.qlen[1] && ri.qlen[1] == ri.qlen[2];
     }
     const bool new_buckets = c->a.g.nbucket != (int32_t)nb || !c->a.b.count;
     uint32_t *count = nullptr;

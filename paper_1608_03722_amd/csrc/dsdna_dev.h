@@ -146,6 +146,7 @@ struct Grid {
     double h;                // cell edge for open dims
     int32_t nbucket;
     int32_t any_open;        // some replica has an open edge
+    int32_t fast_screen;     // one replica, the same fixed-point unit along x, y, z
 };
 
 // Device buffers of one context.

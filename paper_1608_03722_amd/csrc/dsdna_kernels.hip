@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <utility>
 #include <stdint.h>
 
@@ -1580,23 +1581,35 @@ __global__ void __launch_bounds__(EXCL_THREADS, 8) k_build(const StepArgs *__res
     const bool open_any = any_open && !(px && py && pz);
     const int *c = B.c;
 
-    // list test of candidate o (sorted position q): every test evaluated,
-    // no branch
-    auto test = [&](const BeadRec &o, int q) -> bool {
+    // list test of candidate o: every test evaluated, no branch.  (A
+    // candidate is never the bead itself: its own bucket is searched from
+    // the next record on, and the host keeps the 27 cells around any cell in
+    // distinct buckets.)  FAST: one replica (no record of another replica
+    // shares a bucket) and the same fixed-point unit along x, y and z, so the
+    // squared distance is compared in those units.
+    const float rcs2u = rcs2 / (qx * qx), rcx2u = rcx2 / (qx * qx);
+    auto test = [&](const BeadRec &o, auto fast) -> bool {
         const uint32_t ot = o.tag & 3u;
         const bool same = ((ot ^ mt) & 1u) == 0u;
-        const float dx = (float)(int32_t)(o.x - me.x) * qx;
-        const float dy = (float)(int32_t)(o.y - me.y) * qy;
-        const float dz = (float)(int32_t)(o.z - me.z) * qz;
-        const float r2f = dx * dx + dy * dy + dz * dz;
-        return (r2f < (same ? rcs2 : rcx2)) & (((accept >> ot) & 1u) != 0u) & ((o.tag >> 2) == rep) & (q != p);
+        const float dx = (float)(int32_t)(o.x - me.x);
+        const float dy = (float)(int32_t)(o.y - me.y);
+        const float dz = (float)(int32_t)(o.z - me.z);
+        if constexpr (decltype(fast)::value) {
+            const float r2u = dx * dx + dy * dy + dz * dz;
+            return (r2u < (same ? rcs2u : rcx2u)) & (((accept >> ot) & 1u) != 0u);
+        } else {
+            const float ex = dx * qx, ey = dy * qy, ez = dz * qz;
+            const float r2f = ex * ex + ey * ey + ez * ez;
+            return (r2f < (same ? rcs2 : rcx2)) & (((accept >> ot) & 1u) != 0u) & ((o.tag >> 2) == rep);
+        }
     };
+    const std::false_type general{};
     // a candidate that passed the test (or, with `check`, one to test):
     // into the list unless it is chain-local.  The lanes of a wave that
     // append in the same call take their slots with one atomic between them.
     auto hit = [&](int q, bool check) {
         const BeadRec o = srec[q];
-        bool keep = !check || test(o, q);
+        bool keep = !check || test(o, general);
         // open edges: the fixed-point difference is exact only modulo 2^32
         // units, so a record of a far cell that shares a bucket with a
         // neighbour cell is rejected by its cell coordinates
@@ -1632,53 +1645,45 @@ __global__ void __launch_bounds__(EXCL_THREADS, 8) k_build(const StepArgs *__res
     // packed s_pre[1..4] that are <= k (no borrow between bytes while k, pre
     // < 128); larger k take the plain search
     const int nfast = min(total, 127);
-    // sorted position of stream entry k (clamped into the stream; entries
-    // past the end are fetched again and ignored)
+    // sorted position of stream entry k < nfast
     auto locate = [&](int k) -> int {
-        k = k < nfast ? k : nfast - 1;
         uint32_t kb = (uint32_t)k | 0x80u;
         kb |= kb << 8;
         kb |= kb << 16;
         const int q = __popc((kb - pk) & 0x80808080u);
         return k + s_sh[q][src];
     };
-    // software pipeline: the records of the next U entries are in flight
-    // while the current U are evaluated (two register sets, so the pipeline
-    // needs no copies)
-    constexpr int U = 2;
-    // The stream is screened without branches: a candidate within the list
-    // cutoff sets bit k of the hit masks (k < 128), and the hits are
-    // processed afterwards.
+    // The stream is screened without branches, SW entries at a time: the
+    // entry index k is the same in every lane (so its byte pattern is scalar
+    // arithmetic), a lane past the end of its own stream fetches some valid
+    // record and ignores it, and a candidate within the list cutoff sets bit
+    // k of the hit masks (k < 128); the hits are processed afterwards.
+    const uint32_t last = (uint32_t)(a.n_nt - 1);
     uint64_t hit0 = 0, hit1 = 0;
-    auto mark = [&](int k, bool h) {
-        const uint64_t bit = (uint64_t)h << (k & 63);
-        if (k < 64) hit0 |= bit;  // k is the same in every lane
-        else hit1 |= bit;
+    constexpr int SW = 4;  // entries per pass (a power of 2, so no pass straddles bit 64)
+    auto screen = [&](auto fast) {
+        for (int k0 = 0; k0 < nfast; k0 += SW) {
+            BeadRec o[SW];
+#pragma unroll
+            for (int v = 0; v < SW; ++v) {
+                const uint32_t at = (uint32_t)locate(k0 + v);
+                o[v] = srec[min(at, last)];
+            }
+            uint32_t bits = 0u;
+#pragma unroll
+            for (int v = 0; v < SW; ++v) bits |= (uint32_t)test(o[v], fast) << v;
+            if (k0 < 64) hit0 |= (uint64_t)bits << k0;
+            else hit1 |= (uint64_t)bits << (k0 - 64);
+        }
     };
-    if (nfast > 0) {
-        BeadRec oa[U], ob[U];
-        int pa[U], pb[U];
-#pragma unroll
-        for (int v = 0; v < U; ++v) {
-            pa[v] = locate(v);
-            oa[v] = srec[pa[v]];
-        }
-        for (int k0 = 0; k0 < nfast; k0 += 2 * U) {
-#pragma unroll
-            for (int v = 0; v < U; ++v) {
-                pb[v] = locate(k0 + U + v);
-                ob[v] = srec[pb[v]];
-            }
-#pragma unroll
-            for (int v = 0; v < U; ++v) mark(k0 + v, (k0 + v < nfast) & test(oa[v], pa[v]));
-#pragma unroll
-            for (int v = 0; v < U; ++v) {
-                pa[v] = locate(k0 + 2 * U + v);
-                oa[v] = srec[pa[v]];
-            }
-#pragma unroll
-            for (int v = 0; v < U; ++v) mark(k0 + U + v, (k0 + U + v < nfast) & test(ob[v], pb[v]));
-        }
+    if (a.g.fast_screen) screen(std::true_type{});
+    else screen(general);
+    // entries past the lane's own stream
+    if (nfast < 64) {
+        hit0 &= (1ull << nfast) - 1ull;
+        hit1 = 0;
+    } else {
+        hit1 &= (1ull << (nfast - 64)) - 1ull;
     }
     for (uint64_t h = hit0; h; h &= h - 1) hit(locate(__builtin_ctzll(h)), false);
     for (uint64_t h = hit1; h; h &= h - 1) hit(locate(64 + __builtin_ctzll(h)), false);

@@ -1478,7 +1478,7 @@ __global__ void __launch_bounds__(EXCL_THREADS, 8) k_build(const StepArgs *__res
     __shared__ int s_pre[5][EXCL_THREADS];
     __shared__ uint32_t s_pk[EXCL_THREADS];
     __shared__ int s_tot[EXCL_THREADS];
-    __shared__ uint8_t s_wr[EXCL_THREADS];
+    __shared__ uint16_t s_wr[EXCL_THREADS];
     __shared__ int s_hist[64];
     __shared__ int s_order[EXCL_THREADS];
     const int nblk = (int)((a.n_nt + EXCL_THREADS - 1) / EXCL_THREADS);
@@ -1492,8 +1492,11 @@ __global__ void __launch_bounds__(EXCL_THREADS, 8) k_build(const StepArgs *__res
     // q sits at k + s_sh[q] in the sorted records; s_pre[q] = first stream
     // position of range q.  Range 0: the rest of the own bucket and the next
     // cell; ranges 1..4: rows (dy, dz) = (+1, 0), (-1, +1), (0, +1), (+1, +1)
-    // over the needed dx.  A range that wraps (periodic x or bucket index)
-    // is empty here and walked cell by cell later (bit q of s_wr).
+    // over the needed dx.  At a periodic x face the neighbour cell across
+    // the face is not next to the others in bucket order: the range keeps
+    // the contiguous cells and that one cell is walked later (bit 8 + q of
+    // s_wr).  A range whose buckets would wrap past the end of the bucket
+    // array (rare) is empty here and walked cell by cell (bit q).
     int key = 0;
     {
         int total = 0;
@@ -1515,22 +1518,29 @@ __global__ void __launch_bounds__(EXCL_THREADS, 8) k_build(const StepArgs *__res
             for (int q = 0; q < 5; ++q) {
                 int l0 = 0, h0 = 0;
                 bool wr = false;
+                // the cells cx + dlo .. cx + dhi are contiguous buckets; a
+                // neighbour across a periodic x face is walked separately
+                const bool face_lo = B.px && B.c[0] == 0 && xm, face_hi = B.px && B.c[0] == ncx - 1 && xp;
+                const int dlo = (xm && !face_lo) ? -1 : 0, dhi = (xp && !face_hi) ? 1 : 0;
+                bool face = false;
                 if (q == 0) {
-                    wr = xp && ((B.px && B.c[0] == ncx - 1) || B.kown + 1u > a.g.mask);
+                    face = face_hi;
+                    wr = dhi > 0 && B.kown == a.g.mask;
                     l0 = p + 1;
-                    h0 = wr ? p + 1 : start[B.kown + (xp ? 2 : 1)];
+                    h0 = wr ? p + 1 : start[B.kown + dhi + 1];
                 } else {
                     const int dy = q == 1 ? 1 : q - 3, dz = q == 1 ? 0 : 1;
                     const bool need = (dy > 0 ? yp : (dy < 0 ? ym : true)) && (dz == 0 || zp);
                     if (need) {
                         const int cy = wrap(B.c[1] + dy, ncy, B.py), cz = wrap(B.c[2] + dz, ncz, B.pz);
-                        const uint32_t k0 = bucket_of(a.g, B.c[0] - 1, cy, cz, (int)B.rep);
-                        wr = (B.px && (B.c[0] == 0 || B.c[0] == ncx - 1)) || k0 + 2u > a.g.mask;
-                        l0 = wr ? 0 : start[k0 + (xm ? 0 : 1)];
-                        h0 = wr ? 0 : start[k0 + (xp ? 3 : 2)];
+                        const uint32_t kc = bucket_of(a.g, B.c[0], cy, cz, (int)B.rep);
+                        face = face_lo || face_hi;
+                        wr = (dlo < 0 && kc == 0u) || (dhi > 0 && kc == a.g.mask);
+                        l0 = wr ? 0 : start[(int)kc + dlo];
+                        h0 = wr ? 0 : start[(int)kc + dhi + 1];
                     }
                 }
-                wrapped |= (uint32_t)wr << q;
+                wrapped |= ((uint32_t)wr << q) | ((uint32_t)(face && !wr) << (8 + q));
                 s_pre[q][t] = total;
                 s_sh[q][t] = l0 - total;
                 if (q >= 1) pk |= (uint32_t)min(total, 127) << (8 * (q - 1));
@@ -1542,7 +1552,7 @@ __global__ void __launch_bounds__(EXCL_THREADS, 8) k_build(const StepArgs *__res
         }
         s_pk[t] = pk;
         s_tot[t] = total;
-        s_wr[t] = (uint8_t)wrapped;
+        s_wr[t] = (uint16_t)wrapped;
         // (clamped: every key is a histogram bin, so s_order below is always a
         // full permutation of the workgroup's threads)
         key = min(max(total >> 1, 0), 63);
@@ -1692,26 +1702,40 @@ __global__ void __launch_bounds__(EXCL_THREADS, 8) k_build(const StepArgs *__res
         for (int r = 1; r < 5; ++r) q = (k >= s_pre[r][src]) ? r : q;
         hit(k + s_sh[q][src], true);
     }
-    // ranges that wrap: cell by cell (rare), over the dx a ghost needs
-    if (wrapped & 0x1Fu) {
+    // cells outside the fast stream: the neighbour across a periodic x face
+    // (bit 8 + q), or every cell of a range that wraps the bucket array
+    // (bit q, rare); their records are screened four per pass
+    if (wrapped & 0x1F1Fu) {
         const int ncx = ri.ncell[0], ncy = ri.ncell[1], ncz = ri.ncell[2];
         auto wrap = [&](int v, int n, bool per_) { return per_ ? (v < 0 ? v + n : (v >= n ? v - n : v)) : v; };
+        auto walk = [&](int lo, int hi) {
+            for (int q0 = lo; q0 < hi; q0 += 4) {
+                BeadRec o[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) o[v] = srec[min(q0 + v, hi - 1)];
+                uint32_t bits = 0u;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) bits |= (uint32_t)((q0 + v < hi) & test(o[v], general)) << v;
+                for (uint32_t b = bits; b; b &= b - 1) hit(q0 + __builtin_ctz(b), false);
+            }
+        };
+        auto cell = [&](int cx, int cy, int cz) {
+            const uint32_t kb = bucket_of(a.g, wrap(cx, ncx, px), cy, cz, (int)rep);
+            walk(start[kb], start[kb + 1]);
+        };
         const int dxlo = (wrapped & 0x20u) ? -1 : 0, dxhi = (wrapped & 0x40u) ? 1 : 0;
 #pragma unroll 1
         for (int q = 0; q < 5; ++q) {
+            const int dy = q == 0 ? 0 : (q == 1 ? 1 : q - 3), dz = q <= 1 ? 0 : 1;
+            const int cy = wrap(c[1] + dy, ncy, py), cz = wrap(c[2] + dz, ncz, pz);
+            if ((wrapped >> (8 + q)) & 1u) cell(c[0] == 0 ? -1 : c[0] + 1, cy, cz);
             if (!((wrapped >> q) & 1u)) continue;
             if (q == 0) {
-                for (int q2 = p + 1; q2 < start[B.kown + 1]; ++q2) hit(q2, true);
-                const uint32_t kb = bucket_of(a.g, wrap(c[0] + 1, ncx, px), c[1], c[2], (int)rep);
-                for (int q2 = start[kb]; q2 < start[kb + 1]; ++q2) hit(q2, true);
+                walk(p + 1, start[B.kown + 1]);
+                cell(c[0] + 1, c[1], c[2]);
                 continue;
             }
-            const int dy = q == 1 ? 1 : q - 3, dz = q == 1 ? 0 : 1;
-            const int cy = wrap(c[1] + dy, ncy, py), cz = wrap(c[2] + dz, ncz, pz);
-            for (int dx = dxlo; dx <= dxhi; ++dx) {
-                const uint32_t kb = bucket_of(a.g, wrap(c[0] + dx, ncx, px), cy, cz, (int)rep);
-                for (int q2 = start[kb]; q2 < start[kb + 1]; ++q2) hit(q2, true);
-            }
+            for (int dx = dxlo; dx <= dxhi; ++dx) cell(c[0] + dx, cy, cz);
         }
     }
     }  // p < n_nt

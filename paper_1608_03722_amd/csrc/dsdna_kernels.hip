@@ -1450,8 +1450,8 @@ __device__ __forceinline__ bool local_pair(const RepInfo &ri, int64_t i, int64_t
 // differences; the list cutoffs carry a slack for their FP32 evaluation).
 constexpr int EXCL_THREADS = 256;  // records per workgroup (sorted by load together)
 
-// (8 waves per SIMD: the search is latency-bound, and 64 VGPRs cost two
-// spilled registers; measured faster at 1 Mbp than 6 waves at 75 VGPRs)
+// (8 waves per SIMD: the search is latency-bound, and 64 VGPRs cost a few
+// spilled registers; measured faster at 1 Mbp than 6 waves at 72-75 VGPRs)
 template <bool any_open>
 __global__ void __launch_bounds__(EXCL_THREADS, 8) k_build(const StepArgs *__restrict__ A, const BeadRec *__restrict__ srec,
                                               const int *__restrict__ sid, const int4 *__restrict__ scell,

@@ -145,7 +145,11 @@ def test_forces_periodic_box(D):
     b, p = O.sites_from_bodies(P, R, u)
     pairs = O.wca_pairs(P, S, b, use_cells=True)
     seam = [(i, j) for i, j in pairs if abs(b[i, 2] - b[j, 2]) > box[0, 5] / 2]
-    assert len(pairs) > 100 and len(seam) >= 1
+    # contacts across the x face: the list build screens the cell across a
+    # periodic x face apart from the contiguous cells of its row
+    wx = np.mod(b[:, 0], box[0, 3])
+    xface = [(i, j) for i, j in pairs if abs(wx[i] - wx[j]) > box[0, 3] / 2]
+    assert len(pairs) > 100 and len(seam) >= 1 and len(xface) >= 50
     ref = None
     for cell, skin in ((0.0, 0.0), (1.83, 0.3), (2.4, 1.0)):
         for lg in (12, 16):
